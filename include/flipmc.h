@@ -1,0 +1,222 @@
+/*
+ * flipmc.h -- C ABI of the MI355X (gfx950) flip Monte Carlo engine.
+ *
+ * The engine samples the NVT ensemble of M identical rigid triangular
+ * molecules with sites A, B, C (diameters 0.9, 1.0, 1.1) interacting through
+ * the site-site WCA potential (Simon, Barrat & Berthier, Sec. II.A, Eq. 1) in
+ * a cubic periodic box at site density 1.2, with Metropolis sweeps that mix
+ * whole-molecule translations, rotations and the intramolecular "flip" move
+ * of Sec. II.B (exchange the types of two sites of one molecule).
+ *
+ * Conventions for every call:
+ *   - Return value: MC_OK (0) or a negative MC_E* code; mc_last_error() then
+ *     returns a thread-local message.  No call aborts or throws.
+ *   - Device memory is owned by the caller: mc_init_system() carves its
+ *     state out of one caller-provided device buffer of at least
+ *     mc_required_bytes() bytes, which must outlive the system.  The library
+ *     owns only the opaque handles and small host mirrors.
+ *   - All GPU work of a system is enqueued on the HIP stream given at
+ *     mc_init_system() (NULL = the null stream).  mc_sweep() and
+ *     mc_batch_run() only enqueue; calls that return host data (mc_energy,
+ *     mc_observables, mc_get_state, mc_samples) synchronise that stream.
+ *   - Host arrays are plain C arrays in the layouts stated per call; device
+ *     pointers are marked as such.
+ */
+#ifndef FLIPMC_H
+#define FLIPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    MC_OK = 0,
+    MC_EINVAL = -1,      /* invalid argument or parameter                      */
+    MC_ENOMEM = -2,      /* buffer too small or host allocation failed         */
+    MC_EDEVICE = -3,     /* a HIP runtime call failed                          */
+    MC_EGEOM = -4,       /* cell decomposition does not fit the box            */
+    MC_ENONFINITE = -5,  /* total energy is not finite (overlapping sites)     */
+    MC_EBUSY = -6,       /* batch has no free slot                             */
+    MC_ENOTIMPL = -7     /* combination not supported                          */
+};
+
+/* Precision of the pair-energy differences.  The state (centres of mass,
+ * quaternions), the proposals, the acceptance test, the accumulated energy
+ * and the periodic total-energy re-sum are always FP64. */
+enum { MC_FP64 = 0, MC_FP32_DE = 1 };
+
+enum { MC_TRANSLATE = 0, MC_ROTATE = 1, MC_FLIP = 2 };
+
+/* mc_params.flags: keep the working arrays in HBM even when the system would
+ * fit in one workgroup's LDS (the path large systems take). */
+enum { MC_FLAG_HBM_STATE = 1 };
+
+#define MC_GOFR_MAX_BINS 256
+#define MC_C2_MAX 32
+
+/* Parameters of one system.  mc_params_default() fills the paper's values
+ * (Sec. II.A: sigma = 0.9 / 1.0 / 1.1, density 1.2; Sec. II.B: p_flip = 0.2). */
+typedef struct {
+    uint32_t n_molecules;      /* M (>= 1, <= 65535)                                 */
+    uint32_t precision;        /* MC_FP64 or MC_FP32_DE                              */
+    double   density;          /* sites per unit volume, N / V with N = 3 M          */
+    double   temperature;      /* T > 0, k_B = 1                                     */
+    double   sigma[3];         /* diameters of types A, B, C                         */
+    double   bond_length;      /* side of the rigid equilateral triangle; <= 0 picks
+                                  b*, the minimum of WCA + FENE (Eq. 1 + Eq. 2) of a
+                                  sigma_ij = 1 bond                                   */
+    double   p_flip;           /* probability that a trial is a flip                 */
+    double   p_translate;      /* probability of a translation; rotations get the rest */
+    double   max_displacement; /* translation: uniform in [-d, d) per component      */
+    double   max_rotation;     /* rotation: angle uniform in [-theta, theta), axis
+                                  uniform on the sphere                               */
+    uint64_t seed;             /* Philox4x32-10 key                                  */
+    uint32_t colours_per_axis; /* k of the checkerboard (>= 2); 0 = choose           */
+    uint32_t cells_per_side;   /* n_c, multiple of k, (k-1) L / n_c >= W; 0 = choose  */
+    uint32_t resum_interval;   /* sweeps between FP64 re-sums of E (0 = never)       */
+    uint32_t obs_interval;     /* sweeps between E/M samples (0 = never)             */
+    uint32_t gofr_interval;    /* sweeps between g(r) frames (0 = never)             */
+    uint32_t obs_start;        /* samples are taken from this sweep on (relative to
+                                  the observable origin, see mc_reset_observables)    */
+    uint32_t max_samples;      /* capacity of the E/M and drift sample arrays        */
+    uint32_t flags;            /* MC_FLAG_* bits                                     */
+    double   gofr_dr;          /* g(r) bin width; r_max = min(L/2, 5)                */
+} mc_params;
+
+typedef struct mc_system mc_system;
+typedef struct mc_batch mc_batch;
+
+/* One attempted move, written by the device when a decision log is enabled. */
+typedef struct {
+    double   delta_e;    /* E_m(new) - E_m(old) over the moved sites, as computed  */
+    double   scale;      /* E_m(new) + E_m(old) over the moved sites               */
+    double   t_log_u;    /* T ln(u_acc) of the Metropolis test                     */
+    uint64_t sweep;
+    uint32_t molecule;
+    uint8_t  move;       /* MC_TRANSLATE / MC_ROTATE / MC_FLIP                     */
+    uint8_t  accepted;
+    uint8_t  exited;     /* translation left the molecule's cell: rejected        */
+    uint8_t  axis;       /* flip axis site, 255 for other moves                    */
+    uint32_t pair_terms; /* site-pair terms inside the cut-off, old + new          */
+    uint32_t pad;
+} mc_move_record;        /* 48 bytes */
+
+/* Host-side snapshot of a system's accumulators (mc_observables). */
+typedef struct {
+    uint64_t sweep;              /* sweeps done since mc_init_system              */
+    uint64_t attempts[3];        /* per move kind                                  */
+    uint64_t accepts[3];
+    uint64_t exits;              /* translations rejected for leaving their cell   */
+    uint64_t pair_terms;         /* interacting site-pair terms evaluated          */
+    uint64_t pair_tests;         /* candidate site-pair distance tests             */
+    double   e_acc;              /* E_0 + sum of accepted dE (FP64)                */
+    double   e_resum;            /* last FP64 re-sum                               */
+    double   drift;              /* e_acc - e_resum at the last re-sum             */
+    double   max_abs_drift;      /* over all re-sums except the first window       */
+    uint64_t resum_sweep;        /* sweep of the last re-sum                        */
+    uint32_t n_energy_samples;
+    uint32_t n_drift_samples;
+    double   energy_sum;         /* sum of E/M samples                             */
+    double   energy_sumsq;
+    uint32_t n_gofr_frames;
+    uint32_t gofr_nbins;
+    double   gofr_dr;
+    double   gofr_rmax;
+    uint64_t gofr_all[MC_GOFR_MAX_BINS];   /* ordered site pairs, all              */
+    uint64_t gofr_inter[MC_GOFR_MAX_BINS]; /* ordered site pairs of distinct molecules */
+    uint32_t n_c2;
+    uint32_t pad;
+    uint64_t c2_sweep[MC_C2_MAX];          /* sweeps after the observable origin   */
+    double   c2[MC_C2_MAX];                /* C_2(t) (Sec. III.B, Eq. 7, l = 2)    */
+} mc_obs;
+
+/* ---- single system ------------------------------------------------------ */
+
+/* Fill *p with the paper's model values and this engine's defaults. */
+void mc_params_default(mc_params* p);
+
+/* Box side L = (3 M / density)^(1/3) and the decomposition the engine will
+ * use (k, n_c) for these parameters (after "choose" defaults). */
+int mc_geometry(const mc_params* p, double* box, uint32_t* colours_per_axis,
+                uint32_t* cells_per_side);
+
+/* Bytes of device memory mc_init_system needs for these parameters. */
+int mc_required_bytes(const mc_params* p, size_t* bytes);
+
+/* Create a system in device_buf (>= mc_required_bytes).  With com, quat and
+ * types all NULL the start is the seeded simple-cubic lattice (M = n^3,
+ * random uniform orientations, types A, B, C on sites 0, 1, 2); otherwise
+ * they are host arrays com[3M] (xyz per molecule), quat[4M] (w, x, y, z,
+ * unit) and types[3M] (0 = A, 1 = B, 2 = C, a permutation per molecule).
+ * Computes E_0 by an FP64 re-sum; fails with MC_ENONFINITE if it is not
+ * finite.  hip_stream is a hipStream_t (NULL = null stream). */
+int mc_init_system(const mc_params* p, const double* com, const double* quat,
+                   const uint8_t* types, void* device_buf, size_t buf_bytes,
+                   void* hip_stream, mc_system** out);
+
+/* Enqueue n checkerboard sweeps (each attempts every molecule once). */
+int mc_sweep(mc_system* s, uint64_t n_sweeps);
+
+/* FP64 total inter-molecular energy now (a fresh re-sum), E/M, and the drift
+ * e_acc - e_total.  Synchronises. Any output pointer may be NULL. */
+int mc_energy(mc_system* s, double* e_total, double* e_per_molecule, double* drift);
+
+/* Copy the accumulators to *out.  Synchronises. */
+int mc_observables(mc_system* s, mc_obs* out);
+
+/* Copy up to cap E/M samples and drift samples (NULL to skip either). */
+int mc_samples(mc_system* s, double* energy, double* drift, size_t cap, size_t* n_energy,
+               size_t* n_drift);
+
+/* Clear the observable accumulators and take the current state as the
+ * reference of C_2 and the origin of sampling times. */
+int mc_reset_observables(mc_system* s);
+
+/* Read / overwrite the state (host arrays in the layouts of mc_init_system;
+ * any output pointer may be NULL).  mc_set_state also sets the sweep counter
+ * (which keys the random numbers) and the accumulated energy; e_acc NaN means
+ * "re-sum it". */
+int mc_get_state(mc_system* s, double* com, double* quat, uint8_t* types, uint64_t* sweep,
+                 double* e_acc);
+int mc_set_state(mc_system* s, const double* com, const double* quat, const uint8_t* types,
+                 uint64_t sweep, double e_acc);
+
+/* Record every attempted move of the next sweeps into a caller-owned DEVICE
+ * array of capacity records: record (sweep - first_sweep) * M + molecule.
+ * Sweeps beyond capacity / M are not recorded.  records = NULL disables. */
+int mc_decision_log(mc_system* s, void* device_records, size_t capacity);
+
+void mc_destroy(mc_system* s);
+const char* mc_last_error(void);
+
+/* ---- batches: many systems in one persistent launch ---------------------- */
+
+/* A batch holds up to max_slots systems of one precision; one mc_batch_run
+ * launch advances every occupied slot, one workgroup per system. */
+int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc_batch** out);
+
+/* Put an initialised system into a free slot with n_sweeps of work; the
+ * system must use the batch's precision.  MC_EBUSY when no slot is free. */
+int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
+
+/* Enqueue one launch in which each occupied slot runs
+ * min(remaining, max(1, max_moves_per_slot / M)) sweeps (0 = all remaining). */
+int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched);
+
+/* Synchronise, then report (and free) the slots whose work is complete:
+ * their slot indices and systems. */
+int mc_batch_poll(mc_batch* b, uint32_t* slots, mc_system** systems, size_t cap, size_t* n);
+
+/* Remove a system from its slot before its work is done. */
+int mc_batch_cancel(mc_batch* b, uint32_t slot);
+
+void mc_batch_destroy(mc_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLIPMC_H */

@@ -1,0 +1,807 @@
+// capi.hip -- host side of the C ABI declared in include/flipmc.h.
+//
+// Validates parameters, lays the system out in the caller's device buffer,
+// fills the device descriptor (SysDev) and enqueues the kernels of
+// kernels.hip on the caller's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "flipmc.h"
+
+using namespace flipmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                       \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess) return fail(MC_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+// Side of the rigid triangle: the minimum of WCA + FENE (Eq. 1 + Eq. 2) of a
+// sigma_ij = 1 bond, found by Newton's method on the slope.
+double bond_star()
+{
+    auto slope = [](double x) {
+        return -48.0 * std::pow(x, -13.0) + 24.0 * std::pow(x, -7.0) +
+               30.0 * x / (1.0 - x * x / 2.25);
+    };
+    auto curvature = [](double x) {
+        const double d = 1.0 - x * x / 2.25;
+        return 624.0 * std::pow(x, -14.0) - 168.0 * std::pow(x, -8.0) +
+               30.0 / d + 30.0 * x * (2.0 * x / 2.25) / (d * d);
+    };
+    double x = 0.96;
+    for (int it = 0; it < 100; ++it) {
+        const double nx = x - slope(x) / curvature(x);
+        if (nx == x) break;
+        x = nx;
+    }
+    return x;
+}
+
+size_t device_lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 163840;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0) {
+        (void)hipGetLastError();
+        return 163840;
+    }
+    return (size_t)v;
+}
+
+struct Geometry {
+    double L, bond, radius, reach;
+    uint32_t k, nc, ncell;
+    bool resident;
+    size_t lds;
+};
+
+double cost_estimate(uint32_t M, uint32_t k, uint32_t nc)
+{
+    // phases x trials of the most loaded wave x candidate molecules per trial
+    const double per_cell = (double)M / ((double)nc * nc * nc);
+    const double na3 = std::pow((double)(nc / k), 3.0);
+    const double waves = std::ceil(na3 / kWaves);
+    const double span = std::min((double)nc, 2.0 * (k - 1) + 1.0);
+    const double stencil = std::min((double)M, span * span * span * per_cell);
+    return (double)k * k * k * waves * std::max(1.0, per_cell) * (stencil + 32.0) + 2000.0 * k * k * k;
+}
+
+int geometry(const mc_params* p, Geometry* g)
+{
+    if (!p) return fail(MC_EINVAL, "null parameters");
+    if (p->n_molecules < 1 || p->n_molecules > (uint32_t)kMaxMolecules)
+        return fail(MC_EINVAL, "n_molecules must be in [1, %d]", kMaxMolecules);
+    if (p->precision != MC_FP64 && p->precision != MC_FP32_DE)
+        return fail(MC_EINVAL, "precision must be MC_FP64 or MC_FP32_DE");
+    if (!(p->density > 0) || !(p->temperature > 0))
+        return fail(MC_EINVAL, "density and temperature must be positive");
+    for (int i = 0; i < 3; ++i)
+        if (!(p->sigma[i] > 0)) return fail(MC_EINVAL, "sigma must be positive");
+    if (!(p->p_flip >= 0) || !(p->p_translate >= 0) || p->p_flip + p->p_translate > 1.0)
+        return fail(MC_EINVAL, "move probabilities out of range");
+    if (!(p->max_displacement >= 0) || !(p->max_rotation >= 0))
+        return fail(MC_EINVAL, "step sizes must be non-negative");
+    if (!(p->gofr_dr > 0)) return fail(MC_EINVAL, "gofr_dr must be positive");
+    g->L = std::cbrt(3.0 * (double)p->n_molecules / p->density);
+    g->bond = p->bond_length > 0 ? p->bond_length : bond_star();
+    g->radius = g->bond / std::sqrt(3.0);
+    const double smax = std::max(p->sigma[0], std::max(p->sigma[1], p->sigma[2]));
+    const double rcmax = std::pow(2.0, 1.0 / 6.0) * smax;
+    g->reach = rcmax + 2.0 * g->radius;
+    if (g->L < 2.0 * (rcmax + 2.0 * p->max_displacement))
+        return fail(MC_EGEOM, "box side %.4f too small for the minimum-image convention", g->L);
+    uint32_t k = p->colours_per_axis, nc = p->cells_per_side;
+    if (k == 0 && nc == 0) {
+        double best = std::numeric_limits<double>::infinity();
+        for (uint32_t kk = 2; kk <= 3; ++kk) {
+            uint32_t n = (uint32_t)std::floor((kk - 1) * g->L / g->reach);
+            n -= n % kk;
+            while (n >= 2 && std::pow((double)n, 3.0) > 65535.0) n -= kk;
+            if (n < 2 || n < kk) continue;
+            const double c = cost_estimate(p->n_molecules, kk, n);
+            if (c < best) {
+                best = c;
+                k = kk;
+                nc = n;
+            }
+        }
+        if (k == 0) return fail(MC_EGEOM, "no checkerboard fits a box of side %.4f", g->L);
+    } else if (k == 0 || nc == 0) {
+        return fail(MC_EINVAL, "give both colours_per_axis and cells_per_side, or neither");
+    }
+    if (k < 2 || k > 3) return fail(MC_EGEOM, "colours_per_axis must be 2 or 3");
+    if (nc < 2 || nc % k != 0) return fail(MC_EGEOM, "cells_per_side must be a multiple of k >= 2");
+    if ((double)(k - 1) * (g->L / (double)nc) < g->reach)
+        return fail(MC_EGEOM, "(k-1) * cell width %.5f is below the interaction reach %.5f",
+                    (double)(k - 1) * g->L / nc, g->reach);
+    const double ncell = (double)nc * nc * nc;
+    if (ncell > 65535.0) return fail(MC_EGEOM, "too many cells (%u per side)", nc);
+    g->k = k;
+    g->nc = nc;
+    g->ncell = nc * nc * nc;
+    const bool fp64 = p->precision == MC_FP64;
+    const size_t limit = device_lds_limit();
+    const LdsLayout res = lds_layout(fp64, true, p->n_molecules, g->ncell);
+    g->resident = res.total <= limit && !(p->flags & MC_FLAG_HBM_STATE);
+    g->lds = g->resident ? res.total : lds_layout(fp64, false, p->n_molecules, g->ncell).total;
+    return MC_OK;
+}
+
+struct BufLayout {
+    size_t sys, stats, com, quat, types, u0, kref, esamp, dsamp, gall, ginter, c2, c2s;
+    size_t gsite, gcell, gcellid, glist, total;
+};
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+BufLayout buf_layout(const mc_params* p, const Geometry& g)
+{
+    BufLayout b{};
+    const size_t M = p->n_molecules;
+    size_t o = 0;
+    b.sys = o;    o = al(o + sizeof(SysDev));
+    b.stats = o;  o = al(o + sizeof(Stats));
+    b.com = o;    o = al(o + 3 * M * sizeof(double));
+    b.quat = o;   o = al(o + 4 * M * sizeof(double));
+    b.types = o;  o = al(o + M * sizeof(uint32_t));
+    b.u0 = o;     o = al(o + 3 * M * sizeof(double));
+    b.kref = o;   o = al(o + M);
+    b.esamp = o;  o = al(o + size_t(p->max_samples) * sizeof(double));
+    b.dsamp = o;  o = al(o + size_t(p->max_samples) * sizeof(double));
+    b.gall = o;   o = al(o + kGofrBins * sizeof(uint64_t));
+    b.ginter = o; o = al(o + kGofrBins * sizeof(uint64_t));
+    b.c2 = o;     o = al(o + kC2Max * sizeof(double));
+    b.c2s = o;    o = al(o + kC2Max * sizeof(uint64_t));
+    if (!g.resident) {
+        const bool fp64 = p->precision == MC_FP64;
+        b.gsite = o;   o = al(o + 3 * M * site_bytes(fp64));
+        b.gcell = o;   o = al(o + (size_t(g.ncell) + 1) * sizeof(uint32_t));
+        b.gcellid = o; o = al(o + M * sizeof(uint16_t));
+        b.glist = o;   o = al(o + M * sizeof(uint16_t));
+    }
+    b.total = o;
+    return b;
+}
+
+}  // namespace
+
+struct mc_system {
+    mc_params p;
+    Geometry g;
+    BufLayout lay;
+    SysDev host;
+    SysDev* dev;
+    uint8_t* buf;
+    hipStream_t stream;
+    uint64_t sweep;   // host mirror of the device sweep counter
+    uint64_t origin;  // host mirror of the observable origin
+    mc_batch* batch;
+};
+
+struct mc_batch {
+    uint32_t max_slots;
+    uint32_t precision;
+    hipStream_t stream;
+    std::vector<mc_system*> sys;
+    std::vector<uint64_t> remaining;
+    Slot* dev_slots[2];   // per parity: [resident | non-resident | events] x max_slots
+    Slot* host_slots[2];
+    hipEvent_t copied[2];
+    bool pending[2];
+    int parity;
+};
+
+namespace {
+
+int upload_desc(mc_system* s)
+{
+    HIPCHK(hipMemcpyAsync(s->dev, &s->host, sizeof(SysDev), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+int launch_events_one(mc_system* s, uint32_t flags)
+{
+    Slot one{};
+    one.sys = s->dev;
+    one.flags = flags;
+    HIPCHK(launch_events(nullptr, one, 1, s->stream));
+    return MC_OK;
+}
+
+bool is_c2_time(uint64_t t)
+{
+    if (t == 0) return false;
+    while (t % 10 == 0) t /= 10;
+    return t == 1 || t == 2 || t == 5;
+}
+
+// Event work due right after sweep `sweep` of system s.
+uint32_t events_at(const mc_system* s, uint64_t sweep)
+{
+    uint32_t f = 0;
+    const mc_params& p = s->p;
+    if (p.resum_interval && sweep % p.resum_interval == 0) f |= kFlagResumPeriodic;
+    const uint64_t t = sweep - s->origin;
+    if (p.gofr_interval && t >= p.obs_start && t % p.gofr_interval == 0) f |= kFlagGofr;
+    if (is_c2_time(t)) f |= kFlagC2;
+    return f;
+}
+
+// First sweep after s->sweep at which some event work is due.
+uint64_t next_event(const mc_system* s)
+{
+    const mc_params& p = s->p;
+    const uint64_t now = s->sweep;
+    uint64_t best = UINT64_MAX;
+    if (p.resum_interval) best = std::min(best, (now / p.resum_interval + 1) * p.resum_interval);
+    const uint64_t t = now - s->origin;
+    if (p.gofr_interval) {
+        uint64_t n = (t / p.gofr_interval + 1) * p.gofr_interval;
+        if (n < p.obs_start) n = ((p.obs_start + p.gofr_interval - 1) / p.gofr_interval) * p.gofr_interval;
+        best = std::min(best, s->origin + n);
+    }
+    for (uint64_t dec = 1; dec <= (uint64_t)1e18; dec *= 10) {
+        bool found = false;
+        for (uint64_t m : {1ull, 2ull, 5ull}) {
+            if (m * dec > t) {
+                best = std::min(best, s->origin + m * dec);
+                found = true;
+                break;
+            }
+        }
+        if (found) break;
+    }
+    return best;
+}
+
+// Enqueue n sweeps of one system, split at event sweeps.
+int advance(mc_system* s, uint64_t n)
+{
+    Slot one{};
+    one.sys = s->dev;
+    while (n > 0) {
+        const uint64_t chunk = std::min<uint64_t>(n, next_event(s) - s->sweep);
+        one.n_sweeps = chunk;
+        one.flags = 0;
+        HIPCHK(launch_sweeps(s->p.precision == MC_FP64, s->g.resident, nullptr, one, 1, s->g.lds,
+                             s->stream));
+        s->sweep += chunk;
+        n -= chunk;
+        const uint32_t f = events_at(s, s->sweep);
+        if (f) {
+            const int rc = launch_events_one(s, f);
+            if (rc) return rc;
+        }
+    }
+    return MC_OK;
+}
+
+int read_stats(mc_system* s, Stats* st)
+{
+    HIPCHK(hipMemcpyAsync(st, s->host.stats, sizeof(Stats), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+int write_stats(mc_system* s, const Stats* st)
+{
+    HIPCHK(hipMemcpyAsync(s->host.stats, st, sizeof(Stats), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+int upload_state(mc_system* s, const double* com, const double* quat, const uint8_t* types)
+{
+    const size_t M = s->p.n_molecules;
+    std::vector<double> c(3 * M), q(4 * M);
+    std::vector<uint32_t> t(M);
+    for (size_t m = 0; m < M; ++m) {
+        for (int a = 0; a < 3; ++a) c[a * M + m] = com[3 * m + a];
+        double nrm = 0;
+        for (int a = 0; a < 4; ++a) nrm += quat[4 * m + a] * quat[4 * m + a];
+        if (!(std::fabs(nrm - 1.0) < 1e-6))
+            return fail(MC_EINVAL, "quaternion of molecule %zu is not a unit quaternion", m);
+        for (int a = 0; a < 4; ++a) q[a * M + m] = quat[4 * m + a];
+        const uint8_t a0 = types[3 * m], a1 = types[3 * m + 1], a2 = types[3 * m + 2];
+        if (a0 > 2 || a1 > 2 || a2 > 2 || a0 == a1 || a0 == a2 || a1 == a2)
+            return fail(MC_EINVAL, "types of molecule %zu are not a permutation of A, B, C", m);
+        t[m] = (uint32_t)a0 | ((uint32_t)a1 << 8) | ((uint32_t)a2 << 16);
+    }
+    HIPCHK(hipMemcpyAsync(s->host.com, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->host.quat, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->host.types, t.data(), t.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mc_last_error(void) { return g_err.c_str(); }
+
+void mc_params_default(mc_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->n_molecules = 1000;
+    p->precision = MC_FP64;
+    p->density = 1.2;
+    p->temperature = 3.0;
+    p->sigma[0] = 0.9;
+    p->sigma[1] = 1.0;
+    p->sigma[2] = 1.1;
+    p->bond_length = 0.0;
+    p->p_flip = 0.2;
+    p->p_translate = 0.4;
+    p->max_displacement = 0.1;
+    p->max_rotation = 0.2;
+    p->seed = 1;
+    p->colours_per_axis = 0;
+    p->cells_per_side = 0;
+    p->resum_interval = 100;
+    p->obs_interval = 10;
+    p->gofr_interval = 100;
+    p->obs_start = 0;
+    p->max_samples = 4096;
+    p->gofr_dr = 0.02;
+}
+
+int mc_geometry(const mc_params* p, double* box, uint32_t* k, uint32_t* nc)
+{
+    Geometry g;
+    const int rc = geometry(p, &g);
+    if (rc) return rc;
+    if (box) *box = g.L;
+    if (k) *k = g.k;
+    if (nc) *nc = g.nc;
+    return MC_OK;
+}
+
+int mc_required_bytes(const mc_params* p, size_t* bytes)
+{
+    Geometry g;
+    const int rc = geometry(p, &g);
+    if (rc) return rc;
+    if (!bytes) return fail(MC_EINVAL, "null output");
+    *bytes = buf_layout(p, g).total;
+    return MC_OK;
+}
+
+int mc_init_system(const mc_params* p, const double* com, const double* quat, const uint8_t* types,
+                   void* device_buf, size_t buf_bytes, void* hip_stream, mc_system** out)
+{
+    if (!out) return fail(MC_EINVAL, "null output handle");
+    *out = nullptr;
+    Geometry g;
+    int rc = geometry(p, &g);
+    if (rc) return rc;
+    const bool lattice = !com && !quat && !types;
+    if (!lattice && !(com && quat && types))
+        return fail(MC_EINVAL, "give com, quat and types together, or none of them");
+    if (lattice) {
+        uint32_t n = 1;
+        while ((n + 1) * (n + 1) * (n + 1) <= p->n_molecules) ++n;
+        if (n * n * n != p->n_molecules)
+            return fail(MC_EINVAL, "lattice start needs n_molecules = n^3 (got %u)", p->n_molecules);
+    }
+    if (!device_buf) return fail(MC_EINVAL, "null device buffer");
+    if (((uintptr_t)device_buf & 255u) != 0) return fail(MC_EINVAL, "device buffer must be 256-byte aligned");
+    const BufLayout lay = buf_layout(p, g);
+    if (buf_bytes < lay.total)
+        return fail(MC_ENOMEM, "device buffer of %zu bytes, %zu needed", buf_bytes, lay.total);
+
+    mc_system* s = new mc_system();
+    s->p = *p;
+    s->g = g;
+    s->lay = lay;
+    s->buf = (uint8_t*)device_buf;
+    s->stream = (hipStream_t)hip_stream;
+    s->sweep = 0;
+    s->batch = nullptr;
+    SysDev& D = s->host;
+    std::memset(&D, 0, sizeof D);
+    uint8_t* b = s->buf;
+    D.M = p->n_molecules;
+    D.k = g.k;
+    D.nc = g.nc;
+    D.ncell = g.ncell;
+    D.precision = p->precision;
+    D.resident = g.resident ? 1u : 0u;
+    D.seed_lo = (uint32_t)p->seed;
+    D.seed_hi = (uint32_t)(p->seed >> 32);
+    D.L = g.L;
+    D.w = g.L / (double)g.nc;
+    D.T = p->temperature;
+    D.p_flip = p->p_flip;
+    D.p_ft = p->p_flip + p->p_translate;
+    D.dmax = p->max_displacement;
+    D.rot_max = p->max_rotation;
+    const double reach = g.reach * (1.0 + 1e-9);
+    D.reach2 = reach * reach;
+    D.radius = g.radius;
+    D.rc2_factor = std::cbrt(2.0);
+    const double body[9] = {g.radius, 0.0, 0.0, -0.5 * g.radius, 0.5 * g.bond, 0.0,
+                            -0.5 * g.radius, -0.5 * g.bond, 0.0};
+    std::memcpy(D.body, body, sizeof body);
+    for (int i = 0; i < 3; ++i) D.sigma[i] = p->sigma[i];
+    D.resum_interval = p->resum_interval;
+    D.obs_interval = p->obs_interval;
+    D.gofr_interval = p->gofr_interval;
+    D.obs_start = p->obs_start;
+    D.max_samples = p->max_samples;
+    const double rmax = std::min(0.5 * g.L, 5.0);
+    uint32_t nb = (uint32_t)std::floor(rmax / p->gofr_dr + 1e-6);
+    if (nb > (uint32_t)kGofrBins) nb = kGofrBins;
+    D.gofr_nbins = nb;
+    D.gofr_dr = p->gofr_dr;
+    D.gofr_rmax = rmax;
+    D.lds_bytes = (uint32_t)g.lds;
+    D.com = (double*)(b + lay.com);
+    D.quat = (double*)(b + lay.quat);
+    D.types = (uint32_t*)(b + lay.types);
+    D.u0 = (double*)(b + lay.u0);
+    D.kref = (uint8_t*)(b + lay.kref);
+    D.stats = (Stats*)(b + lay.stats);
+    D.e_samples = (double*)(b + lay.esamp);
+    D.drift_samples = (double*)(b + lay.dsamp);
+    D.gofr_all = (uint64_t*)(b + lay.gall);
+    D.gofr_inter = (uint64_t*)(b + lay.ginter);
+    D.c2 = (double*)(b + lay.c2);
+    D.c2_sweep = (uint64_t*)(b + lay.c2s);
+    if (!g.resident) {
+        D.g_site = (void*)(b + lay.gsite);
+        D.g_cell = (uint32_t*)(b + lay.gcell);
+        D.g_cellid = (uint16_t*)(b + lay.gcellid);
+        D.g_list = (uint16_t*)(b + lay.glist);
+    }
+    s->dev = (SysDev*)(b + lay.sys);
+
+    auto bail = [&](int code) {
+        delete s;
+        return code;
+    };
+    hipError_t e = hipMemsetAsync(device_buf, 0, lay.total, s->stream);
+    if (e != hipSuccess) return bail(fail(MC_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e)));
+    if ((rc = upload_desc(s))) return bail(rc);
+    if (lattice) {
+        e = launch_init_lattice(s->dev, p->n_molecules, s->stream);
+        if (e != hipSuccess) return bail(fail(MC_EDEVICE, "lattice kernel: %s", hipGetErrorString(e)));
+    } else if ((rc = upload_state(s, com, quat, types))) {
+        return bail(rc);
+    }
+    s->origin = 0;
+    if ((rc = launch_events_one(s, kFlagResumSet | kFlagObsReset))) return bail(rc);
+    Stats st;
+    if ((rc = read_stats(s, &st))) return bail(rc);
+    if (!std::isfinite(st.e_acc))
+        return bail(fail(MC_ENONFINITE, "initial energy is not finite (overlapping sites)"));
+    *out = s;
+    return MC_OK;
+}
+
+int mc_sweep(mc_system* s, uint64_t n)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    if (s->batch) return fail(MC_EBUSY, "system is in a batch");
+    return advance(s, n);
+}
+
+int mc_energy(mc_system* s, double* e_total, double* e_per_molecule, double* drift)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    int rc = launch_events_one(s, kFlagResumReport);
+    if (rc) return rc;
+    Stats st;
+    if ((rc = read_stats(s, &st))) return rc;
+    if (e_total) *e_total = st.e_resum;
+    if (e_per_molecule) *e_per_molecule = st.e_resum / (double)s->p.n_molecules;
+    if (drift) *drift = st.e_acc - st.e_resum;
+    if (!std::isfinite(st.e_resum)) return fail(MC_ENONFINITE, "energy is not finite");
+    return MC_OK;
+}
+
+int mc_observables(mc_system* s, mc_obs* o)
+{
+    if (!s || !o) return fail(MC_EINVAL, "null argument");
+    Stats st;
+    int rc = read_stats(s, &st);
+    if (rc) return rc;
+    std::memset(o, 0, sizeof *o);
+    o->sweep = st.sweep;
+    for (int i = 0; i < 3; ++i) {
+        o->attempts[i] = st.attempts[i];
+        o->accepts[i] = st.accepts[i];
+    }
+    o->exits = st.exits;
+    o->pair_terms = st.pair_terms;
+    o->pair_tests = st.pair_tests;
+    o->e_acc = st.e_acc;
+    o->e_resum = st.e_resum;
+    o->drift = st.drift;
+    o->max_abs_drift = st.max_abs_drift;
+    o->resum_sweep = st.resum_sweep;
+    o->n_energy_samples = st.n_e;
+    o->n_drift_samples = st.n_drift;
+    o->energy_sum = st.e_sum;
+    o->energy_sumsq = st.e_sumsq;
+    o->n_gofr_frames = st.n_gofr;
+    o->gofr_nbins = s->host.gofr_nbins;
+    o->gofr_dr = s->host.gofr_dr;
+    o->gofr_rmax = s->host.gofr_rmax;
+    o->n_c2 = st.n_c2;
+    HIPCHK(hipMemcpyAsync(o->gofr_all, s->host.gofr_all, sizeof o->gofr_all, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->gofr_inter, s->host.gofr_inter, sizeof o->gofr_inter, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->c2, s->host.c2, sizeof o->c2, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->c2_sweep, s->host.c2_sweep, sizeof o->c2_sweep, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+int mc_samples(mc_system* s, double* energy, double* drift, size_t cap, size_t* n_energy,
+               size_t* n_drift)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    Stats st;
+    int rc = read_stats(s, &st);
+    if (rc) return rc;
+    const size_t ne = std::min<size_t>({(size_t)st.n_e, (size_t)s->p.max_samples, cap});
+    const size_t nd = std::min<size_t>({(size_t)st.n_drift, (size_t)s->p.max_samples, cap});
+    if (energy && ne)
+        HIPCHK(hipMemcpyAsync(energy, s->host.e_samples, ne * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    if (drift && nd)
+        HIPCHK(hipMemcpyAsync(drift, s->host.drift_samples, nd * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (n_energy) *n_energy = ne;
+    if (n_drift) *n_drift = nd;
+    return MC_OK;
+}
+
+int mc_reset_observables(mc_system* s)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    if (s->batch) return fail(MC_EBUSY, "system is in a batch");
+    s->origin = s->sweep;
+    return launch_events_one(s, kFlagObsReset);
+}
+
+int mc_get_state(mc_system* s, double* com, double* quat, uint8_t* types, uint64_t* sweep,
+                 double* e_acc)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    const size_t M = s->p.n_molecules;
+    std::vector<double> c(3 * M), q(4 * M);
+    std::vector<uint32_t> t(M);
+    Stats st;
+    HIPCHK(hipMemcpyAsync(c.data(), s->host.com, c.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(q.data(), s->host.quat, q.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(t.data(), s->host.types, t.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+    int rc = read_stats(s, &st);
+    if (rc) return rc;
+    for (size_t m = 0; m < M; ++m) {
+        if (com)
+            for (int a = 0; a < 3; ++a) com[3 * m + a] = c[a * M + m];
+        if (quat)
+            for (int a = 0; a < 4; ++a) quat[4 * m + a] = q[a * M + m];
+        if (types)
+            for (int a = 0; a < 3; ++a) types[3 * m + a] = (uint8_t)((t[m] >> (8 * a)) & 0xFFu);
+    }
+    if (sweep) *sweep = st.sweep;
+    if (e_acc) *e_acc = st.e_acc;
+    return MC_OK;
+}
+
+int mc_set_state(mc_system* s, const double* com, const double* quat, const uint8_t* types,
+                 uint64_t sweep, double e_acc)
+{
+    if (!s || !com || !quat || !types) return fail(MC_EINVAL, "null argument");
+    if (s->batch) return fail(MC_EBUSY, "system is in a batch");
+    int rc = upload_state(s, com, quat, types);
+    if (rc) return rc;
+    Stats st;
+    if ((rc = read_stats(s, &st))) return rc;
+    st.sweep = sweep;
+    st.e_acc = std::isnan(e_acc) ? 0.0 : e_acc;
+    if (sweep < s->origin) {
+        st.obs_origin = sweep;
+        s->origin = sweep;
+    }
+    if ((rc = write_stats(s, &st))) return rc;
+    s->sweep = sweep;
+    if (std::isnan(e_acc)) {
+        if ((rc = launch_events_one(s, kFlagResumSet))) return rc;
+        if ((rc = read_stats(s, &st))) return rc;
+        if (!std::isfinite(st.e_acc)) return fail(MC_ENONFINITE, "energy of the new state is not finite");
+    }
+    return MC_OK;
+}
+
+int mc_decision_log(mc_system* s, void* device_records, size_t capacity)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    Stats st;
+    int rc = read_stats(s, &st);
+    if (rc) return rc;
+    s->host.log = device_records;
+    s->host.log_sweep0 = st.sweep;
+    s->host.log_sweeps = device_records ? capacity / s->p.n_molecules : 0;
+    return upload_desc(s);
+}
+
+void mc_destroy(mc_system* s)
+{
+    if (!s) return;
+    if (s->batch) {
+        mc_batch* b = s->batch;
+        for (size_t i = 0; i < b->sys.size(); ++i)
+            if (b->sys[i] == s) b->sys[i] = nullptr;
+    }
+    delete s;
+}
+
+// ------------------------------------------------------------------ batches --
+
+int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc_batch** out)
+{
+    if (!out || max_slots == 0) return fail(MC_EINVAL, "bad arguments");
+    if (precision != MC_FP64 && precision != MC_FP32_DE) return fail(MC_EINVAL, "bad precision");
+    mc_batch* b = new mc_batch();
+    b->max_slots = max_slots;
+    b->precision = precision;
+    b->stream = (hipStream_t)hip_stream;
+    b->sys.assign(max_slots, nullptr);
+    b->remaining.assign(max_slots, 0);
+    b->parity = 0;
+    for (int i = 0; i < 2; ++i) {
+        b->dev_slots[i] = nullptr;
+        b->host_slots[i] = nullptr;
+        b->pending[i] = false;
+        b->copied[i] = nullptr;
+        // slot tables: one per residency class, double-buffered
+        if (hipMalloc((void**)&b->dev_slots[i], 3 * sizeof(Slot) * max_slots) != hipSuccess ||
+            hipHostMalloc((void**)&b->host_slots[i], 3 * sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b->copied[i], hipEventDisableTiming) != hipSuccess) {
+            mc_batch_destroy(b);
+            return fail(MC_EDEVICE, "could not allocate the slot tables");
+        }
+    }
+    *out = b;
+    return MC_OK;
+}
+
+int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot)
+{
+    if (!b || !s) return fail(MC_EINVAL, "null argument");
+    if (s->batch) return fail(MC_EINVAL, "system is already in a batch");
+    if (s->p.precision != b->precision) return fail(MC_EINVAL, "precision differs from the batch's");
+    if (s->stream != b->stream) return fail(MC_EINVAL, "system must use the batch's stream");
+    for (uint32_t i = 0; i < b->max_slots; ++i) {
+        if (!b->sys[i]) {
+            b->sys[i] = s;
+            b->remaining[i] = n_sweeps;
+            s->batch = b;
+            if (slot) *slot = i;
+            return MC_OK;
+        }
+    }
+    return fail(MC_EBUSY, "no free slot");
+}
+
+int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
+{
+    if (!b) return fail(MC_EINVAL, "null batch");
+    const int par = b->parity;
+    b->parity ^= 1;
+    if (b->pending[par]) {
+        HIPCHK(hipEventSynchronize(b->copied[par]));
+        b->pending[par] = false;
+    }
+    Slot* hs = b->host_slots[par];
+    const uint32_t S = b->max_slots;
+    uint32_t n[3] = {0, 0, 0};
+    size_t lds[2] = {0, 0};
+    for (uint32_t i = 0; i < S; ++i) {
+        mc_system* s = b->sys[i];
+        if (!s || b->remaining[i] == 0) continue;
+        uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
+        if (max_moves_per_slot)
+            k = std::min<uint64_t>(k, std::max<uint64_t>(1, max_moves_per_slot / s->p.n_molecules));
+        const int cls = s->g.resident ? 0 : 1;
+        Slot sl{};
+        sl.sys = s->dev;
+        sl.n_sweeps = k;
+        hs[cls * S + n[cls]++] = sl;
+        lds[cls] = std::max(lds[cls], s->g.lds);
+        b->remaining[i] -= k;
+        s->sweep += k;
+        const uint32_t f = events_at(s, s->sweep);
+        if (f) {
+            Slot ev{};
+            ev.sys = s->dev;
+            ev.flags = f;
+            hs[2 * S + n[2]++] = ev;
+        }
+    }
+    if (n[0] + n[1]) {
+        HIPCHK(hipMemcpyAsync(b->dev_slots[par], hs, 3 * sizeof(Slot) * S, hipMemcpyHostToDevice,
+                              b->stream));
+        HIPCHK(hipEventRecord(b->copied[par], b->stream));
+        b->pending[par] = true;
+        Slot none{};
+        for (int cls = 0; cls < 2; ++cls)
+            if (n[cls])
+                HIPCHK(launch_sweeps(b->precision == MC_FP64, cls == 0, b->dev_slots[par] + cls * S,
+                                     none, n[cls], lds[cls], b->stream));
+        if (n[2]) HIPCHK(launch_events(b->dev_slots[par] + 2 * S, none, n[2], b->stream));
+    }
+    if (n_launched) *n_launched = n[0] + n[1];
+    return MC_OK;
+}
+
+int mc_batch_poll(mc_batch* b, uint32_t* slots, mc_system** systems, size_t cap, size_t* n)
+{
+    if (!b) return fail(MC_EINVAL, "null batch");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    size_t k = 0;
+    for (uint32_t i = 0; i < b->max_slots && k < cap; ++i) {
+        mc_system* s = b->sys[i];
+        if (!s || b->remaining[i] != 0) continue;
+        if (slots) slots[k] = i;
+        if (systems) systems[k] = s;
+        s->batch = nullptr;
+        b->sys[i] = nullptr;
+        ++k;
+    }
+    if (n) *n = k;
+    return MC_OK;
+}
+
+int mc_batch_cancel(mc_batch* b, uint32_t slot)
+{
+    if (!b || slot >= b->max_slots || !b->sys[slot]) return fail(MC_EINVAL, "no such slot");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->sys[slot]->batch = nullptr;
+    b->sys[slot] = nullptr;
+    b->remaining[slot] = 0;
+    return MC_OK;
+}
+
+void mc_batch_destroy(mc_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto* s : b->sys)
+        if (s) s->batch = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (b->dev_slots[i]) (void)hipFree(b->dev_slots[i]);
+        if (b->host_slots[i]) (void)hipHostFree(b->host_slots[i]);
+        if (b->copied[i]) (void)hipEventDestroy(b->copied[i]);
+    }
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// engine.h -- device-side data layout of the flip Monte Carlo engine.
+//
+// One system = one workgroup of 512 threads (8 wave64s).  A system whose
+// state fits in the workgroup's LDS ("resident") keeps centres of mass, site
+// offsets and cell lists there for the whole launch; larger systems keep them
+// in HBM and the same code reads them through global pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace flipmc {
+
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxSeg = 64;        // stencil row segments per cell (k <= 3: <= 50)
+constexpr int kGofrBins = 256;
+constexpr int kC2Max = 32;
+constexpr int kMaxMolecules = 65535;  // indices are stored as u16 in cell lists
+
+// Work of the event kernel (Slot::flags).
+enum : uint32_t {
+    kFlagResumSet = 1u,       // re-sum E and take it as the accumulated energy
+    kFlagResumReport = 2u,    // re-sum E and store it as e_resum / drift
+    kFlagObsReset = 4u,       // take the current state as the C_2 reference / time origin
+    kFlagResumPeriodic = 8u,  // scheduled re-sum: also record the drift sample
+    kFlagGofr = 16u,          // accumulate one g(r) frame
+    kFlagC2 = 32u,            // record one C_2 sample
+};
+
+// Device accumulators of one system.
+struct Stats {
+    uint64_t sweep;          // sweeps done (keys the random numbers)
+    uint64_t obs_origin;     // sweep at the last observable reset
+    double e_acc;            // E_0 + sum of accepted dE
+    double e_resum;          // last FP64 re-sum
+    double drift;            // e_acc - e_resum at that re-sum
+    double max_abs_drift;    // over re-sums after the first window
+    uint64_t resum_sweep;
+    uint64_t n_resum;
+    uint64_t attempts[3];
+    uint64_t accepts[3];
+    uint64_t exits;
+    uint64_t pair_terms;
+    uint64_t pair_tests;
+    double e_sum;
+    double e_sumsq;
+    uint32_t n_e;
+    uint32_t n_drift;
+    uint32_t n_gofr;
+    uint32_t n_c2;
+};
+
+// Everything a workgroup needs about its system; lives in the system's device
+// buffer and is written by the host.
+struct SysDev {
+    uint32_t M, k, nc, ncell;
+    uint32_t precision, resident, seed_lo, seed_hi;
+    double L, w, T, p_flip, p_ft, dmax, rot_max, reach2, radius, rc2_factor;
+    double body[9];      // body-frame site offsets, row s = site s
+    double sigma[3];     // diameters of types A, B, C
+    uint32_t resum_interval, obs_interval, gofr_interval, obs_start;
+    uint32_t max_samples, gofr_nbins, lds_bytes, pad0;
+    double gofr_dr, gofr_rmax;
+    // state
+    double* com;         // SoA [3][M]
+    double* quat;        // SoA [4][M], (w, x, y, z)
+    uint32_t* types;     // [M]: byte s = type of site s
+    double* u0;          // SoA [3][M] C_2 reference orientation
+    uint8_t* kref;       // [M] site index followed by C_2
+    Stats* stats;
+    double* e_samples;
+    double* drift_samples;
+    uint64_t* gofr_all;
+    uint64_t* gofr_inter;
+    double* c2;
+    uint64_t* c2_sweep;
+    // HBM copies of the work arrays of non-resident systems
+    void* g_site;        // Real4 [3M]: offset xyz + sigma of the site's type
+    uint32_t* g_cell;    // [ncell + 1] cell starts
+    uint16_t* g_cellid;  // [M]
+    uint16_t* g_list;    // [M] molecules sorted by cell, ascending inside a cell
+    // decision log
+    void* log;
+    uint64_t log_sweep0;
+    uint64_t log_sweeps;
+};
+
+struct Slot {
+    SysDev* sys;
+    uint64_t n_sweeps;
+    uint32_t flags;
+    uint32_t pad;
+};
+
+struct MoveRecord {   // mirrors mc_move_record
+    double delta_e;
+    double scale;
+    double t_log_u;
+    uint64_t sweep;
+    uint32_t molecule;
+    uint8_t move, accepted, exited, axis;
+    uint32_t pair_terms;
+    uint32_t pad;
+};
+static_assert(sizeof(MoveRecord) == 48, "record layout");
+
+// Candidate-pair buffer entries per wave.
+// At least 64: one 64-lane ballot may append 64 entries after a flush.
+__host__ __device__ constexpr int cand_cap(bool) { return 64; }
+__host__ __device__ constexpr size_t cand_bytes(bool fp64) { return fp64 ? 32 : 16; }
+__host__ __device__ constexpr size_t site_bytes(bool fp64) { return fp64 ? 32 : 16; }
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// LDS carve-up, shared by the host (launch size) and the kernel (pointers).
+struct LdsLayout {
+    size_t cand, seglo, segoff, red, wpart, bins, misc, wstat, tsite;
+    size_t com, site, cell, cellid, list, total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(bool fp64, bool resident, uint32_t M,
+                                                 uint32_t ncell)
+{
+    LdsLayout l{};
+    size_t o = 0;
+    l.cand = o;   o = align16(o + kWaves * cand_cap(fp64) * cand_bytes(fp64));
+    l.seglo = o;  o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
+    l.segoff = o; o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
+    l.red = o;    o = align16(o + kWaves * sizeof(double));
+    l.wpart = o;  o = align16(o + kWaves * sizeof(double));
+    l.bins = o;   o = align16(o + 2 * kGofrBins * sizeof(uint32_t));
+    l.misc = o;   o = align16(o + 16 * sizeof(double));
+    l.wstat = o;  o = align16(o + kWaves * 80);
+    l.tsite = o;  o = align16(o + kWaves * 6 * site_bytes(fp64));
+    if (resident) {
+        l.com = o;    o = align16(o + 3 * size_t(M) * sizeof(double));
+        l.site = o;   o = align16(o + 3 * size_t(M) * site_bytes(fp64));
+        l.cell = o;   o = align16(o + (size_t(ncell) + 1) * sizeof(uint32_t));
+        l.cellid = o; o = align16(o + size_t(M) * sizeof(uint16_t));
+        l.list = o;   o = align16(o + size_t(M) * sizeof(uint16_t));
+    }
+    l.total = o;
+    return l;
+}
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_sweeps(bool fp64, bool resident, const Slot* dev_slots, const Slot& one,
+                         uint32_t n_blocks, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
+                         hipStream_t stream);
+hipError_t launch_init_lattice(SysDev* dev_sys, uint32_t M, hipStream_t stream);
+
+}  // namespace flipmc

@@ -1,0 +1,1083 @@
+// kernels.hip -- gfx950 kernels of the flip Monte Carlo engine.
+//
+// Method (Simon, Barrat & Berthier, Sec. II): Metropolis sweeps over rigid
+// triangular A/B/C molecules with the site-site WCA potential (Eq. 1), mixing
+// translations, rotations and the intramolecular flip of Sec. II.B.
+//
+// Execution model: one workgroup of 8 wave64s owns one system for the whole
+// launch and runs many sweeps back to back.  A sweep is a checkerboard over a
+// randomly shifted cubic cell grid: the k^3 colours run one after another, the
+// cells of one colour are spread over the 8 waves, and the molecules of a
+// cell are tried in ascending index by that wave.  Cells of one colour are at
+// least (k-1) cells apart, farther than any two molecules can interact, so the
+// waves never race.  Inside a trial the 64 lanes share the energy difference:
+// lanes scan the 27 / 125 neighbour cells, keep molecules whose centre of mass
+// is within reach, compact them into a per-wave LDS buffer and then evaluate
+// (candidate site x moved site) pair terms; a wave butterfly reduction in FP64
+// gives dE in a fixed order.  Proposals of all molecules of a cell are drawn in
+// parallel (one lane each) before the cell's sequential trials.
+//
+// The random numbers are Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11)
+// keyed by the seed and counted by (molecule, sweep low, sweep high, tag), so a
+// run is reproducible regardless of how systems are batched.
+#include "engine.h"
+
+namespace flipmc {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586;
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t a0 = 0xD2511F53u * c0, a1 = __umulhi(0xD2511F53u, c0);
+        const uint32_t b0 = 0xCD9E8D57u * c2, b1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = b1 ^ c1 ^ k0;
+        const uint32_t n2 = a1 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = b0;
+        c2 = n2;
+        c3 = a0;
+    }
+    return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ double unit_open(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+__device__ __forceinline__ double unit_53(uint32_t lo, uint32_t hi)
+{
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    return (double)((v >> 11) + 1) * 0x1p-53;
+}
+
+template <typename Real>
+struct alignas(16) R4 {
+    Real x, y, z, w;
+};
+
+template <typename Real>
+struct alignas(16) Cand {
+    Real x, y, z;
+    uint32_t j;
+};
+
+// ---------------------------------------------------------------- wave ops --
+
+__device__ __forceinline__ uint32_t rl_u(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ float rl_f(float v, int l) { return __int_as_float((int)rl_u(__float_as_uint(v), l)); }
+__device__ __forceinline__ double rl_d(double v, int l)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = rl_u((uint32_t)b, l), hi = rl_u((uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+__device__ __forceinline__ float rl_r(float v, int l) { return rl_f(v, l); }
+__device__ __forceinline__ double rl_r(double v, int l) { return rl_d(v, l); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Exclusive prefix sum over the wave; *total gets the wave total.
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
+{
+    const int lane = __lane_id();
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    *total = __shfl(inc, 63);
+    return inc - v;
+}
+
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over the workgroup in a fixed order (identical bits in every thread).
+__device__ double block_sum(double v, double* red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kWaves; ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// In-place exclusive scan of a[0..n) by the whole workgroup.
+__device__ void block_excl_scan(uint32_t* a, uint32_t n, uint32_t* scratch)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t per = (n + kThreads - 1) / kThreads;
+    const uint32_t beg = min(n, tid * per), end = min(n, beg + per);
+    uint32_t s = 0;
+    for (uint32_t i = beg; i < end; ++i) s += a[i];
+    uint32_t tot;
+    const uint32_t ex = wave_excl_scan(s, &tot);
+    if (lane == 0) scratch[wave] = tot;
+    __syncthreads();
+    uint32_t run = ex;
+    for (int w = 0; w < wave; ++w) run += scratch[w];
+    for (uint32_t i = beg; i < end; ++i) {
+        const uint32_t t = a[i];
+        a[i] = run;
+        run += t;
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------- geometry --
+
+__device__ __forceinline__ double wrap(double x, double L) { return x - L * floor(x / L); }
+
+__device__ __forceinline__ double min_image(double d, double L, double invL)
+{
+    return d - L * rint(d * invL);
+}
+
+__device__ __forceinline__ int cell_axis(double x, double h, double L, double w, int nc)
+{
+    const double g = wrap(x - h, L);
+    int c = (int)floor(g / w);
+    c = c < 0 ? 0 : c;
+    return c >= nc ? nc - 1 : c;
+}
+
+__device__ __forceinline__ void rotation(double qw, double qx, double qy, double qz, double r[9])
+{
+    r[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+    r[1] = 2.0 * (qx * qy - qw * qz);
+    r[2] = 2.0 * (qx * qz + qw * qy);
+    r[3] = 2.0 * (qx * qy + qw * qz);
+    r[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
+    r[5] = 2.0 * (qy * qz - qw * qx);
+    r[6] = 2.0 * (qx * qz - qw * qy);
+    r[7] = 2.0 * (qy * qz + qw * qx);
+    r[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+}
+
+// Shifted WCA of Eq. (1) written as (2 (s/r)^6 - 1)^2, given s^2 and r^2.
+__device__ __forceinline__ float pair_u(float s2, float r2)
+{
+    const float x = s2 * __builtin_amdgcn_rcpf(r2);
+    const float x3 = x * x * x;
+    const float t = fmaf(2.0f, x3, -1.0f);
+    return t * t;
+}
+__device__ __forceinline__ double pair_u(double s2, double r2)
+{
+    const double x = s2 / r2;
+    const double x3 = x * x * x;
+    const double t = fma(2.0, x3, -1.0);
+    return t * t;
+}
+
+// Body-frame coordinate a of site s of the equilateral triangle.
+template <class Cx>
+__device__ __forceinline__ double body_at(const Cx& C, uint32_t s, int a)
+{
+    if (a == 0) return s == 0 ? C.bR : -0.5 * C.bR;
+    if (a == 1) return s == 0 ? 0.0 : (s == 1 ? C.bH : -C.bH);
+    return 0.0;
+}
+
+// Diameter of type t, from the 3-entry table in LDS (filled at kernel entry);
+// a table lookup keeps the per-system constants out of dynamically indexed
+// memory.
+template <class Cx>
+__device__ __forceinline__ double sigma_of(const Cx& C, uint32_t t)
+{
+    return C.misc[1 + t];
+}
+
+// ------------------------------------------------------------- per system --
+
+// Everything a workgroup needs, copied from the system descriptor at kernel
+// entry (before any store, so the copies are scalar loads kept in SGPRs) plus
+// the LDS or HBM addresses of the work arrays.
+template <typename Real, bool kRes>
+struct Ctx {
+    uint32_t M, k, nc, ncell, seed_lo, seed_hi;
+    uint32_t resum_interval, obs_interval, gofr_interval, obs_start, max_samples, gofr_nbins;
+    double L, invL, w, T, p_flip, p_ft, dmax, rot_max, reach2, radius, rc2_factor;
+    double bR, bH;            // body frame: site 0 at (bR, 0, 0), sites 1, 2 at (-bR/2, +-bH, 0)
+    double sig0, sig1, sig2;  // diameters of types A, B, C
+    double gofr_dr, gofr_rmax;
+    double* gcom;
+    double* quat;
+    uint32_t* types;
+    double* u0;
+    uint8_t* kref;
+    Stats* stats;
+    double* e_samples;
+    double* drift_samples;
+    uint64_t* gofr_all;
+    uint64_t* gofr_inter;
+    double* c2;
+    uint64_t* c2_sweep;
+    MoveRecord* log;
+    uint64_t log_sweep0, log_sweeps;
+    // work arrays (LDS when resident)
+    double* com;
+    R4<Real>* site;
+    uint32_t* cellb;
+    uint16_t* cellid;
+    uint16_t* list;
+    double* red;
+    double* wpart;
+    uint32_t* bins;
+    double* misc;
+};
+
+// Proposal of one molecule, held by one lane until the wave reaches it.  The
+// new centre of mass (translation) and the new site offsets (rotation) are
+// rebuilt from dl / qn by the wave when the trial runs.
+struct Prop {
+    uint32_t m;
+    uint32_t kind;  // move | exited << 4 | axis << 8
+    double thr;     // T ln u_acc
+    double dl0, dl1, dl2;       // translation: displacement
+    double qn0, qn1, qn2, qn3;  // rotation: new quaternion
+};
+
+// Draw and build the proposal of molecule m (one lane per molecule).
+template <typename Real, bool kRes>
+__device__ Prop propose(const Ctx<Real, kRes>& C, uint32_t m, uint64_t sweep, double hx,
+                        double hy, double hz, int cx, int cy, int cz)
+{
+    Prop p;
+    p.m = m;
+    const uint32_t slo = (uint32_t)sweep, shi = (uint32_t)(sweep >> 32);
+    const U4 b0 = philox10(m, slo, shi, 0u, C.seed_lo, C.seed_hi);
+    const U4 b1 = philox10(m, slo, shi, 1u, C.seed_lo, C.seed_hi);
+    const double uacc = unit_53(b0.x, b0.y), ut = unit_open(b0.z);
+    const double p0 = unit_open(b1.x), p1 = unit_open(b1.y), p2 = unit_open(b1.z);
+    p.thr = C.T * log(uacc);
+    const uint32_t move = ut < C.p_flip ? 2u : (ut < C.p_ft ? 0u : 1u);
+    uint32_t exited = 0, axis = 255;
+    const uint32_t M = C.M;
+    p.dl0 = p.dl1 = p.dl2 = 0.0;
+    p.qn0 = p.qn1 = p.qn2 = p.qn3 = 0.0;
+    if (move == 0u) {
+        const double c0 = C.com[m], c1 = C.com[M + m], c2 = C.com[2 * M + m];
+        p.dl0 = C.dmax * (2.0 * p0 - 1.0);
+        p.dl1 = C.dmax * (2.0 * p1 - 1.0);
+        p.dl2 = C.dmax * (2.0 * p2 - 1.0);
+        const int nc = (int)C.nc;
+        exited = (cell_axis(wrap(c0 + p.dl0, C.L), hx, C.L, C.w, nc) != cx) ||
+                 (cell_axis(wrap(c1 + p.dl1, C.L), hy, C.L, C.w, nc) != cy) ||
+                 (cell_axis(wrap(c2 + p.dl2, C.L), hz, C.L, C.w, nc) != cz);
+    } else if (move == 1u) {
+        const double z = 2.0 * p0 - 1.0;
+        const double phi = kTwoPi * p1;
+        const double st = sqrt(1.0 - z * z);
+        const double nx = st * cos(phi), ny = st * sin(phi), nz = z;
+        const double th = C.rot_max * (2.0 * p2 - 1.0);
+        const double ch = cos(0.5 * th), sh = sin(0.5 * th);
+        const double dw = ch, dx = nx * sh, dy = ny * sh, dz = nz * sh;
+        const double qw = C.quat[m], qx = C.quat[M + m], qy = C.quat[2 * M + m],
+                     qz = C.quat[3 * M + m];
+        const double rw = dw * qw - dx * qx - dy * qy - dz * qz;
+        const double rx = dw * qx + dx * qw + dy * qz - dz * qy;
+        const double ry = dw * qy - dx * qz + dy * qw + dz * qx;
+        const double rz = dw * qz + dx * qy - dy * qx + dz * qw;
+        const double nrm = sqrt(rw * rw + rx * rx + ry * ry + rz * rz);
+        p.qn0 = rw / nrm; p.qn1 = rx / nrm; p.qn2 = ry / nrm; p.qn3 = rz / nrm;
+    } else {
+        int a = (int)(3.0 * p0);
+        axis = (uint32_t)(a > 2 ? 2 : a);
+    }
+    p.kind = move | (exited << 4) | (axis << 8);
+    return p;
+}
+
+template <typename Real, bool kRes>
+__device__ __forceinline__ void store_sites_from_quat(const Ctx<Real, kRes>& C, uint32_t m)
+{
+    const uint32_t M = C.M;
+    double r[9];
+    rotation(C.quat[m], C.quat[M + m], C.quat[2 * M + m], C.quat[3 * M + m], r);
+    const uint32_t ty = C.types[m];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        R4<Real> v;
+        v.x = (Real)(r[0] * body_at(C, s, 0) + r[1] * body_at(C, s, 1) + r[2] * body_at(C, s, 2));
+        v.y = (Real)(r[3] * body_at(C, s, 0) + r[4] * body_at(C, s, 1) + r[5] * body_at(C, s, 2));
+        v.z = (Real)(r[6] * body_at(C, s, 0) + r[7] * body_at(C, s, 1) + r[8] * body_at(C, s, 2));
+        v.w = (Real)sigma_of(C, (ty >> (8 * s)) & 0xFFu);
+        C.site[3 * m + s] = v;
+    }
+}
+
+// FP64 offsets of molecule m straight from its quaternion, plus site sigmas.
+template <typename Real, bool kRes>
+__device__ __forceinline__ void offsets_f64(const Ctx<Real, kRes>& C, uint32_t m, double o[9],
+                                            double sg[3])
+{
+    const uint32_t M = C.M;
+    double r[9];
+    rotation(C.quat[m], C.quat[M + m], C.quat[2 * M + m], C.quat[3 * M + m], r);
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            o[3 * s + a] = r[3 * a] * body_at(C, s, 0) + r[3 * a + 1] * body_at(C, s, 1) +
+                           r[3 * a + 2] * body_at(C, s, 2);
+    const uint32_t ty = C.types[m];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) sg[s] = sigma_of(C, (ty >> (8 * s)) & 0xFFu);
+}
+
+// Total inter-molecular energy in FP64 over balanced molecule pairs.
+template <typename Real, bool kRes>
+__device__ double resum_energy(const Ctx<Real, kRes>& C)
+{
+    const uint32_t M = C.M, half = M / 2;
+    double e = 0.0;
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        double om[9], sm[3];
+        offsets_f64(C, m, om, sm);
+        const double cx = C.com[m], cy = C.com[M + m], cz = C.com[2 * M + m];
+        for (uint32_t dj = 1; dj <= half; ++dj) {
+            if ((M & 1u) == 0u && dj == half && m >= half) break;
+            uint32_t j = m + dj;
+            if (j >= M) j -= M;
+            const double dx = min_image(C.com[j] - cx, C.L, C.invL);
+            const double dy = min_image(C.com[M + j] - cy, C.L, C.invL);
+            const double dz = min_image(C.com[2 * M + j] - cz, C.L, C.invL);
+            if (dx * dx + dy * dy + dz * dz >= C.reach2) continue;
+            double oj[9], sj[3];
+            offsets_f64(C, j, oj, sj);
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const double rx = dx + oj[3 * t] - om[3 * s];
+                    const double ry = dy + oj[3 * t + 1] - om[3 * s + 1];
+                    const double rz = dz + oj[3 * t + 2] - om[3 * s + 2];
+                    const double r2 = rx * rx + ry * ry + rz * rz;
+                    const double sg = 0.5 * (sm[s] + sj[t]);
+                    const double s2 = sg * sg;
+                    if (r2 < C.rc2_factor * s2) e += pair_u(s2, r2);
+                }
+        }
+    }
+    return block_sum(e, C.red);
+}
+
+__device__ __forceinline__ bool is_c2_time(uint64_t t)
+{
+    if (t == 0) return false;
+    while (t % 10 == 0) t /= 10;
+    return t == 1 || t == 2 || t == 5;
+}
+
+template <typename Real, bool kRes>
+__device__ double c2_value(const Ctx<Real, kRes>& C)
+{
+    const uint32_t M = C.M;
+    double v = 0.0;
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        double r[9];
+        rotation(C.quat[m], C.quat[M + m], C.quat[2 * M + m], C.quat[3 * M + m], r);
+        const int k = C.kref[m];
+        double dot = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double u = (r[3 * a] * body_at(C, k, 0) + r[3 * a + 1] * body_at(C, k, 1) +
+                              r[3 * a + 2] * body_at(C, k, 2)) / C.radius;
+            dot += u * C.u0[a * M + m];
+        }
+        v += 0.5 * (3.0 * dot * dot - 1.0);
+    }
+    return block_sum(v, C.red) / (double)M;
+}
+
+template <typename Real, bool kRes>
+__device__ void reset_observables(const Ctx<Real, kRes>& C)
+{
+    const uint32_t M = C.M;
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        const uint32_t ty = C.types[m];
+        int k = 0;
+        for (int s = 0; s < 3; ++s)
+            if (((ty >> (8 * s)) & 0xFFu) == 1u) k = s;
+        C.kref[m] = (uint8_t)k;
+        double r[9];
+        rotation(C.quat[m], C.quat[M + m], C.quat[2 * M + m], C.quat[3 * M + m], r);
+        for (int a = 0; a < 3; ++a)
+            C.u0[a * M + m] = (r[3 * a] * body_at(C, k, 0) + r[3 * a + 1] * body_at(C, k, 1) +
+                               r[3 * a + 2] * body_at(C, k, 2)) / C.radius;
+    }
+    for (uint32_t b = threadIdx.x; b < kGofrBins; b += kThreads) {
+        C.gofr_all[b] = 0;
+        C.gofr_inter[b] = 0;
+    }
+    if (threadIdx.x == 0) {
+        Stats* st = C.stats;
+        st->obs_origin = st->sweep;
+        st->n_e = st->n_drift = st->n_gofr = st->n_c2 = 0;
+        st->e_sum = st->e_sumsq = 0.0;
+        st->max_abs_drift = 0.0;
+    }
+}
+
+// One g(r) frame (Eq. 3 numerator): every ordered pair of distinct sites.
+template <typename Real, bool kRes>
+__device__ void gofr_frame(const Ctx<Real, kRes>& C)
+{
+    const uint32_t M = C.M, half = M / 2, nb = C.gofr_nbins;
+    uint32_t* ball = C.bins;
+    uint32_t* binter = C.bins + kGofrBins;
+    for (uint32_t b = threadIdx.x; b < 2 * kGofrBins; b += kThreads) C.bins[b] = 0;
+    __syncthreads();
+    const double dr = C.gofr_dr, rmax = C.gofr_rmax;
+    const double cut = rmax + 2.0 * C.radius;
+    const double cut2 = cut * cut;
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        double om[9], sm[3];
+        offsets_f64(C, m, om, sm);
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int t = s + 1; t < 3; ++t) {
+                const double rx = om[3 * t] - om[3 * s], ry = om[3 * t + 1] - om[3 * s + 1],
+                             rz = om[3 * t + 2] - om[3 * s + 2];
+                const int b = (int)floor(sqrt(rx * rx + ry * ry + rz * rz) / dr);
+                if (b >= 0 && b < (int)nb) atomicAdd(&ball[b], 2u);
+            }
+        const double cx = C.com[m], cy = C.com[M + m], cz = C.com[2 * M + m];
+        for (uint32_t dj = 1; dj <= half; ++dj) {
+            if ((M & 1u) == 0u && dj == half && m >= half) break;
+            uint32_t j = m + dj;
+            if (j >= M) j -= M;
+            const double dx = min_image(C.com[j] - cx, C.L, C.invL);
+            const double dy = min_image(C.com[M + j] - cy, C.L, C.invL);
+            const double dz = min_image(C.com[2 * M + j] - cz, C.L, C.invL);
+            if (dx * dx + dy * dy + dz * dz >= cut2) continue;
+            double oj[9], sj[3];
+            offsets_f64(C, j, oj, sj);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const double bx = dx + oj[3 * t], by = dy + oj[3 * t + 1], bz = dz + oj[3 * t + 2];
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    const double rx = bx - om[3 * s], ry = by - om[3 * s + 1], rz = bz - om[3 * s + 2];
+                    const int b = (int)floor(sqrt(rx * rx + ry * ry + rz * rz) / dr);
+                    if (b >= 0 && b < (int)nb) {
+                        atomicAdd(&ball[b], 2u);
+                        atomicAdd(&binter[b], 2u);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
+        C.gofr_all[b] += ball[b];
+        C.gofr_inter[b] += binter[b];
+    }
+    if (threadIdx.x == 0) C.stats->n_gofr += 1;
+}
+
+// Cell grid of one sweep: counting sort of molecules by cell.
+template <typename Real, bool kRes>
+__device__ void build_cells(const Ctx<Real, kRes>& C, double hx, double hy, double hz,
+                            uint32_t* scratch)
+{
+    const uint32_t M = C.M, ncell = C.ncell;
+    const int nc = (int)C.nc;
+    for (uint32_t i = threadIdx.x; i <= ncell; i += kThreads) C.cellb[i] = 0;
+    __syncthreads();
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        const int ix = cell_axis(C.com[m], hx, C.L, C.w, nc);
+        const int iy = cell_axis(C.com[M + m], hy, C.L, C.w, nc);
+        const int iz = cell_axis(C.com[2 * M + m], hz, C.L, C.w, nc);
+        const uint32_t cid = (uint32_t)(ix + nc * (iy + nc * iz));
+        C.cellid[m] = (uint16_t)cid;
+        atomicAdd(&C.cellb[cid + 1], 1u);
+    }
+    __syncthreads();
+    block_excl_scan(C.cellb + 1, ncell, scratch);
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        const uint32_t pos = atomicAdd(&C.cellb[C.cellid[m] + 1u], 1u);
+        C.list[pos] = (uint16_t)m;
+    }
+    __syncthreads();
+    // ascending molecule index inside every cell
+    for (uint32_t c = threadIdx.x; c < ncell; c += kThreads) {
+        const uint32_t b = C.cellb[c], e = C.cellb[c + 1];
+        for (uint32_t i = b + 1; i < e; ++i) {
+            const uint16_t v = C.list[i];
+            uint32_t q = i;
+            while (q > b && C.list[q - 1] > v) {
+                C.list[q] = C.list[q - 1];
+                --q;
+            }
+            C.list[q] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// Per-wave accumulators, kept in LDS and updated by lane 0.
+struct WaveStats {
+    uint64_t att[3], acc[3], exits, terms, tests;
+    double e;  // accepted dE of the current sweep
+};
+
+// Per-wave description of the trial in flight: the moved sites before and
+// after the move (offset from the molecule's centre + sigma of the type).
+template <typename Real>
+struct TrialSites {
+    R4<Real> old_site[3];
+    R4<Real> new_site[3];
+};
+
+// All trials of one cell, run by one wave.
+template <typename Real, bool kRes>
+__device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint64_t sweep,
+                         double hx, double hy, double hz, Cand<Real>* cand, uint16_t* seglo,
+                         uint16_t* segoff, TrialSites<Real>* ts, WaveStats* ws)
+{
+    const int lane = __lane_id();
+    const uint32_t M = C.M;
+    const int nc = (int)C.nc;
+    const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
+    const uint32_t beg = C.cellb[cell], cnt = C.cellb[cell + 1] - beg;
+    if (cnt == 0) return;
+
+    // Neighbour cells as row segments along x: (2r+1)^2 rows, 1 or 2 x-ranges.
+    const int r = (int)C.k - 1;
+    const bool full = 2 * r + 1 >= nc;
+    const int nrow = full ? nc : 2 * r + 1;
+    int xa0, xb0, xa1 = 0, xb1 = -1;
+    if (full) {
+        xa0 = 0; xb0 = nc - 1;
+    } else if (cx - r < 0) {
+        xa0 = cx - r + nc; xb0 = nc - 1; xa1 = 0; xb1 = cx + r;
+    } else if (cx + r >= nc) {
+        xa0 = cx - r; xb0 = nc - 1; xa1 = 0; xb1 = cx + r - nc;
+    } else {
+        xa0 = cx - r; xb0 = cx + r;
+    }
+    const int nxr = xb1 >= xa1 ? 2 : 1;
+    const int nseg = nrow * nrow * nxr;
+    uint32_t scnt = 0, slo = 0;
+    if (lane < nseg) {
+        const int ixr = lane % nxr, iy = (lane / nxr) % nrow, iz = lane / (nxr * nrow);
+        const int y = full ? iy : (cy - r + iy + nc) % nc;
+        const int z = full ? iz : (cz - r + iz + nc) % nc;
+        const int xa = ixr ? xa1 : xa0, xb = ixr ? xb1 : xb0;
+        const uint32_t rowbase = (uint32_t)(nc * (y + nc * z));
+        slo = C.cellb[rowbase + xa];
+        scnt = C.cellb[rowbase + xb + 1] - slo;
+    }
+    uint32_t total;
+    const uint32_t soff = wave_excl_scan(scnt, &total);
+    if (lane < nseg) {
+        seglo[lane] = (uint16_t)slo;
+        segoff[lane] = (uint16_t)soff;
+    }
+    wave_lds_sync();
+
+    constexpr int kCap = cand_cap(sizeof(Real) == 8);
+    static_assert(kCap >= 64, "a ballot can append 64 candidates");
+    const Real rc2f = (Real)C.rc2_factor;
+    for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+        const uint32_t nin = min(64u, cnt - c0);
+        Prop pr;
+        if ((uint32_t)lane < nin)
+            pr = propose(C, (uint32_t)C.list[beg + c0 + lane], sweep, hx, hy, hz, cx, cy, cz);
+        for (uint32_t i = 0; i < nin; ++i) {
+            const uint32_t m = rl_u(pr.m, (int)i);
+            const uint32_t kind = rl_u(pr.kind, (int)i);
+            const uint32_t move = kind & 15u, exited = (kind >> 4) & 1u, axis = kind >> 8;
+            const double thr = rl_d(pr.thr, (int)i);
+            const bool logging = C.log != nullptr && sweep - C.log_sweep0 < C.log_sweeps;
+            if (lane == 0) ws->att[move] += 1;
+            if (exited) {
+                if (lane == 0) {
+                    ws->exits += 1;
+                    if (logging) {
+                        MoveRecord rec;
+                        rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = thr; rec.sweep = sweep;
+                        rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = 0;
+                        rec.exited = 1; rec.axis = (uint8_t)axis; rec.pair_terms = 0; rec.pad = 0;
+                        (C.log)[(sweep - C.log_sweep0) * M + m] = rec;
+                    }
+                }
+                continue;
+            }
+            // moved sites: all three, or the two swapped ones of a flip
+            const bool flip = move == 2u;
+            const uint32_t a1 = flip ? (axis + 1) % 3 : 0u, a2 = flip ? (axis + 2) % 3 : 1u;
+            const int nmv = flip ? 2 : 3;
+            const double dl0 = rl_d(pr.dl0, (int)i), dl1 = rl_d(pr.dl1, (int)i),
+                         dl2 = rl_d(pr.dl2, (int)i);
+            if (lane < 3) {
+                const uint32_t sidx = lane == 0 ? a1 : (lane == 1 ? a2 : 2u);
+                const R4<Real> o = C.site[3 * m + sidx];
+                R4<Real> n = o;
+                if (flip) {
+                    n.w = C.site[3 * m + (lane == 0 ? a2 : a1)].w;
+                } else if (move == 1u) {
+                    double rm[9];
+                    rotation(rl_d(pr.qn0, (int)i), rl_d(pr.qn1, (int)i), rl_d(pr.qn2, (int)i),
+                             rl_d(pr.qn3, (int)i), rm);
+                    const double b0 = body_at(C, sidx, 0), b1 = body_at(C, sidx, 1),
+                                 b2 = body_at(C, sidx, 2);
+                    n.x = (Real)(rm[0] * b0 + rm[1] * b1 + rm[2] * b2);
+                    n.y = (Real)(rm[3] * b0 + rm[4] * b1 + rm[5] * b2);
+                    n.z = (Real)(rm[6] * b0 + rm[7] * b1 + rm[8] * b2);
+                }
+                ts->old_site[lane] = o;
+                ts->new_site[lane] = n;
+            }
+            wave_lds_sync();
+            const Real dlx = (Real)dl0, dly = (Real)dl1, dlz = (Real)dl2;
+            const double cmx = C.com[m], cmy = C.com[M + m], cmz = C.com[2 * M + m];
+
+            Real acc = Real(0), accs = Real(0);
+            uint32_t nterm = 0;
+            uint32_t ntest = 0;
+            auto flush = [&](uint32_t nb) __attribute__((always_inline)) {
+                wave_lds_sync();
+                const uint32_t nitems = nb * 3u;
+                ntest += nitems * (uint32_t)nmv * 2u;
+                for (uint32_t it = (uint32_t)lane; it < nitems; it += 64u) {
+                    const uint32_t ci = it / 3u, t = it - 3u * ci;
+                    const Cand<Real> cd = cand[ci];
+                    const R4<Real> sj = C.site[3u * cd.j + t];
+                    const Real bx = cd.x + sj.x, by = cd.y + sj.y, bz = cd.z + sj.z;
+                    const Real qx0 = bx - dlx, qy0 = by - dly, qz0 = bz - dlz;
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) {
+                        if (v < nmv) {
+                            const R4<Real> o = ts->old_site[v], n = ts->new_site[v];
+                            const Real rx = bx - o.x, ry = by - o.y, rz = bz - o.z;
+                            const Real r2 = rx * rx + ry * ry + rz * rz;
+                            const Real sg = Real(0.5) * (o.w + sj.w);
+                            const Real s2 = sg * sg, rc2 = rc2f * s2;
+                            const Real uo = r2 < rc2 ? pair_u(s2, r2) : Real(0);
+                            Real r2n;
+                            if (flip) {
+                                r2n = r2;
+                            } else {
+                                const Real qx = qx0 - n.x, qy = qy0 - n.y, qz = qz0 - n.z;
+                                r2n = qx * qx + qy * qy + qz * qz;
+                            }
+                            const Real sgn = Real(0.5) * (n.w + sj.w);
+                            const Real s2n = sgn * sgn, rc2n = rc2f * s2n;
+                            const Real un = r2n < rc2n ? pair_u(s2n, r2n) : Real(0);
+                            acc += un - uo;
+                            accs += un + uo;
+                            nterm += (r2 < rc2 ? 1u : 0u) + (r2n < rc2n ? 1u : 0u);
+                        }
+                    }
+                }
+                wave_lds_sync();
+            };
+
+            uint32_t nbuf = 0;
+            for (uint32_t base = 0; base < total; base += 64u) {
+                const uint32_t idx = base + (uint32_t)lane;
+                bool pass = false;
+                uint32_t j = 0;
+                double dx = 0.0, dy = 0.0, dz = 0.0;
+                if (idx < total) {
+                    int lo = 0, hi = nseg;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if ((uint32_t)segoff[mid] <= idx) lo = mid; else hi = mid;
+                    }
+                    j = C.list[(uint32_t)seglo[lo] + (idx - (uint32_t)segoff[lo])];
+                    if (j != m) {
+                        dx = min_image(C.com[j] - cmx, C.L, C.invL);
+                        dy = min_image(C.com[M + j] - cmy, C.L, C.invL);
+                        dz = min_image(C.com[2 * M + j] - cmz, C.L, C.invL);
+                        const double r2o = dx * dx + dy * dy + dz * dz;
+                        const double ex = dx - dl0, ey = dy - dl1, ez = dz - dl2;
+                        const double r2n = ex * ex + ey * ey + ez * ez;
+                        pass = (r2o < C.reach2) || (r2n < C.reach2);
+                    }
+                }
+                const uint64_t bm = __ballot(pass);
+                const uint32_t np = (uint32_t)__popcll(bm);
+                if (nbuf + np > (uint32_t)kCap) {
+                    flush(nbuf);
+                    nbuf = 0;
+                }
+                if (pass) {
+                    Cand<Real> cd;
+                    cd.x = (Real)dx; cd.y = (Real)dy; cd.z = (Real)dz; cd.j = j;
+                    cand[nbuf + rank_below(bm)] = cd;
+                }
+                nbuf += np;
+            }
+            if (nbuf) flush(nbuf);
+
+            const double de = wave_sum((double)acc);
+            const double sc = wave_sum((double)accs);
+            const uint32_t terms = wave_sum_u(nterm);
+            const bool accept = (de <= 0.0) || (thr < -de);
+            if (lane == 0) {
+                ws->terms += terms;
+                ws->tests += ntest;
+                if (accept) {
+                    ws->acc[move] += 1;
+                    ws->e += de;
+                    if (move == 0u) {
+                        C.com[m] = wrap(cmx + dl0, C.L);
+                        C.com[M + m] = wrap(cmy + dl1, C.L);
+                        C.com[2 * M + m] = wrap(cmz + dl2, C.L);
+                    } else if (move == 1u) {
+                        C.site[3 * m] = ts->new_site[0];
+                        C.site[3 * m + 1] = ts->new_site[1];
+                        C.site[3 * m + 2] = ts->new_site[2];
+                    } else {
+                        C.site[3 * m + a1].w = ts->new_site[0].w;
+                        C.site[3 * m + a2].w = ts->new_site[1].w;
+                        const uint32_t ty = C.types[m];
+                        const uint32_t t1 = (ty >> (8 * a1)) & 0xFFu, t2 = (ty >> (8 * a2)) & 0xFFu;
+                        uint32_t nt = ty & ~((0xFFu << (8 * a1)) | (0xFFu << (8 * a2)));
+                        nt |= (t2 << (8 * a1)) | (t1 << (8 * a2));
+                        C.types[m] = nt;
+                    }
+                }
+                if (logging) {
+                    MoveRecord rec;
+                    rec.delta_e = de; rec.scale = sc; rec.t_log_u = thr; rec.sweep = sweep;
+                    rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = accept ? 1 : 0;
+                    rec.exited = 0; rec.axis = (uint8_t)axis; rec.pair_terms = terms; rec.pad = 0;
+                    (C.log)[(sweep - C.log_sweep0) * M + m] = rec;
+                }
+            }
+            if (accept && move == 1u) {
+                const double q0 = rl_d(pr.qn0, (int)i), q1 = rl_d(pr.qn1, (int)i),
+                             q2 = rl_d(pr.qn2, (int)i), q3 = rl_d(pr.qn3, (int)i);
+                if (lane == 0) {
+                    C.quat[m] = q0;
+                    C.quat[M + m] = q1;
+                    C.quat[2 * M + m] = q2;
+                    C.quat[3 * M + m] = q3;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+// Fill the per-system constants of a workgroup (before any store).
+template <typename Real, bool kRes>
+__device__ __forceinline__ void load_ctx(Ctx<Real, kRes>& C, const SysDev* __restrict__ Dp)
+{
+    C.M = Dp->M; C.k = Dp->k; C.nc = Dp->nc; C.ncell = Dp->ncell;
+    C.seed_lo = Dp->seed_lo; C.seed_hi = Dp->seed_hi;
+    C.resum_interval = Dp->resum_interval; C.obs_interval = Dp->obs_interval;
+    C.gofr_interval = Dp->gofr_interval; C.obs_start = Dp->obs_start;
+    C.max_samples = Dp->max_samples; C.gofr_nbins = Dp->gofr_nbins;
+    C.L = Dp->L; C.invL = 1.0 / Dp->L; C.w = Dp->w; C.T = Dp->T;
+    C.p_flip = Dp->p_flip; C.p_ft = Dp->p_ft; C.dmax = Dp->dmax; C.rot_max = Dp->rot_max;
+    C.reach2 = Dp->reach2; C.radius = Dp->radius; C.rc2_factor = Dp->rc2_factor;
+    C.bR = Dp->body[0]; C.bH = Dp->body[4];
+    C.sig0 = Dp->sigma[0]; C.sig1 = Dp->sigma[1]; C.sig2 = Dp->sigma[2];
+    C.gofr_dr = Dp->gofr_dr; C.gofr_rmax = Dp->gofr_rmax;
+    C.gcom = Dp->com; C.quat = Dp->quat; C.types = Dp->types; C.u0 = Dp->u0; C.kref = Dp->kref;
+    C.stats = Dp->stats; C.e_samples = Dp->e_samples; C.drift_samples = Dp->drift_samples;
+    C.gofr_all = Dp->gofr_all; C.gofr_inter = Dp->gofr_inter; C.c2 = Dp->c2;
+    C.c2_sweep = Dp->c2_sweep;
+    C.log = (MoveRecord*)Dp->log; C.log_sweep0 = Dp->log_sweep0; C.log_sweeps = Dp->log_sweeps;
+}
+
+// The hot kernel: n checkerboard sweeps of every slot's system, one
+// workgroup per system, with the state resident in LDS when it fits.
+template <typename Real, bool kRes>
+__global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ slots, Slot one)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Slot sl = slots ? slots[blockIdx.x] : one;
+    if (sl.sys == nullptr || sl.n_sweeps == 0) return;
+    const SysDev* __restrict__ Dp = sl.sys;
+    Ctx<Real, kRes> C;
+    load_ctx(C, Dp);
+    void* g_site = Dp->g_site;
+    uint32_t* g_cell = Dp->g_cell;
+    uint16_t* g_cellid = Dp->g_cellid;
+    uint16_t* g_list = Dp->g_list;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool fp64 = sizeof(Real) == 8;
+    const LdsLayout L = lds_layout(fp64, kRes, C.M, C.ncell);
+    C.red = (double*)(smem + L.red);
+    C.wpart = (double*)(smem + L.wpart);
+    C.bins = (uint32_t*)(smem + L.bins);
+    C.misc = (double*)(smem + L.misc);
+    if (kRes) {
+        C.com = (double*)(smem + L.com);
+        C.site = (R4<Real>*)(smem + L.site);
+        C.cellb = (uint32_t*)(smem + L.cell);
+        C.cellid = (uint16_t*)(smem + L.cellid);
+        C.list = (uint16_t*)(smem + L.list);
+    } else {
+        C.com = C.gcom;
+        C.site = (R4<Real>*)g_site;
+        C.cellb = g_cell;
+        C.cellid = g_cellid;
+        C.list = g_list;
+    }
+    Cand<Real>* cand = (Cand<Real>*)(smem + L.cand) + wave * cand_cap(fp64);
+    uint16_t* seglo = (uint16_t*)(smem + L.seglo) + wave * kMaxSeg;
+    uint16_t* segoff = (uint16_t*)(smem + L.segoff) + wave * kMaxSeg;
+    uint32_t* uscratch = (uint32_t*)(C.misc + 8);
+    const uint32_t M = C.M;
+
+    Stats* st = C.stats;
+    if (tid == 0) {
+        C.misc[0] = st->e_acc;
+        C.misc[1] = C.sig0;
+        C.misc[2] = C.sig1;
+        C.misc[3] = C.sig2;
+    }
+    __syncthreads();
+    if (kRes)
+        for (uint32_t i = tid; i < 3 * M; i += kThreads) C.com[i] = C.gcom[i];
+    for (uint32_t m = tid; m < M; m += kThreads) store_sites_from_quat(C, m);
+    WaveStats* ws = (WaveStats*)(smem + L.wstat) + wave;
+    TrialSites<Real>* ts = (TrialSites<Real>*)(smem + L.tsite) + wave;
+    if (lane == 0) {
+        for (int i = 0; i < 3; ++i) ws->att[i] = ws->acc[i] = 0;
+        ws->exits = ws->terms = ws->tests = 0;
+        ws->e = 0.0;
+    }
+    uint64_t sweep = st->sweep;
+    const uint64_t origin = st->obs_origin;
+    __syncthreads();
+
+    const int k = (int)C.k, nc = (int)C.nc, na = nc / k;
+    const int nact = na * na * na, ncol = k * k * k;
+    for (uint64_t it = 0; it < sl.n_sweeps; ++it) {
+        const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, C.seed_lo,
+                              C.seed_hi);
+        const double hx = C.w * unit_open(g.x), hy = C.w * unit_open(g.y),
+                     hz = C.w * unit_open(g.z);
+        build_cells(C, hx, hy, hz, uscratch);
+        for (int col = 0; col < ncol; ++col) {
+            const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
+            for (int a = wave; a < nact; a += kWaves) {
+                const int ax = a % na, ay = (a / na) % na, az = a / (na * na);
+                run_cell(C, kx + k * ax, ky + k * ay, kz + k * az, sweep, hx, hy, hz, cand, seglo,
+                         segoff, ts, ws);
+            }
+            __syncthreads();
+        }
+        // accumulated energy in a fixed wave order; E/M samples
+        if (lane == 0) {
+            C.wpart[wave] = ws->e;
+            ws->e = 0.0;
+        }
+        ++sweep;
+        __syncthreads();
+        if (tid == 0) {
+            double e = C.misc[0];
+            for (int w = 0; w < kWaves; ++w) e += C.wpart[w];
+            C.misc[0] = e;
+            const uint64_t t = sweep - origin;
+            if (t >= C.obs_start && C.obs_interval && t % C.obs_interval == 0) {
+                const double em = e / (double)M;
+                if (st->n_e < C.max_samples) C.e_samples[st->n_e] = em;
+                st->n_e += 1;
+                st->e_sum += em;
+                st->e_sumsq += em * em;
+            }
+        }
+    }
+
+    // write back
+    if (kRes)
+        for (uint32_t i = tid; i < 3 * M; i += kThreads) C.gcom[i] = C.com[i];
+    if (lane == 0) {
+        for (int i = 0; i < 3; ++i) {
+            if (ws->att[i]) atomicAdd((unsigned long long*)&st->attempts[i], (unsigned long long)ws->att[i]);
+            if (ws->acc[i]) atomicAdd((unsigned long long*)&st->accepts[i], (unsigned long long)ws->acc[i]);
+        }
+        if (ws->exits) atomicAdd((unsigned long long*)&st->exits, (unsigned long long)ws->exits);
+        if (ws->terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)ws->terms);
+        if (ws->tests) atomicAdd((unsigned long long*)&st->pair_tests, (unsigned long long)ws->tests);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        st->sweep = sweep;
+        st->e_acc = C.misc[0];
+    }
+}
+
+// Cold work at event sweeps, straight from the HBM state in FP64: re-sum of
+// the energy (and drift), a g(r) frame, a C_2 sample, observable reset.
+__global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ slots, Slot one)
+{
+    __shared__ double red[kWaves];
+    __shared__ double misc[16];
+    __shared__ uint32_t bins[2 * kGofrBins];
+    const Slot sl = slots ? slots[blockIdx.x] : one;
+    if (sl.sys == nullptr || sl.flags == 0) return;
+    Ctx<double, false> C;
+    load_ctx(C, sl.sys);
+    C.com = C.gcom;
+    C.red = red;
+    C.misc = misc;
+    C.bins = bins;
+    C.wpart = nullptr;
+    C.site = nullptr;
+    C.cellb = nullptr;
+    C.cellid = nullptr;
+    C.list = nullptr;
+    const int tid = threadIdx.x;
+    Stats* st = C.stats;
+    if (tid == 0) {
+        misc[1] = C.sig0;
+        misc[2] = C.sig1;
+        misc[3] = C.sig2;
+    }
+    const uint64_t sweep = st->sweep;
+    const double e_acc = st->e_acc;
+    __syncthreads();
+    const uint32_t f = sl.flags;
+    if (f & kFlagObsReset) {
+        reset_observables(C);
+        __syncthreads();
+    }
+    if (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) {
+        const double e = resum_energy(C);
+        if (tid == 0) {
+            const double acc = (f & kFlagResumSet) ? e : e_acc;
+            if (f & kFlagResumSet) st->e_acc = e;
+            const double drift = acc - e;
+            st->e_resum = e;
+            st->drift = drift;
+            st->resum_sweep = sweep;
+            if (f & kFlagResumPeriodic) {
+                st->n_resum += 1;
+                if (st->n_drift < C.max_samples) C.drift_samples[st->n_drift] = drift;
+                st->n_drift += 1;
+                if (sweep > C.resum_interval && fabs(drift) > st->max_abs_drift)
+                    st->max_abs_drift = fabs(drift);
+            }
+        }
+        __syncthreads();
+    }
+    if (f & kFlagGofr) {
+        gofr_frame(C);
+        __syncthreads();
+    }
+    if (f & kFlagC2) {
+        const double c2 = c2_value(C);
+        if (tid == 0 && st->n_c2 < kC2Max) {
+            C.c2[st->n_c2] = c2;
+            C.c2_sweep[st->n_c2] = sweep - st->obs_origin;
+            st->n_c2 += 1;
+        }
+    }
+}
+
+__global__ void k_init_lattice(SysDev* Dp, uint32_t n)
+{
+    const SysDev& D = *Dp;
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t M = D.M;
+    if (m >= M) return;
+    const double a = D.L / (double)n;
+    const uint32_t i = m % n, j = (m / n) % n, l = m / (n * n);
+    D.com[m] = ((double)i + 0.5) * a;
+    D.com[M + m] = ((double)j + 0.5) * a;
+    D.com[2 * M + m] = ((double)l + 0.5) * a;
+    const U4 g = philox10(m, 0xFFFFFFFFu, 0xFFFFFFFFu, 2u, D.seed_lo, D.seed_hi);
+    const double u1 = unit_open(g.x), u2 = unit_open(g.y), u3 = unit_open(g.z);
+    const double r1 = sqrt(1.0 - u1), r2 = sqrt(u1);
+    D.quat[m] = r2 * cos(kTwoPi * u3);
+    D.quat[M + m] = r1 * sin(kTwoPi * u2);
+    D.quat[2 * M + m] = r1 * cos(kTwoPi * u2);
+    D.quat[3 * M + m] = r2 * sin(kTwoPi * u3);
+    D.types[m] = 0u | (1u << 8) | (2u << 16);
+}
+
+template <typename Real, bool kRes>
+hipError_t launch_one(const Slot* dev_slots, const Slot& one, uint32_t n_blocks, size_t lds,
+                      hipStream_t stream)
+{
+    static size_t configured = 0;
+    if (lds > configured) {
+        hipError_t e = hipFuncSetAttribute((const void*)&k_sweeps<Real, kRes>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        configured = lds;
+    }
+    hipLaunchKernelGGL((k_sweeps<Real, kRes>), dim3(n_blocks), dim3(kThreads), lds, stream,
+                       dev_slots, one);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweeps(bool fp64, bool resident, const Slot* dev_slots, const Slot& one,
+                         uint32_t n_blocks, size_t lds_bytes, hipStream_t stream)
+{
+    if (fp64)
+        return resident ? launch_one<double, true>(dev_slots, one, n_blocks, lds_bytes, stream)
+                        : launch_one<double, false>(dev_slots, one, n_blocks, lds_bytes, stream);
+    return resident ? launch_one<float, true>(dev_slots, one, n_blocks, lds_bytes, stream)
+                    : launch_one<float, false>(dev_slots, one, n_blocks, lds_bytes, stream);
+}
+
+hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
+                         hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_events, dim3(n_blocks), dim3(kThreads), 0, stream, dev_slots, one);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_lattice(SysDev* dev_sys, uint32_t M, hipStream_t stream)
+{
+    uint32_t n = 1;
+    while ((n + 1) * (n + 1) * (n + 1) <= M) ++n;
+    hipLaunchKernelGGL(k_init_lattice, dim3((M + 255) / 256), dim3(256), 0, stream, dev_sys, n);
+    return hipGetLastError();
+}
+
+}  // namespace flipmc

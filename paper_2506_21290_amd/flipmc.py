@@ -1,0 +1,347 @@
+"""Python binding of the flip Monte Carlo C ABI (``include/flipmc.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libflipmc.so``.  PyTorch provides the device buffers and the streams.
+The functions keep the C names; ``System`` and ``Batch`` are thin owners of
+a handle plus its torch buffer.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflipmc.so")
+
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_EDEVICE, MC_EGEOM, MC_ENONFINITE, MC_EBUSY, MC_ENOTIMPL = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+MC_FP64, MC_FP32_DE = 0, 1
+MC_TRANSLATE, MC_ROTATE, MC_FLIP = 0, 1, 2
+MC_FLAG_HBM_STATE = 1
+MC_GOFR_MAX_BINS = 256
+MC_C2_MAX = 32
+
+EXPORTED = [
+    "mc_params_default", "mc_geometry", "mc_required_bytes", "mc_init_system", "mc_sweep",
+    "mc_energy", "mc_observables", "mc_samples", "mc_reset_observables", "mc_get_state",
+    "mc_set_state", "mc_decision_log", "mc_destroy", "mc_last_error", "mc_batch_create",
+    "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
+]
+
+
+class McError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"flipmc error {code}: {msg}")
+        self.code = code
+
+
+class mc_params(C.Structure):
+    _fields_ = [
+        ("n_molecules", C.c_uint32),
+        ("precision", C.c_uint32),
+        ("density", C.c_double),
+        ("temperature", C.c_double),
+        ("sigma", C.c_double * 3),
+        ("bond_length", C.c_double),
+        ("p_flip", C.c_double),
+        ("p_translate", C.c_double),
+        ("max_displacement", C.c_double),
+        ("max_rotation", C.c_double),
+        ("seed", C.c_uint64),
+        ("colours_per_axis", C.c_uint32),
+        ("cells_per_side", C.c_uint32),
+        ("resum_interval", C.c_uint32),
+        ("obs_interval", C.c_uint32),
+        ("gofr_interval", C.c_uint32),
+        ("obs_start", C.c_uint32),
+        ("max_samples", C.c_uint32),
+        ("flags", C.c_uint32),
+        ("gofr_dr", C.c_double),
+    ]
+
+
+class mc_obs(C.Structure):
+    _fields_ = [
+        ("sweep", C.c_uint64),
+        ("attempts", C.c_uint64 * 3),
+        ("accepts", C.c_uint64 * 3),
+        ("exits", C.c_uint64),
+        ("pair_terms", C.c_uint64),
+        ("pair_tests", C.c_uint64),
+        ("e_acc", C.c_double),
+        ("e_resum", C.c_double),
+        ("drift", C.c_double),
+        ("max_abs_drift", C.c_double),
+        ("resum_sweep", C.c_uint64),
+        ("n_energy_samples", C.c_uint32),
+        ("n_drift_samples", C.c_uint32),
+        ("energy_sum", C.c_double),
+        ("energy_sumsq", C.c_double),
+        ("n_gofr_frames", C.c_uint32),
+        ("gofr_nbins", C.c_uint32),
+        ("gofr_dr", C.c_double),
+        ("gofr_rmax", C.c_double),
+        ("gofr_all", C.c_uint64 * MC_GOFR_MAX_BINS),
+        ("gofr_inter", C.c_uint64 * MC_GOFR_MAX_BINS),
+        ("n_c2", C.c_uint32),
+        ("pad", C.c_uint32),
+        ("c2_sweep", C.c_uint64 * MC_C2_MAX),
+        ("c2", C.c_double * MC_C2_MAX),
+    ]
+
+
+MOVE_RECORD_DTYPE = np.dtype(
+    [
+        ("delta_e", "<f8"), ("scale", "<f8"), ("t_log_u", "<f8"), ("sweep", "<u8"),
+        ("molecule", "<u4"), ("move", "u1"), ("accepted", "u1"), ("exited", "u1"),
+        ("axis", "u1"), ("pair_terms", "<u4"), ("pad", "<u4"),
+    ]
+)
+assert MOVE_RECORD_DTYPE.itemsize == 48
+
+_lib = None
+
+
+def lib():
+    """Load libflipmc.so; fails loudly when the HIP extension is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')"
+            )
+        L = C.CDLL(LIB_PATH)
+        vp, dp, u8p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint8)
+        u32p, u64p, szp = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), C.POINTER(C.c_size_t)
+        pp = C.POINTER(mc_params)
+        L.mc_params_default.argtypes = [pp]
+        L.mc_params_default.restype = None
+        L.mc_geometry.argtypes = [pp, dp, u32p, u32p]
+        L.mc_required_bytes.argtypes = [pp, szp]
+        L.mc_init_system.argtypes = [pp, dp, dp, u8p, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.mc_sweep.argtypes = [vp, C.c_uint64]
+        L.mc_energy.argtypes = [vp, dp, dp, dp]
+        L.mc_observables.argtypes = [vp, C.POINTER(mc_obs)]
+        L.mc_samples.argtypes = [vp, dp, dp, C.c_size_t, szp, szp]
+        L.mc_reset_observables.argtypes = [vp]
+        L.mc_get_state.argtypes = [vp, dp, dp, u8p, u64p, dp]
+        L.mc_set_state.argtypes = [vp, dp, dp, u8p, C.c_uint64, C.c_double]
+        L.mc_decision_log.argtypes = [vp, vp, C.c_size_t]
+        L.mc_destroy.argtypes = [vp]
+        L.mc_destroy.restype = None
+        L.mc_last_error.restype = C.c_char_p
+        L.mc_batch_create.argtypes = [C.c_uint32, C.c_uint32, vp, C.POINTER(vp)]
+        L.mc_batch_add.argtypes = [vp, vp, C.c_uint64, u32p]
+        L.mc_batch_run.argtypes = [vp, C.c_uint64, u32p]
+        L.mc_batch_poll.argtypes = [vp, u32p, C.POINTER(vp), C.c_size_t, szp]
+        L.mc_batch_cancel.argtypes = [vp, C.c_uint32]
+        L.mc_batch_destroy.argtypes = [vp]
+        L.mc_batch_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MC_OK:
+        raise McError(rc, lib().mc_last_error().decode())
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+# ------------------------------------------------------------------ C names --
+
+def mc_params_default(**overrides) -> mc_params:
+    p = mc_params()
+    lib().mc_params_default(C.byref(p))
+    for k, v in overrides.items():
+        if k == "sigma":
+            p.sigma = (C.c_double * 3)(*v)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def mc_geometry(p: mc_params):
+    box, k, nc = C.c_double(), C.c_uint32(), C.c_uint32()
+    _check(lib().mc_geometry(C.byref(p), C.byref(box), C.byref(k), C.byref(nc)))
+    return box.value, k.value, nc.value
+
+
+def mc_required_bytes(p: mc_params) -> int:
+    n = C.c_size_t()
+    _check(lib().mc_required_bytes(C.byref(p), C.byref(n)))
+    return n.value
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream), stream
+
+
+class System:
+    """One Markov chain whose state lives in a torch-owned device buffer."""
+
+    def __init__(self, params: mc_params, com=None, quat=None, types=None, stream=None, device="cuda"):
+        import torch
+
+        self.params = params
+        self.M = params.n_molecules
+        nbytes = mc_required_bytes(params)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._stream_handle, self.stream = _stream_handle(stream)
+        h = C.c_void_p()
+        if com is None:
+            args = (None, None, None)
+        else:
+            com = np.ascontiguousarray(com, dtype=np.float64).reshape(-1)
+            quat = np.ascontiguousarray(quat, dtype=np.float64).reshape(-1)
+            types = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
+            args = (_ptr(com, C.c_double), _ptr(quat, C.c_double), _ptr(types, C.c_uint8))
+        _check(lib().mc_init_system(C.byref(params), *args, C.c_void_p(self.buffer.data_ptr()),
+                                    nbytes, self._stream_handle, C.byref(h)))
+        self.h = h
+        self._log = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().mc_destroy(h)
+            self.h = None
+
+    def sweep(self, n=1):
+        _check(lib().mc_sweep(self.h, int(n)))
+
+    def energy(self):
+        e, em, d = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().mc_energy(self.h, C.byref(e), C.byref(em), C.byref(d)))
+        return e.value, em.value, d.value
+
+    def observables(self) -> dict:
+        o = mc_obs()
+        _check(lib().mc_observables(self.h, C.byref(o)))
+        nb = o.gofr_nbins
+        return {
+            "sweep": o.sweep,
+            "attempts": np.array(o.attempts[:], dtype=np.uint64),
+            "accepts": np.array(o.accepts[:], dtype=np.uint64),
+            "exits": o.exits,
+            "pair_terms": o.pair_terms,
+            "pair_tests": o.pair_tests,
+            "e_acc": o.e_acc,
+            "e_resum": o.e_resum,
+            "drift": o.drift,
+            "max_abs_drift": o.max_abs_drift,
+            "resum_sweep": o.resum_sweep,
+            "n_energy_samples": o.n_energy_samples,
+            "n_drift_samples": o.n_drift_samples,
+            "energy_sum": o.energy_sum,
+            "energy_sumsq": o.energy_sumsq,
+            "n_gofr_frames": o.n_gofr_frames,
+            "gofr_dr": o.gofr_dr,
+            "gofr_rmax": o.gofr_rmax,
+            "gofr_all": np.array(o.gofr_all[:nb], dtype=np.uint64),
+            "gofr_inter": np.array(o.gofr_inter[:nb], dtype=np.uint64),
+            "c2_sweep": np.array(o.c2_sweep[: o.n_c2], dtype=np.uint64),
+            "c2": np.array(o.c2[: o.n_c2]),
+        }
+
+    def samples(self, cap=None):
+        cap = cap or self.params.max_samples
+        e = np.zeros(cap)
+        d = np.zeros(cap)
+        ne, nd = C.c_size_t(), C.c_size_t()
+        _check(lib().mc_samples(self.h, _ptr(e, C.c_double), _ptr(d, C.c_double), cap,
+                                C.byref(ne), C.byref(nd)))
+        return e[: ne.value], d[: nd.value]
+
+    def reset_observables(self):
+        _check(lib().mc_reset_observables(self.h))
+
+    def get_state(self):
+        M = self.M
+        com, quat = np.zeros(3 * M), np.zeros(4 * M)
+        types = np.zeros(3 * M, dtype=np.uint8)
+        sweep, e = C.c_uint64(), C.c_double()
+        _check(lib().mc_get_state(self.h, _ptr(com, C.c_double), _ptr(quat, C.c_double),
+                                  _ptr(types, C.c_uint8), C.byref(sweep), C.byref(e)))
+        return {"com": com.reshape(M, 3), "quat": quat.reshape(M, 4), "types": types.reshape(M, 3),
+                "sweep": sweep.value, "e_acc": e.value}
+
+    def set_state(self, com, quat, types, sweep, e_acc=math.nan):
+        com = np.ascontiguousarray(com, dtype=np.float64).reshape(-1)
+        quat = np.ascontiguousarray(quat, dtype=np.float64).reshape(-1)
+        types = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
+        _check(lib().mc_set_state(self.h, _ptr(com, C.c_double), _ptr(quat, C.c_double),
+                                  _ptr(types, C.c_uint8), int(sweep), float(e_acc)))
+
+    def decision_log(self, n_sweeps):
+        """Record the next n_sweeps sweeps; returns a torch buffer of records."""
+        import torch
+
+        if n_sweeps <= 0:
+            _check(lib().mc_decision_log(self.h, None, 0))
+            self._log = None
+            return None
+        cap = n_sweeps * self.M
+        buf = torch.zeros(cap * MOVE_RECORD_DTYPE.itemsize, dtype=torch.uint8, device=self.buffer.device)
+        _check(lib().mc_decision_log(self.h, C.c_void_p(buf.data_ptr()), cap))
+        self._log = buf
+        return buf
+
+    def read_log(self):
+        if self._log is None:
+            return None
+        self.stream.synchronize()
+        return np.frombuffer(self._log.cpu().numpy().tobytes(), dtype=MOVE_RECORD_DTYPE).copy()
+
+
+class Batch:
+    """Several systems advanced by one persistent launch per call."""
+
+    def __init__(self, max_slots, precision=MC_FP32_DE, stream=None):
+        self._stream_handle, self.stream = _stream_handle(stream)
+        h = C.c_void_p()
+        _check(lib().mc_batch_create(int(max_slots), int(precision), self._stream_handle, C.byref(h)))
+        self.h = h
+        self.max_slots = max_slots
+        self.members = {}
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().mc_batch_destroy(h)
+            self.h = None
+
+    def add(self, system: System, n_sweeps) -> int:
+        slot = C.c_uint32()
+        _check(lib().mc_batch_add(self.h, system.h, int(n_sweeps), C.byref(slot)))
+        self.members[slot.value] = system
+        return slot.value
+
+    def run(self, max_moves_per_slot=0) -> int:
+        n = C.c_uint32()
+        _check(lib().mc_batch_run(self.h, int(max_moves_per_slot), C.byref(n)))
+        return n.value
+
+    def poll(self):
+        cap = self.max_slots
+        slots = np.zeros(cap, dtype=np.uint32)
+        systems = (C.c_void_p * cap)()
+        n = C.c_size_t()
+        _check(lib().mc_batch_poll(self.h, _ptr(slots, C.c_uint32), systems, cap, C.byref(n)))
+        done = []
+        for i in range(n.value):
+            done.append((int(slots[i]), self.members.pop(int(slots[i]))))
+        return done
+
+    def cancel(self, slot):
+        _check(lib().mc_batch_cancel(self.h, int(slot)))
+        return self.members.pop(int(slot))

@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/flipmc.h declares, and rejects bad parameters with a
+status code and a message before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2506_21290_amd import flipmc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "flipmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "mc_init_system" in names and "mc_sweep" in names
+    assert "mc_energy" in names and "mc_observables" in names
+    L = C.CDLL(flipmc.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(flipmc.EXPORTED)
+
+
+def test_params_default_matches_the_paper():
+    p = flipmc.mc_params_default()
+    assert list(p.sigma) == [0.9, 1.0, 1.1]  # Sec. II.A
+    assert p.density == 1.2 and p.p_flip == 0.2
+    assert p.p_translate == 0.4 and p.max_displacement == 0.1 and p.max_rotation == 0.2
+
+
+def test_geometry_choices():
+    # (k - 1) w must reach W = 2^(1/6) 1.1 + 2 b*/sqrt(3) ~ 2.3443
+    for M in [64, 216, 512, 1000, 1728, 8000, 27000]:
+        p = flipmc.mc_params_default(n_molecules=M)
+        L, k, nc = flipmc.mc_geometry(p)
+        assert L == pytest.approx((3 * M / 1.2) ** (1 / 3), rel=1e-14)
+        assert nc % k == 0 and (k - 1) * L / nc >= 2.3442
+    p = flipmc.mc_params_default(n_molecules=1000, colours_per_axis=3, cells_per_side=9)
+    assert flipmc.mc_geometry(p)[1:] == (3, 9)
+
+
+@pytest.mark.parametrize(
+    "kw,code",
+    [
+        (dict(n_molecules=0), flipmc.MC_EINVAL),
+        (dict(temperature=-1.0), flipmc.MC_EINVAL),
+        (dict(precision=7), flipmc.MC_EINVAL),
+        (dict(p_flip=0.8, p_translate=0.4), flipmc.MC_EINVAL),
+        (dict(n_molecules=1000, colours_per_axis=2, cells_per_side=6), flipmc.MC_EGEOM),
+        (dict(n_molecules=1000, colours_per_axis=3, cells_per_side=8), flipmc.MC_EGEOM),
+        (dict(n_molecules=1000, colours_per_axis=4, cells_per_side=8), flipmc.MC_EGEOM),
+        (dict(n_molecules=8, density=1.2), flipmc.MC_EGEOM),
+    ],
+)
+def test_invalid_parameters(kw, code):
+    p = flipmc.mc_params_default(**kw)
+    with pytest.raises(flipmc.McError) as e:
+        flipmc.mc_required_bytes(p)
+    assert e.value.code == code
+    assert len(flipmc.lib().mc_last_error()) > 0
+
+
+def test_init_rejects_bad_buffers_without_a_device():
+    L = flipmc.lib()
+    p = flipmc.mc_params_default(n_molecules=64)
+    h = C.c_void_p()
+    assert L.mc_init_system(C.byref(p), None, None, None, None, 0, None, C.byref(h)) == flipmc.MC_EINVAL
+    nbytes = flipmc.mc_required_bytes(p)
+    fake = C.c_void_p(0x100000)
+    rc = L.mc_init_system(C.byref(p), None, None, None, fake, nbytes - 1, None, C.byref(h))
+    assert rc == flipmc.MC_ENOMEM
+    p2 = flipmc.mc_params_default(n_molecules=100)  # not a cube: no lattice start
+    assert L.mc_init_system(C.byref(p2), None, None, None, fake, 1 << 30, None, C.byref(h)) == flipmc.MC_EINVAL
+    assert b"n^3" in L.mc_last_error()
+
+
+def test_required_bytes_grows_with_state():
+    a = flipmc.mc_required_bytes(flipmc.mc_params_default(n_molecules=1000))
+    b = flipmc.mc_required_bytes(flipmc.mc_params_default(n_molecules=1000, flags=flipmc.MC_FLAG_HBM_STATE))
+    c = flipmc.mc_required_bytes(flipmc.mc_params_default(n_molecules=8000))
+    assert a < b < c
+    assert a < 1 << 20
