@@ -1,0 +1,349 @@
+#!/usr/bin/env python3
+"""Benchmark of the flip Monte Carlo hot path on one MI355X.
+
+Default workload: 1000 rigid A/B/C triangles at T = 0.75 (the lowest
+equilibrated temperature of the paper), density 1.2, seeded lattice start,
+checkerboard sweeps with FP32 energy differences and an FP64 re-sum every 100
+sweeps; a step is 100 sweeps (one re-sum window) including the cell builds,
+the re-sum, E/M samples, the g(r) frame and C_2 samples.  The same run in
+plain FP64 is timed beside it.  Prints one JSON line.
+
+Other workloads (--workload): c2 (8000 molecules), c3 (256 uneven replicas in
+one persistent launch) and c4 (the serving loop).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import numpy as np
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "attempted molecule-moves/s on 1 MI355X (+ p50/p99 request latency) vs plain FP64"
+FLOP_PER_PAIR_TERM = 25  # 3 sub, 3 mul + 2 fma for r^2, cut-off test, rcp, 3 mul, fma, mul, add, ...
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+SWEEPS_PER_STEP = 100
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "engine.h"):
+        with open(os.path.join(ROOT, "paper_2506_21290_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on another version of the kernel."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=3, nc=9, seed=1):
+    p = flipmc.mc_params_default(
+        n_molecules=M, temperature=T, precision=precision, colours_per_axis=k, cells_per_side=nc,
+        seed=seed, resum_interval=100, obs_interval=10, gofr_interval=100, obs_start=0,
+        max_samples=8192)
+    s = flipmc.System(p)
+    for _ in range(warmup):
+        s.sweep(SWEEPS_PER_STEP)
+    torch.cuda.synchronize()
+    o0 = s.observables()
+    s.timing_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        s.sweep(SWEEPS_PER_STEP)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    tm = s.timing_read()
+    o1 = s.observables()
+    e, em, drift = s.energy()
+    moves = steps * SWEEPS_PER_STEP * M
+    att = [int(o1["attempts"][i] - o0["attempts"][i]) for i in range(3)]
+    acc = [int(o1["accepts"][i] - o0["accepts"][i]) for i in range(3)]
+    return {
+        "ms": ms,
+        "moves": moves,
+        "moves_per_s": moves / (ms / 1e3),
+        "sweep_kernel_ms": tm["sweep_ms"],
+        "sweep_launches": tm["sweep_launches"],
+        "event_kernel_ms": tm["event_ms"],
+        "pair_terms": int(o1["pair_terms"] - o0["pair_terms"]),
+        "pair_tests": int(o1["pair_tests"] - o0["pair_tests"]),
+        "exits": int(o1["exits"] - o0["exits"]),
+        "accept_rate": {kind: (acc[i] / att[i] if att[i] else None)
+                        for i, kind in enumerate(["translate", "rotate", "flip"])},
+        "energy_per_molecule": em,
+        "max_abs_drift_per_window": o1["max_abs_drift"],
+        "last_drift": drift,
+        "sweeps_done": int(o1["sweep"]),
+    }
+
+
+def cpu_baseline(seconds, M=1000, T=0.75, k=3, nc=9):
+    from oracle import oracle
+
+    oracle.build()
+    s = oracle.System(oracle.Params(n_molecules=M, temperature=T, colours_per_axis=k,
+                                    cells_per_side=nc, seed=1))
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        s.sweep_checkerboard(1)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
+    return {
+        "value": n * M / dt,
+        "unit": "molecule-moves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n} checkerboard sweeps ({n * M} attempted moves) of the same 1000-molecule "
+                  f"system from its lattice start, serial FP64 oracle, {dt:.1f} s",
+    }
+
+
+def bench_c1(args, flipmc, torch):
+    f32 = run_system(flipmc, torch, flipmc.MC_FP32_DE, args.steps, args.warmup)
+    f64 = run_system(flipmc, torch, flipmc.MC_FP64, args.steps, args.warmup)
+    launches = max(1, f32["sweep_launches"])
+    flops = f32["pair_terms"] * FLOP_PER_PAIR_TERM
+    kern_s = f32["sweep_kernel_ms"] / 1e3
+    achieved = flops / kern_s / 1e12
+    traffic = measured_traffic("k_sweeps_c1")
+    out = {
+        "metric": METRIC,
+        "value": f32["moves_per_s"],
+        "unit": "molecule-moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "1000 rigid A/B/C triangles (sites 0.9/1.0/1.1, WCA), density 1.2, T=0.75, "
+                        "seeded lattice start, checkerboard k=3 n_c=9, FP32 dE + FP64 re-sum every "
+                        "100 sweeps; step = 100 sweeps",
+            "molecules": 1000,
+            "sweeps_per_step": SWEEPS_PER_STEP,
+            "temperature": 0.75,
+            "precision": "FP32 dE, FP64 state/accept/re-sum",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_TFLOPS["f32"],
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS["f32"],
+            "traffic": traffic,
+            "kernel": "k_sweeps<float, resident>",
+            "avg_launch_ms": f32["sweep_kernel_ms"] / launches,
+            "flops_per_launch": flops / launches,
+            "flop_per_pair_term": FLOP_PER_PAIR_TERM,
+        },
+        "fp64": {
+            "value": f64["moves_per_s"],
+            "ms_per_step": f64["ms"] / args.steps,
+            "accept_rate": f64["accept_rate"],
+            "max_abs_drift_per_window": f64["max_abs_drift_per_window"],
+            "energy_per_molecule": f64["energy_per_molecule"],
+        },
+        "fp32_over_fp64": f32["moves_per_s"] / f64["moves_per_s"],
+        "pair_interactions_per_s": f32["pair_terms"] / (f32["ms"] / 1e3),
+        "candidate_pair_tests_per_s": f32["pair_tests"] / (f32["ms"] / 1e3),
+        "accept_rate": f32["accept_rate"],
+        "exits_per_move": f32["exits"] / f32["moves"],
+        "energy_per_molecule": f32["energy_per_molecule"],
+        "max_abs_drift_per_window": f32["max_abs_drift_per_window"],
+        "sweeps_done": f32["sweeps_done"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
+    return out
+
+
+def bench_c2(args, flipmc, torch):
+    """8000 molecules at T = 1.1 (mid-range), FP32 dE + FP64 re-sum every 100
+    sweeps, 100 warm-up + 1000 timed sweeps; decomposition from the engine's
+    table."""
+    M, T = 8000, 1.1
+    p = flipmc.mc_params_default(n_molecules=M, temperature=T, precision=flipmc.MC_FP32_DE,
+                                 seed=1, resum_interval=100, obs_interval=10, gofr_interval=0)
+    L, k, nc = flipmc.mc_geometry(p)
+    resident, lds = flipmc.mc_placement(p)
+    s = flipmc.System(p)
+    s.sweep(100)
+    torch.cuda.synchronize()
+    o0 = s.observables()
+    s.timing_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    n_sweeps = 1000
+    s.sweep(n_sweeps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    tm = s.timing_read()
+    o1 = s.observables()
+    terms = int(o1["pair_terms"] - o0["pair_terms"])
+    kern_s = tm["sweep_ms"] / 1e3
+    achieved = terms * FLOP_PER_PAIR_TERM / kern_s / 1e12
+    return {
+        "workload": "c2: 8000 molecules, T=1.1, FP32 dE + FP64 re-sum every 100 sweeps, 1000 timed sweeps",
+        "k": k, "n_c": nc, "resident_in_lds": resident,
+        "moves_per_s": M * n_sweeps / (ms / 1e3),
+        "pair_interactions_per_s": terms / (ms / 1e3),
+        "candidate_pair_tests_per_s": int(o1["pair_tests"] - o0["pair_tests"]) / (ms / 1e3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
+                     "traffic": measured_traffic("k_sweeps_c2")},
+        "ms": ms,
+    }
+
+
+def bench_c3(args, flipmc, torch):
+    """256 independent replicas, M in {216, 512, 1000, 1728}, T over the
+    paper's range, FP32 dE, 1000 sweeps each, all advanced by one batch."""
+    from paper_2506_21290_amd import workloads
+
+    jobs = workloads.replica_set(256, sweeps=1000, seed=1)
+    b = flipmc.Batch(256, flipmc.MC_FP32_DE)
+    systems = []
+    for j in jobs:
+        p = flipmc.mc_params_default(n_molecules=j.n_molecules, temperature=j.temperature,
+                                     precision=flipmc.MC_FP32_DE, seed=j.seed,
+                                     resum_interval=100, obs_interval=10, gofr_interval=0)
+        s = flipmc.System(p, stream=b.stream)
+        b.add(s, j.sweeps)
+        systems.append(s)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    done = 0
+    launches = 0
+    while done < len(jobs):
+        launches += b.run(0) > 0
+        done += len(b.poll())
+    stop.record(b.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    moves = sum(j.n_molecules * j.sweeps for j in jobs)
+    # the same kind of replica alone, plain FP64: a stratified sample of 8
+    sample = [j for size in workloads.REPLICA_SIZES for j in jobs if j.n_molecules == size][:0]
+    by_size = {}
+    for j in jobs:
+        by_size.setdefault(j.n_molecules, []).append(j)
+    sample = [by_size[m][i] for m in sorted(by_size) for i in range(min(2, len(by_size[m])))]
+    t_seq = 0.0
+    m_seq = 0
+    for j in sample:
+        p = flipmc.mc_params_default(n_molecules=j.n_molecules, temperature=j.temperature,
+                                     precision=flipmc.MC_FP64, seed=j.seed, resum_interval=100,
+                                     obs_interval=10, gofr_interval=0)
+        s = flipmc.System(p)
+        torch.cuda.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        s.sweep(j.sweeps)
+        z.record()
+        torch.cuda.synchronize()
+        t_seq += a.elapsed_time(z) / 1e3
+        m_seq += j.n_molecules * j.sweeps
+    return {
+        "workload": "c3: 256 replicas, M in {216,512,1000,1728}, T in [0.75,3], FP32 dE, 1000 sweeps each",
+        "moves_per_s": moves / (ms / 1e3),
+        "ms": ms,
+        "moves": moves,
+        "launches": launches,
+        "fp64_one_by_one_moves_per_s": m_seq / t_seq,
+        "fp64_sample": f"{len(sample)} replicas (2 per size) run alone in FP64",
+    }
+
+
+def bench_c4(args, flipmc, torch):
+    """Poisson stream of sampling jobs served with continuous batching."""
+    from paper_2506_21290_amd import serve, workloads
+
+    jobs = workloads.serving_stream(n_jobs=args.jobs, rate=200.0, seed=1, m_max=args.m_max,
+                                    s_max=args.s_max)
+    srv = serve.Server(memory_budget=args.budget, precision=flipmc.MC_FP32_DE,
+                       quantum_moves=args.quantum)
+    t0 = time.perf_counter()
+    res = srv.serve(jobs, time_limit=args.time_limit)
+    wall = time.perf_counter() - t0
+    lat = np.array([r.latency for r in res])
+    moves = sum(r.moves for r in res)
+    offered = sum(j.n_molecules * j.sweeps for j in jobs) / (jobs[-1].arrival - jobs[0].arrival)
+    return {
+        "workload": f"c4: {len(jobs)} Poisson jobs at 200/s, M=n^3 log-uniform in [125,{args.m_max}], "
+                    f"T in [0.75,3], sweeps log-uniform in [100,{args.s_max}], FP32 dE",
+        "completed": len(res),
+        "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+        "moves_per_s": moves / wall,
+        "offered_moves_per_s": offered,
+        "wall_s": wall,
+        "peak_concurrent_jobs": srv.peak_active,
+        "peak_bytes": srv.peak_bytes,
+        "budget_bytes": args.budget,
+        "launches": srv.launches,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--jobs", type=int, default=2000)
+    ap.add_argument("--m-max", type=int, default=27000)
+    ap.add_argument("--s-max", type=int, default=10000)
+    ap.add_argument("--budget", type=int, default=4 << 30)
+    ap.add_argument("--quantum", type=int, default=400_000)
+    ap.add_argument("--time-limit", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": f"--gpus {args.gpus}: this engine runs on one GPU; "
+                                   "multi-GPU runs are not part of this build"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2506_21290_amd import flipmc
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    if args.workload == "c1":
+        out = bench_c1(args, flipmc, torch)
+    else:
+        out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[args.workload](args, flipmc, torch)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,7 +77,9 @@ typedef struct {
     uint64_t seed;             /* Philox4x32-10 key                                  */
     uint32_t colours_per_axis; /* k of the checkerboard (>= 2); 0 = choose           */
     uint32_t cells_per_side;   /* n_c, multiple of k, (k-1) L / n_c >= W; 0 = choose  */
-    uint32_t resum_interval;   /* sweeps between FP64 re-sums of E (0 = never)       */
+    uint32_t resum_interval;   /* sweeps between FP64 re-sums of E (0 = never); each
+                                  records the window's drift e_acc - E and then resets
+                                  e_acc to the re-summed E                           */
     uint32_t obs_interval;     /* sweeps between E/M samples (0 = never)             */
     uint32_t gofr_interval;    /* sweeps between g(r) frames (0 = never)             */
     uint32_t obs_start;        /* samples are taken from this sweep on (relative to
@@ -115,7 +117,8 @@ typedef struct {
     uint64_t pair_tests;         /* candidate site-pair distance tests             */
     double   e_acc;              /* E_0 + sum of accepted dE (FP64)                */
     double   e_resum;            /* last FP64 re-sum                               */
-    double   drift;              /* e_acc - e_resum at the last re-sum             */
+    double   drift;              /* e_acc - e_resum at the last re-sum: the error
+                                    accumulated since the previous re-sum          */
     double   max_abs_drift;      /* over all re-sums except the first window       */
     uint64_t resum_sweep;        /* sweep of the last re-sum                        */
     uint32_t n_energy_samples;
@@ -143,6 +146,11 @@ void mc_params_default(mc_params* p);
  * use (k, n_c) for these parameters (after "choose" defaults). */
 int mc_geometry(const mc_params* p, double* box, uint32_t* colours_per_axis,
                 uint32_t* cells_per_side);
+
+/* Where a system with these parameters keeps its working arrays: *resident = 1
+ * when they fit in one workgroup's LDS (then *lds_bytes of dynamic LDS per
+ * launch), 0 when they stay in HBM.  Either output may be NULL. */
+int mc_placement(const mc_params* p, int* resident, size_t* lds_bytes);
 
 /* Bytes of device memory mc_init_system needs for these parameters. */
 int mc_required_bytes(const mc_params* p, size_t* bytes);
@@ -190,6 +198,14 @@ int mc_set_state(mc_system* s, const double* com, const double* quat, const uint
  * Sweeps beyond capacity / M are not recorded.  records = NULL disables. */
 int mc_decision_log(mc_system* s, void* device_records, size_t capacity);
 
+/* Time every launch of the sweep kernel and of the event kernel of this system
+ * with HIP events recorded on its stream (enable = 0 stops and clears). */
+int mc_timing_enable(mc_system* s, int enable);
+
+/* Sum of the recorded launch durations (ms) and launch counts.  Synchronises. */
+int mc_timing_read(mc_system* s, double* sweep_ms, uint64_t* sweep_launches, double* event_ms,
+                   uint64_t* event_launches);
+
 void mc_destroy(mc_system* s);
 const char* mc_last_error(void);
 
@@ -200,7 +216,10 @@ const char* mc_last_error(void);
 int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc_batch** out);
 
 /* Put an initialised system into a free slot with n_sweeps of work; the
- * system must use the batch's precision.  MC_EBUSY when no slot is free. */
+ * system must use the batch's precision.  MC_EBUSY when no slot is free.
+ * While in a batch the system is advanced on the batch's stream: mc_sweep,
+ * mc_energy, mc_set_state, mc_reset_observables and mc_decision_log return
+ * MC_EBUSY, and the reading calls first synchronise the batch's stream. */
 int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
 
 /* Enqueue one launch in which each occupied slot runs

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "engine.h"
@@ -199,6 +200,10 @@ struct mc_system {
     uint64_t sweep;   // host mirror of the device sweep counter
     uint64_t origin;  // host mirror of the observable origin
     mc_batch* batch;
+    // launch timing (mc_timing_enable)
+    bool timing;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_event;
 };
 
 struct mc_batch {
@@ -216,6 +221,14 @@ struct mc_batch {
 
 namespace {
 
+// A system inside a batch is advanced on the batch's stream: wait for it
+// before reading the system's state on its own stream.
+int sync_owner(mc_system* s)
+{
+    if (s->batch) HIPCHK(hipStreamSynchronize(s->batch->stream));
+    return MC_OK;
+}
+
 int upload_desc(mc_system* s)
 {
     HIPCHK(hipMemcpyAsync(s->dev, &s->host, sizeof(SysDev), hipMemcpyHostToDevice, s->stream));
@@ -223,12 +236,43 @@ int upload_desc(mc_system* s)
     return MC_OK;
 }
 
+hipEvent_t take_event(mc_system* s)
+{
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Record a start event when timing is on (nullptr otherwise).
+hipEvent_t timing_start(mc_system* s)
+{
+    if (!s->timing) return nullptr;
+    hipEvent_t a = take_event(s);
+    if (a && hipEventRecord(a, s->stream) != hipSuccess) return nullptr;
+    return a;
+}
+
+void timing_stop(mc_system* s, hipEvent_t a, bool sweep_kernel)
+{
+    if (!a) return;
+    hipEvent_t b = take_event(s);
+    if (!b || hipEventRecord(b, s->stream) != hipSuccess) return;
+    (sweep_kernel ? s->ev_sweep : s->ev_event).emplace_back(a, b);
+}
+
 int launch_events_one(mc_system* s, uint32_t flags)
 {
     Slot one{};
     one.sys = s->dev;
     one.flags = flags;
+    hipEvent_t t0 = timing_start(s);
     HIPCHK(launch_events(nullptr, one, 1, s->stream));
+    timing_stop(s, t0, false);
     return MC_OK;
 }
 
@@ -287,8 +331,10 @@ int advance(mc_system* s, uint64_t n)
         const uint64_t chunk = std::min<uint64_t>(n, next_event(s) - s->sweep);
         one.n_sweeps = chunk;
         one.flags = 0;
+        hipEvent_t t0 = timing_start(s);
         HIPCHK(launch_sweeps(s->p.precision == MC_FP64, s->g.resident, nullptr, one, 1, s->g.lds,
                              s->stream));
+        timing_stop(s, t0, true);
         s->sweep += chunk;
         n -= chunk;
         const uint32_t f = events_at(s, s->sweep);
@@ -302,6 +348,7 @@ int advance(mc_system* s, uint64_t n)
 
 int read_stats(mc_system* s, Stats* st)
 {
+    if (int rc = sync_owner(s)) return rc;
     HIPCHK(hipMemcpyAsync(st, s->host.stats, sizeof(Stats), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return MC_OK;
@@ -382,6 +429,16 @@ int mc_geometry(const mc_params* p, double* box, uint32_t* k, uint32_t* nc)
     return MC_OK;
 }
 
+int mc_placement(const mc_params* p, int* resident, size_t* lds_bytes)
+{
+    Geometry g;
+    const int rc = geometry(p, &g);
+    if (rc) return rc;
+    if (resident) *resident = g.resident ? 1 : 0;
+    if (lds_bytes) *lds_bytes = g.lds;
+    return MC_OK;
+}
+
 int mc_required_bytes(const mc_params* p, size_t* bytes)
 {
     Geometry g;
@@ -423,6 +480,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
     s->stream = (hipStream_t)hip_stream;
     s->sweep = 0;
     s->batch = nullptr;
+    s->timing = false;
     SysDev& D = s->host;
     std::memset(&D, 0, sizeof D);
     uint8_t* b = s->buf;
@@ -514,6 +572,7 @@ int mc_sweep(mc_system* s, uint64_t n)
 int mc_energy(mc_system* s, double* e_total, double* e_per_molecule, double* drift)
 {
     if (!s) return fail(MC_EINVAL, "null system");
+    if (s->batch) return fail(MC_EBUSY, "system is in a batch");
     int rc = launch_events_one(s, kFlagResumReport);
     if (rc) return rc;
     Stats st;
@@ -597,6 +656,7 @@ int mc_get_state(mc_system* s, double* com, double* quat, uint8_t* types, uint64
     std::vector<double> c(3 * M), q(4 * M);
     std::vector<uint32_t> t(M);
     Stats st;
+    if (int rc0 = sync_owner(s)) return rc0;
     HIPCHK(hipMemcpyAsync(c.data(), s->host.com, c.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(q.data(), s->host.quat, q.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(t.data(), s->host.types, t.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
@@ -643,6 +703,7 @@ int mc_set_state(mc_system* s, const double* com, const double* quat, const uint
 int mc_decision_log(mc_system* s, void* device_records, size_t capacity)
 {
     if (!s) return fail(MC_EINVAL, "null system");
+    if (s->batch) return fail(MC_EBUSY, "system is in a batch");
     Stats st;
     int rc = read_stats(s, &st);
     if (rc) return rc;
@@ -652,9 +713,45 @@ int mc_decision_log(mc_system* s, void* device_records, size_t capacity)
     return upload_desc(s);
 }
 
+int mc_timing_enable(mc_system* s, int enable)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (auto& pr : s->ev_sweep) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
+    for (auto& pr : s->ev_event) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
+    s->ev_sweep.clear();
+    s->ev_event.clear();
+    s->timing = enable != 0;
+    return MC_OK;
+}
+
+int mc_timing_read(mc_system* s, double* sweep_ms, uint64_t* sweep_launches, double* event_ms,
+                   uint64_t* event_launches)
+{
+    if (!s) return fail(MC_EINVAL, "null system");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    double t[2] = {0.0, 0.0};
+    const std::vector<std::pair<hipEvent_t, hipEvent_t>>* v[2] = {&s->ev_sweep, &s->ev_event};
+    for (int i = 0; i < 2; ++i)
+        for (auto& pr : *v[i]) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            t[i] += ms;
+        }
+    if (sweep_ms) *sweep_ms = t[0];
+    if (sweep_launches) *sweep_launches = s->ev_sweep.size();
+    if (event_ms) *event_ms = t[1];
+    if (event_launches) *event_launches = s->ev_event.size();
+    return MC_OK;
+}
+
 void mc_destroy(mc_system* s)
 {
     if (!s) return;
+    if (!s->ev_sweep.empty() || !s->ev_event.empty()) (void)hipStreamSynchronize(s->stream);
+    for (auto& pr : s->ev_sweep) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
+    for (auto& pr : s->ev_event) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->batch) {
         mc_batch* b = s->batch;
         for (size_t i = 0; i < b->sys.size(); ++i)
@@ -698,7 +795,6 @@ int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot)
     if (!b || !s) return fail(MC_EINVAL, "null argument");
     if (s->batch) return fail(MC_EINVAL, "system is already in a batch");
     if (s->p.precision != b->precision) return fail(MC_EINVAL, "precision differs from the batch's");
-    if (s->stream != b->stream) return fail(MC_EINVAL, "system must use the batch's stream");
     for (uint32_t i = 0; i < b->max_slots; ++i) {
         if (!b->sys[i]) {
             b->sys[i] = s;

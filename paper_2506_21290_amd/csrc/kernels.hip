@@ -499,7 +499,10 @@ __device__ void gofr_frame(const Ctx<Real, kRes>& C)
                 const double bx = dx + oj[3 * t], by = dy + oj[3 * t + 1], bz = dz + oj[3 * t + 2];
 #pragma unroll
                 for (int s = 0; s < 3; ++s) {
-                    const double rx = bx - om[3 * s], ry = by - om[3 * s + 1], rz = bz - om[3 * s + 2];
+                    // each site pair takes its own nearest image: r reaches L / 2
+                    const double rx = min_image(bx - om[3 * s], C.L, C.invL);
+                    const double ry = min_image(by - om[3 * s + 1], C.L, C.invL);
+                    const double rz = min_image(bz - om[3 * s + 2], C.L, C.invL);
                     const int b = (int)floor(sqrt(rx * rx + ry * ry + rz * rz) / dr);
                     if (b >= 0 && b < (int)nb) {
                         atomicAdd(&ball[b], 2u);
@@ -987,7 +990,9 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
         const double e = resum_energy(C);
         if (tid == 0) {
             const double acc = (f & kFlagResumSet) ? e : e_acc;
-            if (f & kFlagResumSet) st->e_acc = e;
+            // a set or a scheduled re-sum re-anchors the accumulated energy, so
+            // each drift sample is the error of one window
+            if (f & (kFlagResumSet | kFlagResumPeriodic)) st->e_acc = e;
             const double drift = acc - e;
             st->e_resum = e;
             st->drift = drift;

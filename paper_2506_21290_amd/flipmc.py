@@ -25,9 +25,10 @@ MC_GOFR_MAX_BINS = 256
 MC_C2_MAX = 32
 
 EXPORTED = [
-    "mc_params_default", "mc_geometry", "mc_required_bytes", "mc_init_system", "mc_sweep",
+    "mc_params_default", "mc_geometry", "mc_placement", "mc_required_bytes", "mc_init_system", "mc_sweep",
     "mc_energy", "mc_observables", "mc_samples", "mc_reset_observables", "mc_get_state",
-    "mc_set_state", "mc_decision_log", "mc_destroy", "mc_last_error", "mc_batch_create",
+    "mc_set_state", "mc_decision_log", "mc_timing_enable", "mc_timing_read", "mc_destroy",
+    "mc_last_error", "mc_batch_create",
     "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
 ]
 
@@ -120,6 +121,7 @@ def lib():
         L.mc_params_default.argtypes = [pp]
         L.mc_params_default.restype = None
         L.mc_geometry.argtypes = [pp, dp, u32p, u32p]
+        L.mc_placement.argtypes = [pp, C.POINTER(C.c_int), szp]
         L.mc_required_bytes.argtypes = [pp, szp]
         L.mc_init_system.argtypes = [pp, dp, dp, u8p, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.mc_sweep.argtypes = [vp, C.c_uint64]
@@ -130,6 +132,8 @@ def lib():
         L.mc_get_state.argtypes = [vp, dp, dp, u8p, u64p, dp]
         L.mc_set_state.argtypes = [vp, dp, dp, u8p, C.c_uint64, C.c_double]
         L.mc_decision_log.argtypes = [vp, vp, C.c_size_t]
+        L.mc_timing_enable.argtypes = [vp, C.c_int]
+        L.mc_timing_read.argtypes = [vp, dp, u64p, dp, u64p]
         L.mc_destroy.argtypes = [vp]
         L.mc_destroy.restype = None
         L.mc_last_error.restype = C.c_char_p
@@ -170,6 +174,13 @@ def mc_geometry(p: mc_params):
     box, k, nc = C.c_double(), C.c_uint32(), C.c_uint32()
     _check(lib().mc_geometry(C.byref(p), C.byref(box), C.byref(k), C.byref(nc)))
     return box.value, k.value, nc.value
+
+
+def mc_placement(p: mc_params):
+    """(resident in LDS?, dynamic LDS bytes per launch)"""
+    r, n = C.c_int(), C.c_size_t()
+    _check(lib().mc_placement(C.byref(p), C.byref(r), C.byref(n)))
+    return bool(r.value), n.value
 
 
 def mc_required_bytes(p: mc_params) -> int:
@@ -295,6 +306,16 @@ class System:
         _check(lib().mc_decision_log(self.h, C.c_void_p(buf.data_ptr()), cap))
         self._log = buf
         return buf
+
+    def timing_enable(self, on=True):
+        _check(lib().mc_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self):
+        a, b = C.c_double(), C.c_double()
+        na, nb = C.c_uint64(), C.c_uint64()
+        _check(lib().mc_timing_read(self.h, C.byref(a), C.byref(na), C.byref(b), C.byref(nb)))
+        return {"sweep_ms": a.value, "sweep_launches": na.value, "event_ms": b.value,
+                "event_launches": nb.value}
 
     def read_log(self):
         if self._log is None:
