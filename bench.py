@@ -51,11 +51,12 @@ def measured_traffic(name):
     return t.get("bytes_per_launch")
 
 
-def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=3, nc=9, seed=1):
+def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=0, nc=0, seed=1):
     p = flipmc.mc_params_default(
         n_molecules=M, temperature=T, precision=precision, colours_per_axis=k, cells_per_side=nc,
         seed=seed, resum_interval=100, obs_interval=10, gofr_interval=100, obs_start=0,
         max_samples=8192)
+    _, k, nc = flipmc.mc_geometry(p)
     s = flipmc.System(p)
     for _ in range(warmup):
         s.sweep(SWEEPS_PER_STEP)
@@ -93,10 +94,12 @@ def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=3, nc=
         "max_abs_drift_per_window": o1["max_abs_drift"],
         "last_drift": drift,
         "sweeps_done": int(o1["sweep"]),
+        "k": k,
+        "n_c": nc,
     }
 
 
-def cpu_baseline(seconds, M=1000, T=0.75, k=3, nc=9):
+def cpu_baseline(seconds, M=1000, T=0.75, k=2, nc=4):
     from oracle import oracle
 
     oracle.build()
@@ -128,6 +131,7 @@ def bench_c1(args, flipmc, torch):
     kern_s = f32["sweep_kernel_ms"] / 1e3
     achieved = flops / kern_s / 1e12
     traffic = measured_traffic("k_sweeps_c1")
+    cpu_k, cpu_nc = f32["k"], f32["n_c"]
     out = {
         "metric": METRIC,
         "value": f32["moves_per_s"],
@@ -143,8 +147,8 @@ def bench_c1(args, flipmc, torch):
         "data": "synthetic",
         "config": {
             "workload": "1000 rigid A/B/C triangles (sites 0.9/1.0/1.1, WCA), density 1.2, T=0.75, "
-                        "seeded lattice start, checkerboard k=3 n_c=9, FP32 dE + FP64 re-sum every "
-                        "100 sweeps; step = 100 sweeps",
+                        f"seeded lattice start, checkerboard k={f32['k']} n_c={f32['n_c']}, FP32 dE + "
+                        "FP64 re-sum every 100 sweeps; step = 100 sweeps",
             "molecules": 1000,
             "sweeps_per_step": SWEEPS_PER_STEP,
             "temperature": 0.75,
@@ -179,7 +183,7 @@ def bench_c1(args, flipmc, torch):
         "sweeps_done": f32["sweeps_done"],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, k=cpu_k, nc=cpu_nc)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
     return out
 

@@ -79,15 +79,24 @@ struct Geometry {
     size_t lds;
 };
 
-double cost_estimate(uint32_t M, uint32_t k, uint32_t nc)
+// Critical path of one sweep of the resident kernel in cycles (a model fitted
+// to measured per-cell and per-trial costs): k^3 colour phases; in each, the
+// busiest wave builds the neighbour list of each of its cells and runs the
+// cell's trials one after another.
+double cost_estimate(uint32_t M, double L, double reach, uint32_t k, uint32_t nc)
 {
-    // phases x trials of the most loaded wave x candidate molecules per trial
-    const double per_cell = (double)M / ((double)nc * nc * nc);
+    const double ncell = (double)nc * nc * nc;
+    const double per_cell = (double)M / ncell;
+    const double w = L / nc;
     const double na3 = std::pow((double)(nc / k), 3.0);
-    const double waves = std::ceil(na3 / kWaves);
+    const double cells_per_wave = std::ceil(na3 / kWaves);
     const double span = std::min((double)nc, 2.0 * (k - 1) + 1.0);
     const double stencil = std::min((double)M, span * span * span * per_cell);
-    return (double)k * k * k * waves * std::max(1.0, per_cell) * (stencil + 32.0) + 2000.0 * k * k * k;
+    const double region = 0.75 * std::pow(w + 2.0 * reach, 3.0) * (double)M / (L * L * L);
+    const double listed = std::min(stencil, region);
+    const double t_list = 300.0 + 20.0 * stencil;
+    const double t_trial = 1800.0 + 12.0 * listed;
+    return (double)k * k * k * (cells_per_wave * (t_list + std::max(1.0, per_cell) * t_trial) + 300.0);
 }
 
 int geometry(const mc_params* p, Geometry* g)
@@ -122,7 +131,7 @@ int geometry(const mc_params* p, Geometry* g)
             n -= n % kk;
             while (n >= 2 && std::pow((double)n, 3.0) > 65535.0) n -= kk;
             if (n < 2 || n < kk) continue;
-            const double c = cost_estimate(p->n_molecules, kk, n);
+            const double c = cost_estimate(p->n_molecules, g->L, g->reach, kk, n);
             if (c < best) {
                 best = c;
                 k = kk;
@@ -153,7 +162,7 @@ int geometry(const mc_params* p, Geometry* g)
 
 struct BufLayout {
     size_t sys, stats, com, quat, types, u0, kref, esamp, dsamp, gall, ginter, c2, c2s;
-    size_t gsite, gcell, gcellid, glist, total;
+    size_t props, gsite, gcell, gcellid, glist, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -176,6 +185,7 @@ BufLayout buf_layout(const mc_params* p, const Geometry& g)
     b.ginter = o; o = al(o + kGofrBins * sizeof(uint64_t));
     b.c2 = o;     o = al(o + kC2Max * sizeof(double));
     b.c2s = o;    o = al(o + kC2Max * sizeof(uint64_t));
+    b.props = o;  o = al(o + M * 48);
     if (!g.resident) {
         const bool fp64 = p->precision == MC_FP64;
         b.gsite = o;   o = al(o + 3 * M * site_bytes(fp64));
@@ -531,6 +541,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
     D.gofr_inter = (uint64_t*)(b + lay.ginter);
     D.c2 = (double*)(b + lay.c2);
     D.c2_sweep = (uint64_t*)(b + lay.c2s);
+    D.props = (void*)(b + lay.props);
     if (!g.resident) {
         D.g_site = (void*)(b + lay.gsite);
         D.g_cell = (uint32_t*)(b + lay.gcell);

@@ -18,6 +18,7 @@ constexpr int kMaxSeg = 64;        // stencil row segments per cell (k <= 3: <= 
 constexpr int kGofrBins = 256;
 constexpr int kC2Max = 32;
 constexpr int kMaxMolecules = 65535;  // indices are stored as u16 in cell lists
+constexpr int kCellListCap = 192;     // per-wave list of molecules near the current cell
 
 // Work of the event kernel (Slot::flags).
 enum : uint32_t {
@@ -81,6 +82,7 @@ struct SysDev {
     uint32_t* g_cell;    // [ncell + 1] cell starts
     uint16_t* g_cellid;  // [M]
     uint16_t* g_list;    // [M] molecules sorted by cell, ascending inside a cell
+    void* props;         // [M] proposals of the current sweep (48 bytes each)
     // decision log
     void* log;
     uint64_t log_sweep0;
@@ -116,7 +118,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 
 // LDS carve-up, shared by the host (launch size) and the kernel (pointers).
 struct LdsLayout {
-    size_t cand, seglo, segoff, red, wpart, bins, misc, wstat, tsite;
+    size_t cand, seglo, segoff, clist, wpart, misc, wstat, tsite;
     size_t com, site, cell, cellid, list, total;
 };
 
@@ -128,9 +130,8 @@ __host__ __device__ inline LdsLayout lds_layout(bool fp64, bool resident, uint32
     l.cand = o;   o = align16(o + kWaves * cand_cap(fp64) * cand_bytes(fp64));
     l.seglo = o;  o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
     l.segoff = o; o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
-    l.red = o;    o = align16(o + kWaves * sizeof(double));
+    l.clist = o;  o = align16(o + kWaves * kCellListCap * 8);
     l.wpart = o;  o = align16(o + kWaves * sizeof(double));
-    l.bins = o;   o = align16(o + 2 * kGofrBins * sizeof(uint32_t));
     l.misc = o;   o = align16(o + 16 * sizeof(double));
     l.wstat = o;  o = align16(o + kWaves * 80);
     l.tsite = o;  o = align16(o + kWaves * 6 * site_bytes(fp64));

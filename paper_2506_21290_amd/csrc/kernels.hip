@@ -101,6 +101,30 @@ __device__ __forceinline__ uint32_t wave_sum_u(uint32_t v)
     return v;
 }
 
+// Wave-wide sum with DPP row shifts and row broadcasts (a fixed addition
+// order, so the result does not depend on timing); every lane gets it.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, kRowMask, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, kRowMask, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);  // row_shr:8  -> lane 15 of a row holds the row sum
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 -> lane 31 holds rows 0 + 1
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 -> lane 63 holds all rows
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
 // Exclusive prefix sum over the wave; *total gets the wave total.
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
 {
@@ -266,24 +290,23 @@ struct Ctx {
     double* misc;
 };
 
-// Proposal of one molecule, held by one lane until the wave reaches it.  The
-// new centre of mass (translation) and the new site offsets (rotation) are
-// rebuilt from dl / qn by the wave when the trial runs.
-struct Prop {
-    uint32_t m;
+// Proposal of one molecule for the current sweep.  All proposals of a sweep
+// are drawn at its start by the whole workgroup (they depend only on the
+// molecule's own state, which no earlier trial of the sweep can change) and
+// kept in HBM; a wave loads those of a cell when it reaches the cell.
+struct alignas(16) PropRec {
     uint32_t kind;  // move | exited << 4 | axis << 8
+    uint32_t pad;
     double thr;     // T ln u_acc
-    double dl0, dl1, dl2;       // translation: displacement
-    double qn0, qn1, qn2, qn3;  // rotation: new quaternion
+    double a0, a1, a2, a3;  // translation: displacement a0..a2; rotation: new quaternion
 };
+static_assert(sizeof(PropRec) == 48, "proposal record");
 
-// Draw and build the proposal of molecule m (one lane per molecule).
 template <typename Real, bool kRes>
-__device__ Prop propose(const Ctx<Real, kRes>& C, uint32_t m, uint64_t sweep, double hx,
-                        double hy, double hz, int cx, int cy, int cz)
+__device__ PropRec propose(const Ctx<Real, kRes>& C, uint32_t m, uint64_t sweep, double hx,
+                           double hy, double hz, int cx, int cy, int cz)
 {
-    Prop p;
-    p.m = m;
+    PropRec p;
     const uint32_t slo = (uint32_t)sweep, shi = (uint32_t)(sweep >> 32);
     const U4 b0 = philox10(m, slo, shi, 0u, C.seed_lo, C.seed_hi);
     const U4 b1 = philox10(m, slo, shi, 1u, C.seed_lo, C.seed_hi);
@@ -293,17 +316,17 @@ __device__ Prop propose(const Ctx<Real, kRes>& C, uint32_t m, uint64_t sweep, do
     const uint32_t move = ut < C.p_flip ? 2u : (ut < C.p_ft ? 0u : 1u);
     uint32_t exited = 0, axis = 255;
     const uint32_t M = C.M;
-    p.dl0 = p.dl1 = p.dl2 = 0.0;
-    p.qn0 = p.qn1 = p.qn2 = p.qn3 = 0.0;
+    p.pad = 0;
+    p.a0 = p.a1 = p.a2 = p.a3 = 0.0;
     if (move == 0u) {
         const double c0 = C.com[m], c1 = C.com[M + m], c2 = C.com[2 * M + m];
-        p.dl0 = C.dmax * (2.0 * p0 - 1.0);
-        p.dl1 = C.dmax * (2.0 * p1 - 1.0);
-        p.dl2 = C.dmax * (2.0 * p2 - 1.0);
+        p.a0 = C.dmax * (2.0 * p0 - 1.0);
+        p.a1 = C.dmax * (2.0 * p1 - 1.0);
+        p.a2 = C.dmax * (2.0 * p2 - 1.0);
         const int nc = (int)C.nc;
-        exited = (cell_axis(wrap(c0 + p.dl0, C.L), hx, C.L, C.w, nc) != cx) ||
-                 (cell_axis(wrap(c1 + p.dl1, C.L), hy, C.L, C.w, nc) != cy) ||
-                 (cell_axis(wrap(c2 + p.dl2, C.L), hz, C.L, C.w, nc) != cz);
+        exited = (cell_axis(wrap(c0 + p.a0, C.L), hx, C.L, C.w, nc) != cx) ||
+                 (cell_axis(wrap(c1 + p.a1, C.L), hy, C.L, C.w, nc) != cy) ||
+                 (cell_axis(wrap(c2 + p.a2, C.L), hz, C.L, C.w, nc) != cz);
     } else if (move == 1u) {
         const double z = 2.0 * p0 - 1.0;
         const double phi = kTwoPi * p1;
@@ -319,13 +342,26 @@ __device__ Prop propose(const Ctx<Real, kRes>& C, uint32_t m, uint64_t sweep, do
         const double ry = dw * qy - dx * qz + dy * qw + dz * qx;
         const double rz = dw * qz + dx * qy - dy * qx + dz * qw;
         const double nrm = sqrt(rw * rw + rx * rx + ry * ry + rz * rz);
-        p.qn0 = rw / nrm; p.qn1 = rx / nrm; p.qn2 = ry / nrm; p.qn3 = rz / nrm;
+        p.a0 = rw / nrm; p.a1 = rx / nrm; p.a2 = ry / nrm; p.a3 = rz / nrm;
     } else {
         int a = (int)(3.0 * p0);
         axis = (uint32_t)(a > 2 ? 2 : a);
     }
     p.kind = move | (exited << 4) | (axis << 8);
     return p;
+}
+
+// Proposals of every molecule for this sweep (after the cell build).
+template <typename Real, bool kRes>
+__device__ void propose_all(const Ctx<Real, kRes>& C, PropRec* props, uint64_t sweep, double hx,
+                            double hy, double hz)
+{
+    const int nc = (int)C.nc;
+    for (uint32_t m = threadIdx.x; m < C.M; m += kThreads) {
+        const int cid = C.cellid[m];
+        const int cx = cid % nc, cy = (cid / nc) % nc, cz = cid / (nc * nc);
+        props[m] = propose(C, m, sweep, hx, hy, hz, cx, cy, cz);
+    }
 }
 
 template <typename Real, bool kRes>
@@ -574,20 +610,26 @@ struct TrialSites {
     R4<Real> new_site[3];
 };
 
-// All trials of one cell, run by one wave.
+// Per-wave LDS work areas.
+template <typename Real>
+struct WaveLds {
+    Cand<Real>* cand;     // compacted candidates of the trial in flight
+    uint16_t* seglo;      // neighbour row segments of the current cell
+    uint16_t* segoff;
+    uint16_t* clist;      // molecules near the current cell
+    TrialSites<Real>* ts;
+    WaveStats* ws;
+};
+
+// Neighbour cells of cell (cx, cy, cz) as row segments along x: (2r+1)^2 rows
+// of 1 or 2 x-ranges (r = k - 1).  Writes the segment table, returns the
+// number of segments and the number of molecules they hold.
 template <typename Real, bool kRes>
-__device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint64_t sweep,
-                         double hx, double hy, double hz, Cand<Real>* cand, uint16_t* seglo,
-                         uint16_t* segoff, TrialSites<Real>* ts, WaveStats* ws)
+__device__ __forceinline__ int stencil_segments(const Ctx<Real, kRes>& C, int cx, int cy, int cz,
+                                                uint16_t* seglo, uint16_t* segoff, uint32_t* total)
 {
     const int lane = __lane_id();
-    const uint32_t M = C.M;
     const int nc = (int)C.nc;
-    const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
-    const uint32_t beg = C.cellb[cell], cnt = C.cellb[cell + 1] - beg;
-    if (cnt == 0) return;
-
-    // Neighbour cells as row segments along x: (2r+1)^2 rows, 1 or 2 x-ranges.
     const int r = (int)C.k - 1;
     const bool full = 2 * r + 1 >= nc;
     const int nrow = full ? nc : 2 * r + 1;
@@ -613,38 +655,153 @@ __device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint6
         slo = C.cellb[rowbase + xa];
         scnt = C.cellb[rowbase + xb + 1] - slo;
     }
-    uint32_t total;
-    const uint32_t soff = wave_excl_scan(scnt, &total);
+    const uint32_t soff = wave_excl_scan(scnt, total);
     if (lane < nseg) {
         seglo[lane] = (uint16_t)slo;
         segoff[lane] = (uint16_t)soff;
     }
     wave_lds_sync();
+    return nseg;
+}
 
+// idx-th molecule of the stencil (segment table in LDS).
+template <typename Real, bool kRes>
+__device__ __forceinline__ uint32_t stencil_molecule(const Ctx<Real, kRes>& C, const uint16_t* seglo,
+                                                     const uint16_t* segoff, int nseg, uint32_t idx)
+{
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((uint32_t)segoff[mid] <= idx) lo = mid; else hi = mid;
+    }
+    return C.list[(uint32_t)seglo[lo] + (idx - (uint32_t)segoff[lo])];
+}
+
+// A molecule near the current cell: its index and its centre relative to the
+// cell centre (nearest image), rounded to FP16.  The coordinates only prune
+// candidates (with a margin); exact distances are formed in FP64 later.
+struct alignas(8) NearEntry {
+    uint16_t j;
+    __fp16 rx, ry, rz;
+};
+static_assert(sizeof(NearEntry) == 8, "near-list entry");
+
+constexpr uint32_t kListCap = kCellListCap;
+
+// All trials of the cells of colour `col` owned by this wave.
+template <typename Real, bool kRes>
+__device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int col, uint64_t sweep,
+                          double hx, double hy, double hz, const WaveLds<Real>& W,
+                          uint32_t& lane_terms)
+{
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t M = C.M;
+    const int k = (int)C.k, nc = (int)C.nc, na = nc / k;
+    const int nact = na * na * na;
+    const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
+    const int ncw = nact > wave ? (nact - 1 - wave) / kWaves + 1 : 0;
     constexpr int kCap = cand_cap(sizeof(Real) == 8);
     static_assert(kCap >= 64, "a ballot can append 64 candidates");
     const Real rc2f = (Real)C.rc2_factor;
-    for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
-        const uint32_t nin = min(64u, cnt - c0);
-        Prop pr;
-        if ((uint32_t)lane < nin)
-            pr = propose(C, (uint32_t)C.list[beg + c0 + lane], sweep, hx, hy, hz, cx, cy, cz);
-        for (uint32_t i = 0; i < nin; ++i) {
-            const uint32_t m = rl_u(pr.m, (int)i);
-            const uint32_t kind = rl_u(pr.kind, (int)i);
+    const bool logging = C.log != nullptr && sweep - C.log_sweep0 < C.log_sweeps;
+    const double half_w = 0.5 * C.w;
+    const double reach = sqrt(C.reach2);
+    const double reach_box = (reach + 1e-6) * (reach + 1e-6);
+    // prune radius on the FP16 relative centres: own move + a neighbour of the
+    // same cell that moved earlier in this cell + rounding
+    const double step = C.dmax * 1.7320508075688772;
+    const float prune_r = (float)(reach + 2.0 * step + 0.02);
+    // the relative centres are unique images only while the list region stays
+    // below half the box; otherwise every listed molecule goes to the exact test
+    // (and FP16 keeps the rounding below the 0.02 margin only up to |r| < 16)
+    const bool prune_ok = half_w + (double)prune_r + step < fmin(0.5 * C.L - 1e-3, 16.0);
+    const float prune2 = prune_ok ? prune_r * prune_r : 3.0e38f;
+    NearEntry* nlist = (NearEntry*)W.clist;
+
+    for (int ci = 0; ci < ncw; ++ci) {
+        const int a = wave + kWaves * ci;
+        const int cx = kx + k * (a % na), cy = ky + k * ((a / na) % na), cz = kz + k * (a / (na * na));
+        const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
+        const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
+        if (ccnt == 0) continue;
+        // proposals of the cell's first 64 molecules, one lane each (the load
+        // overlaps the neighbour list build below)
+        PropRec pr;
+        if ((uint32_t)lane < ccnt) pr = props[C.list[cbeg + lane]];
+
+        // molecules whose centre is within reach of this cell's box, walking
+        // the row segments with several lanes per segment
+        uint32_t total;
+        const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
+        const double bx0 = hx + ((double)cx + 0.5) * C.w;
+        const double by0 = hy + ((double)cy + 0.5) * C.w;
+        const double bz0 = hz + ((double)cz + 0.5) * C.w;
+        const int per = 64 / nseg;  // lanes per segment (nseg <= 50)
+        const int my_seg = lane / per, my_sub = lane - my_seg * per;
+        uint32_t my_lo = 0, my_len = 0, longest = 0;
+        if (my_seg < nseg) {
+            my_lo = W.seglo[my_seg];
+            const uint32_t end = my_seg + 1 < nseg ? (uint32_t)W.segoff[my_seg + 1] : total;
+            my_len = end - (uint32_t)W.segoff[my_seg];
+        }
+        {
+            uint32_t v = my_len;
+#pragma unroll
+            for (int o = 32; o; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o));
+            longest = v;
+        }
+        uint32_t nnear = 0;
+        bool overflow = false;
+        for (uint32_t t = (uint32_t)my_sub, t0 = 0; t0 < longest; t0 += (uint32_t)per, t += (uint32_t)per) {
+            bool keep = false;
+            uint32_t j = 0;
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            if (my_seg < nseg && t < my_len) {
+                j = C.list[my_lo + t];
+                const double rx = min_image(C.com[j] - bx0, C.L, C.invL);
+                const double ry = min_image(C.com[M + j] - by0, C.L, C.invL);
+                const double rz = min_image(C.com[2 * M + j] - bz0, C.L, C.invL);
+                const double ex = fmax(fabs(rx) - half_w, 0.0), ey = fmax(fabs(ry) - half_w, 0.0),
+                             ez = fmax(fabs(rz) - half_w, 0.0);
+                keep = ex * ex + ey * ey + ez * ez < reach_box;
+                fx = (float)rx; fy = (float)ry; fz = (float)rz;
+            }
+            const uint64_t bm = __ballot(keep);
+            const uint32_t np = (uint32_t)__popcll(bm);
+            if (nnear + np > kListCap) {
+                overflow = true;
+                break;
+            }
+            if (keep) {
+                NearEntry e;
+                e.j = (uint16_t)j;
+                e.rx = (__fp16)fx; e.ry = (__fp16)fy; e.rz = (__fp16)fz;
+                nlist[nnear + rank_below(bm)] = e;
+            }
+            nnear += np;
+        }
+        wave_lds_sync();
+        const uint32_t ncand = overflow ? total : nnear;
+
+        for (uint32_t q = 0; q < ccnt; ++q) {
+            if (q && (q & 63u) == 0) {
+                if ((uint32_t)lane < ccnt - q) pr = props[C.list[cbeg + q + lane]];
+            }
+            const int i = (int)(q & 63u);
+            const uint32_t m = C.list[cbeg + q];
+            const uint32_t kind = rl_u(pr.kind, i);
             const uint32_t move = kind & 15u, exited = (kind >> 4) & 1u, axis = kind >> 8;
-            const double thr = rl_d(pr.thr, (int)i);
-            const bool logging = C.log != nullptr && sweep - C.log_sweep0 < C.log_sweeps;
-            if (lane == 0) ws->att[move] += 1;
+            const double thr = rl_d(pr.thr, i);
+            if (lane == 0) W.ws->att[move] += 1;
             if (exited) {
                 if (lane == 0) {
-                    ws->exits += 1;
+                    W.ws->exits += 1;
                     if (logging) {
                         MoveRecord rec;
                         rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = thr; rec.sweep = sweep;
                         rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = 0;
                         rec.exited = 1; rec.axis = (uint8_t)axis; rec.pair_terms = 0; rec.pad = 0;
-                        (C.log)[(sweep - C.log_sweep0) * M + m] = rec;
+                        C.log[(sweep - C.log_sweep0) * M + m] = rec;
                     }
                 }
                 continue;
@@ -653,8 +810,13 @@ __device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint6
             const bool flip = move == 2u;
             const uint32_t a1 = flip ? (axis + 1) % 3 : 0u, a2 = flip ? (axis + 2) % 3 : 1u;
             const int nmv = flip ? 2 : 3;
-            const double dl0 = rl_d(pr.dl0, (int)i), dl1 = rl_d(pr.dl1, (int)i),
-                         dl2 = rl_d(pr.dl2, (int)i);
+            const double a0d = rl_d(pr.a0, i), a1d = rl_d(pr.a1, i), a2d = rl_d(pr.a2, i);
+            const double dl0 = move == 0u ? a0d : 0.0, dl1 = move == 0u ? a1d : 0.0,
+                         dl2 = move == 0u ? a2d : 0.0;
+            double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+            if (move == 1u) {
+                q0 = a0d; q1 = a1d; q2 = a2d; q3 = rl_d(pr.a3, i);
+            }
             if (lane < 3) {
                 const uint32_t sidx = lane == 0 ? a1 : (lane == 1 ? a2 : 2u);
                 const R4<Real> o = C.site[3 * m + sidx];
@@ -663,38 +825,40 @@ __device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint6
                     n.w = C.site[3 * m + (lane == 0 ? a2 : a1)].w;
                 } else if (move == 1u) {
                     double rm[9];
-                    rotation(rl_d(pr.qn0, (int)i), rl_d(pr.qn1, (int)i), rl_d(pr.qn2, (int)i),
-                             rl_d(pr.qn3, (int)i), rm);
+                    rotation(q0, q1, q2, q3, rm);
                     const double b0 = body_at(C, sidx, 0), b1 = body_at(C, sidx, 1),
                                  b2 = body_at(C, sidx, 2);
                     n.x = (Real)(rm[0] * b0 + rm[1] * b1 + rm[2] * b2);
                     n.y = (Real)(rm[3] * b0 + rm[4] * b1 + rm[5] * b2);
                     n.z = (Real)(rm[6] * b0 + rm[7] * b1 + rm[8] * b2);
                 }
-                ts->old_site[lane] = o;
-                ts->new_site[lane] = n;
+                W.ts->old_site[lane] = o;
+                W.ts->new_site[lane] = n;
             }
             wave_lds_sync();
             const Real dlx = (Real)dl0, dly = (Real)dl1, dlz = (Real)dl2;
             const double cmx = C.com[m], cmy = C.com[M + m], cmz = C.com[2 * M + m];
+            const float mrx = (float)min_image(cmx - bx0, C.L, C.invL);
+            const float mry = (float)min_image(cmy - by0, C.L, C.invL);
+            const float mrz = (float)min_image(cmz - bz0, C.L, C.invL);
 
             Real acc = Real(0), accs = Real(0);
-            uint32_t nterm = 0;
-            uint32_t ntest = 0;
+            uint64_t ntest = 0;
+            const uint32_t terms_before = logging ? wave_sum_u(lane_terms) : 0u;
             auto flush = [&](uint32_t nb) __attribute__((always_inline)) {
                 wave_lds_sync();
                 const uint32_t nitems = nb * 3u;
-                ntest += nitems * (uint32_t)nmv * 2u;
+                ntest += (uint64_t)nitems * (uint32_t)nmv * 2u;
                 for (uint32_t it = (uint32_t)lane; it < nitems; it += 64u) {
-                    const uint32_t ci = it / 3u, t = it - 3u * ci;
-                    const Cand<Real> cd = cand[ci];
+                    const uint32_t cj = it / 3u, t = it - 3u * cj;
+                    const Cand<Real> cd = W.cand[cj];
                     const R4<Real> sj = C.site[3u * cd.j + t];
                     const Real bx = cd.x + sj.x, by = cd.y + sj.y, bz = cd.z + sj.z;
                     const Real qx0 = bx - dlx, qy0 = by - dly, qz0 = bz - dlz;
 #pragma unroll
                     for (int v = 0; v < 3; ++v) {
                         if (v < nmv) {
-                            const R4<Real> o = ts->old_site[v], n = ts->new_site[v];
+                            const R4<Real> o = W.ts->old_site[v], n = W.ts->new_site[v];
                             const Real rx = bx - o.x, ry = by - o.y, rz = bz - o.z;
                             const Real r2 = rx * rx + ry * ry + rz * rz;
                             const Real sg = Real(0.5) * (o.w + sj.w);
@@ -712,7 +876,7 @@ __device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint6
                             const Real un = r2n < rc2n ? pair_u(s2n, r2n) : Real(0);
                             acc += un - uo;
                             accs += un + uo;
-                            nterm += (r2 < rc2 ? 1u : 0u) + (r2n < rc2n ? 1u : 0u);
+                            lane_terms += (r2 < rc2 ? 1u : 0u) + (r2n < rc2n ? 1u : 0u);
                         }
                     }
                 }
@@ -720,19 +884,22 @@ __device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint6
             };
 
             uint32_t nbuf = 0;
-            for (uint32_t base = 0; base < total; base += 64u) {
+            for (uint32_t base = 0; base < ncand; base += 64u) {
                 const uint32_t idx = base + (uint32_t)lane;
                 bool pass = false;
                 uint32_t j = 0;
                 double dx = 0.0, dy = 0.0, dz = 0.0;
-                if (idx < total) {
-                    int lo = 0, hi = nseg;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if ((uint32_t)segoff[mid] <= idx) lo = mid; else hi = mid;
+                if (idx < ncand) {
+                    bool near = true;
+                    if (overflow) {
+                        j = stencil_molecule(C, W.seglo, W.segoff, nseg, idx);
+                    } else {
+                        const NearEntry e = nlist[idx];
+                        j = e.j;
+                        const float px = (float)e.rx - mrx, py = (float)e.ry - mry, pz = (float)e.rz - mrz;
+                        near = px * px + py * py + pz * pz < prune2;
                     }
-                    j = C.list[(uint32_t)seglo[lo] + (idx - (uint32_t)segoff[lo])];
-                    if (j != m) {
+                    if (near && j != m) {
                         dx = min_image(C.com[j] - cmx, C.L, C.invL);
                         dy = min_image(C.com[M + j] - cmy, C.L, C.invL);
                         dz = min_image(C.com[2 * M + j] - cmz, C.L, C.invL);
@@ -751,33 +918,40 @@ __device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint6
                 if (pass) {
                     Cand<Real> cd;
                     cd.x = (Real)dx; cd.y = (Real)dy; cd.z = (Real)dz; cd.j = j;
-                    cand[nbuf + rank_below(bm)] = cd;
+                    W.cand[nbuf + rank_below(bm)] = cd;
                 }
                 nbuf += np;
             }
             if (nbuf) flush(nbuf);
 
-            const double de = wave_sum((double)acc);
-            const double sc = wave_sum((double)accs);
-            const uint32_t terms = wave_sum_u(nterm);
+            const double de = wave_sum_dpp((double)acc);
             const bool accept = (de <= 0.0) || (thr < -de);
+            double sc = 0.0;
+            uint32_t terms = 0;
+            if (logging) {
+                sc = wave_sum_dpp((double)accs);
+                terms = wave_sum_u(lane_terms) - terms_before;
+            }
             if (lane == 0) {
-                ws->terms += terms;
-                ws->tests += ntest;
+                W.ws->tests += ntest;
                 if (accept) {
-                    ws->acc[move] += 1;
-                    ws->e += de;
+                    W.ws->acc[move] += 1;
+                    W.ws->e += de;
                     if (move == 0u) {
                         C.com[m] = wrap(cmx + dl0, C.L);
                         C.com[M + m] = wrap(cmy + dl1, C.L);
                         C.com[2 * M + m] = wrap(cmz + dl2, C.L);
                     } else if (move == 1u) {
-                        C.site[3 * m] = ts->new_site[0];
-                        C.site[3 * m + 1] = ts->new_site[1];
-                        C.site[3 * m + 2] = ts->new_site[2];
+                        C.site[3 * m] = W.ts->new_site[0];
+                        C.site[3 * m + 1] = W.ts->new_site[1];
+                        C.site[3 * m + 2] = W.ts->new_site[2];
+                        C.quat[m] = q0;
+                        C.quat[M + m] = q1;
+                        C.quat[2 * M + m] = q2;
+                        C.quat[3 * M + m] = q3;
                     } else {
-                        C.site[3 * m + a1].w = ts->new_site[0].w;
-                        C.site[3 * m + a2].w = ts->new_site[1].w;
+                        C.site[3 * m + a1].w = W.ts->new_site[0].w;
+                        C.site[3 * m + a2].w = W.ts->new_site[1].w;
                         const uint32_t ty = C.types[m];
                         const uint32_t t1 = (ty >> (8 * a1)) & 0xFFu, t2 = (ty >> (8 * a2)) & 0xFFu;
                         uint32_t nt = ty & ~((0xFFu << (8 * a1)) | (0xFFu << (8 * a2)));
@@ -790,17 +964,7 @@ __device__ void run_cell(const Ctx<Real, kRes>& C, int cx, int cy, int cz, uint6
                     rec.delta_e = de; rec.scale = sc; rec.t_log_u = thr; rec.sweep = sweep;
                     rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = accept ? 1 : 0;
                     rec.exited = 0; rec.axis = (uint8_t)axis; rec.pair_terms = terms; rec.pad = 0;
-                    (C.log)[(sweep - C.log_sweep0) * M + m] = rec;
-                }
-            }
-            if (accept && move == 1u) {
-                const double q0 = rl_d(pr.qn0, (int)i), q1 = rl_d(pr.qn1, (int)i),
-                             q2 = rl_d(pr.qn2, (int)i), q3 = rl_d(pr.qn3, (int)i);
-                if (lane == 0) {
-                    C.quat[m] = q0;
-                    C.quat[M + m] = q1;
-                    C.quat[2 * M + m] = q2;
-                    C.quat[3 * M + m] = q3;
+                    C.log[(sweep - C.log_sweep0) * M + m] = rec;
                 }
             }
             wave_lds_sync();
@@ -848,9 +1012,9 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool fp64 = sizeof(Real) == 8;
     const LdsLayout L = lds_layout(fp64, kRes, C.M, C.ncell);
-    C.red = (double*)(smem + L.red);
+    C.red = nullptr;
+    C.bins = nullptr;
     C.wpart = (double*)(smem + L.wpart);
-    C.bins = (uint32_t*)(smem + L.bins);
     C.misc = (double*)(smem + L.misc);
     if (kRes) {
         C.com = (double*)(smem + L.com);
@@ -865,9 +1029,14 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
         C.cellid = g_cellid;
         C.list = g_list;
     }
-    Cand<Real>* cand = (Cand<Real>*)(smem + L.cand) + wave * cand_cap(fp64);
-    uint16_t* seglo = (uint16_t*)(smem + L.seglo) + wave * kMaxSeg;
-    uint16_t* segoff = (uint16_t*)(smem + L.segoff) + wave * kMaxSeg;
+    WaveLds<Real> W;
+    W.cand = (Cand<Real>*)(smem + L.cand) + wave * cand_cap(fp64);
+    W.seglo = (uint16_t*)(smem + L.seglo) + wave * kMaxSeg;
+    W.segoff = (uint16_t*)(smem + L.segoff) + wave * kMaxSeg;
+    W.clist = (uint16_t*)(smem + L.clist + (size_t)wave * kListCap * sizeof(NearEntry));
+    W.ts = (TrialSites<Real>*)(smem + L.tsite) + wave;
+    W.ws = (WaveStats*)(smem + L.wstat) + wave;
+    PropRec* props = (PropRec*)Dp->props;
     uint32_t* uscratch = (uint32_t*)(C.misc + 8);
     const uint32_t M = C.M;
 
@@ -882,8 +1051,8 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
     if (kRes)
         for (uint32_t i = tid; i < 3 * M; i += kThreads) C.com[i] = C.gcom[i];
     for (uint32_t m = tid; m < M; m += kThreads) store_sites_from_quat(C, m);
-    WaveStats* ws = (WaveStats*)(smem + L.wstat) + wave;
-    TrialSites<Real>* ts = (TrialSites<Real>*)(smem + L.tsite) + wave;
+    WaveStats* ws = W.ws;
+    uint32_t lane_terms = 0;
     if (lane == 0) {
         for (int i = 0; i < 3; ++i) ws->att[i] = ws->acc[i] = 0;
         ws->exits = ws->terms = ws->tests = 0;
@@ -893,21 +1062,17 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
     const uint64_t origin = st->obs_origin;
     __syncthreads();
 
-    const int k = (int)C.k, nc = (int)C.nc, na = nc / k;
-    const int nact = na * na * na, ncol = k * k * k;
+    const int ncol = (int)(C.k * C.k * C.k);
     for (uint64_t it = 0; it < sl.n_sweeps; ++it) {
         const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, C.seed_lo,
                               C.seed_hi);
         const double hx = C.w * unit_open(g.x), hy = C.w * unit_open(g.y),
                      hz = C.w * unit_open(g.z);
         build_cells(C, hx, hy, hz, uscratch);
+        propose_all(C, props, sweep, hx, hy, hz);
+        __syncthreads();
         for (int col = 0; col < ncol; ++col) {
-            const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
-            for (int a = wave; a < nact; a += kWaves) {
-                const int ax = a % na, ay = (a / na) % na, az = a / (na * na);
-                run_cell(C, kx + k * ax, ky + k * ay, kz + k * az, sweep, hx, hy, hz, cand, seglo,
-                         segoff, ts, ws);
-            }
+            run_phase(C, props, col, sweep, hx, hy, hz, W, lane_terms);
             __syncthreads();
         }
         // accumulated energy in a fixed wave order; E/M samples
@@ -935,6 +1100,10 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
     // write back
     if (kRes)
         for (uint32_t i = tid; i < 3 * M; i += kThreads) C.gcom[i] = C.com[i];
+    uint64_t wt = lane_terms;
+#pragma unroll
+    for (int o = 32; o; o >>= 1) wt += __shfl_xor(wt, o);
+    if (lane == 0) ws->terms += wt;
     if (lane == 0) {
         for (int i = 0; i < 3; ++i) {
             if (ws->att[i]) atomicAdd((unsigned long long*)&st->attempts[i], (unsigned long long)ws->att[i]);

@@ -110,6 +110,13 @@ def lib():
     """Load libflipmc.so; fails loudly when the HIP extension is missing."""
     global _lib
     if _lib is None:
+        # torch carries its own HIP runtime with the same soname as the system
+        # one; loading torch first makes this library bind to that runtime, so
+        # torch's streams and buffers and these kernels share one HIP instance
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')"
