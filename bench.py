@@ -292,7 +292,7 @@ def bench_c4(args, flipmc, torch):
 
     jobs = workloads.serving_stream(n_jobs=args.jobs, rate=200.0, seed=1, m_max=args.m_max,
                                     s_max=args.s_max)
-    srv = serve.Server(memory_budget=args.budget, precision=flipmc.MC_FP32_DE,
+    srv = serve.Server(memory_budget=args.budget, backend=serve.GpuBackend(flipmc.MC_FP32_DE),
                        quantum_moves=args.quantum)
     t0 = time.perf_counter()
     res = srv.serve(jobs, time_limit=args.time_limit)
@@ -326,7 +326,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=27000)
     ap.add_argument("--s-max", type=int, default=10000)
     ap.add_argument("--budget", type=int, default=4 << 30)
-    ap.add_argument("--quantum", type=int, default=400_000)
+    ap.add_argument("--quantum", type=int, default=200_000)
     ap.add_argument("--time-limit", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

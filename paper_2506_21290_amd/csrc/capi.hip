@@ -835,8 +835,14 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         mc_system* s = b->sys[i];
         if (!s || b->remaining[i] == 0) continue;
         uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
-        if (max_moves_per_slot)
-            k = std::min<uint64_t>(k, std::max<uint64_t>(1, max_moves_per_slot / s->p.n_molecules));
+        if (max_moves_per_slot) {
+            // equal time slices: a workgroup's moves/s falls for small systems
+            // (fewer independent cells per colour phase)
+            const double M = (double)s->p.n_molecules;
+            const double rate = std::min(1.0, 0.25 + 0.75 * M / 1000.0);
+            const uint64_t cap = (uint64_t)((double)max_moves_per_slot * rate / M);
+            k = std::min<uint64_t>(k, std::max<uint64_t>(1, cap));
+        }
         const int cls = s->g.resident ? 0 : 1;
         Slot sl{};
         sl.sys = s->dev;

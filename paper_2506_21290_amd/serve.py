@@ -3,14 +3,22 @@
 Requests are sampling jobs (M molecules at temperature T for S sweeps).  Their
 configurations stay resident in HBM for the job's life; a job is admitted as
 soon as a slot and enough of the memory budget are free, and every launch
-advances all admitted jobs by a time slice (``quantum_moves`` attempted moves
-per job), so jobs that arrive while others run join the next launch and their
-work overlaps on the device.  Systems whose working set fits one workgroup's
-LDS go to one batch, larger ones to a second batch on a second stream, so the
-two kinds of launch run side by side.
+advances all admitted jobs by one time slice, so jobs that arrive while others
+run join the next launch and their work overlaps on the device.  Systems whose
+working set fits one workgroup's LDS go to one batch, larger ones to a second
+batch on a second stream, so the two kinds of launch run side by side.
+
+The time slice is given in attempted moves per job; the engine scales it by
+its model of per-workgroup throughput against system size (small systems run
+fewer moves per second on one workgroup), so every job of a launch gets a
+similar share of time.
 
 Each finished job returns E/M (mean over the second half of its sweeps), g(r)
 (frames over the second half) and C_2(t) (Sec. III, Eq. 3 and Eq. 7).
+
+The device work goes through a backend object (``GpuBackend`` by default); the
+admission, budget and slot accounting is plain Python and can be exercised with
+any object that offers the same few methods.
 """
 from __future__ import annotations
 
@@ -21,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import flipmc
+from . import flipmc, tune
 
 
 @dataclass
@@ -39,12 +47,17 @@ class Result:
 
 
 def job_params(job, precision):
+    """Engine parameters of a job: the tuned decomposition for its size, FP64
+    re-sum every 100 sweeps, E/M every 10 sweeps and about five g(r) frames over
+    the second half of the run."""
     S = job.sweeps
     gofr_every = max(10, (S // 2) // 5 // 10 * 10)
+    k, nc = tune.choose(job.n_molecules, precision)
     return flipmc.mc_params_default(
         n_molecules=job.n_molecules, temperature=job.temperature, precision=precision,
-        seed=job.seed, resum_interval=100, obs_interval=10, gofr_interval=gofr_every,
-        obs_start=S // 2, max_samples=max(16, S // 10 + 2))
+        seed=job.seed, colours_per_axis=k, cells_per_side=nc, resum_interval=100,
+        obs_interval=10, gofr_interval=gofr_every, obs_start=S // 2,
+        max_samples=max(16, S // 10 + 2))
 
 
 def gofr_normalised(obs, n_sites, box):
@@ -59,99 +72,125 @@ def gofr_normalised(obs, n_sites, box):
     return 0.5 * (r[1:] + r[:-1]), g
 
 
-class Server:
-    def __init__(self, memory_budget, precision=flipmc.MC_FP32_DE, max_slots=1024,
-                 quantum_moves=400_000):
+class GpuBackend:
+    """Jobs as flipmc systems in two batches (LDS-resident, HBM-resident)."""
+
+    def __init__(self, precision=flipmc.MC_FP32_DE, max_slots=1024):
         import torch
 
         self.torch = torch
         self.precision = precision
-        self.budget = int(memory_budget)
-        self.used = 0
-        self.quantum = int(quantum_moves)
         self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]
         self.admit_stream = torch.cuda.Stream()
         self.batches = [flipmc.Batch(max_slots, precision, stream=s) for s in self.streams]
         self.max_slots = max_slots
-        self.active = {}  # (batch, slot) -> (job, system, bytes, t_admit)
+
+    def size(self, job):
+        """(bytes of device memory, batch index)"""
+        p = job_params(job, self.precision)
+        resident, _ = flipmc.mc_placement(p)
+        return flipmc.mc_required_bytes(p), 0 if resident else 1
+
+    def free_slots(self, bi):
+        return self.max_slots - len(self.batches[bi].members)
+
+    def start(self, job, bi):
+        with self.torch.cuda.stream(self.admit_stream):
+            s = flipmc.System(job_params(job, self.precision), stream=self.admit_stream)
+        return self.batches[bi].add(s, job.sweeps), s
+
+    def launch(self, quantum_moves):
+        n = 0
+        for b in self.batches:
+            if b.members:
+                b.run(quantum_moves)
+                n += 1
+        return n
+
+    def harvest(self):
+        """[(batch index, slot, system)] of finished jobs."""
+        out = []
+        for bi, b in enumerate(self.batches):
+            if b.members:
+                out += [(bi, slot, s) for slot, s in b.poll()]
+        return out
+
+    def cancel(self, bi, slot):
+        self.batches[bi].cancel(slot)
+
+    def result(self, job, s):
+        obs = s.observables()
+        box = flipmc.mc_geometry(s.params)[0]
+        r, g = gofr_normalised(obs, 3 * job.n_molecules, box)
+        n_e = max(1, obs["n_energy_samples"])
+        att, acc = obs["attempts"], obs["accepts"]
+        return dict(energy_per_molecule=obs["energy_sum"] / n_e, gofr_r=r, gofr=g,
+                    c2_t=obs["c2_sweep"], c2=obs["c2"],
+                    accept={k: float(acc[i]) / max(1, int(att[i]))
+                            for i, k in enumerate(["translate", "rotate", "flip"])})
+
+
+class Server:
+    def __init__(self, memory_budget, backend=None, quantum_moves=200_000):
+        self.backend = backend if backend is not None else GpuBackend()
+        self.budget = int(memory_budget)
+        self.used = 0
+        self.quantum = int(quantum_moves)
+        self.active = {}  # (batch, slot) -> (job, handle, bytes, t_admit)
         self.peak_active = 0
         self.peak_bytes = 0
         self.launches = 0
 
-    def _admit(self, job, now):
-        p = job_params(job, self.precision)
-        need = flipmc.mc_required_bytes(p)
+    def try_admit(self, job, now):
+        need, bi = self.backend.size(job)
         if need > self.budget:
             raise ValueError(f"job {job.index} needs {need} bytes, above the whole budget")
-        if self.used + need > self.budget:
+        if self.used + need > self.budget or self.backend.free_slots(bi) <= 0:
             return False
-        resident, _ = flipmc.mc_placement(p)
-        bi = 0 if resident else 1
-        b = self.batches[bi]
-        if len(b.members) >= self.max_slots:
-            return False
-        with self.torch.cuda.stream(self.admit_stream):
-            s = flipmc.System(p, stream=self.admit_stream)
-        slot = b.add(s, job.sweeps)
-        self.active[(bi, slot)] = (job, s, need, now)
+        slot, handle = self.backend.start(job, bi)
+        self.active[(bi, slot)] = (job, handle, need, now)
         self.used += need
         self.peak_active = max(self.peak_active, len(self.active))
         self.peak_bytes = max(self.peak_bytes, self.used)
         return True
 
-    def _harvest(self, bi, slot, system, t0):
-        job, s, need, t_admit = self.active.pop((bi, slot))
-        obs = s.observables()
-        now = time.perf_counter() - t0
-        box = flipmc.mc_geometry(s.params)[0]
-        r, g = gofr_normalised(obs, 3 * job.n_molecules, box)
-        n_e = max(1, obs["n_energy_samples"])
-        att, acc = obs["attempts"], obs["accepts"]
-        res = Result(
-            job=job, latency=now - job.arrival, wait=t_admit - job.arrival,
-            energy_per_molecule=obs["energy_sum"] / n_e, gofr_r=r, gofr=g,
-            c2_t=obs["c2_sweep"], c2=obs["c2"], moves=job.n_molecules * job.sweeps,
-            accept={k: float(acc[i]) / max(1, int(att[i]))
-                    for i, k in enumerate(["translate", "rotate", "flip"])},
-        )
+    def finish(self, bi, slot, now):
+        job, handle, need, t_admit = self.active.pop((bi, slot))
         self.used -= need
-        del s
-        return res
+        r = self.backend.result(job, handle)
+        return Result(job=job, latency=now - job.arrival, wait=t_admit - job.arrival,
+                      moves=job.n_molecules * job.sweeps, **r)
 
     def cancel(self, bi, slot):
         """Drop a running job: its slot and budget are free for the next admission."""
-        job, s, need, _ = self.active.pop((bi, slot))
-        self.batches[bi].cancel(slot)
+        job, handle, need, _ = self.active.pop((bi, slot))
+        self.backend.cancel(bi, slot)
         self.used -= need
         return job
 
-    def serve(self, jobs, time_limit=None):
-        """Run the arrival stream to completion; returns the results in
-        completion order."""
+    def serve(self, jobs, time_limit=None, clock=None):
+        """Run an arrival stream to completion; returns results in completion
+        order.  `clock` (seconds since start) defaults to the wall clock."""
+        t0 = time.perf_counter()
+        clock = clock or (lambda: time.perf_counter() - t0)
         jobs = sorted(jobs, key=lambda j: j.arrival)
         queue = collections.deque()
         results = []
         i = 0
-        t0 = time.perf_counter()
         while i < len(jobs) or queue or self.active:
-            now = time.perf_counter() - t0
+            now = clock()
             if time_limit is not None and now > time_limit:
                 break
             while i < len(jobs) and jobs[i].arrival <= now:
                 queue.append(jobs[i])
                 i += 1
-            while queue and self._admit(queue[0], now):
+            while queue and self.try_admit(queue[0], now):
                 queue.popleft()
             if not self.active:
                 if i < len(jobs):
-                    time.sleep(max(0.0, jobs[i].arrival - (time.perf_counter() - t0)))
+                    time.sleep(max(0.0, min(0.05, jobs[i].arrival - clock())))
                 continue
-            for b in self.batches:
-                if b.members:
-                    b.run(self.quantum)
-                    self.launches += 1
-            for bi, b in enumerate(self.batches):
-                if b.members:
-                    for slot, system in b.poll():
-                        results.append(self._harvest(bi, slot, system, t0))
+            self.launches += self.backend.launch(self.quantum)
+            for bi, slot, _ in self.backend.harvest():
+                results.append(self.finish(bi, slot, clock()))
         return results

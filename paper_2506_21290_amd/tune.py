@@ -1,0 +1,119 @@
+"""Autotuner of the checkerboard decomposition.
+
+For a system size M and a precision, every valid (k, n_c) is a correct
+sampler with its own trajectory; they differ in speed (colour phases, cells per
+wave, neighbour-list length).  The tuner times each candidate on the GPU and
+records the fastest in ``tuned.json`` next to this file.  ``choose`` reads the
+table (falling back to the engine's own model when a size is missing), so a
+job's decomposition is a fixed function of (M, precision) and can be
+reproduced by the oracle.
+
+Run on the GPU:  python -m paper_2506_21290_amd.tune --out tuned.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+from . import flipmc
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tuned.json")
+PREC_NAME = {flipmc.MC_FP64: "fp64", flipmc.MC_FP32_DE: "fp32"}
+_table = None
+
+
+def candidates(M, precision, per_k=3):
+    """Valid (k, n_c) for an M-molecule box at the default density: the
+    `per_k` finest grids of each k (coarser grids only lengthen the chains of
+    trials inside a cell)."""
+    out = []
+    for k in (2, 3):
+        ok = []
+        for nc in range(k, 41, k):
+            p = flipmc.mc_params_default(n_molecules=M, precision=precision,
+                                         colours_per_axis=k, cells_per_side=nc)
+            try:
+                flipmc.mc_geometry(p)
+            except flipmc.McError:
+                continue
+            ok.append((k, nc))
+        out += ok[-per_k:]
+    return out
+
+
+def table():
+    global _table
+    if _table is None:
+        _table = {}
+        if os.path.exists(TABLE):
+            with open(TABLE) as f:
+                _table = json.load(f)
+    return _table
+
+
+def choose(M, precision):
+    """(k, n_c) for M molecules: the tuned entry, else (0, 0) = engine model."""
+    entry = table().get(PREC_NAME[precision], {}).get(str(M))
+    if entry:
+        return int(entry["k"]), int(entry["n_c"])
+    return 0, 0
+
+
+def time_candidate(M, precision, k, nc, sweeps, T=1.0):
+    import torch
+
+    p = flipmc.mc_params_default(n_molecules=M, temperature=T, precision=precision,
+                                 colours_per_axis=k, cells_per_side=nc, resum_interval=0,
+                                 obs_interval=0, gofr_interval=0)
+    s = flipmc.System(p)
+    s.sweep(max(5, sweeps // 5))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.sweep(sweeps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / sweeps
+
+
+def tune(sizes, precisions, budget_moves=600_000):
+    result = {}
+    for prec in precisions:
+        name = PREC_NAME[prec]
+        result[name] = {}
+        for M in sizes:
+            sweeps = max(10, min(200, budget_moves // M))
+            timed = []
+            for k, nc in candidates(M, prec):
+                dt = time_candidate(M, prec, k, nc, sweeps)
+                timed.append((dt, k, nc))
+                print(f"{name} M={M} k={k} n_c={nc}: {dt * 1e6:.1f} us/sweep", flush=True)
+            dt, k, nc = min(timed)
+            result[name][str(M)] = {"k": k, "n_c": nc, "us_per_sweep": dt * 1e6,
+                                    "moves_per_s": M / dt}
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", default=",".join(str(n ** 3) for n in range(4, 31)))
+    ap.add_argument("--precisions", default="fp32")
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args()
+    sizes = [int(x) for x in args.sizes.split(",")]
+    precs = [{"fp32": flipmc.MC_FP32_DE, "fp64": flipmc.MC_FP64}[x] for x in args.precisions.split(",")]
+    res = tune(sizes, precs)
+    old = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
+    for name, entries in res.items():
+        old.setdefault(name, {}).update(entries)
+    with open(args.out, "w") as f:
+        json.dump(old, f, indent=1, sort_keys=True)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
