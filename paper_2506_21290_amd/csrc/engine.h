@@ -108,17 +108,16 @@ struct MoveRecord {   // mirrors mc_move_record
 };
 static_assert(sizeof(MoveRecord) == 48, "record layout");
 
-// Candidate-pair buffer entries per wave.
-// At least 64: one 64-lane ballot may append 64 entries after a flush.
-__host__ __device__ constexpr int cand_cap(bool) { return 64; }
-__host__ __device__ constexpr size_t cand_bytes(bool fp64) { return fp64 ? 32 : 16; }
+// Per-wave LDS work areas: the molecules near the current cell, the
+// survivors of a trial's prune, the trial in flight.
 __host__ __device__ constexpr size_t site_bytes(bool fp64) { return fp64 ? 32 : 16; }
+__host__ __device__ constexpr size_t trial_bytes(bool fp64) { return fp64 ? 272 : 160; }
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 // LDS carve-up, shared by the host (launch size) and the kernel (pointers).
 struct LdsLayout {
-    size_t cand, seglo, segoff, clist, wpart, misc, wstat, tsite;
+    size_t surv, seglo, segoff, near, wpart, misc, trial;
     size_t com, site, cell, cellid, list, total;
 };
 
@@ -127,14 +126,13 @@ __host__ __device__ inline LdsLayout lds_layout(bool fp64, bool resident, uint32
 {
     LdsLayout l{};
     size_t o = 0;
-    l.cand = o;   o = align16(o + kWaves * cand_cap(fp64) * cand_bytes(fp64));
+    l.surv = o;   o = align16(o + kWaves * kCellListCap * sizeof(uint16_t));
     l.seglo = o;  o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
     l.segoff = o; o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
-    l.clist = o;  o = align16(o + kWaves * kCellListCap * 8);
+    l.near = o;   o = align16(o + kWaves * kCellListCap * 8);
     l.wpart = o;  o = align16(o + kWaves * sizeof(double));
     l.misc = o;   o = align16(o + 16 * sizeof(double));
-    l.wstat = o;  o = align16(o + kWaves * 80);
-    l.tsite = o;  o = align16(o + kWaves * 6 * site_bytes(fp64));
+    l.trial = o;  o = align16(o + kWaves * trial_bytes(fp64));
     if (resident) {
         l.com = o;    o = align16(o + 3 * size_t(M) * sizeof(double));
         l.site = o;   o = align16(o + 3 * size_t(M) * site_bytes(fp64));

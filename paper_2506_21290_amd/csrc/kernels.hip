@@ -11,11 +11,13 @@
 // cell are tried in ascending index by that wave.  Cells of one colour are at
 // least (k-1) cells apart, farther than any two molecules can interact, so the
 // waves never race.  Inside a trial the 64 lanes share the energy difference:
-// lanes scan the 27 / 125 neighbour cells, keep molecules whose centre of mass
-// is within reach, compact them into a per-wave LDS buffer and then evaluate
-// (candidate site x moved site) pair terms; a wave butterfly reduction in FP64
-// gives dE in a fixed order.  Proposals of all molecules of a cell are drawn in
-// parallel (one lane each) before the cell's sequential trials.
+// the molecules near the cell (built once per cell) are pruned against the
+// trial molecule's centre, the survivors' sites that can reach a moved site are
+// compacted into a per-wave LDS buffer, one 64-lane pass evaluates them against
+// the moved sites before and after the move, and a DPP reduction in FP64 gives
+// dE in a fixed order.  Proposals of all molecules of a sweep are drawn in
+// parallel before its first colour; the lane that holds a molecule's proposal
+// publishes its moved sites and commits the accepted move.
 //
 // The random numbers are Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11)
 // keyed by the seed and counted by (molecule, sweep low, sweep high, tag), so a
@@ -63,12 +65,6 @@ __device__ __forceinline__ double unit_53(uint32_t lo, uint32_t hi)
 template <typename Real>
 struct alignas(16) R4 {
     Real x, y, z, w;
-};
-
-template <typename Real>
-struct alignas(16) Cand {
-    Real x, y, z;
-    uint32_t j;
 };
 
 // ---------------------------------------------------------------- wave ops --
@@ -597,28 +593,45 @@ __device__ void build_cells(const Ctx<Real, kRes>& C, double hx, double hy, doub
 }
 
 // Per-wave accumulators, kept in LDS and updated by lane 0.
-struct WaveStats {
-    uint64_t att[3], acc[3], exits, terms, tests;
-    double e;  // accepted dE of the current sweep
+// Per-wave counters, kept in registers for the whole launch.
+struct WaveCount {
+    uint32_t att0, att1, att2, acc0, acc1, acc2, exits;
+    uint64_t terms, tests;
+    double e;  // accepted dE of the current sweep, in trial order
 };
 
-// Per-wave description of the trial in flight: the moved sites before and
-// after the move (offset from the molecule's centre + sigma of the type).
+// The trial in flight, written by the lane that holds the molecule's proposal
+// and read by the whole wave.
 template <typename Real>
-struct TrialSites {
-    R4<Real> old_site[3];
-    R4<Real> new_site[3];
+struct alignas(16) TrialLds {
+    R4<Real> old_site[3];  // moved sites before the move: offset from the old centre + sigma
+    R4<Real> new_site[3];  // after the move: offset from the new centre + sigma
+    double cm[3];          // centre of mass before the move
+    float mr[3];           // the same relative to the cell centre (pruning only)
+    Real dl[3];            // displacement of a translation, zero for the other moves
+    uint32_t info;         // molecule | move << 16
 };
+static_assert(sizeof(TrialLds<float>) <= trial_bytes(false), "trial record (FP32)");
+static_assert(sizeof(TrialLds<double>) <= trial_bytes(true), "trial record (FP64)");
+
+// A molecule near the current cell: its index and its centre relative to the
+// cell centre (nearest image), rounded to FP16.  The coordinates only prune
+// candidates (with a margin); the positions used for energies are formed from
+// the FP64 centres.
+struct alignas(8) NearEntry {
+    uint16_t j;
+    __fp16 rx, ry, rz;
+};
+static_assert(sizeof(NearEntry) == 8, "near-list entry");
 
 // Per-wave LDS work areas.
 template <typename Real>
 struct WaveLds {
-    Cand<Real>* cand;     // compacted candidates of the trial in flight
+    uint16_t* surv;       // molecules that passed the prune of the trial in flight
     uint16_t* seglo;      // neighbour row segments of the current cell
     uint16_t* segoff;
-    uint16_t* clist;      // molecules near the current cell
-    TrialSites<Real>* ts;
-    WaveStats* ws;
+    NearEntry* near;      // molecules near the current cell
+    TrialLds<Real>* tr;
 };
 
 // Neighbour cells of cell (cx, cy, cz) as row segments along x: (2r+1)^2 rows
@@ -677,22 +690,93 @@ __device__ __forceinline__ uint32_t stencil_molecule(const Ctx<Real, kRes>& C, c
     return C.list[(uint32_t)seglo[lo] + (idx - (uint32_t)segoff[lo])];
 }
 
-// A molecule near the current cell: its index and its centre relative to the
-// cell centre (nearest image), rounded to FP16.  The coordinates only prune
-// candidates (with a margin); exact distances are formed in FP64 later.
-struct alignas(8) NearEntry {
-    uint16_t j;
-    __fp16 rx, ry, rz;
-};
-static_assert(sizeof(NearEntry) == 8, "near-list entry");
-
 constexpr uint32_t kListCap = kCellListCap;
+constexpr uint32_t kNoMolecule = 0xFFFFFFFFu;
+
+// The moved sites of the trial in flight, in registers (wave-uniform).
+template <typename Real>
+struct Moved {
+    R4<Real> o[3], n[3];
+    Real dlx, dly, dlz;
+    double cx, cy, cz;
+    int nmv;
+    bool flip;
+};
+
+// Pair terms of one candidate item: site t of survivor s (it = 3 s + t) with
+// the moved sites before and after the move (Eq. 1 within each pair's
+// cut-off).  Returns u_new - u_old (0 for it >= nit); *sc gets u_new + u_old,
+// *in_o / *in_n the cut-off tests.
+template <typename Real, bool kRes>
+__device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const uint16_t* surv,
+                                           const Moved<Real>& mv, uint32_t it, uint32_t nit,
+                                           Real rc2f, Real& sc, uint32_t (&inb)[6])
+{
+    const bool valid = it < nit;
+    const uint32_t itc = valid ? it : 0u;
+    const uint32_t s = itc / 3u, t = itc - 3u * s;
+    const uint32_t j = surv[s];
+    const uint32_t M = C.M;
+    const double dx = min_image(C.com[j] - mv.cx, C.L, C.invL);
+    const double dy = min_image(C.com[M + j] - mv.cy, C.L, C.invL);
+    const double dz = min_image(C.com[2 * M + j] - mv.cz, C.L, C.invL);
+    const R4<Real> sj = C.site[3u * j + t];
+    Real px = (Real)dx + sj.x, py = (Real)dy + sj.y, pz = (Real)dz + sj.z;
+    if (!valid) px = Real(1e4);
+    const Real qx0 = px - mv.dlx, qy0 = py - mv.dly, qz0 = pz - mv.dlz;
+    Real d = Real(0);
+    sc = Real(0);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        if (v < mv.nmv) {
+            const R4<Real> o = mv.o[v], n = mv.n[v];
+            const Real rx = px - o.x, ry = py - o.y, rz = pz - o.z;
+            const Real r2 = rx * rx + ry * ry + rz * rz;
+            const Real sg = Real(0.5) * (o.w + sj.w);
+            const Real s2 = sg * sg, rc2 = rc2f * s2;
+            const bool io = r2 < rc2;
+            const Real uo = io ? pair_u(s2, r2) : Real(0);
+            Real r2n;
+            if (mv.flip) {
+                r2n = r2;
+            } else {
+                const Real qx = qx0 - n.x, qy = qy0 - n.y, qz = qz0 - n.z;
+                r2n = qx * qx + qy * qy + qz * qz;
+            }
+            const Real sgn = Real(0.5) * (n.w + sj.w);
+            const Real s2n = sgn * sgn, rc2n = rc2f * s2n;
+            const bool in = r2n < rc2n;
+            const Real un = in ? pair_u(s2n, r2n) : Real(0);
+            d += un - uo;
+            sc += un + uo;
+            inb[2 * v] = io ? 1u : 0u;
+            inb[2 * v + 1] = in ? 1u : 0u;
+        } else {
+            inb[2 * v] = inb[2 * v + 1] = 0u;
+        }
+    }
+    return d;
+}
 
 // All trials of the cells of colour `col` owned by this wave.
+//
+// Per cell: the list of molecules whose centre is within reach of the cell's
+// box is built once (and kept in registers, three entries per lane), and the
+// lanes load the proposals, centres and rotated offsets of the cell's
+// molecules (one lane each).  Per trial, in the cell's ascending order:
+//   1. the lane holding the proposal publishes the moved sites;
+//   2. the near list is pruned against the molecule's centre (FP32 on the
+//      FP16 relative centres, with margins for the trial's own move and for
+//      earlier moves of the same cell) and the survivors are compacted;
+//   3. every site of every survivor takes a lane: the separation of the
+//      centres is formed in FP64 with the nearest image and the site is
+//      evaluated against the moved sites before and after the move (two
+//      64-lane passes issued together);
+//   4. a DPP reduction in FP64 gives dE in a fixed order, Metropolis decides
+//      and the owning lane commits the move.
 template <typename Real, bool kRes>
 __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int col, uint64_t sweep,
-                          double hx, double hy, double hz, const WaveLds<Real>& W,
-                          uint32_t& lane_terms)
+                          double hx, double hy, double hz, const WaveLds<Real>& W, WaveCount& wc)
 {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const uint32_t M = C.M;
@@ -700,8 +784,6 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
     const int nact = na * na * na;
     const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
     const int ncw = nact > wave ? (nact - 1 - wave) / kWaves + 1 : 0;
-    constexpr int kCap = cand_cap(sizeof(Real) == 8);
-    static_assert(kCap >= 64, "a ballot can append 64 candidates");
     const Real rc2f = (Real)C.rc2_factor;
     const bool logging = C.log != nullptr && sweep - C.log_sweep0 < C.log_sweeps;
     const double half_w = 0.5 * C.w;
@@ -712,11 +794,11 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
     const double step = C.dmax * 1.7320508075688772;
     const float prune_r = (float)(reach + 2.0 * step + 0.02);
     // the relative centres are unique images only while the list region stays
-    // below half the box; otherwise every listed molecule goes to the exact test
+    // below half the box; otherwise every listed molecule survives the prune
     // (and FP16 keeps the rounding below the 0.02 margin only up to |r| < 16)
     const bool prune_ok = half_w + (double)prune_r + step < fmin(0.5 * C.L - 1e-3, 16.0);
     const float prune2 = prune_ok ? prune_r * prune_r : 3.0e38f;
-    NearEntry* nlist = (NearEntry*)W.clist;
+    TrialLds<Real>* tr = W.tr;
 
     for (int ci = 0; ci < ncw; ++ci) {
         const int a = wave + kWaves * ci;
@@ -724,250 +806,267 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
         const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
         const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
         if (ccnt == 0) continue;
-        // proposals of the cell's first 64 molecules, one lane each (the load
-        // overlaps the neighbour list build below)
-        PropRec pr;
-        if ((uint32_t)lane < ccnt) pr = props[C.list[cbeg + lane]];
+        const double bx0 = hx + ((double)cx + 0.5) * C.w;
+        const double by0 = hy + ((double)cy + 0.5) * C.w;
+        const double bz0 = hz + ((double)cz + 0.5) * C.w;
 
         // molecules whose centre is within reach of this cell's box, walking
         // the row segments with several lanes per segment
         uint32_t total;
         const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
-        const double bx0 = hx + ((double)cx + 0.5) * C.w;
-        const double by0 = hy + ((double)cy + 0.5) * C.w;
-        const double bz0 = hz + ((double)cz + 0.5) * C.w;
-        const int per = 64 / nseg;  // lanes per segment (nseg <= 50)
-        const int my_seg = lane / per, my_sub = lane - my_seg * per;
-        uint32_t my_lo = 0, my_len = 0, longest = 0;
-        if (my_seg < nseg) {
-            my_lo = W.seglo[my_seg];
-            const uint32_t end = my_seg + 1 < nseg ? (uint32_t)W.segoff[my_seg + 1] : total;
-            my_len = end - (uint32_t)W.segoff[my_seg];
-        }
-        {
-            uint32_t v = my_len;
-#pragma unroll
-            for (int o = 32; o; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o));
-            longest = v;
-        }
         uint32_t nnear = 0;
         bool overflow = false;
-        for (uint32_t t = (uint32_t)my_sub, t0 = 0; t0 < longest; t0 += (uint32_t)per, t += (uint32_t)per) {
-            bool keep = false;
-            uint32_t j = 0;
-            float fx = 0.f, fy = 0.f, fz = 0.f;
-            if (my_seg < nseg && t < my_len) {
-                j = C.list[my_lo + t];
-                const double rx = min_image(C.com[j] - bx0, C.L, C.invL);
-                const double ry = min_image(C.com[M + j] - by0, C.L, C.invL);
-                const double rz = min_image(C.com[2 * M + j] - bz0, C.L, C.invL);
-                const double ex = fmax(fabs(rx) - half_w, 0.0), ey = fmax(fabs(ry) - half_w, 0.0),
-                             ez = fmax(fabs(rz) - half_w, 0.0);
-                keep = ex * ex + ey * ey + ez * ez < reach_box;
-                fx = (float)rx; fy = (float)ry; fz = (float)rz;
+        {
+            const int per = 64 / nseg;  // lanes per segment (nseg <= 50)
+            const int my_seg = lane / per, my_sub = lane - my_seg * per;
+            uint32_t my_lo = 0, my_len = 0;
+            if (my_seg < nseg) {
+                my_lo = W.seglo[my_seg];
+                const uint32_t end = my_seg + 1 < nseg ? (uint32_t)W.segoff[my_seg + 1] : total;
+                my_len = end - (uint32_t)W.segoff[my_seg];
             }
-            const uint64_t bm = __ballot(keep);
-            const uint32_t np = (uint32_t)__popcll(bm);
-            if (nnear + np > kListCap) {
-                overflow = true;
-                break;
+            uint32_t longest = my_len;
+#pragma unroll
+            for (int o = 32; o; o >>= 1) longest = max(longest, (uint32_t)__shfl_xor(longest, o));
+            for (uint32_t t = (uint32_t)my_sub, t0 = 0; t0 < longest; t0 += (uint32_t)per, t += (uint32_t)per) {
+                bool keep = false;
+                uint32_t j = 0;
+                float fx = 0.f, fy = 0.f, fz = 0.f;
+                if (my_seg < nseg && t < my_len) {
+                    j = C.list[my_lo + t];
+                    const double rx = min_image(C.com[j] - bx0, C.L, C.invL);
+                    const double ry = min_image(C.com[M + j] - by0, C.L, C.invL);
+                    const double rz = min_image(C.com[2 * M + j] - bz0, C.L, C.invL);
+                    const double ex = fmax(fabs(rx) - half_w, 0.0), ey = fmax(fabs(ry) - half_w, 0.0),
+                                 ez = fmax(fabs(rz) - half_w, 0.0);
+                    keep = ex * ex + ey * ey + ez * ez < reach_box;
+                    fx = (float)rx; fy = (float)ry; fz = (float)rz;
+                }
+                const uint64_t bm = __ballot(keep);
+                const uint32_t np = (uint32_t)__popcll(bm);
+                if (nnear + np > kListCap) {
+                    overflow = true;
+                    break;
+                }
+                if (keep) {
+                    NearEntry e;
+                    e.j = (uint16_t)j;
+                    e.rx = (__fp16)fx; e.ry = (__fp16)fy; e.rz = (__fp16)fz;
+                    W.near[nnear + rank_below(bm)] = e;
+                }
+                nnear += np;
             }
-            if (keep) {
-                NearEntry e;
-                e.j = (uint16_t)j;
-                e.rx = (__fp16)fx; e.ry = (__fp16)fy; e.rz = (__fp16)fz;
-                nlist[nnear + rank_below(bm)] = e;
-            }
-            nnear += np;
         }
         wave_lds_sync();
-        const uint32_t ncand = overflow ? total : nnear;
-
-        for (uint32_t q = 0; q < ccnt; ++q) {
-            if (q && (q & 63u) == 0) {
-                if ((uint32_t)lane < ccnt - q) pr = props[C.list[cbeg + q + lane]];
+        // the near list in registers: entries lane, lane + 64, lane + 128
+        uint32_t nj[3];
+        float nx[3], ny[3], nz[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t idx = (uint32_t)lane + 64u * c;
+            nj[c] = kNoMolecule;
+            nx[c] = ny[c] = nz[c] = 0.f;
+            if (!overflow && idx < nnear) {
+                const NearEntry e = W.near[idx];
+                nj[c] = e.j;
+                nx[c] = (float)e.rx; ny[c] = (float)e.ry; nz[c] = (float)e.rz;
             }
-            const int i = (int)(q & 63u);
-            const uint32_t m = C.list[cbeg + q];
-            const uint32_t kind = rl_u(pr.kind, i);
-            const uint32_t move = kind & 15u, exited = (kind >> 4) & 1u, axis = kind >> 8;
-            const double thr = rl_d(pr.thr, i);
-            if (lane == 0) W.ws->att[move] += 1;
-            if (exited) {
-                if (lane == 0) {
-                    W.ws->exits += 1;
-                    if (logging) {
+        }
+
+        for (uint32_t q0 = 0; q0 < ccnt; q0 += 64u) {
+            const uint32_t n = min(64u, ccnt - q0);
+            // one lane per molecule: proposal, centre, relative centre and,
+            // for a rotation, the rotated offsets
+            PropRec pr;
+            uint32_t mi = 0;
+            double cmx = 0.0, cmy = 0.0, cmz = 0.0;
+            float mrx = 0.f, mry = 0.f, mrz = 0.f;
+            Real no[9];
+            if ((uint32_t)lane < n) {
+                mi = C.list[cbeg + q0 + lane];
+                pr = props[mi];
+                cmx = C.com[mi]; cmy = C.com[M + mi]; cmz = C.com[2 * M + mi];
+                mrx = (float)min_image(cmx - bx0, C.L, C.invL);
+                mry = (float)min_image(cmy - by0, C.L, C.invL);
+                mrz = (float)min_image(cmz - bz0, C.L, C.invL);
+                if ((pr.kind & 15u) == 1u) {
+                    double rm[9];
+                    rotation(pr.a0, pr.a1, pr.a2, pr.a3, rm);
+#pragma unroll
+                    for (int s = 0; s < 3; ++s) {
+                        const double b0 = body_at(C, s, 0), b1 = body_at(C, s, 1),
+                                     b2 = body_at(C, s, 2);
+                        no[3 * s] = (Real)(rm[0] * b0 + rm[1] * b1 + rm[2] * b2);
+                        no[3 * s + 1] = (Real)(rm[3] * b0 + rm[4] * b1 + rm[5] * b2);
+                        no[3 * s + 2] = (Real)(rm[6] * b0 + rm[7] * b1 + rm[8] * b2);
+                    }
+                }
+            }
+
+            for (uint32_t q = 0; q < n; ++q) {
+                const int i = (int)q;
+                const uint32_t kind = rl_u(pr.kind, i);
+                const uint32_t move = kind & 15u, exited = (kind >> 4) & 1u, axis = kind >> 8;
+                const uint32_t m = rl_u(mi, i);
+                wc.att0 += move == 0u;
+                wc.att1 += move == 1u;
+                wc.att2 += move == 2u;
+                if (exited) {
+                    wc.exits += 1;
+                    if (logging && lane == i) {
                         MoveRecord rec;
-                        rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = thr; rec.sweep = sweep;
+                        rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = pr.thr; rec.sweep = sweep;
                         rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = 0;
                         rec.exited = 1; rec.axis = (uint8_t)axis; rec.pair_terms = 0; rec.pad = 0;
                         C.log[(sweep - C.log_sweep0) * M + m] = rec;
                     }
+                    continue;
                 }
-                continue;
-            }
-            // moved sites: all three, or the two swapped ones of a flip
-            const bool flip = move == 2u;
-            const uint32_t a1 = flip ? (axis + 1) % 3 : 0u, a2 = flip ? (axis + 2) % 3 : 1u;
-            const int nmv = flip ? 2 : 3;
-            const double a0d = rl_d(pr.a0, i), a1d = rl_d(pr.a1, i), a2d = rl_d(pr.a2, i);
-            const double dl0 = move == 0u ? a0d : 0.0, dl1 = move == 0u ? a1d : 0.0,
-                         dl2 = move == 0u ? a2d : 0.0;
-            double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-            if (move == 1u) {
-                q0 = a0d; q1 = a1d; q2 = a2d; q3 = rl_d(pr.a3, i);
-            }
-            if (lane < 3) {
-                const uint32_t sidx = lane == 0 ? a1 : (lane == 1 ? a2 : 2u);
-                const R4<Real> o = C.site[3 * m + sidx];
-                R4<Real> n = o;
-                if (flip) {
-                    n.w = C.site[3 * m + (lane == 0 ? a2 : a1)].w;
-                } else if (move == 1u) {
-                    double rm[9];
-                    rotation(q0, q1, q2, q3, rm);
-                    const double b0 = body_at(C, sidx, 0), b1 = body_at(C, sidx, 1),
-                                 b2 = body_at(C, sidx, 2);
-                    n.x = (Real)(rm[0] * b0 + rm[1] * b1 + rm[2] * b2);
-                    n.y = (Real)(rm[3] * b0 + rm[4] * b1 + rm[5] * b2);
-                    n.z = (Real)(rm[6] * b0 + rm[7] * b1 + rm[8] * b2);
-                }
-                W.ts->old_site[lane] = o;
-                W.ts->new_site[lane] = n;
-            }
-            wave_lds_sync();
-            const Real dlx = (Real)dl0, dly = (Real)dl1, dlz = (Real)dl2;
-            const double cmx = C.com[m], cmy = C.com[M + m], cmz = C.com[2 * M + m];
-            const float mrx = (float)min_image(cmx - bx0, C.L, C.invL);
-            const float mry = (float)min_image(cmy - by0, C.L, C.invL);
-            const float mrz = (float)min_image(cmz - bz0, C.L, C.invL);
-
-            Real acc = Real(0), accs = Real(0);
-            uint64_t ntest = 0;
-            const uint32_t terms_before = logging ? wave_sum_u(lane_terms) : 0u;
-            auto flush = [&](uint32_t nb) __attribute__((always_inline)) {
-                wave_lds_sync();
-                const uint32_t nitems = nb * 3u;
-                ntest += (uint64_t)nitems * (uint32_t)nmv * 2u;
-                for (uint32_t it = (uint32_t)lane; it < nitems; it += 64u) {
-                    const uint32_t cj = it / 3u, t = it - 3u * cj;
-                    const Cand<Real> cd = W.cand[cj];
-                    const R4<Real> sj = C.site[3u * cd.j + t];
-                    const Real bx = cd.x + sj.x, by = cd.y + sj.y, bz = cd.z + sj.z;
-                    const Real qx0 = bx - dlx, qy0 = by - dly, qz0 = bz - dlz;
+                // 1. publish the moved sites: all three, or the two swapped
+                // ones of a flip
+                const bool flip = move == 2u;
+                const uint32_t a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
+                if (lane == i) {
+                    const R4<Real>* sp = C.site + 3 * m;
+                    if (flip) {
+                        const Real x1 = sp[a1].x, y1 = sp[a1].y, z1 = sp[a1].z, w1 = sp[a1].w;
+                        const Real x2 = sp[a2].x, y2 = sp[a2].y, z2 = sp[a2].z, w2 = sp[a2].w;
+                        tr->old_site[0] = R4<Real>{x1, y1, z1, w1};
+                        tr->old_site[1] = R4<Real>{x2, y2, z2, w2};
+                        tr->new_site[0] = R4<Real>{x1, y1, z1, w2};
+                        tr->new_site[1] = R4<Real>{x2, y2, z2, w1};
+                    } else {
 #pragma unroll
-                    for (int v = 0; v < 3; ++v) {
-                        if (v < nmv) {
-                            const R4<Real> o = W.ts->old_site[v], n = W.ts->new_site[v];
-                            const Real rx = bx - o.x, ry = by - o.y, rz = bz - o.z;
-                            const Real r2 = rx * rx + ry * ry + rz * rz;
-                            const Real sg = Real(0.5) * (o.w + sj.w);
-                            const Real s2 = sg * sg, rc2 = rc2f * s2;
-                            const Real uo = r2 < rc2 ? pair_u(s2, r2) : Real(0);
-                            Real r2n;
-                            if (flip) {
-                                r2n = r2;
-                            } else {
-                                const Real qx = qx0 - n.x, qy = qy0 - n.y, qz = qz0 - n.z;
-                                r2n = qx * qx + qy * qy + qz * qz;
+                        for (int s = 0; s < 3; ++s) {
+                            const R4<Real> o = sp[s];
+                            R4<Real> nn = o;
+                            if (move == 1u) {
+                                nn.x = no[3 * s]; nn.y = no[3 * s + 1]; nn.z = no[3 * s + 2];
                             }
-                            const Real sgn = Real(0.5) * (n.w + sj.w);
-                            const Real s2n = sgn * sgn, rc2n = rc2f * s2n;
-                            const Real un = r2n < rc2n ? pair_u(s2n, r2n) : Real(0);
-                            acc += un - uo;
-                            accs += un + uo;
-                            lane_terms += (r2 < rc2 ? 1u : 0u) + (r2n < rc2n ? 1u : 0u);
+                            tr->old_site[s] = o;
+                            tr->new_site[s] = nn;
                         }
                     }
+                    tr->cm[0] = cmx; tr->cm[1] = cmy; tr->cm[2] = cmz;
+                    tr->mr[0] = mrx; tr->mr[1] = mry; tr->mr[2] = mrz;
+                    tr->dl[0] = move == 0u ? (Real)pr.a0 : Real(0);
+                    tr->dl[1] = move == 0u ? (Real)pr.a1 : Real(0);
+                    tr->dl[2] = move == 0u ? (Real)pr.a2 : Real(0);
                 }
                 wave_lds_sync();
-            };
+                Moved<Real> mv;
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    mv.o[s] = tr->old_site[s];
+                    mv.n[s] = tr->new_site[s];
+                }
+                mv.cx = tr->cm[0]; mv.cy = tr->cm[1]; mv.cz = tr->cm[2];
+                mv.dlx = tr->dl[0]; mv.dly = tr->dl[1]; mv.dlz = tr->dl[2];
+                mv.flip = flip;
+                mv.nmv = flip ? 2 : 3;
+                const float tmx = tr->mr[0], tmy = tr->mr[1], tmz = tr->mr[2];
 
-            uint32_t nbuf = 0;
-            for (uint32_t base = 0; base < ncand; base += 64u) {
-                const uint32_t idx = base + (uint32_t)lane;
-                bool pass = false;
-                uint32_t j = 0;
-                double dx = 0.0, dy = 0.0, dz = 0.0;
-                if (idx < ncand) {
-                    bool near = true;
-                    if (overflow) {
-                        j = stencil_molecule(C, W.seglo, W.segoff, nseg, idx);
-                    } else {
-                        const NearEntry e = nlist[idx];
-                        j = e.j;
-                        const float px = (float)e.rx - mrx, py = (float)e.ry - mry, pz = (float)e.rz - mrz;
-                        near = px * px + py * py + pz * pz < prune2;
+                Real acc = Real(0), accs = Real(0);
+                uint32_t terms = 0, tests = 0;
+                // 3. one lane per (survivor, site), two passes at a time
+                auto eval_items = [&](uint32_t nit) __attribute__((always_inline)) {
+                    wave_lds_sync();
+                    tests += nit * (uint32_t)mv.nmv * 2u;
+                    for (uint32_t base = 0; base < nit; base += 128u) {
+                        Real sa, sb;
+                        uint32_t ia[6], ib[6];
+                        const Real da = item_terms(C, W.surv, mv, base + (uint32_t)lane, nit, rc2f, sa, ia);
+                        const Real db = item_terms(C, W.surv, mv, base + 64u + (uint32_t)lane, nit, rc2f, sb, ib);
+                        acc += da + db;
+                        accs += sa + sb;
+#pragma unroll
+                        for (int u = 0; u < 6; ++u)
+                            terms += (uint32_t)__popcll(__ballot(ia[u] != 0u)) +
+                                     (uint32_t)__popcll(__ballot(ib[u] != 0u));
                     }
-                    if (near && j != m) {
-                        dx = min_image(C.com[j] - cmx, C.L, C.invL);
-                        dy = min_image(C.com[M + j] - cmy, C.L, C.invL);
-                        dz = min_image(C.com[2 * M + j] - cmz, C.L, C.invL);
-                        const double r2o = dx * dx + dy * dy + dz * dz;
-                        const double ex = dx - dl0, ey = dy - dl1, ez = dz - dl2;
-                        const double r2n = ex * ex + ey * ey + ez * ez;
-                        pass = (r2o < C.reach2) || (r2n < C.reach2);
-                    }
-                }
-                const uint64_t bm = __ballot(pass);
-                const uint32_t np = (uint32_t)__popcll(bm);
-                if (nbuf + np > (uint32_t)kCap) {
-                    flush(nbuf);
-                    nbuf = 0;
-                }
-                if (pass) {
-                    Cand<Real> cd;
-                    cd.x = (Real)dx; cd.y = (Real)dy; cd.z = (Real)dz; cd.j = j;
-                    W.cand[nbuf + rank_below(bm)] = cd;
-                }
-                nbuf += np;
-            }
-            if (nbuf) flush(nbuf);
+                };
 
-            const double de = wave_sum_dpp((double)acc);
-            const bool accept = (de <= 0.0) || (thr < -de);
-            double sc = 0.0;
-            uint32_t terms = 0;
-            if (logging) {
-                sc = wave_sum_dpp((double)accs);
-                terms = wave_sum_u(lane_terms) - terms_before;
-            }
-            if (lane == 0) {
-                W.ws->tests += ntest;
+                // 2. prune and compact the survivors
+                if (!overflow) {
+                    uint32_t nsurv = 0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float px = nx[c] - tmx, py = ny[c] - tmy, pz = nz[c] - tmz;
+                        const bool keep = nj[c] != kNoMolecule && nj[c] != m &&
+                                          px * px + py * py + pz * pz < prune2;
+                        const uint64_t bm = __ballot(keep);
+                        if (keep) W.surv[nsurv + rank_below(bm)] = (uint16_t)nj[c];
+                        nsurv += (uint32_t)__popcll(bm);
+                    }
+                    if (nsurv) eval_items(3u * nsurv);
+                } else {
+                    // list overflow: every stencil molecule, 64 at a time
+                    for (uint32_t base = 0; base < total; base += 64u) {
+                        const uint32_t idx = base + (uint32_t)lane;
+                        uint32_t j = kNoMolecule;
+                        if (idx < total) j = stencil_molecule(C, W.seglo, W.segoff, nseg, idx);
+                        const bool keep = j != kNoMolecule && j != m;
+                        const uint64_t bm = __ballot(keep);
+                        wave_lds_sync();
+                        if (keep) W.surv[rank_below(bm)] = (uint16_t)j;
+                        const uint32_t ns = (uint32_t)__popcll(bm);
+                        if (ns) eval_items(3u * ns);
+                    }
+                }
+
+                // 4. Metropolis on the FP64 sum
+                const double de = wave_sum_dpp((double)acc);
+                const double thr = rl_d(pr.thr, i);
+                const bool accept = (de <= 0.0) || (thr < -de);
+                double sc = 0.0;
+                if (logging) sc = wave_sum_dpp((double)accs);
+                wc.terms += terms;
+                wc.tests += tests;
                 if (accept) {
-                    W.ws->acc[move] += 1;
-                    W.ws->e += de;
-                    if (move == 0u) {
-                        C.com[m] = wrap(cmx + dl0, C.L);
-                        C.com[M + m] = wrap(cmy + dl1, C.L);
-                        C.com[2 * M + m] = wrap(cmz + dl2, C.L);
-                    } else if (move == 1u) {
-                        C.site[3 * m] = W.ts->new_site[0];
-                        C.site[3 * m + 1] = W.ts->new_site[1];
-                        C.site[3 * m + 2] = W.ts->new_site[2];
-                        C.quat[m] = q0;
-                        C.quat[M + m] = q1;
-                        C.quat[2 * M + m] = q2;
-                        C.quat[3 * M + m] = q3;
-                    } else {
-                        C.site[3 * m + a1].w = W.ts->new_site[0].w;
-                        C.site[3 * m + a2].w = W.ts->new_site[1].w;
-                        const uint32_t ty = C.types[m];
-                        const uint32_t t1 = (ty >> (8 * a1)) & 0xFFu, t2 = (ty >> (8 * a2)) & 0xFFu;
-                        uint32_t nt = ty & ~((0xFFu << (8 * a1)) | (0xFFu << (8 * a2)));
-                        nt |= (t2 << (8 * a1)) | (t1 << (8 * a2));
-                        C.types[m] = nt;
+                    wc.acc0 += move == 0u;
+                    wc.acc1 += move == 1u;
+                    wc.acc2 += move == 2u;
+                    wc.e += de;
+                }
+                if (lane == i) {
+                    if (accept) {
+                        R4<Real>* sp = C.site + 3 * m;
+                        if (move == 0u) {
+                            C.com[m] = wrap(cmx + pr.a0, C.L);
+                            C.com[M + m] = wrap(cmy + pr.a1, C.L);
+                            C.com[2 * M + m] = wrap(cmz + pr.a2, C.L);
+                        } else if (move == 1u) {
+#pragma unroll
+                            for (int s = 0; s < 3; ++s) {
+                                sp[s].x = no[3 * s];
+                                sp[s].y = no[3 * s + 1];
+                                sp[s].z = no[3 * s + 2];
+                            }
+                            C.quat[m] = pr.a0;
+                            C.quat[M + m] = pr.a1;
+                            C.quat[2 * M + m] = pr.a2;
+                            C.quat[3 * M + m] = pr.a3;
+                        } else {
+                            const Real w1 = sp[a1].w, w2 = sp[a2].w;
+                            sp[a1].w = w2;
+                            sp[a2].w = w1;
+                            const uint32_t ty = C.types[m];
+                            const uint32_t t1 = (ty >> (8 * a1)) & 0xFFu, t2 = (ty >> (8 * a2)) & 0xFFu;
+                            uint32_t nt = ty & ~((0xFFu << (8 * a1)) | (0xFFu << (8 * a2)));
+                            nt |= (t2 << (8 * a1)) | (t1 << (8 * a2));
+                            C.types[m] = nt;
+                        }
+                    }
+                    if (logging) {
+                        MoveRecord rec;
+                        rec.delta_e = de; rec.scale = sc; rec.t_log_u = thr; rec.sweep = sweep;
+                        rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = accept ? 1 : 0;
+                        rec.exited = 0; rec.axis = (uint8_t)axis; rec.pair_terms = terms; rec.pad = 0;
+                        C.log[(sweep - C.log_sweep0) * M + m] = rec;
                     }
                 }
-                if (logging) {
-                    MoveRecord rec;
-                    rec.delta_e = de; rec.scale = sc; rec.t_log_u = thr; rec.sweep = sweep;
-                    rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = accept ? 1 : 0;
-                    rec.exited = 0; rec.axis = (uint8_t)axis; rec.pair_terms = terms; rec.pad = 0;
-                    C.log[(sweep - C.log_sweep0) * M + m] = rec;
-                }
+                wave_lds_sync();
             }
-            wave_lds_sync();
         }
     }
 }
@@ -1030,12 +1129,11 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
         C.list = g_list;
     }
     WaveLds<Real> W;
-    W.cand = (Cand<Real>*)(smem + L.cand) + wave * cand_cap(fp64);
+    W.surv = (uint16_t*)(smem + L.surv) + wave * kCellListCap;
     W.seglo = (uint16_t*)(smem + L.seglo) + wave * kMaxSeg;
     W.segoff = (uint16_t*)(smem + L.segoff) + wave * kMaxSeg;
-    W.clist = (uint16_t*)(smem + L.clist + (size_t)wave * kListCap * sizeof(NearEntry));
-    W.ts = (TrialSites<Real>*)(smem + L.tsite) + wave;
-    W.ws = (WaveStats*)(smem + L.wstat) + wave;
+    W.near = (NearEntry*)(smem + L.near) + wave * kListCap;
+    W.tr = (TrialLds<Real>*)(smem + L.trial + (size_t)wave * trial_bytes(fp64));
     PropRec* props = (PropRec*)Dp->props;
     uint32_t* uscratch = (uint32_t*)(C.misc + 8);
     const uint32_t M = C.M;
@@ -1051,13 +1149,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
     if (kRes)
         for (uint32_t i = tid; i < 3 * M; i += kThreads) C.com[i] = C.gcom[i];
     for (uint32_t m = tid; m < M; m += kThreads) store_sites_from_quat(C, m);
-    WaveStats* ws = W.ws;
-    uint32_t lane_terms = 0;
-    if (lane == 0) {
-        for (int i = 0; i < 3; ++i) ws->att[i] = ws->acc[i] = 0;
-        ws->exits = ws->terms = ws->tests = 0;
-        ws->e = 0.0;
-    }
+    WaveCount wc{};
     uint64_t sweep = st->sweep;
     const uint64_t origin = st->obs_origin;
     __syncthreads();
@@ -1072,14 +1164,12 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
         propose_all(C, props, sweep, hx, hy, hz);
         __syncthreads();
         for (int col = 0; col < ncol; ++col) {
-            run_phase(C, props, col, sweep, hx, hy, hz, W, lane_terms);
+            run_phase(C, props, col, sweep, hx, hy, hz, W, wc);
             __syncthreads();
         }
         // accumulated energy in a fixed wave order; E/M samples
-        if (lane == 0) {
-            C.wpart[wave] = ws->e;
-            ws->e = 0.0;
-        }
+        if (lane == 0) C.wpart[wave] = wc.e;
+        wc.e = 0.0;
         ++sweep;
         __syncthreads();
         if (tid == 0) {
@@ -1100,18 +1190,16 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
     // write back
     if (kRes)
         for (uint32_t i = tid; i < 3 * M; i += kThreads) C.gcom[i] = C.com[i];
-    uint64_t wt = lane_terms;
-#pragma unroll
-    for (int o = 32; o; o >>= 1) wt += __shfl_xor(wt, o);
-    if (lane == 0) ws->terms += wt;
     if (lane == 0) {
+        const uint64_t att[3] = {wc.att0, wc.att1, wc.att2}, acc[3] = {wc.acc0, wc.acc1, wc.acc2};
+#pragma unroll
         for (int i = 0; i < 3; ++i) {
-            if (ws->att[i]) atomicAdd((unsigned long long*)&st->attempts[i], (unsigned long long)ws->att[i]);
-            if (ws->acc[i]) atomicAdd((unsigned long long*)&st->accepts[i], (unsigned long long)ws->acc[i]);
+            if (att[i]) atomicAdd((unsigned long long*)&st->attempts[i], (unsigned long long)att[i]);
+            if (acc[i]) atomicAdd((unsigned long long*)&st->accepts[i], (unsigned long long)acc[i]);
         }
-        if (ws->exits) atomicAdd((unsigned long long*)&st->exits, (unsigned long long)ws->exits);
-        if (ws->terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)ws->terms);
-        if (ws->tests) atomicAdd((unsigned long long*)&st->pair_tests, (unsigned long long)ws->tests);
+        if (wc.exits) atomicAdd((unsigned long long*)&st->exits, (unsigned long long)wc.exits);
+        if (wc.terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)wc.terms);
+        if (wc.tests) atomicAdd((unsigned long long*)&st->pair_tests, (unsigned long long)wc.tests);
     }
     __syncthreads();
     if (tid == 0) {
