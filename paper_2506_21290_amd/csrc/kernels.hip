@@ -703,59 +703,81 @@ struct Moved {
     bool flip;
 };
 
-// Pair terms of one candidate item: site t of survivor s (it = 3 s + t) with
-// the moved sites before and after the move (Eq. 1 within each pair's
-// cut-off).  Returns u_new - u_old (0 for it >= nit); *sc gets u_new + u_old,
-// *in_o / *in_n the cut-off tests.
-template <typename Real, bool kRes>
-__device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const uint16_t* surv,
-                                           const Moved<Real>& mv, uint32_t it, uint32_t nit,
-                                           Real rc2f, Real& sc, uint32_t (&inb)[6])
+// Pair terms of one candidate item (a site of a survivor, with the survivor's
+// centre and the site's offset already loaded) with the moved sites before and
+// after a move of kind kMove (0 translation, 1 rotation, 2 flip): Eq. (1)
+// within each pair's cut-off.  Returns u_new - u_old (0 for an invalid item);
+// sc gets u_new + u_old; terms counts the pairs inside the cut-off over the
+// wave (popcounts of the compare masks).
+template <int kMove, typename Real, bool kRes>
+__device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const Moved<Real>& mv,
+                                           double jx, double jy, double jz, const R4<Real>& sj,
+                                           bool valid, Real rc2f, Real& sc, uint32_t& terms)
 {
-    const bool valid = it < nit;
-    const uint32_t itc = valid ? it : 0u;
-    const uint32_t s = itc / 3u, t = itc - 3u * s;
-    const uint32_t j = surv[s];
-    const uint32_t M = C.M;
-    const double dx = min_image(C.com[j] - mv.cx, C.L, C.invL);
-    const double dy = min_image(C.com[M + j] - mv.cy, C.L, C.invL);
-    const double dz = min_image(C.com[2 * M + j] - mv.cz, C.L, C.invL);
-    const R4<Real> sj = C.site[3u * j + t];
+    const double dx = fma(-C.L, rint((jx - mv.cx) * C.invL), jx - mv.cx);
+    const double dy = fma(-C.L, rint((jy - mv.cy) * C.invL), jy - mv.cy);
+    const double dz = fma(-C.L, rint((jz - mv.cz) * C.invL), jz - mv.cz);
     Real px = (Real)dx + sj.x, py = (Real)dy + sj.y, pz = (Real)dz + sj.z;
     if (!valid) px = Real(1e4);
-    const Real qx0 = px - mv.dlx, qy0 = py - mv.dly, qz0 = pz - mv.dlz;
     Real d = Real(0);
     sc = Real(0);
+    constexpr int kNmv = kMove == 2 ? 2 : 3;
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-        if (v < mv.nmv) {
-            const R4<Real> o = mv.o[v], n = mv.n[v];
-            const Real rx = px - o.x, ry = py - o.y, rz = pz - o.z;
-            const Real r2 = rx * rx + ry * ry + rz * rz;
-            const Real sg = Real(0.5) * (o.w + sj.w);
-            const Real s2 = sg * sg, rc2 = rc2f * s2;
-            const bool io = r2 < rc2;
-            const Real uo = io ? pair_u(s2, r2) : Real(0);
-            Real r2n;
-            if (mv.flip) {
-                r2n = r2;
-            } else {
-                const Real qx = qx0 - n.x, qy = qy0 - n.y, qz = qz0 - n.z;
-                r2n = qx * qx + qy * qy + qz * qz;
-            }
-            const Real sgn = Real(0.5) * (n.w + sj.w);
-            const Real s2n = sgn * sgn, rc2n = rc2f * s2n;
-            const bool in = r2n < rc2n;
-            const Real un = in ? pair_u(s2n, r2n) : Real(0);
-            d += un - uo;
-            sc += un + uo;
-            inb[2 * v] = io ? 1u : 0u;
-            inb[2 * v + 1] = in ? 1u : 0u;
-        } else {
-            inb[2 * v] = inb[2 * v + 1] = 0u;
+    for (int v = 0; v < kNmv; ++v) {
+        const R4<Real> o = mv.o[v];
+        const Real rx = px - o.x, ry = py - o.y, rz = pz - o.z;
+        const Real r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+        const Real sg = Real(0.5) * (o.w + sj.w);
+        const Real s2 = sg * sg, rc2 = rc2f * s2;
+        const bool io = r2 < rc2;
+        const Real uo = io ? pair_u(s2, r2) : Real(0);
+        Real r2n, s2n, rc2n;
+        if (kMove == 0) {  // same offsets about the displaced centre
+            const Real qx = rx - mv.dlx, qy = ry - mv.dly, qz = rz - mv.dlz;
+            r2n = fma(qx, qx, fma(qy, qy, qz * qz));
+            s2n = s2; rc2n = rc2;
+        } else if (kMove == 1) {  // rotated offsets about the same centre
+            const R4<Real> n = mv.n[v];
+            const Real qx = px - n.x, qy = py - n.y, qz = pz - n.z;
+            r2n = fma(qx, qx, fma(qy, qy, qz * qz));
+            s2n = s2; rc2n = rc2;
+        } else {  // same position, swapped type
+            const Real sgn = Real(0.5) * (mv.n[v].w + sj.w);
+            r2n = r2;
+            s2n = sgn * sgn; rc2n = rc2f * s2n;
         }
+        const bool in = r2n < rc2n;
+        const Real un = in ? pair_u(s2n, r2n) : Real(0);
+        d += un - uo;
+        sc += un + uo;
+        terms += (uint32_t)__popcll(__ballot(io)) + (uint32_t)__popcll(__ballot(in));
     }
     return d;
+}
+
+// One step of the item loop: items base + lane and base + 64 + lane, with the
+// loads of both passes issued before any arithmetic.
+template <int kMove, typename Real, bool kRes>
+__device__ __forceinline__ void item_pair_pass(const Ctx<Real, kRes>& C, const uint16_t* surv,
+                                               const Moved<Real>& mv, uint32_t base, uint32_t nit,
+                                               Real rc2f, Real& acc, Real& accs, uint32_t& terms)
+{
+    const uint32_t M = C.M;
+    const uint32_t itA = base + (uint32_t)__lane_id(), itB = itA + 64u;
+    const bool vA = itA < nit, vB = itB < nit;
+    const uint32_t cA = vA ? itA : 0u, cB = vB ? itB : 0u;
+    const uint32_t sA = cA / 3u, sB = cB / 3u;
+    const uint32_t tA = cA - 3u * sA, tB = cB - 3u * sB;
+    const uint32_t jA = surv[sA], jB = surv[sB];
+    const double xA = C.com[jA], yA = C.com[M + jA], zA = C.com[2 * M + jA];
+    const double xB = C.com[jB], yB = C.com[M + jB], zB = C.com[2 * M + jB];
+    const R4<Real> gA = C.site[3u * jA + tA], gB = C.site[3u * jB + tB];
+    __builtin_amdgcn_sched_barrier(0);
+    Real sa, sb;
+    const Real da = item_terms<kMove>(C, mv, xA, yA, zA, gA, vA, rc2f, sa, terms);
+    const Real db = item_terms<kMove>(C, mv, xB, yB, zB, gB, vB, rc2f, sb, terms);
+    acc += da + db;
+    accs += sa + sb;
 }
 
 // All trials of the cells of colour `col` owned by this wave.
@@ -965,6 +987,7 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
                 mv.flip = flip;
                 mv.nmv = flip ? 2 : 3;
                 const float tmx = tr->mr[0], tmy = tr->mr[1], tmz = tr->mr[2];
+                __builtin_amdgcn_sched_barrier(0);
 
                 Real acc = Real(0), accs = Real(0);
                 uint32_t terms = 0, tests = 0;
@@ -973,16 +996,12 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
                     wave_lds_sync();
                     tests += nit * (uint32_t)mv.nmv * 2u;
                     for (uint32_t base = 0; base < nit; base += 128u) {
-                        Real sa, sb;
-                        uint32_t ia[6], ib[6];
-                        const Real da = item_terms(C, W.surv, mv, base + (uint32_t)lane, nit, rc2f, sa, ia);
-                        const Real db = item_terms(C, W.surv, mv, base + 64u + (uint32_t)lane, nit, rc2f, sb, ib);
-                        acc += da + db;
-                        accs += sa + sb;
-#pragma unroll
-                        for (int u = 0; u < 6; ++u)
-                            terms += (uint32_t)__popcll(__ballot(ia[u] != 0u)) +
-                                     (uint32_t)__popcll(__ballot(ib[u] != 0u));
+                        if (move == 0u)
+                            item_pair_pass<0>(C, W.surv, mv, base, nit, rc2f, acc, accs, terms);
+                        else if (move == 1u)
+                            item_pair_pass<1>(C, W.surv, mv, base, nit, rc2f, acc, accs, terms);
+                        else
+                            item_pair_pass<2>(C, W.surv, mv, base, nit, rc2f, acc, accs, terms);
                     }
                 };
 
