@@ -709,7 +709,7 @@ struct Moved {
 // within each pair's cut-off.  Returns u_new - u_old (0 for an invalid item);
 // sc gets u_new + u_old; terms counts the pairs inside the cut-off over the
 // wave (popcounts of the compare masks).
-template <int kMove, typename Real, bool kRes>
+template <int kMove, bool kLog, typename Real, bool kRes>
 __device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const Moved<Real>& mv,
                                            double jx, double jy, double jz, const R4<Real>& sj,
                                            bool valid, Real rc2f, Real& sc, uint32_t& terms)
@@ -749,7 +749,7 @@ __device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const Moved
         const bool in = r2n < rc2n;
         const Real un = in ? pair_u(s2n, r2n) : Real(0);
         d += un - uo;
-        sc += un + uo;
+        if (kLog) sc += un + uo;
         terms += (uint32_t)__popcll(__ballot(io)) + (uint32_t)__popcll(__ballot(in));
     }
     return d;
@@ -757,10 +757,16 @@ __device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const Moved
 
 // One step of the item loop: items base + lane and base + 64 + lane, with the
 // loads of both passes issued before any arithmetic.
-template <int kMove, typename Real, bool kRes>
-__device__ __forceinline__ void item_pair_pass(const Ctx<Real, kRes>& C, const uint16_t* surv,
-                                               const Moved<Real>& mv, uint32_t base, uint32_t nit,
-                                               Real rc2f, Real& acc, Real& accs, uint32_t& terms)
+template <typename Real>
+struct PassSum {
+    Real d, s;       // sum of u_new - u_old, of u_new + u_old
+    uint32_t terms;  // pairs inside the cut-off (wave total)
+};
+
+template <int kMove, bool kLog, typename Real, bool kRes>
+__device__ __forceinline__ PassSum<Real> item_pair_pass(const Ctx<Real, kRes>& C,
+                                                        const uint16_t* surv, const Moved<Real>& mv,
+                                                        uint32_t base, uint32_t nit, Real rc2f)
 {
     const uint32_t M = C.M;
     const uint32_t itA = base + (uint32_t)__lane_id(), itB = itA + 64u;
@@ -773,11 +779,11 @@ __device__ __forceinline__ void item_pair_pass(const Ctx<Real, kRes>& C, const u
     const double xB = C.com[jB], yB = C.com[M + jB], zB = C.com[2 * M + jB];
     const R4<Real> gA = C.site[3u * jA + tA], gB = C.site[3u * jB + tB];
     __builtin_amdgcn_sched_barrier(0);
-    Real sa, sb;
-    const Real da = item_terms<kMove>(C, mv, xA, yA, zA, gA, vA, rc2f, sa, terms);
-    const Real db = item_terms<kMove>(C, mv, xB, yB, zB, gB, vB, rc2f, sb, terms);
-    acc += da + db;
-    accs += sa + sb;
+    Real sa = Real(0), sb = Real(0);
+    uint32_t terms = 0;
+    const Real da = item_terms<kMove, kLog>(C, mv, xA, yA, zA, gA, vA, rc2f, sa, terms);
+    const Real db = item_terms<kMove, kLog>(C, mv, xB, yB, zB, gB, vB, rc2f, sb, terms);
+    return PassSum<Real>{da + db, sa + sb, terms};
 }
 
 // All trials of the cells of colour `col` owned by this wave.
@@ -850,33 +856,46 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
             uint32_t longest = my_len;
 #pragma unroll
             for (int o = 32; o; o >>= 1) longest = max(longest, (uint32_t)__shfl_xor(longest, o));
-            for (uint32_t t = (uint32_t)my_sub, t0 = 0; t0 < longest; t0 += (uint32_t)per, t += (uint32_t)per) {
-                bool keep = false;
-                uint32_t j = 0;
-                float fx = 0.f, fy = 0.f, fz = 0.f;
-                if (my_seg < nseg && t < my_len) {
-                    j = C.list[my_lo + t];
-                    const double rx = min_image(C.com[j] - bx0, C.L, C.invL);
-                    const double ry = min_image(C.com[M + j] - by0, C.L, C.invL);
-                    const double rz = min_image(C.com[2 * M + j] - bz0, C.L, C.invL);
-                    const double ex = fmax(fabs(rx) - half_w, 0.0), ey = fmax(fabs(ry) - half_w, 0.0),
-                                 ez = fmax(fabs(rz) - half_w, 0.0);
-                    keep = ex * ex + ey * ey + ez * ez < reach_box;
-                    fx = (float)rx; fy = (float)ry; fz = (float)rz;
-                }
-                const uint64_t bm = __ballot(keep);
-                const uint32_t np = (uint32_t)__popcll(bm);
-                if (nnear + np > kListCap) {
+            // two molecules per lane and step, loads issued before arithmetic
+            const bool seg_ok = my_seg < nseg;
+            const uint32_t step2 = 2u * (uint32_t)per;
+            for (uint32_t t0 = 0; t0 < longest; t0 += step2) {
+                const uint32_t tA = t0 + (uint32_t)my_sub, tB = tA + (uint32_t)per;
+                const bool vA = seg_ok && tA < my_len, vB = seg_ok && tB < my_len;
+                const uint32_t jA = C.list[vA ? my_lo + tA : 0u];
+                const uint32_t jB = C.list[vB ? my_lo + tB : 0u];
+                const double xA = C.com[jA], yA = C.com[M + jA], zA = C.com[2 * M + jA];
+                const double xB = C.com[jB], yB = C.com[M + jB], zB = C.com[2 * M + jB];
+                __builtin_amdgcn_sched_barrier(0);
+                double rxA = min_image(xA - bx0, C.L, C.invL), ryA = min_image(yA - by0, C.L, C.invL),
+                       rzA = min_image(zA - bz0, C.L, C.invL);
+                double rxB = min_image(xB - bx0, C.L, C.invL), ryB = min_image(yB - by0, C.L, C.invL),
+                       rzB = min_image(zB - bz0, C.L, C.invL);
+                const double exA = fmax(fabs(rxA) - half_w, 0.0), eyA = fmax(fabs(ryA) - half_w, 0.0),
+                             ezA = fmax(fabs(rzA) - half_w, 0.0);
+                const double exB = fmax(fabs(rxB) - half_w, 0.0), eyB = fmax(fabs(ryB) - half_w, 0.0),
+                             ezB = fmax(fabs(rzB) - half_w, 0.0);
+                const bool keepA = vA && exA * exA + eyA * eyA + ezA * ezA < reach_box;
+                const bool keepB = vB && exB * exB + eyB * eyB + ezB * ezB < reach_box;
+                const uint64_t bmA = __ballot(keepA), bmB = __ballot(keepB);
+                const uint32_t npA = (uint32_t)__popcll(bmA), npB = (uint32_t)__popcll(bmB);
+                if (nnear + npA + npB > kListCap) {
                     overflow = true;
                     break;
                 }
-                if (keep) {
+                if (keepA) {
                     NearEntry e;
-                    e.j = (uint16_t)j;
-                    e.rx = (__fp16)fx; e.ry = (__fp16)fy; e.rz = (__fp16)fz;
-                    W.near[nnear + rank_below(bm)] = e;
+                    e.j = (uint16_t)jA;
+                    e.rx = (__fp16)(float)rxA; e.ry = (__fp16)(float)ryA; e.rz = (__fp16)(float)rzA;
+                    W.near[nnear + rank_below(bmA)] = e;
                 }
-                nnear += np;
+                if (keepB) {
+                    NearEntry e;
+                    e.j = (uint16_t)jB;
+                    e.rx = (__fp16)(float)rxB; e.ry = (__fp16)(float)ryB; e.rz = (__fp16)(float)rzB;
+                    W.near[nnear + npA + rank_below(bmB)] = e;
+                }
+                nnear += npA + npB;
             }
         }
         wave_lds_sync();
@@ -904,10 +923,12 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
             double cmx = 0.0, cmy = 0.0, cmz = 0.0;
             float mrx = 0.f, mry = 0.f, mrz = 0.f;
             Real no[9];
+            R4<Real> os0{}, os1{}, os2{};  // the molecule's sites before its trial
             if ((uint32_t)lane < n) {
                 mi = C.list[cbeg + q0 + lane];
                 pr = props[mi];
                 cmx = C.com[mi]; cmy = C.com[M + mi]; cmz = C.com[2 * M + mi];
+                os0 = C.site[3 * mi]; os1 = C.site[3 * mi + 1]; os2 = C.site[3 * mi + 2];
                 mrx = (float)min_image(cmx - bx0, C.L, C.invL);
                 mry = (float)min_image(cmy - by0, C.L, C.invL);
                 mrz = (float)min_image(cmz - bz0, C.L, C.invL);
@@ -949,24 +970,25 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
                 const bool flip = move == 2u;
                 const uint32_t a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
                 if (lane == i) {
-                    const R4<Real>* sp = C.site + 3 * m;
                     if (flip) {
-                        const Real x1 = sp[a1].x, y1 = sp[a1].y, z1 = sp[a1].z, w1 = sp[a1].w;
-                        const Real x2 = sp[a2].x, y2 = sp[a2].y, z2 = sp[a2].z, w2 = sp[a2].w;
-                        tr->old_site[0] = R4<Real>{x1, y1, z1, w1};
-                        tr->old_site[1] = R4<Real>{x2, y2, z2, w2};
-                        tr->new_site[0] = R4<Real>{x1, y1, z1, w2};
-                        tr->new_site[1] = R4<Real>{x2, y2, z2, w1};
+                        const R4<Real> x1 = a1 == 0u ? os0 : (a1 == 1u ? os1 : os2);
+                        const R4<Real> x2 = a2 == 0u ? os0 : (a2 == 1u ? os1 : os2);
+                        tr->old_site[0] = x1;
+                        tr->old_site[1] = x2;
+                        tr->new_site[0] = R4<Real>{x1.x, x1.y, x1.z, x2.w};
+                        tr->new_site[1] = R4<Real>{x2.x, x2.y, x2.z, x1.w};
                     } else {
-#pragma unroll
-                        for (int s = 0; s < 3; ++s) {
-                            const R4<Real> o = sp[s];
-                            R4<Real> nn = o;
-                            if (move == 1u) {
-                                nn.x = no[3 * s]; nn.y = no[3 * s + 1]; nn.z = no[3 * s + 2];
-                            }
-                            tr->old_site[s] = o;
-                            tr->new_site[s] = nn;
+                        tr->old_site[0] = os0;
+                        tr->old_site[1] = os1;
+                        tr->old_site[2] = os2;
+                        if (move == 1u) {
+                            tr->new_site[0] = R4<Real>{no[0], no[1], no[2], os0.w};
+                            tr->new_site[1] = R4<Real>{no[3], no[4], no[5], os1.w};
+                            tr->new_site[2] = R4<Real>{no[6], no[7], no[8], os2.w};
+                        } else {
+                            tr->new_site[0] = os0;
+                            tr->new_site[1] = os1;
+                            tr->new_site[2] = os2;
                         }
                     }
                     tr->cm[0] = cmx; tr->cm[1] = cmy; tr->cm[2] = cmz;
@@ -996,12 +1018,25 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
                     wave_lds_sync();
                     tests += nit * (uint32_t)mv.nmv * 2u;
                     for (uint32_t base = 0; base < nit; base += 128u) {
-                        if (move == 0u)
-                            item_pair_pass<0>(C, W.surv, mv, base, nit, rc2f, acc, accs, terms);
-                        else if (move == 1u)
-                            item_pair_pass<1>(C, W.surv, mv, base, nit, rc2f, acc, accs, terms);
-                        else
-                            item_pair_pass<2>(C, W.surv, mv, base, nit, rc2f, acc, accs, terms);
+                        PassSum<Real> ps;
+                        if (logging) {
+                            if (move == 0u)
+                                ps = item_pair_pass<0, true>(C, W.surv, mv, base, nit, rc2f);
+                            else if (move == 1u)
+                                ps = item_pair_pass<1, true>(C, W.surv, mv, base, nit, rc2f);
+                            else
+                                ps = item_pair_pass<2, true>(C, W.surv, mv, base, nit, rc2f);
+                        } else {
+                            if (move == 0u)
+                                ps = item_pair_pass<0, false>(C, W.surv, mv, base, nit, rc2f);
+                            else if (move == 1u)
+                                ps = item_pair_pass<1, false>(C, W.surv, mv, base, nit, rc2f);
+                            else
+                                ps = item_pair_pass<2, false>(C, W.surv, mv, base, nit, rc2f);
+                        }
+                        acc += ps.d;
+                        accs += ps.s;
+                        terms += ps.terms;
                     }
                 };
 
