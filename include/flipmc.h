@@ -51,9 +51,16 @@ enum { MC_FP64 = 0, MC_FP32_DE = 1 };
 
 enum { MC_TRANSLATE = 0, MC_ROTATE = 1, MC_FLIP = 2 };
 
-/* mc_params.flags: keep the working arrays in HBM even when the system would
- * fit in one workgroup's LDS (the path large systems take). */
-enum { MC_FLAG_HBM_STATE = 1 };
+/* mc_params.flags: MC_FLAG_HBM_STATE keeps the working arrays in HBM even
+ * when the system would fit in one workgroup's LDS; MC_FLAG_SINGLE_WORKGROUP
+ * runs a system whose arrays stay in HBM on one workgroup (as inside a
+ * batch) instead of the multi-workgroup engine. */
+enum { MC_FLAG_HBM_STATE = 1, MC_FLAG_SINGLE_WORKGROUP = 2 };
+
+/* Engines (mc_engine): one workgroup with the state in LDS, one workgroup
+ * with the state in HBM, many workgroups in one cooperative launch with the
+ * state in HBM and each cell's neighbourhood staged in LDS. */
+enum { MC_ENGINE_LDS = 0, MC_ENGINE_HBM = 1, MC_ENGINE_SPREAD = 2 };
 
 #define MC_GOFR_MAX_BINS 256
 #define MC_C2_MAX 32
@@ -151,6 +158,12 @@ int mc_geometry(const mc_params* p, double* box, uint32_t* colours_per_axis,
  * when they fit in one workgroup's LDS (then *lds_bytes of dynamic LDS per
  * launch), 0 when they stay in HBM.  Either output may be NULL. */
 int mc_placement(const mc_params* p, int* resident, size_t* lds_bytes);
+
+/* The engine mc_sweep uses for a system with these parameters (MC_ENGINE_*)
+ * and, for MC_ENGINE_SPREAD, the number of workgroups of its launches
+ * (*workgroups = 1 otherwise).  Systems inside a batch always run on one
+ * workgroup each.  Either output may be NULL. */
+int mc_engine(const mc_params* p, int* engine, uint32_t* workgroups);
 
 /* Bytes of device memory mc_init_system needs for these parameters. */
 int mc_required_bytes(const mc_params* p, size_t* bytes);

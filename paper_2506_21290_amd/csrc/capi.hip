@@ -3,6 +3,7 @@
 // Validates parameters, lays the system out in the caller's device buffer,
 // fills the device descriptor (SysDev) and enqueues the kernels of
 // kernels.hip on the caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -76,6 +77,8 @@ struct Geometry {
     double L, bond, radius, reach;
     uint32_t k, nc, ncell;
     bool resident;
+    bool spread;          // standalone sweeps on the multi-workgroup engine
+    uint32_t spread_blocks;
     size_t lds;
 };
 
@@ -157,12 +160,35 @@ int geometry(const mc_params* p, Geometry* g)
     const LdsLayout res = lds_layout(fp64, true, p->n_molecules, g->ncell);
     g->resident = res.total <= limit && !(p->flags & MC_FLAG_HBM_STATE);
     g->lds = g->resident ? res.total : lds_layout(fp64, false, p->n_molecules, g->ncell).total;
+    g->spread = !g->resident && !(p->flags & MC_FLAG_SINGLE_WORKGROUP);
+    g->spread_blocks = 1;
+    if (g->spread) {
+        // one wave per cell of a colour, within one cooperative wave of the device
+        uint32_t maxb = 0;
+        const hipError_t e = spread_max_blocks(fp64, &maxb);
+        if (e != hipSuccess || maxb == 0) {
+            (void)hipGetLastError();
+            g->spread = false;
+        } else {
+            const uint32_t na = nc / k;
+            const uint32_t want = (na * na * na + kSpreadWaves - 1) / kSpreadWaves;
+            g->spread_blocks = std::max(1u, std::min({want, maxb, (uint32_t)(kMaxParts / kSpreadWaves)}));
+        }
+    }
     return MC_OK;
+}
+
+// Workgroups of the multi-workgroup event kernel for M molecules (one
+// molecule per thread of the O(M^2) loops), 1 = single-workgroup events.
+uint32_t event_blocks(uint32_t M)
+{
+    if (M < 2048) return 1;
+    return std::min((uint32_t)kMaxParts, (M + kThreads - 1) / kThreads);
 }
 
 struct BufLayout {
     size_t sys, stats, com, quat, types, u0, kref, esamp, dsamp, gall, ginter, c2, c2s;
-    size_t props, gsite, gcell, gcellid, glist, total;
+    size_t props, gpart, gsite, gcell, gcellid, glist, gcnt, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -186,12 +212,14 @@ BufLayout buf_layout(const mc_params* p, const Geometry& g)
     b.c2 = o;     o = al(o + kC2Max * sizeof(double));
     b.c2s = o;    o = al(o + kC2Max * sizeof(uint64_t));
     b.props = o;  o = al(o + M * 48);
+    b.gpart = o;  o = al(o + kMaxParts * sizeof(double));
     if (!g.resident) {
         const bool fp64 = p->precision == MC_FP64;
         b.gsite = o;   o = al(o + 3 * M * site_bytes(fp64));
         b.gcell = o;   o = al(o + (size_t(g.ncell) + 1) * sizeof(uint32_t));
         b.gcellid = o; o = al(o + M * sizeof(uint16_t));
         b.glist = o;   o = al(o + M * sizeof(uint16_t));
+        b.gcnt = o;    o = al(o + 2 * size_t(g.ncell) * sizeof(uint32_t));
     }
     b.total = o;
     return b;
@@ -281,6 +309,13 @@ int launch_events_one(mc_system* s, uint32_t flags)
     one.sys = s->dev;
     one.flags = flags;
     hipEvent_t t0 = timing_start(s);
+    const uint32_t nb = event_blocks(s->p.n_molecules);
+    if (nb > 1 && (flags & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic | kFlagGofr))) {
+        // the O(M^2) re-sum and g(r) frame on many workgroups, then the rest
+        HIPCHK(launch_event_parts(one, nb, s->stream));
+        one.flags = flags | kFlagParts;
+        one.pad = nb;
+    }
     HIPCHK(launch_events(nullptr, one, 1, s->stream));
     timing_stop(s, t0, false);
     return MC_OK;
@@ -342,8 +377,12 @@ int advance(mc_system* s, uint64_t n)
         one.n_sweeps = chunk;
         one.flags = 0;
         hipEvent_t t0 = timing_start(s);
-        HIPCHK(launch_sweeps(s->p.precision == MC_FP64, s->g.resident, nullptr, one, 1, s->g.lds,
-                             s->stream));
+        if (s->g.spread)
+            HIPCHK(launch_spread(s->p.precision == MC_FP64, s->dev, chunk, s->g.spread_blocks,
+                                 s->stream));
+        else
+            HIPCHK(launch_sweeps(s->p.precision == MC_FP64, s->g.resident, nullptr, one, 1,
+                                 s->g.lds, s->stream));
         timing_stop(s, t0, true);
         s->sweep += chunk;
         n -= chunk;
@@ -449,6 +488,16 @@ int mc_placement(const mc_params* p, int* resident, size_t* lds_bytes)
     return MC_OK;
 }
 
+int mc_engine(const mc_params* p, int* engine, uint32_t* workgroups)
+{
+    Geometry g;
+    const int rc = geometry(p, &g);
+    if (rc) return rc;
+    if (engine) *engine = g.resident ? MC_ENGINE_LDS : (g.spread ? MC_ENGINE_SPREAD : MC_ENGINE_HBM);
+    if (workgroups) *workgroups = g.spread ? g.spread_blocks : 1u;
+    return MC_OK;
+}
+
 int mc_required_bytes(const mc_params* p, size_t* bytes)
 {
     Geometry g;
@@ -542,11 +591,13 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
     D.c2 = (double*)(b + lay.c2);
     D.c2_sweep = (uint64_t*)(b + lay.c2s);
     D.props = (void*)(b + lay.props);
+    D.g_part = (double*)(b + lay.gpart);
     if (!g.resident) {
         D.g_site = (void*)(b + lay.gsite);
         D.g_cell = (uint32_t*)(b + lay.gcell);
         D.g_cellid = (uint16_t*)(b + lay.gcellid);
         D.g_list = (uint16_t*)(b + lay.glist);
+        D.g_cnt = (uint32_t*)(b + lay.gcnt);
     }
     s->dev = (SysDev*)(b + lay.sys);
 

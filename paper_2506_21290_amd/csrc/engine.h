@@ -28,6 +28,9 @@ enum : uint32_t {
     kFlagResumPeriodic = 8u,  // scheduled re-sum: also record the drift sample
     kFlagGofr = 16u,          // accumulate one g(r) frame
     kFlagC2 = 32u,            // record one C_2 sample
+    kFlagParts = 64u,         // the re-sum and the g(r) frame were done by the
+                              // multi-workgroup event kernel: sum its partial
+                              // energies (Slot::pad of them), count the frame
 };
 
 // Device accumulators of one system.
@@ -83,6 +86,8 @@ struct SysDev {
     uint16_t* g_cellid;  // [M]
     uint16_t* g_list;    // [M] molecules sorted by cell, ascending inside a cell
     void* props;         // [M] proposals of the current sweep (48 bytes each)
+    uint32_t* g_cnt;     // [2 * ncell] cell counts and fill cursors (multi-workgroup engine)
+    double* g_part;      // [kMaxParts] per-wave / per-workgroup partial sums
     // decision log
     void* log;
     uint64_t log_sweep0;
@@ -144,11 +149,47 @@ __host__ __device__ inline LdsLayout lds_layout(bool fp64, bool resident, uint32
     return l;
 }
 
+// Multi-workgroup ("spread") engine for systems larger than one workgroup's
+// LDS: 4 waves per workgroup, every wave takes cells of the current colour and
+// stages each cell's neighbourhood (up to kCellListCap molecules, from a
+// stencil of up to kSpreadPerLane * 64 molecules) in its LDS.
+constexpr int kSpreadThreads = 256;
+constexpr int kSpreadWaves = kSpreadThreads / 64;
+constexpr int kSpreadPerLane = 8;
+constexpr int kMaxParts = 1024;  // workgroups of the event kernel, waves of the spread kernel
+
+__host__ __device__ inline size_t spread_wave_bytes(bool fp64)
+{
+    size_t o = 0;
+    o = align16(o + 3 * size_t(kCellListCap) * sizeof(double));  // staged centres
+    o = align16(o + 3 * size_t(kCellListCap) * site_bytes(fp64));  // staged sites
+    o = align16(o + size_t(kCellListCap) * sizeof(uint16_t));      // molecule of each slot
+    o = align16(o + size_t(kCellListCap) * sizeof(uint16_t));      // slot of each cell molecule
+    o = align16(o + size_t(kCellListCap) * 8);                     // near list
+    o = align16(o + size_t(kCellListCap) * sizeof(uint16_t));      // survivors
+    o = align16(o + 2 * size_t(kMaxSeg) * sizeof(uint16_t));       // stencil segments
+    o = align16(o + trial_bytes(fp64));
+    return o;
+}
+__host__ __device__ inline size_t spread_lds_bytes(bool fp64)
+{
+    return kSpreadWaves * spread_wave_bytes(fp64) + 16 * sizeof(double);
+}
+
 // Kernel launchers (kernels.hip).
 hipError_t launch_sweeps(bool fp64, bool resident, const Slot* dev_slots, const Slot& one,
                          uint32_t n_blocks, size_t lds_bytes, hipStream_t stream);
 hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
                          hipStream_t stream);
 hipError_t launch_init_lattice(SysDev* dev_sys, uint32_t M, hipStream_t stream);
+// Cooperative launch of n sweeps of one system on n_blocks workgroups.
+hipError_t launch_spread(bool fp64, SysDev* dev_sys, uint64_t n_sweeps, uint32_t n_blocks,
+                         hipStream_t stream);
+// Largest cooperative grid of the spread kernel on the current device.
+hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks);
+// The O(M^2) part of an event (re-sum partial energies into g_part, g(r)
+// frame into the histograms) over n_blocks workgroups; follow with
+// launch_events(flags | kFlagParts, pad = n_blocks).
+hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t stream);
 
 }  // namespace flipmc

@@ -24,6 +24,10 @@
 // run is reproducible regardless of how systems are batched.
 #include "engine.h"
 
+#include <hip/hip_cooperative_groups.h>
+
+namespace cg = cooperative_groups;
+
 namespace flipmc {
 namespace {
 
@@ -161,11 +165,12 @@ __device__ double block_sum(double v, double* red)
     return t;
 }
 
-// In-place exclusive scan of a[0..n) by the whole workgroup.
-__device__ void block_excl_scan(uint32_t* a, uint32_t n, uint32_t* scratch)
+// In-place exclusive scan of a[0..n) by a whole workgroup of kT threads.
+template <int kT>
+__device__ void block_excl_scan_t(uint32_t* a, uint32_t n, uint32_t* scratch)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t per = (n + kThreads - 1) / kThreads;
+    const uint32_t per = (n + kT - 1) / kT;
     const uint32_t beg = min(n, tid * per), end = min(n, beg + per);
     uint32_t s = 0;
     for (uint32_t i = beg; i < end; ++i) s += a[i];
@@ -181,6 +186,11 @@ __device__ void block_excl_scan(uint32_t* a, uint32_t n, uint32_t* scratch)
         run += t;
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void block_excl_scan(uint32_t* a, uint32_t n, uint32_t* scratch)
+{
+    block_excl_scan_t<kThreads>(a, n, scratch);
 }
 
 // --------------------------------------------------------------- geometry --
@@ -274,6 +284,7 @@ struct Ctx {
     uint64_t* c2_sweep;
     MoveRecord* log;
     uint64_t log_sweep0, log_sweeps;
+    double* gpart;
     // work arrays (LDS when resident)
     double* com;
     R4<Real>* site;
@@ -399,11 +410,11 @@ __device__ __forceinline__ void offsets_f64(const Ctx<Real, kRes>& C, uint32_t m
 
 // Total inter-molecular energy in FP64 over balanced molecule pairs.
 template <typename Real, bool kRes>
-__device__ double resum_energy(const Ctx<Real, kRes>& C)
+__device__ double resum_energy(const Ctx<Real, kRes>& C, uint32_t m0, uint32_t mstep)
 {
     const uint32_t M = C.M, half = M / 2;
     double e = 0.0;
-    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+    for (uint32_t m = m0; m < M; m += mstep) {
         double om[9], sm[3];
         offsets_f64(C, m, om, sm);
         const double cx = C.com[m], cy = C.com[M + m], cz = C.com[2 * M + m];
@@ -493,7 +504,7 @@ __device__ void reset_observables(const Ctx<Real, kRes>& C)
 
 // One g(r) frame (Eq. 3 numerator): every ordered pair of distinct sites.
 template <typename Real, bool kRes>
-__device__ void gofr_frame(const Ctx<Real, kRes>& C)
+__device__ void gofr_frame(const Ctx<Real, kRes>& C, uint32_t m0, uint32_t mstep, bool shared_out)
 {
     const uint32_t M = C.M, half = M / 2, nb = C.gofr_nbins;
     uint32_t* ball = C.bins;
@@ -503,7 +514,7 @@ __device__ void gofr_frame(const Ctx<Real, kRes>& C)
     const double dr = C.gofr_dr, rmax = C.gofr_rmax;
     const double cut = rmax + 2.0 * C.radius;
     const double cut2 = cut * cut;
-    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+    for (uint32_t m = m0; m < M; m += mstep) {
         double om[9], sm[3];
         offsets_f64(C, m, om, sm);
 #pragma unroll
@@ -546,10 +557,15 @@ __device__ void gofr_frame(const Ctx<Real, kRes>& C)
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        C.gofr_all[b] += ball[b];
-        C.gofr_inter[b] += binter[b];
+        if (shared_out) {  // several workgroups add into the histograms
+            if (ball[b]) atomicAdd((unsigned long long*)&C.gofr_all[b], (unsigned long long)ball[b]);
+            if (binter[b]) atomicAdd((unsigned long long*)&C.gofr_inter[b], (unsigned long long)binter[b]);
+        } else {
+            C.gofr_all[b] += ball[b];
+            C.gofr_inter[b] += binter[b];
+        }
     }
-    if (threadIdx.x == 0) C.stats->n_gofr += 1;
+    if (threadIdx.x == 0 && !shared_out) C.stats->n_gofr += 1;
 }
 
 // Cell grid of one sweep: counting sort of molecules by cell.
@@ -592,7 +608,6 @@ __device__ void build_cells(const Ctx<Real, kRes>& C, double hx, double hy, doub
     __syncthreads();
 }
 
-// Per-wave accumulators, kept in LDS and updated by lane 0.
 // Per-wave counters, kept in registers for the whole launch.
 struct WaveCount {
     uint32_t att0, att1, att2, acc0, acc1, acc2, exits;
@@ -693,6 +708,16 @@ __device__ __forceinline__ uint32_t stencil_molecule(const Ctx<Real, kRes>& C, c
 constexpr uint32_t kListCap = kCellListCap;
 constexpr uint32_t kNoMolecule = 0xFFFFFFFFu;
 
+// Where a cell's trials read positions: centres as [3][stride] and site
+// offsets as [3 * stride], indexed by a local molecule id (the molecule index
+// itself, or the slot of a staged copy of the cell's neighbourhood).
+template <typename Real>
+struct View {
+    double* com;
+    R4<Real>* site;
+    uint32_t stride;
+};
+
 // The moved sites of the trial in flight, in registers (wave-uniform).
 template <typename Real>
 struct Moved {
@@ -709,14 +734,14 @@ struct Moved {
 // within each pair's cut-off.  Returns u_new - u_old (0 for an invalid item);
 // sc gets u_new + u_old; terms counts the pairs inside the cut-off over the
 // wave (popcounts of the compare masks).
-template <int kMove, bool kLog, typename Real, bool kRes>
-__device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const Moved<Real>& mv,
+template <int kMove, bool kLog, typename Real>
+__device__ __forceinline__ Real item_terms(const Moved<Real>& mv, double L, double invL,
                                            double jx, double jy, double jz, const R4<Real>& sj,
                                            bool valid, Real rc2f, Real& sc, uint32_t& terms)
 {
-    const double dx = fma(-C.L, rint((jx - mv.cx) * C.invL), jx - mv.cx);
-    const double dy = fma(-C.L, rint((jy - mv.cy) * C.invL), jy - mv.cy);
-    const double dz = fma(-C.L, rint((jz - mv.cz) * C.invL), jz - mv.cz);
+    const double dx = fma(-L, rint((jx - mv.cx) * invL), jx - mv.cx);
+    const double dy = fma(-L, rint((jy - mv.cy) * invL), jy - mv.cy);
+    const double dz = fma(-L, rint((jz - mv.cz) * invL), jz - mv.cz);
     Real px = (Real)dx + sj.x, py = (Real)dy + sj.y, pz = (Real)dz + sj.z;
     if (!valid) px = Real(1e4);
     Real d = Real(0);
@@ -755,43 +780,163 @@ __device__ __forceinline__ Real item_terms(const Ctx<Real, kRes>& C, const Moved
     return d;
 }
 
-// One step of the item loop: items base + lane and base + 64 + lane, with the
-// loads of both passes issued before any arithmetic.
 template <typename Real>
 struct PassSum {
     Real d, s;       // sum of u_new - u_old, of u_new + u_old
     uint32_t terms;  // pairs inside the cut-off (wave total)
 };
 
-template <int kMove, bool kLog, typename Real, bool kRes>
-__device__ __forceinline__ PassSum<Real> item_pair_pass(const Ctx<Real, kRes>& C,
+// One step of the item loop: items base + lane and base + 64 + lane (item
+// 3 s + t = site t of survivor s), with the loads of both passes issued
+// before any arithmetic.
+template <int kMove, bool kLog, typename Real>
+__device__ __forceinline__ PassSum<Real> item_pair_pass(const View<Real>& V, double L, double invL,
                                                         const uint16_t* surv, const Moved<Real>& mv,
                                                         uint32_t base, uint32_t nit, Real rc2f)
 {
-    const uint32_t M = C.M;
+    const uint32_t S = V.stride;
     const uint32_t itA = base + (uint32_t)__lane_id(), itB = itA + 64u;
     const bool vA = itA < nit, vB = itB < nit;
     const uint32_t cA = vA ? itA : 0u, cB = vB ? itB : 0u;
     const uint32_t sA = cA / 3u, sB = cB / 3u;
     const uint32_t tA = cA - 3u * sA, tB = cB - 3u * sB;
     const uint32_t jA = surv[sA], jB = surv[sB];
-    const double xA = C.com[jA], yA = C.com[M + jA], zA = C.com[2 * M + jA];
-    const double xB = C.com[jB], yB = C.com[M + jB], zB = C.com[2 * M + jB];
-    const R4<Real> gA = C.site[3u * jA + tA], gB = C.site[3u * jB + tB];
+    const double xA = V.com[jA], yA = V.com[S + jA], zA = V.com[2 * S + jA];
+    const double xB = V.com[jB], yB = V.com[S + jB], zB = V.com[2 * S + jB];
+    const R4<Real> gA = V.site[3u * jA + tA], gB = V.site[3u * jB + tB];
     __builtin_amdgcn_sched_barrier(0);
     Real sa = Real(0), sb = Real(0);
     uint32_t terms = 0;
-    const Real da = item_terms<kMove, kLog>(C, mv, xA, yA, zA, gA, vA, rc2f, sa, terms);
-    const Real db = item_terms<kMove, kLog>(C, mv, xB, yB, zB, gB, vB, rc2f, sb, terms);
+    const Real da = item_terms<kMove, kLog>(mv, L, invL, xA, yA, zA, gA, vA, rc2f, sa, terms);
+    const Real db = item_terms<kMove, kLog>(mv, L, invL, xB, yB, zB, gB, vB, rc2f, sb, terms);
     return PassSum<Real>{da + db, sa + sb, terms};
 }
 
-// All trials of the cells of colour `col` owned by this wave.
+// Per-phase constants of the trial loop.
+struct PhaseConst {
+    double half_w, reach_box, step;
+    float prune2;
+    bool logging;
+};
+
+template <typename Real, bool kRes>
+__device__ __forceinline__ PhaseConst phase_const(const Ctx<Real, kRes>& C, uint64_t sweep)
+{
+    PhaseConst P;
+    P.logging = C.log != nullptr && sweep - C.log_sweep0 < C.log_sweeps;
+    P.half_w = 0.5 * C.w;
+    const double reach = sqrt(C.reach2);
+    P.reach_box = (reach + 1e-6) * (reach + 1e-6);
+    // prune radius on the FP16 relative centres: own move + a neighbour of the
+    // same cell that moved earlier in this cell + rounding
+    P.step = C.dmax * 1.7320508075688772;
+    const float prune_r = (float)(reach + 2.0 * P.step + 0.02);
+    // the relative centres are unique images only while the list region stays
+    // below half the box; otherwise every listed molecule survives the prune
+    // (and FP16 keeps the rounding below the 0.02 margin only up to |r| < 16)
+    const bool prune_ok = P.half_w + (double)prune_r + P.step < fmin(0.5 * C.L - 1e-3, 16.0);
+    P.prune2 = prune_ok ? prune_r * prune_r : 3.0e38f;
+    return P;
+}
+
+// The near list as the lanes hold it: entries lane, lane + 64, lane + 128
+// (local ids and FP16-rounded relative centres).
+struct NearRegs {
+    uint32_t j[3];
+    float x[3], y[3], z[3];
+};
+
+__device__ __forceinline__ NearRegs near_regs(const NearEntry* near, uint32_t nnear, bool overflow)
+{
+    NearRegs r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t idx = (uint32_t)__lane_id() + 64u * c;
+        r.j[c] = kNoMolecule;
+        r.x[c] = r.y[c] = r.z[c] = 0.f;
+        if (!overflow && idx < nnear) {
+            const NearEntry e = near[idx];
+            r.j[c] = e.j;
+            r.x[c] = (float)e.rx; r.y[c] = (float)e.ry; r.z[c] = (float)e.rz;
+        }
+    }
+    return r;
+}
+
+// Molecules whose centre is within reach of the box of a cell centred at
+// (bx0, by0, bz0), from the stencil segments of the cell list: their indices
+// and relative centres go to near[]; returns the count (overflow set when it
+// exceeds the list capacity).  Two molecules per lane and step, loads issued
+// before arithmetic.
+template <typename Real, bool kRes>
+__device__ uint32_t build_near(const Ctx<Real, kRes>& C, const PhaseConst& P, int nseg,
+                               uint32_t total, double bx0, double by0, double bz0,
+                               const WaveLds<Real>& W, bool& overflow)
+{
+    const int lane = __lane_id();
+    const uint32_t M = C.M;
+    const int per = 64 / nseg;  // lanes per segment (nseg <= 50)
+    const int my_seg = lane / per, my_sub = lane - my_seg * per;
+    uint32_t my_lo = 0, my_len = 0;
+    if (my_seg < nseg) {
+        my_lo = W.seglo[my_seg];
+        const uint32_t end = my_seg + 1 < nseg ? (uint32_t)W.segoff[my_seg + 1] : total;
+        my_len = end - (uint32_t)W.segoff[my_seg];
+    }
+    uint32_t longest = my_len;
+#pragma unroll
+    for (int o = 32; o; o >>= 1) longest = max(longest, (uint32_t)__shfl_xor(longest, o));
+    const bool seg_ok = my_seg < nseg;
+    const uint32_t step2 = 2u * (uint32_t)per;
+    uint32_t nnear = 0;
+    overflow = false;
+    for (uint32_t t0 = 0; t0 < longest; t0 += step2) {
+        const uint32_t tA = t0 + (uint32_t)my_sub, tB = tA + (uint32_t)per;
+        const bool vA = seg_ok && tA < my_len, vB = seg_ok && tB < my_len;
+        const uint32_t jA = C.list[vA ? my_lo + tA : 0u];
+        const uint32_t jB = C.list[vB ? my_lo + tB : 0u];
+        const double xA = C.com[jA], yA = C.com[M + jA], zA = C.com[2 * M + jA];
+        const double xB = C.com[jB], yB = C.com[M + jB], zB = C.com[2 * M + jB];
+        __builtin_amdgcn_sched_barrier(0);
+        const double rxA = min_image(xA - bx0, C.L, C.invL), ryA = min_image(yA - by0, C.L, C.invL),
+                     rzA = min_image(zA - bz0, C.L, C.invL);
+        const double rxB = min_image(xB - bx0, C.L, C.invL), ryB = min_image(yB - by0, C.L, C.invL),
+                     rzB = min_image(zB - bz0, C.L, C.invL);
+        const double exA = fmax(fabs(rxA) - P.half_w, 0.0), eyA = fmax(fabs(ryA) - P.half_w, 0.0),
+                     ezA = fmax(fabs(rzA) - P.half_w, 0.0);
+        const double exB = fmax(fabs(rxB) - P.half_w, 0.0), eyB = fmax(fabs(ryB) - P.half_w, 0.0),
+                     ezB = fmax(fabs(rzB) - P.half_w, 0.0);
+        const bool keepA = vA && exA * exA + eyA * eyA + ezA * ezA < P.reach_box;
+        const bool keepB = vB && exB * exB + eyB * eyB + ezB * ezB < P.reach_box;
+        const uint64_t bmA = __ballot(keepA), bmB = __ballot(keepB);
+        const uint32_t npA = (uint32_t)__popcll(bmA), npB = (uint32_t)__popcll(bmB);
+        if (nnear + npA + npB > kListCap) {
+            overflow = true;
+            break;
+        }
+        if (keepA) {
+            NearEntry e;
+            e.j = (uint16_t)jA;
+            e.rx = (__fp16)(float)rxA; e.ry = (__fp16)(float)ryA; e.rz = (__fp16)(float)rzA;
+            W.near[nnear + rank_below(bmA)] = e;
+        }
+        if (keepB) {
+            NearEntry e;
+            e.j = (uint16_t)jB;
+            e.rx = (__fp16)(float)rxB; e.ry = (__fp16)(float)ryB; e.rz = (__fp16)(float)rzB;
+            W.near[nnear + npA + rank_below(bmB)] = e;
+        }
+        nnear += npA + npB;
+    }
+    wave_lds_sync();
+    return nnear;
+}
+
+// The trials of one cell (molecules list[cbeg .. cbeg + ccnt), a cell box
+// centred at (bx0, by0, bz0)), in ascending order, by one wave.
 //
-// Per cell: the list of molecules whose centre is within reach of the cell's
-// box is built once (and kept in registers, three entries per lane), and the
-// lanes load the proposals, centres and rotated offsets of the cell's
-// molecules (one lane each).  Per trial, in the cell's ascending order:
+// The lanes load the proposals, centres and rotated offsets of the cell's
+// molecules (one lane each).  Per trial:
 //   1. the lane holding the proposal publishes the moved sites;
 //   2. the near list is pruned against the molecule's centre (FP32 on the
 //      FP16 relative centres, with margins for the trial's own move and for
@@ -802,31 +947,263 @@ __device__ __forceinline__ PassSum<Real> item_pair_pass(const Ctx<Real, kRes>& C
 //      64-lane passes issued together);
 //   4. a DPP reduction in FP64 gives dE in a fixed order, Metropolis decides
 //      and the owning lane commits the move.
+// Positions are read through V (local ids: molecule indices, or slots of a
+// staged neighbourhood when kStaged, where own_slot maps the cell's molecules
+// to their slots and commits also go to the state in C).  After a near-list
+// overflow every stencil molecule is a candidate and V is the state in C.
+template <typename Real, bool kRes, bool kStaged>
+__device__ void cell_trials(const Ctx<Real, kRes>& C, const View<Real>& Vn, const PropRec* props,
+                            uint64_t sweep, const PhaseConst& P, uint32_t cbeg, uint32_t ccnt,
+                            double bx0, double by0, double bz0, const NearRegs& nr, bool overflow,
+                            int nseg, uint32_t total, const uint16_t* own_slot,
+                            const WaveLds<Real>& W, WaveCount& wc)
+{
+    const int lane = __lane_id();
+    const uint32_t M = C.M;
+    const Real rc2f = (Real)C.rc2_factor;
+    const bool staged = kStaged && !overflow;
+    const View<Real> V = (kStaged && overflow) ? View<Real>{C.com, C.site, M} : Vn;
+    const uint32_t S = V.stride;
+    TrialLds<Real>* tr = W.tr;
+
+    for (uint32_t q0 = 0; q0 < ccnt; q0 += 64u) {
+        const uint32_t n = min(64u, ccnt - q0);
+        // one lane per molecule: proposal, centre, relative centre, sites and,
+        // for a rotation, the rotated offsets
+        PropRec pr;
+        uint32_t mi = 0, ml = 0;  // molecule index, local id in V
+        double cmx = 0.0, cmy = 0.0, cmz = 0.0;
+        float mrx = 0.f, mry = 0.f, mrz = 0.f;
+        Real no[9];
+        R4<Real> os0{}, os1{}, os2{};  // the molecule's sites before its trial
+        if ((uint32_t)lane < n) {
+            mi = C.list[cbeg + q0 + lane];
+            ml = staged ? (uint32_t)own_slot[q0 + lane] : mi;
+            pr = props[mi];
+            cmx = V.com[ml]; cmy = V.com[S + ml]; cmz = V.com[2 * S + ml];
+            os0 = V.site[3 * ml]; os1 = V.site[3 * ml + 1]; os2 = V.site[3 * ml + 2];
+            mrx = (float)min_image(cmx - bx0, C.L, C.invL);
+            mry = (float)min_image(cmy - by0, C.L, C.invL);
+            mrz = (float)min_image(cmz - bz0, C.L, C.invL);
+            if ((pr.kind & 15u) == 1u) {
+                double rm[9];
+                rotation(pr.a0, pr.a1, pr.a2, pr.a3, rm);
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    const double b0 = body_at(C, s, 0), b1 = body_at(C, s, 1), b2 = body_at(C, s, 2);
+                    no[3 * s] = (Real)(rm[0] * b0 + rm[1] * b1 + rm[2] * b2);
+                    no[3 * s + 1] = (Real)(rm[3] * b0 + rm[4] * b1 + rm[5] * b2);
+                    no[3 * s + 2] = (Real)(rm[6] * b0 + rm[7] * b1 + rm[8] * b2);
+                }
+            }
+        }
+
+        for (uint32_t q = 0; q < n; ++q) {
+            const int i = (int)q;
+            const uint32_t kind = rl_u(pr.kind, i);
+            const uint32_t move = kind & 15u, exited = (kind >> 4) & 1u, axis = kind >> 8;
+            const uint32_t m = rl_u(mi, i), mloc = rl_u(ml, i);
+            wc.att0 += move == 0u;
+            wc.att1 += move == 1u;
+            wc.att2 += move == 2u;
+            if (exited) {
+                wc.exits += 1;
+                if (P.logging && lane == i) {
+                    MoveRecord rec;
+                    rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = pr.thr; rec.sweep = sweep;
+                    rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = 0;
+                    rec.exited = 1; rec.axis = (uint8_t)axis; rec.pair_terms = 0; rec.pad = 0;
+                    C.log[(sweep - C.log_sweep0) * M + m] = rec;
+                }
+                continue;
+            }
+            // 1. publish the moved sites: all three, or the two swapped ones
+            // of a flip
+            const bool flip = move == 2u;
+            const uint32_t a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
+            if (lane == i) {
+                if (flip) {
+                    const R4<Real> x1 = a1 == 0u ? os0 : (a1 == 1u ? os1 : os2);
+                    const R4<Real> x2 = a2 == 0u ? os0 : (a2 == 1u ? os1 : os2);
+                    tr->old_site[0] = x1;
+                    tr->old_site[1] = x2;
+                    tr->new_site[0] = R4<Real>{x1.x, x1.y, x1.z, x2.w};
+                    tr->new_site[1] = R4<Real>{x2.x, x2.y, x2.z, x1.w};
+                } else {
+                    tr->old_site[0] = os0;
+                    tr->old_site[1] = os1;
+                    tr->old_site[2] = os2;
+                    if (move == 1u) {
+                        tr->new_site[0] = R4<Real>{no[0], no[1], no[2], os0.w};
+                        tr->new_site[1] = R4<Real>{no[3], no[4], no[5], os1.w};
+                        tr->new_site[2] = R4<Real>{no[6], no[7], no[8], os2.w};
+                    } else {
+                        tr->new_site[0] = os0;
+                        tr->new_site[1] = os1;
+                        tr->new_site[2] = os2;
+                    }
+                }
+                tr->cm[0] = cmx; tr->cm[1] = cmy; tr->cm[2] = cmz;
+                tr->mr[0] = mrx; tr->mr[1] = mry; tr->mr[2] = mrz;
+                tr->dl[0] = move == 0u ? (Real)pr.a0 : Real(0);
+                tr->dl[1] = move == 0u ? (Real)pr.a1 : Real(0);
+                tr->dl[2] = move == 0u ? (Real)pr.a2 : Real(0);
+            }
+            wave_lds_sync();
+            Moved<Real> mv;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                mv.o[s] = tr->old_site[s];
+                mv.n[s] = tr->new_site[s];
+            }
+            mv.cx = tr->cm[0]; mv.cy = tr->cm[1]; mv.cz = tr->cm[2];
+            mv.dlx = tr->dl[0]; mv.dly = tr->dl[1]; mv.dlz = tr->dl[2];
+            mv.flip = flip;
+            mv.nmv = flip ? 2 : 3;
+            const float tmx = tr->mr[0], tmy = tr->mr[1], tmz = tr->mr[2];
+            __builtin_amdgcn_sched_barrier(0);
+
+            Real acc = Real(0), accs = Real(0);
+            uint32_t terms = 0, tests = 0;
+            // 3. one lane per (survivor, site), two passes at a time
+            auto eval_items = [&](uint32_t nit) __attribute__((always_inline)) {
+                wave_lds_sync();
+                tests += nit * (uint32_t)mv.nmv * 2u;
+                for (uint32_t base = 0; base < nit; base += 128u) {
+                    PassSum<Real> ps;
+                    if (P.logging) {
+                        if (move == 0u)
+                            ps = item_pair_pass<0, true>(V, C.L, C.invL, W.surv, mv, base, nit, rc2f);
+                        else if (move == 1u)
+                            ps = item_pair_pass<1, true>(V, C.L, C.invL, W.surv, mv, base, nit, rc2f);
+                        else
+                            ps = item_pair_pass<2, true>(V, C.L, C.invL, W.surv, mv, base, nit, rc2f);
+                    } else {
+                        if (move == 0u)
+                            ps = item_pair_pass<0, false>(V, C.L, C.invL, W.surv, mv, base, nit, rc2f);
+                        else if (move == 1u)
+                            ps = item_pair_pass<1, false>(V, C.L, C.invL, W.surv, mv, base, nit, rc2f);
+                        else
+                            ps = item_pair_pass<2, false>(V, C.L, C.invL, W.surv, mv, base, nit, rc2f);
+                    }
+                    acc += ps.d;
+                    accs += ps.s;
+                    terms += ps.terms;
+                }
+            };
+
+            // 2. prune and compact the survivors
+            if (!overflow) {
+                uint32_t nsurv = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float px = nr.x[c] - tmx, py = nr.y[c] - tmy, pz = nr.z[c] - tmz;
+                    const bool keep = nr.j[c] != kNoMolecule && nr.j[c] != mloc &&
+                                      px * px + py * py + pz * pz < P.prune2;
+                    const uint64_t bm = __ballot(keep);
+                    if (keep) W.surv[nsurv + rank_below(bm)] = (uint16_t)nr.j[c];
+                    nsurv += (uint32_t)__popcll(bm);
+                }
+                if (nsurv) eval_items(3u * nsurv);
+            } else {
+                // list overflow: every stencil molecule, 64 at a time
+                for (uint32_t base = 0; base < total; base += 64u) {
+                    const uint32_t idx = base + (uint32_t)lane;
+                    uint32_t j = kNoMolecule;
+                    if (idx < total) j = stencil_molecule(C, W.seglo, W.segoff, nseg, idx);
+                    const bool keep = j != kNoMolecule && j != m;
+                    const uint64_t bm = __ballot(keep);
+                    wave_lds_sync();
+                    if (keep) W.surv[rank_below(bm)] = (uint16_t)j;
+                    const uint32_t ns = (uint32_t)__popcll(bm);
+                    if (ns) eval_items(3u * ns);
+                }
+            }
+
+            // 4. Metropolis on the FP64 sum
+            const double de = wave_sum_dpp((double)acc);
+            const double thr = rl_d(pr.thr, i);
+            const bool accept = (de <= 0.0) || (thr < -de);
+            double sc = 0.0;
+            if (P.logging) sc = wave_sum_dpp((double)accs);
+            wc.terms += terms;
+            wc.tests += tests;
+            if (accept) {
+                wc.acc0 += move == 0u;
+                wc.acc1 += move == 1u;
+                wc.acc2 += move == 2u;
+                wc.e += de;
+            }
+            if (lane == i) {
+                if (accept) {
+                    R4<Real>* sp = V.site + 3 * ml;
+                    R4<Real>* gp = C.site + 3 * mi;
+                    if (move == 0u) {
+                        const double nx = wrap(cmx + pr.a0, C.L), ny = wrap(cmy + pr.a1, C.L),
+                                     nz = wrap(cmz + pr.a2, C.L);
+                        V.com[ml] = nx; V.com[S + ml] = ny; V.com[2 * S + ml] = nz;
+                        if (staged) {
+                            C.com[mi] = nx; C.com[M + mi] = ny; C.com[2 * M + mi] = nz;
+                        }
+                    } else if (move == 1u) {
+#pragma unroll
+                        for (int s = 0; s < 3; ++s) {
+                            sp[s].x = no[3 * s];
+                            sp[s].y = no[3 * s + 1];
+                            sp[s].z = no[3 * s + 2];
+                            if (staged) {
+                                gp[s].x = no[3 * s];
+                                gp[s].y = no[3 * s + 1];
+                                gp[s].z = no[3 * s + 2];
+                            }
+                        }
+                        C.quat[mi] = pr.a0;
+                        C.quat[M + mi] = pr.a1;
+                        C.quat[2 * M + mi] = pr.a2;
+                        C.quat[3 * M + mi] = pr.a3;
+                    } else {
+                        const Real w1 = a1 == 0u ? os0.w : (a1 == 1u ? os1.w : os2.w);
+                        const Real w2 = a2 == 0u ? os0.w : (a2 == 1u ? os1.w : os2.w);
+                        sp[a1].w = w2;
+                        sp[a2].w = w1;
+                        if (staged) {
+                            gp[a1].w = w2;
+                            gp[a2].w = w1;
+                        }
+                        const uint32_t ty = C.types[mi];
+                        const uint32_t t1 = (ty >> (8 * a1)) & 0xFFu, t2 = (ty >> (8 * a2)) & 0xFFu;
+                        uint32_t nt = ty & ~((0xFFu << (8 * a1)) | (0xFFu << (8 * a2)));
+                        nt |= (t2 << (8 * a1)) | (t1 << (8 * a2));
+                        C.types[mi] = nt;
+                    }
+                }
+                if (P.logging) {
+                    MoveRecord rec;
+                    rec.delta_e = de; rec.scale = sc; rec.t_log_u = thr; rec.sweep = sweep;
+                    rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = accept ? 1 : 0;
+                    rec.exited = 0; rec.axis = (uint8_t)axis; rec.pair_terms = terms; rec.pad = 0;
+                    C.log[(sweep - C.log_sweep0) * M + m] = rec;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+// All trials of the cells of colour `col` owned by this wave of the
+// single-workgroup engine: per cell, the near list from the system's own
+// arrays, then the cell's trials.
 template <typename Real, bool kRes>
 __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int col, uint64_t sweep,
                           double hx, double hy, double hz, const WaveLds<Real>& W, WaveCount& wc)
 {
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    const uint32_t M = C.M;
+    const int wave = threadIdx.x >> 6;
     const int k = (int)C.k, nc = (int)C.nc, na = nc / k;
     const int nact = na * na * na;
     const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
     const int ncw = nact > wave ? (nact - 1 - wave) / kWaves + 1 : 0;
-    const Real rc2f = (Real)C.rc2_factor;
-    const bool logging = C.log != nullptr && sweep - C.log_sweep0 < C.log_sweeps;
-    const double half_w = 0.5 * C.w;
-    const double reach = sqrt(C.reach2);
-    const double reach_box = (reach + 1e-6) * (reach + 1e-6);
-    // prune radius on the FP16 relative centres: own move + a neighbour of the
-    // same cell that moved earlier in this cell + rounding
-    const double step = C.dmax * 1.7320508075688772;
-    const float prune_r = (float)(reach + 2.0 * step + 0.02);
-    // the relative centres are unique images only while the list region stays
-    // below half the box; otherwise every listed molecule survives the prune
-    // (and FP16 keeps the rounding below the 0.02 margin only up to |r| < 16)
-    const bool prune_ok = half_w + (double)prune_r + step < fmin(0.5 * C.L - 1e-3, 16.0);
-    const float prune2 = prune_ok ? prune_r * prune_r : 3.0e38f;
-    TrialLds<Real>* tr = W.tr;
+    const PhaseConst P = phase_const(C, sweep);
+    const View<Real> V{C.com, C.site, C.M};
 
     for (int ci = 0; ci < ncw; ++ci) {
         const int a = wave + kWaves * ci;
@@ -837,291 +1214,13 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
         const double bx0 = hx + ((double)cx + 0.5) * C.w;
         const double by0 = hy + ((double)cy + 0.5) * C.w;
         const double bz0 = hz + ((double)cz + 0.5) * C.w;
-
-        // molecules whose centre is within reach of this cell's box, walking
-        // the row segments with several lanes per segment
         uint32_t total;
         const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
-        uint32_t nnear = 0;
-        bool overflow = false;
-        {
-            const int per = 64 / nseg;  // lanes per segment (nseg <= 50)
-            const int my_seg = lane / per, my_sub = lane - my_seg * per;
-            uint32_t my_lo = 0, my_len = 0;
-            if (my_seg < nseg) {
-                my_lo = W.seglo[my_seg];
-                const uint32_t end = my_seg + 1 < nseg ? (uint32_t)W.segoff[my_seg + 1] : total;
-                my_len = end - (uint32_t)W.segoff[my_seg];
-            }
-            uint32_t longest = my_len;
-#pragma unroll
-            for (int o = 32; o; o >>= 1) longest = max(longest, (uint32_t)__shfl_xor(longest, o));
-            // two molecules per lane and step, loads issued before arithmetic
-            const bool seg_ok = my_seg < nseg;
-            const uint32_t step2 = 2u * (uint32_t)per;
-            for (uint32_t t0 = 0; t0 < longest; t0 += step2) {
-                const uint32_t tA = t0 + (uint32_t)my_sub, tB = tA + (uint32_t)per;
-                const bool vA = seg_ok && tA < my_len, vB = seg_ok && tB < my_len;
-                const uint32_t jA = C.list[vA ? my_lo + tA : 0u];
-                const uint32_t jB = C.list[vB ? my_lo + tB : 0u];
-                const double xA = C.com[jA], yA = C.com[M + jA], zA = C.com[2 * M + jA];
-                const double xB = C.com[jB], yB = C.com[M + jB], zB = C.com[2 * M + jB];
-                __builtin_amdgcn_sched_barrier(0);
-                double rxA = min_image(xA - bx0, C.L, C.invL), ryA = min_image(yA - by0, C.L, C.invL),
-                       rzA = min_image(zA - bz0, C.L, C.invL);
-                double rxB = min_image(xB - bx0, C.L, C.invL), ryB = min_image(yB - by0, C.L, C.invL),
-                       rzB = min_image(zB - bz0, C.L, C.invL);
-                const double exA = fmax(fabs(rxA) - half_w, 0.0), eyA = fmax(fabs(ryA) - half_w, 0.0),
-                             ezA = fmax(fabs(rzA) - half_w, 0.0);
-                const double exB = fmax(fabs(rxB) - half_w, 0.0), eyB = fmax(fabs(ryB) - half_w, 0.0),
-                             ezB = fmax(fabs(rzB) - half_w, 0.0);
-                const bool keepA = vA && exA * exA + eyA * eyA + ezA * ezA < reach_box;
-                const bool keepB = vB && exB * exB + eyB * eyB + ezB * ezB < reach_box;
-                const uint64_t bmA = __ballot(keepA), bmB = __ballot(keepB);
-                const uint32_t npA = (uint32_t)__popcll(bmA), npB = (uint32_t)__popcll(bmB);
-                if (nnear + npA + npB > kListCap) {
-                    overflow = true;
-                    break;
-                }
-                if (keepA) {
-                    NearEntry e;
-                    e.j = (uint16_t)jA;
-                    e.rx = (__fp16)(float)rxA; e.ry = (__fp16)(float)ryA; e.rz = (__fp16)(float)rzA;
-                    W.near[nnear + rank_below(bmA)] = e;
-                }
-                if (keepB) {
-                    NearEntry e;
-                    e.j = (uint16_t)jB;
-                    e.rx = (__fp16)(float)rxB; e.ry = (__fp16)(float)ryB; e.rz = (__fp16)(float)rzB;
-                    W.near[nnear + npA + rank_below(bmB)] = e;
-                }
-                nnear += npA + npB;
-            }
-        }
-        wave_lds_sync();
-        // the near list in registers: entries lane, lane + 64, lane + 128
-        uint32_t nj[3];
-        float nx[3], ny[3], nz[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const uint32_t idx = (uint32_t)lane + 64u * c;
-            nj[c] = kNoMolecule;
-            nx[c] = ny[c] = nz[c] = 0.f;
-            if (!overflow && idx < nnear) {
-                const NearEntry e = W.near[idx];
-                nj[c] = e.j;
-                nx[c] = (float)e.rx; ny[c] = (float)e.ry; nz[c] = (float)e.rz;
-            }
-        }
-
-        for (uint32_t q0 = 0; q0 < ccnt; q0 += 64u) {
-            const uint32_t n = min(64u, ccnt - q0);
-            // one lane per molecule: proposal, centre, relative centre and,
-            // for a rotation, the rotated offsets
-            PropRec pr;
-            uint32_t mi = 0;
-            double cmx = 0.0, cmy = 0.0, cmz = 0.0;
-            float mrx = 0.f, mry = 0.f, mrz = 0.f;
-            Real no[9];
-            R4<Real> os0{}, os1{}, os2{};  // the molecule's sites before its trial
-            if ((uint32_t)lane < n) {
-                mi = C.list[cbeg + q0 + lane];
-                pr = props[mi];
-                cmx = C.com[mi]; cmy = C.com[M + mi]; cmz = C.com[2 * M + mi];
-                os0 = C.site[3 * mi]; os1 = C.site[3 * mi + 1]; os2 = C.site[3 * mi + 2];
-                mrx = (float)min_image(cmx - bx0, C.L, C.invL);
-                mry = (float)min_image(cmy - by0, C.L, C.invL);
-                mrz = (float)min_image(cmz - bz0, C.L, C.invL);
-                if ((pr.kind & 15u) == 1u) {
-                    double rm[9];
-                    rotation(pr.a0, pr.a1, pr.a2, pr.a3, rm);
-#pragma unroll
-                    for (int s = 0; s < 3; ++s) {
-                        const double b0 = body_at(C, s, 0), b1 = body_at(C, s, 1),
-                                     b2 = body_at(C, s, 2);
-                        no[3 * s] = (Real)(rm[0] * b0 + rm[1] * b1 + rm[2] * b2);
-                        no[3 * s + 1] = (Real)(rm[3] * b0 + rm[4] * b1 + rm[5] * b2);
-                        no[3 * s + 2] = (Real)(rm[6] * b0 + rm[7] * b1 + rm[8] * b2);
-                    }
-                }
-            }
-
-            for (uint32_t q = 0; q < n; ++q) {
-                const int i = (int)q;
-                const uint32_t kind = rl_u(pr.kind, i);
-                const uint32_t move = kind & 15u, exited = (kind >> 4) & 1u, axis = kind >> 8;
-                const uint32_t m = rl_u(mi, i);
-                wc.att0 += move == 0u;
-                wc.att1 += move == 1u;
-                wc.att2 += move == 2u;
-                if (exited) {
-                    wc.exits += 1;
-                    if (logging && lane == i) {
-                        MoveRecord rec;
-                        rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = pr.thr; rec.sweep = sweep;
-                        rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = 0;
-                        rec.exited = 1; rec.axis = (uint8_t)axis; rec.pair_terms = 0; rec.pad = 0;
-                        C.log[(sweep - C.log_sweep0) * M + m] = rec;
-                    }
-                    continue;
-                }
-                // 1. publish the moved sites: all three, or the two swapped
-                // ones of a flip
-                const bool flip = move == 2u;
-                const uint32_t a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
-                if (lane == i) {
-                    if (flip) {
-                        const R4<Real> x1 = a1 == 0u ? os0 : (a1 == 1u ? os1 : os2);
-                        const R4<Real> x2 = a2 == 0u ? os0 : (a2 == 1u ? os1 : os2);
-                        tr->old_site[0] = x1;
-                        tr->old_site[1] = x2;
-                        tr->new_site[0] = R4<Real>{x1.x, x1.y, x1.z, x2.w};
-                        tr->new_site[1] = R4<Real>{x2.x, x2.y, x2.z, x1.w};
-                    } else {
-                        tr->old_site[0] = os0;
-                        tr->old_site[1] = os1;
-                        tr->old_site[2] = os2;
-                        if (move == 1u) {
-                            tr->new_site[0] = R4<Real>{no[0], no[1], no[2], os0.w};
-                            tr->new_site[1] = R4<Real>{no[3], no[4], no[5], os1.w};
-                            tr->new_site[2] = R4<Real>{no[6], no[7], no[8], os2.w};
-                        } else {
-                            tr->new_site[0] = os0;
-                            tr->new_site[1] = os1;
-                            tr->new_site[2] = os2;
-                        }
-                    }
-                    tr->cm[0] = cmx; tr->cm[1] = cmy; tr->cm[2] = cmz;
-                    tr->mr[0] = mrx; tr->mr[1] = mry; tr->mr[2] = mrz;
-                    tr->dl[0] = move == 0u ? (Real)pr.a0 : Real(0);
-                    tr->dl[1] = move == 0u ? (Real)pr.a1 : Real(0);
-                    tr->dl[2] = move == 0u ? (Real)pr.a2 : Real(0);
-                }
-                wave_lds_sync();
-                Moved<Real> mv;
-#pragma unroll
-                for (int s = 0; s < 3; ++s) {
-                    mv.o[s] = tr->old_site[s];
-                    mv.n[s] = tr->new_site[s];
-                }
-                mv.cx = tr->cm[0]; mv.cy = tr->cm[1]; mv.cz = tr->cm[2];
-                mv.dlx = tr->dl[0]; mv.dly = tr->dl[1]; mv.dlz = tr->dl[2];
-                mv.flip = flip;
-                mv.nmv = flip ? 2 : 3;
-                const float tmx = tr->mr[0], tmy = tr->mr[1], tmz = tr->mr[2];
-                __builtin_amdgcn_sched_barrier(0);
-
-                Real acc = Real(0), accs = Real(0);
-                uint32_t terms = 0, tests = 0;
-                // 3. one lane per (survivor, site), two passes at a time
-                auto eval_items = [&](uint32_t nit) __attribute__((always_inline)) {
-                    wave_lds_sync();
-                    tests += nit * (uint32_t)mv.nmv * 2u;
-                    for (uint32_t base = 0; base < nit; base += 128u) {
-                        PassSum<Real> ps;
-                        if (logging) {
-                            if (move == 0u)
-                                ps = item_pair_pass<0, true>(C, W.surv, mv, base, nit, rc2f);
-                            else if (move == 1u)
-                                ps = item_pair_pass<1, true>(C, W.surv, mv, base, nit, rc2f);
-                            else
-                                ps = item_pair_pass<2, true>(C, W.surv, mv, base, nit, rc2f);
-                        } else {
-                            if (move == 0u)
-                                ps = item_pair_pass<0, false>(C, W.surv, mv, base, nit, rc2f);
-                            else if (move == 1u)
-                                ps = item_pair_pass<1, false>(C, W.surv, mv, base, nit, rc2f);
-                            else
-                                ps = item_pair_pass<2, false>(C, W.surv, mv, base, nit, rc2f);
-                        }
-                        acc += ps.d;
-                        accs += ps.s;
-                        terms += ps.terms;
-                    }
-                };
-
-                // 2. prune and compact the survivors
-                if (!overflow) {
-                    uint32_t nsurv = 0;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const float px = nx[c] - tmx, py = ny[c] - tmy, pz = nz[c] - tmz;
-                        const bool keep = nj[c] != kNoMolecule && nj[c] != m &&
-                                          px * px + py * py + pz * pz < prune2;
-                        const uint64_t bm = __ballot(keep);
-                        if (keep) W.surv[nsurv + rank_below(bm)] = (uint16_t)nj[c];
-                        nsurv += (uint32_t)__popcll(bm);
-                    }
-                    if (nsurv) eval_items(3u * nsurv);
-                } else {
-                    // list overflow: every stencil molecule, 64 at a time
-                    for (uint32_t base = 0; base < total; base += 64u) {
-                        const uint32_t idx = base + (uint32_t)lane;
-                        uint32_t j = kNoMolecule;
-                        if (idx < total) j = stencil_molecule(C, W.seglo, W.segoff, nseg, idx);
-                        const bool keep = j != kNoMolecule && j != m;
-                        const uint64_t bm = __ballot(keep);
-                        wave_lds_sync();
-                        if (keep) W.surv[rank_below(bm)] = (uint16_t)j;
-                        const uint32_t ns = (uint32_t)__popcll(bm);
-                        if (ns) eval_items(3u * ns);
-                    }
-                }
-
-                // 4. Metropolis on the FP64 sum
-                const double de = wave_sum_dpp((double)acc);
-                const double thr = rl_d(pr.thr, i);
-                const bool accept = (de <= 0.0) || (thr < -de);
-                double sc = 0.0;
-                if (logging) sc = wave_sum_dpp((double)accs);
-                wc.terms += terms;
-                wc.tests += tests;
-                if (accept) {
-                    wc.acc0 += move == 0u;
-                    wc.acc1 += move == 1u;
-                    wc.acc2 += move == 2u;
-                    wc.e += de;
-                }
-                if (lane == i) {
-                    if (accept) {
-                        R4<Real>* sp = C.site + 3 * m;
-                        if (move == 0u) {
-                            C.com[m] = wrap(cmx + pr.a0, C.L);
-                            C.com[M + m] = wrap(cmy + pr.a1, C.L);
-                            C.com[2 * M + m] = wrap(cmz + pr.a2, C.L);
-                        } else if (move == 1u) {
-#pragma unroll
-                            for (int s = 0; s < 3; ++s) {
-                                sp[s].x = no[3 * s];
-                                sp[s].y = no[3 * s + 1];
-                                sp[s].z = no[3 * s + 2];
-                            }
-                            C.quat[m] = pr.a0;
-                            C.quat[M + m] = pr.a1;
-                            C.quat[2 * M + m] = pr.a2;
-                            C.quat[3 * M + m] = pr.a3;
-                        } else {
-                            const Real w1 = sp[a1].w, w2 = sp[a2].w;
-                            sp[a1].w = w2;
-                            sp[a2].w = w1;
-                            const uint32_t ty = C.types[m];
-                            const uint32_t t1 = (ty >> (8 * a1)) & 0xFFu, t2 = (ty >> (8 * a2)) & 0xFFu;
-                            uint32_t nt = ty & ~((0xFFu << (8 * a1)) | (0xFFu << (8 * a2)));
-                            nt |= (t2 << (8 * a1)) | (t1 << (8 * a2));
-                            C.types[m] = nt;
-                        }
-                    }
-                    if (logging) {
-                        MoveRecord rec;
-                        rec.delta_e = de; rec.scale = sc; rec.t_log_u = thr; rec.sweep = sweep;
-                        rec.molecule = m; rec.move = (uint8_t)move; rec.accepted = accept ? 1 : 0;
-                        rec.exited = 0; rec.axis = (uint8_t)axis; rec.pair_terms = terms; rec.pad = 0;
-                        C.log[(sweep - C.log_sweep0) * M + m] = rec;
-                    }
-                }
-                wave_lds_sync();
-            }
-        }
+        bool overflow;
+        const uint32_t nnear = build_near(C, P, nseg, total, bx0, by0, bz0, W, overflow);
+        const NearRegs nr = near_regs(W.near, nnear, overflow);
+        cell_trials<Real, kRes, false>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0, nr,
+                                       overflow, nseg, total, nullptr, W, wc);
     }
 }
 
@@ -1145,6 +1244,7 @@ __device__ __forceinline__ void load_ctx(Ctx<Real, kRes>& C, const SysDev* __res
     C.gofr_all = Dp->gofr_all; C.gofr_inter = Dp->gofr_inter; C.c2 = Dp->c2;
     C.c2_sweep = Dp->c2_sweep;
     C.log = (MoveRecord*)Dp->log; C.log_sweep0 = Dp->log_sweep0; C.log_sweeps = Dp->log_sweeps;
+    C.gpart = Dp->g_part;
 }
 
 // The hot kernel: n checkerboard sweeps of every slot's system, one
@@ -1298,7 +1398,13 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
         __syncthreads();
     }
     if (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) {
-        const double e = resum_energy(C);
+        double e;
+        if (f & kFlagParts) {  // partial energies of the multi-workgroup kernel, in order
+            e = 0.0;
+            for (uint32_t b = 0; b < sl.pad; ++b) e += C.gpart[b];
+        } else {
+            e = resum_energy(C, threadIdx.x, kThreads);
+        }
         if (tid == 0) {
             const double acc = (f & kFlagResumSet) ? e : e_acc;
             // a set or a scheduled re-sum re-anchors the accumulated energy, so
@@ -1319,7 +1425,11 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
         __syncthreads();
     }
     if (f & kFlagGofr) {
-        gofr_frame(C);
+        if (f & kFlagParts) {
+            if (tid == 0) st->n_gofr += 1;
+        } else {
+            gofr_frame(C, threadIdx.x, kThreads, false);
+        }
         __syncthreads();
     }
     if (f & kFlagC2) {
@@ -1330,6 +1440,317 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
             st->n_c2 += 1;
         }
     }
+}
+
+// ----------------------------------------------------- multi-workgroup --
+//
+// The spread engine advances one large system with many workgroups in one
+// cooperative launch.  The state stays in HBM.  A sweep is: cell indices,
+// counts and proposals of all molecules (one thread each); an exclusive scan
+// of the counts (workgroup 0); the scatter of molecule indices into the cell
+// list and a sort of every cell's range; then the k^3 colours, each wave
+// taking cells of the colour in turn.  For every cell the wave copies the
+// neighbourhood (molecules within reach of the cell's box) into its LDS and
+// runs the cell's trials on the copy, writing each accepted move through to
+// HBM.  Grid barriers separate the steps; the colours keep the waves apart
+// exactly as in the single-workgroup engine, so the decisions are the same.
+
+// The staged neighbourhood of the cell a wave is working on.
+template <typename Real>
+struct StageLds {
+    double* com;     // [3][kCellListCap] centres
+    R4<Real>* site;  // [3 * kCellListCap] site offsets + sigma
+    uint16_t* gid;   // molecule of each slot
+    uint16_t* own;   // slot of the cell's q-th molecule
+};
+
+// Stage the molecules within reach of the box of the cell centred at
+// (bx0, by0, bz0): centres, sites, near list (slots and FP16 relative centres)
+// and the slots of the cell's own molecules.  Returns the number of slots; sets
+// overflow when the stencil or the neighbourhood is larger than the staging
+// area (the cell then runs on the HBM state).
+template <typename Real>
+__device__ uint32_t stage_cell(const Ctx<Real, false>& C, const PhaseConst& P, int nseg,
+                               uint32_t total, double bx0, double by0, double bz0, uint32_t cbeg,
+                               uint32_t ccnt, const WaveLds<Real>& W, const StageLds<Real>& S,
+                               bool& overflow)
+{
+    const int lane = __lane_id();
+    const uint32_t M = C.M;
+    overflow = total > 64u * kSpreadPerLane || ccnt > kListCap;
+    if (overflow) return 0;
+    uint32_t li[kSpreadPerLane], jj[kSpreadPerLane];
+    bool vv[kSpreadPerLane];
+#pragma unroll
+    for (int r = 0; r < kSpreadPerLane; ++r) {
+        const uint32_t idx = (uint32_t)lane + 64u * r;
+        vv[r] = idx < total;
+        li[r] = 0;
+        if (64u * r < total && vv[r]) {
+            int lo = 0, hi = nseg;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if ((uint32_t)W.segoff[mid] <= idx) lo = mid; else hi = mid;
+            }
+            li[r] = (uint32_t)W.seglo[lo] + (idx - (uint32_t)W.segoff[lo]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kSpreadPerLane; ++r) jj[r] = C.list[li[r]];
+    double xx[kSpreadPerLane], yy[kSpreadPerLane], zz[kSpreadPerLane];
+#pragma unroll
+    for (int r = 0; r < kSpreadPerLane; ++r) {
+        xx[r] = C.com[jj[r]];
+        yy[r] = C.com[M + jj[r]];
+        zz[r] = C.com[2 * M + jj[r]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t n = 0;
+#pragma unroll
+    for (int r = 0; r < kSpreadPerLane; ++r) {
+        if (64u * r >= total) break;
+        const double rx = min_image(xx[r] - bx0, C.L, C.invL);
+        const double ry = min_image(yy[r] - by0, C.L, C.invL);
+        const double rz = min_image(zz[r] - bz0, C.L, C.invL);
+        const double ex = fmax(fabs(rx) - P.half_w, 0.0), ey = fmax(fabs(ry) - P.half_w, 0.0),
+                     ez = fmax(fabs(rz) - P.half_w, 0.0);
+        const bool keep = vv[r] && ex * ex + ey * ey + ez * ez < P.reach_box;
+        const uint64_t bm = __ballot(keep);
+        const uint32_t np = (uint32_t)__popcll(bm);
+        if (n + np > kListCap) {
+            overflow = true;
+            break;
+        }
+        if (keep) {
+            const uint32_t slot = n + rank_below(bm);
+            S.com[slot] = xx[r];
+            S.com[kListCap + slot] = yy[r];
+            S.com[2 * kListCap + slot] = zz[r];
+            S.gid[slot] = (uint16_t)jj[r];
+            NearEntry e;
+            e.j = (uint16_t)slot;
+            e.rx = (__fp16)(float)rx; e.ry = (__fp16)(float)ry; e.rz = (__fp16)(float)rz;
+            W.near[slot] = e;
+            if (li[r] - cbeg < ccnt) S.own[li[r] - cbeg] = (uint16_t)slot;
+        }
+        n += np;
+    }
+    if (overflow) return 0;
+    wave_lds_sync();
+    // the staged molecules' sites, three slots per lane, loads first
+    R4<Real> st[9];
+    uint32_t sl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        sl[c] = (uint32_t)lane + 64u * c;
+        const uint32_t g = sl[c] < n ? (uint32_t)S.gid[sl[c]] : 0u;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) st[3 * c + t] = C.site[3 * g + t];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (sl[c] < n)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) S.site[3 * sl[c] + t] = st[3 * c + t];
+    wave_lds_sync();
+    return n;
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kSpreadThreads) k_spread(SysDev* __restrict__ Dp, uint64_t n_sweeps)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    cg::grid_group grid = cg::this_grid();
+    constexpr bool fp64 = sizeof(Real) == 8;
+    constexpr uint32_t kCap = kListCap;
+    Ctx<Real, false> C;
+    load_ctx(C, Dp);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    unsigned char* wb = smem + (size_t)wave * spread_wave_bytes(fp64);
+    StageLds<Real> S;
+    WaveLds<Real> W;
+    size_t o = 0;
+    S.com = (double*)(wb + o);    o = align16(o + 3 * size_t(kCap) * sizeof(double));
+    S.site = (R4<Real>*)(wb + o); o = align16(o + 3 * size_t(kCap) * site_bytes(fp64));
+    S.gid = (uint16_t*)(wb + o);  o = align16(o + size_t(kCap) * sizeof(uint16_t));
+    S.own = (uint16_t*)(wb + o);  o = align16(o + size_t(kCap) * sizeof(uint16_t));
+    W.near = (NearEntry*)(wb + o); o = align16(o + size_t(kCap) * 8);
+    W.surv = (uint16_t*)(wb + o); o = align16(o + size_t(kCap) * sizeof(uint16_t));
+    W.seglo = (uint16_t*)(wb + o);
+    W.segoff = W.seglo + kMaxSeg; o = align16(o + 2 * size_t(kMaxSeg) * sizeof(uint16_t));
+    W.tr = (TrialLds<Real>*)(wb + o);
+    C.misc = (double*)(smem + kSpreadWaves * spread_wave_bytes(fp64));
+    C.com = C.gcom;
+    C.site = (R4<Real>*)Dp->g_site;
+    C.cellb = Dp->g_cell;
+    C.cellid = Dp->g_cellid;
+    C.list = Dp->g_list;
+    C.red = nullptr;
+    C.bins = nullptr;
+    C.wpart = nullptr;
+    uint32_t* cnt = Dp->g_cnt;
+    uint32_t* fill = cnt + C.ncell;
+    PropRec* props = (PropRec*)Dp->props;
+    Stats* st = C.stats;
+    const uint32_t M = C.M, ncell = C.ncell;
+    const uint32_t gtid = blockIdx.x * kSpreadThreads + tid, GT = gridDim.x * kSpreadThreads;
+    const uint32_t gw = blockIdx.x * kSpreadWaves + wave, NW = gridDim.x * kSpreadWaves;
+    const int k = (int)C.k, nc = (int)C.nc, na = nc / k;
+    const uint32_t nact = (uint32_t)(na * na * na);
+    const int ncol = k * k * k;
+
+    if (tid == 0) {
+        C.misc[1] = C.sig0;
+        C.misc[2] = C.sig1;
+        C.misc[3] = C.sig2;
+    }
+    __syncthreads();
+    for (uint32_t m = gtid; m < M; m += GT) store_sites_from_quat(C, m);
+    for (uint32_t c = gtid; c < 2 * ncell; c += GT) cnt[c] = 0;
+    WaveCount wc{};
+    double e_acc = st->e_acc;
+    uint64_t sweep = st->sweep;
+    const uint64_t origin = st->obs_origin;
+    grid.sync();
+
+    for (uint64_t it = 0; it < n_sweeps; ++it) {
+        const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, C.seed_lo,
+                              C.seed_hi);
+        const double hx = C.w * unit_open(g.x), hy = C.w * unit_open(g.y),
+                     hz = C.w * unit_open(g.z);
+        // cell of every molecule, counts, proposals
+        for (uint32_t m = gtid; m < M; m += GT) {
+            const int ix = cell_axis(C.com[m], hx, C.L, C.w, nc);
+            const int iy = cell_axis(C.com[M + m], hy, C.L, C.w, nc);
+            const int iz = cell_axis(C.com[2 * M + m], hz, C.L, C.w, nc);
+            const uint32_t cid = (uint32_t)(ix + nc * (iy + nc * iz));
+            C.cellid[m] = (uint16_t)cid;
+            atomicAdd(&cnt[cid], 1u);
+            props[m] = propose(C, m, sweep, hx, hy, hz, ix, iy, iz);
+        }
+        grid.sync();
+        // cell starts (exclusive scan of the counts); counts cleared for the
+        // next sweep
+        if (blockIdx.x == 0) {
+            for (uint32_t c = tid; c < ncell; c += kSpreadThreads) C.cellb[c] = cnt[c];
+            __syncthreads();
+            block_excl_scan_t<kSpreadThreads>(C.cellb, ncell, (uint32_t*)(C.misc + 8));
+            if (tid == 0) C.cellb[ncell] = M;
+            for (uint32_t c = tid; c < ncell; c += kSpreadThreads) cnt[c] = 0;
+        }
+        grid.sync();
+        for (uint32_t m = gtid; m < M; m += GT) {
+            const uint32_t c = C.cellid[m];
+            C.list[C.cellb[c] + atomicAdd(&fill[c], 1u)] = (uint16_t)m;
+        }
+        grid.sync();
+        // ascending molecule index inside every cell
+        for (uint32_t c = gtid; c < ncell; c += GT) {
+            const uint32_t b = C.cellb[c], e = C.cellb[c + 1];
+            for (uint32_t i = b + 1; i < e; ++i) {
+                const uint16_t v = C.list[i];
+                uint32_t q = i;
+                while (q > b && C.list[q - 1] > v) {
+                    C.list[q] = C.list[q - 1];
+                    --q;
+                }
+                C.list[q] = v;
+            }
+            fill[c] = 0;
+        }
+        grid.sync();
+
+        const PhaseConst P = phase_const(C, sweep);
+        const View<Real> V{S.com, S.site, kCap};
+        for (int col = 0; col < ncol; ++col) {
+            const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
+            for (uint32_t a = gw; a < nact; a += NW) {
+                const int cx = kx + k * (int)(a % na), cy = ky + k * (int)((a / na) % na),
+                          cz = kz + k * (int)(a / (na * na));
+                const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
+                const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
+                if (ccnt == 0) continue;
+                const double bx0 = hx + ((double)cx + 0.5) * C.w;
+                const double by0 = hy + ((double)cy + 0.5) * C.w;
+                const double bz0 = hz + ((double)cz + 0.5) * C.w;
+                uint32_t total;
+                const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
+                bool overflow;
+                const uint32_t ns = stage_cell(C, P, nseg, total, bx0, by0, bz0, cbeg, ccnt, W, S, overflow);
+                const NearRegs nr = near_regs(W.near, ns, overflow);
+                cell_trials<Real, false, true>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0, nr,
+                                               overflow, nseg, total, S.own, W, wc);
+            }
+            grid.sync();
+        }
+        // accepted dE of the sweep, added in wave order; E/M samples
+        if (lane == 0) C.gpart[gw] = wc.e;
+        wc.e = 0.0;
+        ++sweep;
+        grid.sync();
+        if (blockIdx.x == 0 && tid == 0) {
+            for (uint32_t w = 0; w < NW; ++w) e_acc += C.gpart[w];
+            const uint64_t t = sweep - origin;
+            if (t >= C.obs_start && C.obs_interval && t % C.obs_interval == 0) {
+                const double em = e_acc / (double)M;
+                if (st->n_e < C.max_samples) C.e_samples[st->n_e] = em;
+                st->n_e += 1;
+                st->e_sum += em;
+                st->e_sumsq += em * em;
+            }
+        }
+    }
+
+    if (lane == 0) {
+        const uint64_t att[3] = {wc.att0, wc.att1, wc.att2}, acc[3] = {wc.acc0, wc.acc1, wc.acc2};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (att[i]) atomicAdd((unsigned long long*)&st->attempts[i], (unsigned long long)att[i]);
+            if (acc[i]) atomicAdd((unsigned long long*)&st->accepts[i], (unsigned long long)acc[i]);
+        }
+        if (wc.exits) atomicAdd((unsigned long long*)&st->exits, (unsigned long long)wc.exits);
+        if (wc.terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)wc.terms);
+        if (wc.tests) atomicAdd((unsigned long long*)&st->pair_tests, (unsigned long long)wc.tests);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        st->sweep = sweep;
+        st->e_acc = e_acc;
+    }
+}
+
+// The O(M^2) work of an event on many workgroups: the re-sum's partial energy
+// of each workgroup into g_part, the g(r) frame into the histograms.
+__global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
+{
+    __shared__ double red[kWaves];
+    __shared__ double misc[16];
+    __shared__ uint32_t bins[2 * kGofrBins];
+    Ctx<double, false> C;
+    load_ctx(C, one.sys);
+    C.com = C.gcom;
+    C.red = red;
+    C.misc = misc;
+    C.bins = bins;
+    C.wpart = nullptr;
+    C.site = nullptr;
+    C.cellb = nullptr;
+    C.cellid = nullptr;
+    C.list = nullptr;
+    if (threadIdx.x == 0) {
+        misc[1] = C.sig0;
+        misc[2] = C.sig1;
+        misc[3] = C.sig2;
+    }
+    __syncthreads();
+    const uint32_t f = one.flags;
+    const uint32_t m0 = blockIdx.x * kThreads + threadIdx.x, step = gridDim.x * kThreads;
+    if (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) {
+        const double e = resum_energy(C, m0, step);
+        if (threadIdx.x == 0) C.gpart[blockIdx.x] = e;
+        __syncthreads();
+    }
+    if (f & kFlagGofr) gofr_frame(C, m0, step, true);
 }
 
 __global__ void k_init_lattice(SysDev* Dp, uint32_t n)
@@ -1385,6 +1806,67 @@ hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_bloc
                          hipStream_t stream)
 {
     hipLaunchKernelGGL(k_events, dim3(n_blocks), dim3(kThreads), 0, stream, dev_slots, one);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <typename Real>
+hipError_t spread_configure()
+{
+    static bool done = false;
+    if (done) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute((const void*)&k_spread<Real>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)spread_lds_bytes(sizeof(Real) == 8));
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+template <typename Real>
+hipError_t spread_max_blocks_t(uint32_t* n_blocks)
+{
+    hipError_t e = spread_configure<Real>();
+    if (e != hipSuccess) return e;
+    int occ = 0, dev = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)&k_spread<Real>, kSpreadThreads,
+                                                     spread_lds_bytes(sizeof(Real) == 8));
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    *n_blocks = (uint32_t)(occ * cus);
+    return hipSuccess;
+}
+
+template <typename Real>
+hipError_t launch_spread_t(SysDev* dev_sys, uint64_t n_sweeps, uint32_t n_blocks, hipStream_t stream)
+{
+    hipError_t e = spread_configure<Real>();
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&dev_sys, (void*)&n_sweeps};
+    return hipLaunchCooperativeKernel((const void*)&k_spread<Real>, dim3(n_blocks),
+                                      dim3(kSpreadThreads), args,
+                                      spread_lds_bytes(sizeof(Real) == 8), stream);
+}
+
+}  // namespace
+
+hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks)
+{
+    return fp64 ? spread_max_blocks_t<double>(n_blocks) : spread_max_blocks_t<float>(n_blocks);
+}
+
+hipError_t launch_spread(bool fp64, SysDev* dev_sys, uint64_t n_sweeps, uint32_t n_blocks,
+                         hipStream_t stream)
+{
+    return fp64 ? launch_spread_t<double>(dev_sys, n_sweeps, n_blocks, stream)
+                : launch_spread_t<float>(dev_sys, n_sweeps, n_blocks, stream);
+}
+
+hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_event_parts, dim3(n_blocks), dim3(kThreads), 0, stream, one);
     return hipGetLastError();
 }
 

@@ -20,12 +20,14 @@ MC_OK, MC_EINVAL, MC_ENOMEM, MC_EDEVICE, MC_EGEOM, MC_ENONFINITE, MC_EBUSY, MC_E
     0, -1, -2, -3, -4, -5, -6, -7)
 MC_FP64, MC_FP32_DE = 0, 1
 MC_TRANSLATE, MC_ROTATE, MC_FLIP = 0, 1, 2
-MC_FLAG_HBM_STATE = 1
+MC_FLAG_HBM_STATE, MC_FLAG_SINGLE_WORKGROUP = 1, 2
+MC_ENGINE_LDS, MC_ENGINE_HBM, MC_ENGINE_SPREAD = 0, 1, 2
 MC_GOFR_MAX_BINS = 256
 MC_C2_MAX = 32
 
 EXPORTED = [
-    "mc_params_default", "mc_geometry", "mc_placement", "mc_required_bytes", "mc_init_system", "mc_sweep",
+    "mc_params_default", "mc_geometry", "mc_placement", "mc_engine", "mc_required_bytes",
+    "mc_init_system", "mc_sweep",
     "mc_energy", "mc_observables", "mc_samples", "mc_reset_observables", "mc_get_state",
     "mc_set_state", "mc_decision_log", "mc_timing_enable", "mc_timing_read", "mc_destroy",
     "mc_last_error", "mc_batch_create",
@@ -129,6 +131,7 @@ def lib():
         L.mc_params_default.restype = None
         L.mc_geometry.argtypes = [pp, dp, u32p, u32p]
         L.mc_placement.argtypes = [pp, C.POINTER(C.c_int), szp]
+        L.mc_engine.argtypes = [pp, C.POINTER(C.c_int), u32p]
         L.mc_required_bytes.argtypes = [pp, szp]
         L.mc_init_system.argtypes = [pp, dp, dp, u8p, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.mc_sweep.argtypes = [vp, C.c_uint64]
@@ -188,6 +191,13 @@ def mc_placement(p: mc_params):
     r, n = C.c_int(), C.c_size_t()
     _check(lib().mc_placement(C.byref(p), C.byref(r), C.byref(n)))
     return bool(r.value), n.value
+
+
+def mc_engine(p: mc_params):
+    """(MC_ENGINE_*, workgroups per launch) that mc_sweep uses for p"""
+    e, w = C.c_int(), C.c_uint32()
+    _check(lib().mc_engine(C.byref(p), C.byref(e), C.byref(w)))
+    return e.value, w.value
 
 
 def mc_required_bytes(p: mc_params) -> int:

@@ -109,9 +109,65 @@ def test_fp64_three_colours_many_cells():
 
 
 def test_fp64_hbm_state_path():
-    # the path of systems too large for LDS, forced on a small one
+    # the multi-workgroup engine of systems too large for LDS, forced on a
+    # small one
     gp = gparams(216, 1.0, 3, 6, seed=7, flags=flipmc.MC_FLAG_HBM_STATE)
+    assert flipmc.mc_engine(gp)[0] == flipmc.MC_ENGINE_SPREAD
     run_parity(gp, oparams(216, 1.0, 3, 6, seed=7), 20, False)
+
+
+def test_fp64_hbm_single_workgroup_path():
+    # the HBM state on one workgroup (how large systems run inside a batch)
+    gp = gparams(216, 1.0, 3, 6, seed=8,
+                 flags=flipmc.MC_FLAG_HBM_STATE | flipmc.MC_FLAG_SINGLE_WORKGROUP)
+    assert flipmc.mc_engine(gp) == (flipmc.MC_ENGINE_HBM, 1)
+    run_parity(gp, oparams(216, 1.0, 3, 6, seed=8), 12, False)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_spread_engine_many_workgroups(fp32):
+    # 1728 molecules, k = 2, n_c = 6: 27 cells per colour over 7 workgroups
+    gp = gparams(1728, 0.9, 2, 6, fp32=fp32, seed=21, flags=flipmc.MC_FLAG_HBM_STATE)
+    engine, wg = flipmc.mc_engine(gp)
+    assert engine == flipmc.MC_ENGINE_SPREAD and wg == 7
+    run_parity(gp, oparams(1728, 0.9, 2, 6, seed=21), 4, fp32)
+
+
+def test_spread_engine_full_size_8000_sampled():
+    # the 8000-molecule configuration (T = 1.1, FP32 dE) on its first sweeps,
+    # with the engine's own decomposition, every trial checked
+    gp = flipmc.mc_params_default(n_molecules=8000, temperature=1.1, seed=1,
+                                  precision=flipmc.MC_FP32_DE)
+    _, k, nc = flipmc.mc_geometry(gp)
+    assert flipmc.mc_engine(gp)[0] == flipmc.MC_ENGINE_SPREAD
+    run_parity(gp, oparams(8000, 1.1, k, nc, seed=1), 2, True)
+
+
+def test_spread_engine_events_match_oracle():
+    # 2197 molecules: the re-sum and g(r) run on the multi-workgroup event
+    # kernel; both match the oracle on the same states
+    gp = gparams(2197, 1.2, 2, 4, seed=17, resum_interval=10, gofr_interval=10, obs_start=0)
+    g = flipmc.System(gp)
+    o = oracle.System(oparams(2197, 1.2, 2, 4, seed=17), lattice=False)
+    nb, _ = oracle.gofr_bins(o.box, 0.02)
+    ca = np.zeros(nb, dtype=np.uint64)
+    ci = np.zeros(nb, dtype=np.uint64)
+    for _ in range(2):
+        g.sweep(10)
+        st = g.get_state()
+        o.set_state(st["com"], st["quat"], st["types"], st["sweep"])
+        o.gofr_accumulate(ca, ci)
+    e, em, drift = g.energy()
+    assert e == pytest.approx(o.energy(), rel=1e-12)
+    assert abs(drift) < 1e-9 * abs(e)
+    _, drifts = g.samples()
+    assert len(drifts) == 2 and np.all(np.abs(drifts) < 1e-8 * abs(e))
+    obs = g.observables()
+    assert obs["n_gofr_frames"] == 2
+    diff = np.abs(obs["gofr_all"][:nb].astype(np.int64) - ca.astype(np.int64))
+    assert diff.sum() <= 8  # only pairs sitting on a bin edge may move
+    diff = np.abs(obs["gofr_inter"][:nb].astype(np.int64) - ci.astype(np.int64))
+    assert diff.sum() <= 8
 
 
 def test_fp64_ragged_cell_counts():
