@@ -2,11 +2,13 @@
 
 For a system size M and a precision, every valid (k, n_c) is a correct
 sampler with its own trajectory; they differ in speed (colour phases, cells per
-wave, neighbour-list length).  The tuner times each candidate on the GPU and
-records the fastest in ``tuned.json`` next to this file.  ``choose`` reads the
-table (falling back to the engine's own model when a size is missing), so a
-job's decomposition is a fixed function of (M, precision) and can be
-reproduced by the oracle.
+wave, neighbour-list length, and for the multi-workgroup engine the number of
+workgroups, one wave per cell of a colour).  The tuner times each candidate on
+the engine mc_sweep picks for the size (one workgroup with the state in LDS
+when it fits, else the multi-workgroup engine) and records the fastest in
+``tuned.json`` next to this file.  ``choose`` reads the table (falling back to
+the engine's own model when a size is missing), so a job's decomposition is a
+fixed function of (M, precision) and can be reproduced by the oracle.
 
 Run on the GPU:  python -m paper_2506_21290_amd.tune --out tuned.json
 """
@@ -25,7 +27,7 @@ PREC_NAME = {flipmc.MC_FP64: "fp64", flipmc.MC_FP32_DE: "fp32"}
 _table = None
 
 
-def candidates(M, precision, per_k=3):
+def candidates(M, precision, per_k=4):
     """Valid (k, n_c) for an M-molecule box at the default density: the
     `per_k` finest grids of each k (coarser grids only lengthen the chains of
     trials inside a cell)."""
@@ -90,8 +92,11 @@ def tune(sizes, precisions, budget_moves=600_000):
                 timed.append((dt, k, nc))
                 print(f"{name} M={M} k={k} n_c={nc}: {dt * 1e6:.1f} us/sweep", flush=True)
             dt, k, nc = min(timed)
+            p = flipmc.mc_params_default(n_molecules=M, precision=prec, colours_per_axis=k,
+                                         cells_per_side=nc)
+            engine, wg = flipmc.mc_engine(p)
             result[name][str(M)] = {"k": k, "n_c": nc, "us_per_sweep": dt * 1e6,
-                                    "moves_per_s": M / dt}
+                                    "moves_per_s": M / dt, "engine": engine, "workgroups": wg}
     return result
 
 

@@ -24,6 +24,9 @@ def _need_gpu():
 def test_results_same_alone_and_in_the_mix():
     jobs = workloads.serving_stream(n_jobs=14, rate=200.0, seed=3, m_min=125, m_max=1728,
                                     s_min=60, s_max=300)
+    # two jobs too large for one workgroup's LDS: the multi-workgroup engine
+    t_last = jobs[-1].arrival
+    jobs += [workloads.Job(14, 2197, 1.3, 40, 77, t_last), workloads.Job(15, 2744, 2.0, 30, 78, t_last)]
     prec = flipmc.MC_FP32_DE
     sizes = [flipmc.mc_required_bytes(serve.job_params(j, prec)) for j in jobs]
     budget = 3 * max(sizes)  # a few jobs at a time: later arrivals must wait
@@ -33,9 +36,10 @@ def test_results_same_alone_and_in_the_mix():
     assert srv.peak_bytes <= budget and srv.used == 0
     assert srv.launches > len(jobs)  # time-sliced, not one launch per job
     assert any(r.wait > 0 for r in res)
-    be = serve.GpuBackend(prec)
+    be = srv.backend
+    assert be.size(jobs[14])[1] == 2 and be.size(jobs[15])[1] == 2
     by_index = {r.job.index: r for r in res}
-    for j in jobs[::3]:
+    for j in jobs[::3] + jobs[14:]:
         s = flipmc.System(serve.job_params(j, prec))
         s.sweep(j.sweeps)
         alone = be.result(j, s)
