@@ -316,12 +316,32 @@ def bench_c4(args, flipmc, torch):
     }
 
 
+def bench_copy(args, flipmc, torch):
+    """A plain device-to-device copy of a known size: the reference for
+    scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters to HBM bytes."""
+    n = 256 << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").random_(0, 255)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    reps = 5
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    return {"workload": "copy: 256 MiB device-to-device, 5 repetitions",
+            "bytes_read_per_copy": n, "bytes_written_per_copy": n,
+            "ms_per_copy": ms, "gb_per_s": 2 * n / (ms / 1e3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "copy"])
     ap.add_argument("--jobs", type=int, default=2000)
     ap.add_argument("--m-max", type=int, default=27000)
     ap.add_argument("--s-max", type=int, default=10000)
@@ -345,7 +365,8 @@ def main():
     if args.workload == "c1":
         out = bench_c1(args, flipmc, torch)
     else:
-        out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[args.workload](args, flipmc, torch)
+        out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
+               "copy": bench_copy}[args.workload](args, flipmc, torch)
     print(json.dumps(out), flush=True)
 
 
