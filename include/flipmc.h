@@ -224,8 +224,14 @@ const char* mc_last_error(void);
 
 /* ---- batches: many systems in one persistent launch ---------------------- */
 
-/* A batch holds up to max_slots systems of one precision; one mc_batch_run
- * launch advances every occupied slot, one workgroup per system. */
+/* A batch holds up to max_slots systems of one precision.  mc_batch_run
+ * advances systems that fit one workgroup's LDS (and those flagged
+ * MC_FLAG_SINGLE_WORKGROUP) in one persistent launch, one workgroup per
+ * system; larger systems share one cooperative launch of the multi-workgroup
+ * engine on a second stream the batch creates, each on the workgroups it
+ * uses alone (as many as the device holds at once, the first one rotating
+ * from run to run).  A system gives bitwise the same results in a batch as
+ * alone. */
 int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc_batch** out);
 
 /* Put an initialised system into a free slot with n_sweeps of work; the
@@ -238,8 +244,10 @@ int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
 /* Enqueue one launch in which each occupied slot runs up to
  * max(1, max_moves_per_slot * f(M) / M) of its remaining sweeps, where
  * f(M) = min(1, 0.25 + 0.75 M / 1000) equalises the time slices of large and
- * small systems (0 = all remaining).  Launches also stop at each system's
- * re-sum / g(r) / C_2 sweeps, whose work follows in a second launch. */
+ * small systems (0 = all remaining); systems on the multi-workgroup engine
+ * run max(1, max_moves_per_slot / 1000) sweeps.  Launches also stop at each
+ * system's re-sum / g(r) / C_2 sweeps, whose work follows in a second launch.
+ * *n_launched = number of launches enqueued. */
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched);
 
 /* Synchronise, then report (and free) the slots whose work is complete:

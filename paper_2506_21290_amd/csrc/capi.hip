@@ -255,6 +255,18 @@ struct mc_batch {
     hipEvent_t copied[2];
     bool pending[2];
     int parity;
+    // systems on the multi-workgroup engine: one cooperative launch per run on
+    // stream2, overlapping the batch stream's launches
+    hipStream_t stream2;
+    hipEvent_t go, done;              // stream2 waits for go (stream), stream for done (stream2)
+    SpreadSlot* dev_spread[2];        // per parity: [systems | (events as Slot)] x max_slots
+    SpreadSlot* host_spread[2];
+    Slot* dev_ev2[2];
+    Slot* host_ev2[2];
+    hipEvent_t copied2[2];
+    bool pending2[2];
+    uint32_t spread_max;              // co-resident workgroups of the cooperative launch
+    uint32_t rr;                      // rotation of the first system considered
 };
 
 namespace {
@@ -377,9 +389,15 @@ int advance(mc_system* s, uint64_t n)
         one.n_sweeps = chunk;
         one.flags = 0;
         hipEvent_t t0 = timing_start(s);
-        if (s->g.spread)
-            HIPCHK(launch_spread(s->p.precision == MC_FP64, s->dev, chunk, s->g.spread_blocks,
-                                 s->stream));
+        if (s->g.spread) {
+            SpreadSlot sl{};
+            sl.sys = s->dev;
+            sl.n_sweeps = chunk;
+            sl.first_block = 0;
+            sl.n_blocks = s->g.spread_blocks;
+            HIPCHK(launch_spread(s->p.precision == MC_FP64, nullptr, 1, sl, chunk,
+                                 (int)(s->g.k * s->g.k * s->g.k), s->g.spread_blocks, s->stream));
+        }
         else
             HIPCHK(launch_sweeps(s->p.precision == MC_FP64, s->g.resident, nullptr, one, 1,
                                  s->g.lds, s->stream));
@@ -835,19 +853,47 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
     b->sys.assign(max_slots, nullptr);
     b->remaining.assign(max_slots, 0);
     b->parity = 0;
+    b->stream2 = nullptr;
+    b->go = b->done = nullptr;
+    b->spread_max = 0;
+    b->rr = 0;
     for (int i = 0; i < 2; ++i) {
         b->dev_slots[i] = nullptr;
         b->host_slots[i] = nullptr;
         b->pending[i] = false;
         b->copied[i] = nullptr;
+        b->dev_spread[i] = nullptr;
+        b->host_spread[i] = nullptr;
+        b->dev_ev2[i] = nullptr;
+        b->host_ev2[i] = nullptr;
+        b->copied2[i] = nullptr;
+        b->pending2[i] = false;
+    }
+    for (int i = 0; i < 2; ++i) {
         // slot tables: one per residency class, double-buffered
         if (hipMalloc((void**)&b->dev_slots[i], 3 * sizeof(Slot) * max_slots) != hipSuccess ||
             hipHostMalloc((void**)&b->host_slots[i], 3 * sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
-            hipEventCreateWithFlags(&b->copied[i], hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&b->copied[i], hipEventDisableTiming) != hipSuccess ||
+            hipMalloc((void**)&b->dev_spread[i], sizeof(SpreadSlot) * max_slots) != hipSuccess ||
+            hipHostMalloc((void**)&b->host_spread[i], sizeof(SpreadSlot) * max_slots, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void**)&b->dev_ev2[i], sizeof(Slot) * max_slots) != hipSuccess ||
+            hipHostMalloc((void**)&b->host_ev2[i], sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b->copied2[i], hipEventDisableTiming) != hipSuccess) {
             mc_batch_destroy(b);
             return fail(MC_EDEVICE, "could not allocate the slot tables");
         }
     }
+    if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->go, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        mc_batch_destroy(b);
+        return fail(MC_EDEVICE, "could not create the second stream");
+    }
+    if (spread_max_blocks(precision == MC_FP64, &b->spread_max) != hipSuccess) {
+        (void)hipGetLastError();
+        b->spread_max = 0;
+    }
+    b->spread_max = std::min(b->spread_max, (uint32_t)(kMaxParts / kSpreadWaves));
     *out = b;
     return MC_OK;
 }
@@ -878,13 +924,23 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         HIPCHK(hipEventSynchronize(b->copied[par]));
         b->pending[par] = false;
     }
+    if (b->pending2[par]) {
+        HIPCHK(hipEventSynchronize(b->copied2[par]));
+        b->pending2[par] = false;
+    }
     Slot* hs = b->host_slots[par];
     const uint32_t S = b->max_slots;
+    const bool fp64 = b->precision == MC_FP64;
     uint32_t n[3] = {0, 0, 0};
     size_t lds[2] = {0, 0};
+    std::vector<uint32_t> spread;  // slots of systems on the multi-workgroup engine
     for (uint32_t i = 0; i < S; ++i) {
         mc_system* s = b->sys[i];
         if (!s || b->remaining[i] == 0) continue;
+        if (s->g.spread && s->g.spread_blocks <= b->spread_max) {
+            spread.push_back(i);
+            continue;
+        }
         uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
         if (max_moves_per_slot) {
             // equal time slices: a workgroup's moves/s falls for small systems
@@ -910,6 +966,73 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             hs[2 * S + n[2]++] = ev;
         }
     }
+
+    // multi-workgroup systems: as many as fit in one cooperative launch, the
+    // first one rotating from run to run; a slice is as many sweeps as a
+    // 1000-molecule system of the batch gets (a sweep of these systems takes
+    // about as long)
+    uint32_t ns = 0, ne = 0, blocks = 0;
+    uint64_t max_sw = 0;
+    int max_col = 0;
+    SpreadSlot* hsp = b->host_spread[par];
+    Slot* hev = b->host_ev2[par];
+    std::vector<std::pair<mc_system*, uint32_t>> parts;  // event work of the launch
+    for (size_t j = 0; j < spread.size(); ++j) {
+        const uint32_t i = spread[(b->rr + j) % spread.size()];
+        mc_system* s = b->sys[i];
+        const uint32_t nb = s->g.spread_blocks;
+        if (blocks + nb > b->spread_max) continue;
+        uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
+        if (max_moves_per_slot) k = std::min<uint64_t>(k, std::max<uint64_t>(1, max_moves_per_slot / 1000));
+        SpreadSlot sl{};
+        sl.sys = s->dev;
+        sl.n_sweeps = k;
+        sl.first_block = blocks;
+        sl.n_blocks = nb;
+        hsp[ns++] = sl;
+        blocks += nb;
+        max_sw = std::max(max_sw, k);
+        max_col = std::max(max_col, (int)(s->g.k * s->g.k * s->g.k));
+        b->remaining[i] -= k;
+        s->sweep += k;
+        const uint32_t f = events_at(s, s->sweep);
+        if (f) {
+            Slot ev{};
+            ev.sys = s->dev;
+            ev.flags = f;
+            const uint32_t nbp = event_blocks(s->p.n_molecules);
+            if (nbp > 1 && (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic | kFlagGofr))) {
+                parts.emplace_back(s, f);
+                ev.flags = f | kFlagParts;
+                ev.pad = nbp;
+            }
+            hev[ne++] = ev;
+        }
+    }
+    if (!spread.empty()) b->rr = (b->rr + 1) % (uint32_t)spread.size();
+    if (ns) {
+        HIPCHK(hipEventRecord(b->go, b->stream));
+        HIPCHK(hipStreamWaitEvent(b->stream2, b->go, 0));
+        HIPCHK(hipMemcpyAsync(b->dev_spread[par], hsp, sizeof(SpreadSlot) * ns, hipMemcpyHostToDevice,
+                              b->stream2));
+        if (ne)
+            HIPCHK(hipMemcpyAsync(b->dev_ev2[par], hev, sizeof(Slot) * ne, hipMemcpyHostToDevice,
+                                  b->stream2));
+        HIPCHK(hipEventRecord(b->copied2[par], b->stream2));
+        b->pending2[par] = true;
+        SpreadSlot none{};
+        HIPCHK(launch_spread(fp64, b->dev_spread[par], ns, none, max_sw, max_col, blocks, b->stream2));
+        for (const auto& pe : parts) {
+            Slot one{};
+            one.sys = pe.first->dev;
+            one.flags = pe.second;
+            HIPCHK(launch_event_parts(one, event_blocks(pe.first->p.n_molecules), b->stream2));
+        }
+        Slot none2{};
+        if (ne) HIPCHK(launch_events(b->dev_ev2[par], none2, ne, b->stream2));
+        HIPCHK(hipEventRecord(b->done, b->stream2));
+    }
+
     if (n[0] + n[1]) {
         HIPCHK(hipMemcpyAsync(b->dev_slots[par], hs, 3 * sizeof(Slot) * S, hipMemcpyHostToDevice,
                               b->stream));
@@ -918,11 +1041,14 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         Slot none{};
         for (int cls = 0; cls < 2; ++cls)
             if (n[cls])
-                HIPCHK(launch_sweeps(b->precision == MC_FP64, cls == 0, b->dev_slots[par] + cls * S,
-                                     none, n[cls], lds[cls], b->stream));
+                HIPCHK(launch_sweeps(fp64, cls == 0, b->dev_slots[par] + cls * S, none, n[cls],
+                                     lds[cls], b->stream));
         if (n[2]) HIPCHK(launch_events(b->dev_slots[par] + 2 * S, none, n[2], b->stream));
     }
-    if (n_launched) *n_launched = n[0] + n[1];
+    // later work on the batch stream (the next run, poll, reads) follows the
+    // multi-workgroup launch
+    if (ns) HIPCHK(hipStreamWaitEvent(b->stream, b->done, 0));
+    if (n_launched) *n_launched = n[0] + n[1] + (ns ? 1u : 0u);
     return MC_OK;
 }
 
@@ -960,11 +1086,20 @@ void mc_batch_destroy(mc_batch* b)
     (void)hipStreamSynchronize(b->stream);
     for (auto* s : b->sys)
         if (s) s->batch = nullptr;
+    if (b->stream2) (void)hipStreamSynchronize(b->stream2);
     for (int i = 0; i < 2; ++i) {
         if (b->dev_slots[i]) (void)hipFree(b->dev_slots[i]);
         if (b->host_slots[i]) (void)hipHostFree(b->host_slots[i]);
         if (b->copied[i]) (void)hipEventDestroy(b->copied[i]);
+        if (b->dev_spread[i]) (void)hipFree(b->dev_spread[i]);
+        if (b->host_spread[i]) (void)hipHostFree(b->host_spread[i]);
+        if (b->dev_ev2[i]) (void)hipFree(b->dev_ev2[i]);
+        if (b->host_ev2[i]) (void)hipHostFree(b->host_ev2[i]);
+        if (b->copied2[i]) (void)hipEventDestroy(b->copied2[i]);
     }
+    if (b->go) (void)hipEventDestroy(b->go);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->stream2) (void)hipStreamDestroy(b->stream2);
     delete b;
 }
 

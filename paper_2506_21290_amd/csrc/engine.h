@@ -182,9 +182,20 @@ hipError_t launch_sweeps(bool fp64, bool resident, const Slot* dev_slots, const 
 hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
                          hipStream_t stream);
 hipError_t launch_init_lattice(SysDev* dev_sys, uint32_t M, hipStream_t stream);
-// Cooperative launch of n sweeps of one system on n_blocks workgroups.
-hipError_t launch_spread(bool fp64, SysDev* dev_sys, uint64_t n_sweeps, uint32_t n_blocks,
-                         hipStream_t stream);
+// One system of a multi-workgroup launch: its workgroups and sweeps.
+struct SpreadSlot {
+    SysDev* sys;
+    uint64_t n_sweeps;
+    uint32_t first_block, n_blocks;
+};
+
+// Cooperative launch of the multi-workgroup engine over n_blocks workgroups:
+// the systems of dev_slots[0 .. n_slots) (device array), or `one` when
+// dev_slots is null; max_sweeps / max_colours bound every slot's sweeps and
+// colours per sweep.
+hipError_t launch_spread(bool fp64, const SpreadSlot* dev_slots, uint32_t n_slots,
+                         const SpreadSlot& one, uint64_t max_sweeps, int max_colours,
+                         uint32_t n_blocks, hipStream_t stream);
 // Largest cooperative grid of the spread kernel on the current device.
 hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks);
 // The O(M^2) part of an event (re-sum partial energies into g_part, g(r)

@@ -1557,13 +1557,31 @@ __device__ uint32_t stage_cell(const Ctx<Real, false>& C, const PhaseConst& P, i
     return n;
 }
 
+// One launch can advance several systems: slot i owns workgroups
+// [first_block, first_block + n_blocks) and runs n_sweeps sweeps; every
+// workgroup takes part in every grid barrier (max_sweeps sweeps of max_colours
+// colours), idle where its own system has fewer.
 template <typename Real>
-__global__ void __launch_bounds__(kSpreadThreads) k_spread(SysDev* __restrict__ Dp, uint64_t n_sweeps)
+__global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __restrict__ slots,
+                                                           uint32_t n_slots, SpreadSlot one,
+                                                           uint64_t max_sweeps, int max_colours)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     cg::grid_group grid = cg::this_grid();
     constexpr bool fp64 = sizeof(Real) == 8;
     constexpr uint32_t kCap = kListCap;
+    SpreadSlot sl = one;
+    if (slots) {
+        for (uint32_t i = 0; i < n_slots; ++i) {
+            const SpreadSlot t = slots[i];
+            if (blockIdx.x >= t.first_block && blockIdx.x < t.first_block + t.n_blocks) {
+                sl = t;
+                break;
+            }
+        }
+    }
+    SysDev* __restrict__ Dp = sl.sys;
+    const uint32_t bid = blockIdx.x - sl.first_block, nblk = sl.n_blocks;
     Ctx<Real, false> C;
     load_ctx(C, Dp);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1594,8 +1612,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SysDev* __restrict__ 
     PropRec* props = (PropRec*)Dp->props;
     Stats* st = C.stats;
     const uint32_t M = C.M, ncell = C.ncell;
-    const uint32_t gtid = blockIdx.x * kSpreadThreads + tid, GT = gridDim.x * kSpreadThreads;
-    const uint32_t gw = blockIdx.x * kSpreadWaves + wave, NW = gridDim.x * kSpreadWaves;
+    const uint32_t gtid = bid * kSpreadThreads + tid, GT = nblk * kSpreadThreads;
+    const uint32_t gw = bid * kSpreadWaves + wave, NW = nblk * kSpreadWaves;
     const int k = (int)C.k, nc = (int)C.nc, na = nc / k;
     const uint32_t nact = (uint32_t)(na * na * na);
     const int ncol = k * k * k;
@@ -1614,25 +1632,28 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SysDev* __restrict__ 
     const uint64_t origin = st->obs_origin;
     grid.sync();
 
-    for (uint64_t it = 0; it < n_sweeps; ++it) {
+    for (uint64_t it = 0; it < max_sweeps; ++it) {
+        const bool run = it < sl.n_sweeps;
         const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, C.seed_lo,
                               C.seed_hi);
         const double hx = C.w * unit_open(g.x), hy = C.w * unit_open(g.y),
                      hz = C.w * unit_open(g.z);
         // cell of every molecule, counts, proposals
-        for (uint32_t m = gtid; m < M; m += GT) {
-            const int ix = cell_axis(C.com[m], hx, C.L, C.w, nc);
-            const int iy = cell_axis(C.com[M + m], hy, C.L, C.w, nc);
-            const int iz = cell_axis(C.com[2 * M + m], hz, C.L, C.w, nc);
-            const uint32_t cid = (uint32_t)(ix + nc * (iy + nc * iz));
-            C.cellid[m] = (uint16_t)cid;
-            atomicAdd(&cnt[cid], 1u);
-            props[m] = propose(C, m, sweep, hx, hy, hz, ix, iy, iz);
+        if (run) {
+            for (uint32_t m = gtid; m < M; m += GT) {
+                const int ix = cell_axis(C.com[m], hx, C.L, C.w, nc);
+                const int iy = cell_axis(C.com[M + m], hy, C.L, C.w, nc);
+                const int iz = cell_axis(C.com[2 * M + m], hz, C.L, C.w, nc);
+                const uint32_t cid = (uint32_t)(ix + nc * (iy + nc * iz));
+                C.cellid[m] = (uint16_t)cid;
+                atomicAdd(&cnt[cid], 1u);
+                props[m] = propose(C, m, sweep, hx, hy, hz, ix, iy, iz);
+            }
         }
         grid.sync();
         // cell starts (exclusive scan of the counts); counts cleared for the
         // next sweep
-        if (blockIdx.x == 0) {
+        if (run && bid == 0) {
             for (uint32_t c = tid; c < ncell; c += kSpreadThreads) C.cellb[c] = cnt[c];
             __syncthreads();
             block_excl_scan_t<kSpreadThreads>(C.cellb, ncell, (uint32_t*)(C.misc + 8));
@@ -1640,56 +1661,65 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SysDev* __restrict__ 
             for (uint32_t c = tid; c < ncell; c += kSpreadThreads) cnt[c] = 0;
         }
         grid.sync();
-        for (uint32_t m = gtid; m < M; m += GT) {
-            const uint32_t c = C.cellid[m];
-            C.list[C.cellb[c] + atomicAdd(&fill[c], 1u)] = (uint16_t)m;
+        if (run) {
+            for (uint32_t m = gtid; m < M; m += GT) {
+                const uint32_t c = C.cellid[m];
+                C.list[C.cellb[c] + atomicAdd(&fill[c], 1u)] = (uint16_t)m;
+            }
         }
         grid.sync();
         // ascending molecule index inside every cell
-        for (uint32_t c = gtid; c < ncell; c += GT) {
-            const uint32_t b = C.cellb[c], e = C.cellb[c + 1];
-            for (uint32_t i = b + 1; i < e; ++i) {
-                const uint16_t v = C.list[i];
-                uint32_t q = i;
-                while (q > b && C.list[q - 1] > v) {
-                    C.list[q] = C.list[q - 1];
-                    --q;
+        if (run) {
+            for (uint32_t c = gtid; c < ncell; c += GT) {
+                const uint32_t b = C.cellb[c], e = C.cellb[c + 1];
+                for (uint32_t i = b + 1; i < e; ++i) {
+                    const uint16_t v = C.list[i];
+                    uint32_t q = i;
+                    while (q > b && C.list[q - 1] > v) {
+                        C.list[q] = C.list[q - 1];
+                        --q;
+                    }
+                    C.list[q] = v;
                 }
-                C.list[q] = v;
+                fill[c] = 0;
             }
-            fill[c] = 0;
         }
         grid.sync();
 
         const PhaseConst P = phase_const(C, sweep);
         const View<Real> V{S.com, S.site, kCap};
-        for (int col = 0; col < ncol; ++col) {
-            const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
-            for (uint32_t a = gw; a < nact; a += NW) {
-                const int cx = kx + k * (int)(a % na), cy = ky + k * (int)((a / na) % na),
-                          cz = kz + k * (int)(a / (na * na));
-                const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
-                const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
-                if (ccnt == 0) continue;
-                const double bx0 = hx + ((double)cx + 0.5) * C.w;
-                const double by0 = hy + ((double)cy + 0.5) * C.w;
-                const double bz0 = hz + ((double)cz + 0.5) * C.w;
-                uint32_t total;
-                const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
-                bool overflow;
-                const uint32_t ns = stage_cell(C, P, nseg, total, bx0, by0, bz0, cbeg, ccnt, W, S, overflow);
-                const NearRegs nr = near_regs(W.near, ns, overflow);
-                cell_trials<Real, false, true>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0, nr,
-                                               overflow, nseg, total, S.own, W, wc);
+        for (int col = 0; col < max_colours; ++col) {
+            if (run && col < ncol) {
+                const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
+                for (uint32_t a = gw; a < nact; a += NW) {
+                    const int cx = kx + k * (int)(a % na), cy = ky + k * (int)((a / na) % na),
+                              cz = kz + k * (int)(a / (na * na));
+                    const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
+                    const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
+                    if (ccnt == 0) continue;
+                    const double bx0 = hx + ((double)cx + 0.5) * C.w;
+                    const double by0 = hy + ((double)cy + 0.5) * C.w;
+                    const double bz0 = hz + ((double)cz + 0.5) * C.w;
+                    uint32_t total;
+                    const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
+                    bool overflow;
+                    const uint32_t ns =
+                        stage_cell(C, P, nseg, total, bx0, by0, bz0, cbeg, ccnt, W, S, overflow);
+                    const NearRegs nr = near_regs(W.near, ns, overflow);
+                    cell_trials<Real, false, true>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0,
+                                                   nr, overflow, nseg, total, S.own, W, wc);
+                }
             }
             grid.sync();
         }
         // accepted dE of the sweep, added in wave order; E/M samples
-        if (lane == 0) C.gpart[gw] = wc.e;
-        wc.e = 0.0;
-        ++sweep;
+        if (run) {
+            if (lane == 0) C.gpart[gw] = wc.e;
+            wc.e = 0.0;
+            ++sweep;
+        }
         grid.sync();
-        if (blockIdx.x == 0 && tid == 0) {
+        if (run && bid == 0 && tid == 0) {
             for (uint32_t w = 0; w < NW; ++w) e_acc += C.gpart[w];
             const uint64_t t = sweep - origin;
             if (t >= C.obs_start && C.obs_interval && t % C.obs_interval == 0) {
@@ -1713,7 +1743,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(SysDev* __restrict__ 
         if (wc.terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)wc.terms);
         if (wc.tests) atomicAdd((unsigned long long*)&st->pair_tests, (unsigned long long)wc.tests);
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (bid == 0 && tid == 0) {
         st->sweep = sweep;
         st->e_acc = e_acc;
     }
@@ -1840,11 +1870,15 @@ hipError_t spread_max_blocks_t(uint32_t* n_blocks)
 }
 
 template <typename Real>
-hipError_t launch_spread_t(SysDev* dev_sys, uint64_t n_sweeps, uint32_t n_blocks, hipStream_t stream)
+hipError_t launch_spread_t(const SpreadSlot* dev_slots, uint32_t n_slots, const SpreadSlot& one,
+                           uint64_t max_sweeps, int max_colours, uint32_t n_blocks,
+                           hipStream_t stream)
 {
     hipError_t e = spread_configure<Real>();
     if (e != hipSuccess) return e;
-    void* args[] = {(void*)&dev_sys, (void*)&n_sweeps};
+    SpreadSlot o = one;
+    void* args[] = {(void*)&dev_slots, (void*)&n_slots, (void*)&o, (void*)&max_sweeps,
+                    (void*)&max_colours};
     return hipLaunchCooperativeKernel((const void*)&k_spread<Real>, dim3(n_blocks),
                                       dim3(kSpreadThreads), args,
                                       spread_lds_bytes(sizeof(Real) == 8), stream);
@@ -1857,11 +1891,14 @@ hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks)
     return fp64 ? spread_max_blocks_t<double>(n_blocks) : spread_max_blocks_t<float>(n_blocks);
 }
 
-hipError_t launch_spread(bool fp64, SysDev* dev_sys, uint64_t n_sweeps, uint32_t n_blocks,
-                         hipStream_t stream)
+hipError_t launch_spread(bool fp64, const SpreadSlot* dev_slots, uint32_t n_slots,
+                         const SpreadSlot& one, uint64_t max_sweeps, int max_colours,
+                         uint32_t n_blocks, hipStream_t stream)
 {
-    return fp64 ? launch_spread_t<double>(dev_sys, n_sweeps, n_blocks, stream)
-                : launch_spread_t<float>(dev_sys, n_sweeps, n_blocks, stream);
+    return fp64 ? launch_spread_t<double>(dev_slots, n_slots, one, max_sweeps, max_colours,
+                                          n_blocks, stream)
+                : launch_spread_t<float>(dev_slots, n_slots, one, max_sweeps, max_colours,
+                                         n_blocks, stream);
 }
 
 hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t stream)

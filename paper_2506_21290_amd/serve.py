@@ -6,8 +6,8 @@ soon as a slot and enough of the memory budget are free, and every launch
 advances all admitted jobs by one time slice, so jobs that arrive while others
 run join the next launch and their work overlaps on the device.  Systems whose
 working set fits one workgroup's LDS share one persistent batched launch;
-larger ones run on the multi-workgroup engine, one slice after another on a
-stream of their own, side by side with the batch.
+larger ones share cooperative launches of the multi-workgroup engine (each on
+its own workgroups), on a second stream, side by side with the first batch.
 
 The time slice is given in attempted moves per job; the engine scales it by
 its model of per-workgroup throughput against system size (small systems run
@@ -74,90 +74,54 @@ def gofr_normalised(obs, n_sites, box):
 
 
 class GpuBackend:
-    """Jobs as flipmc systems.  A job whose state fits one workgroup's LDS
-    joins batch 0; a larger one runs alone on the multi-workgroup engine on a
-    stream of its own kind (lane 2), one time slice at a time, or — with
-    spread=False — joins batch 1 with one workgroup per system."""
+    """Jobs as flipmc systems in two batches on two streams: batch 0 holds the
+    jobs whose state fits one workgroup's LDS (one persistent launch, one
+    workgroup per job), batch 1 the larger ones, which the batch advances
+    together in one cooperative launch of the multi-workgroup engine (each job
+    on its own workgroups; as many as fit, in rotation)."""
 
-    def __init__(self, precision=flipmc.MC_FP32_DE, max_slots=1024, spread=True):
+    def __init__(self, precision=flipmc.MC_FP32_DE, max_slots=1024):
         import torch
 
         self.torch = torch
         self.precision = precision
         self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]
         self.admit_stream = torch.cuda.Stream()
-        self.spread_stream = torch.cuda.Stream()
         self.batches = [flipmc.Batch(max_slots, precision, stream=s) for s in self.streams]
         self.max_slots = max_slots
-        self.use_spread = spread
-        self.spread_jobs = {}  # slot -> [system, sweeps not yet enqueued, M, event of the last slice]
-        self.next_spread = 0
 
     def size(self, job):
-        """(bytes of device memory, lane)"""
+        """(bytes of device memory, batch index)"""
         p = job_params(job, self.precision)
         engine, _ = flipmc.mc_engine(p)
-        if engine == flipmc.MC_ENGINE_LDS:
-            lane = 0
-        elif engine == flipmc.MC_ENGINE_SPREAD and self.use_spread:
-            lane = 2
-        else:
-            lane = 1
-        return flipmc.mc_required_bytes(p), lane
+        return flipmc.mc_required_bytes(p), 0 if engine == flipmc.MC_ENGINE_LDS else 1
 
     def free_slots(self, bi):
-        if bi == 2:
-            return self.max_slots - len(self.spread_jobs)
         return self.max_slots - len(self.batches[bi].members)
 
     def start(self, job, bi):
-        if bi == 2:
-            s = flipmc.System(job_params(job, self.precision), stream=self.spread_stream)
-            slot = self.next_spread
-            self.next_spread += 1
-            self.spread_jobs[slot] = [s, job.sweeps, job.n_molecules, None]
-            return slot, s
         with self.torch.cuda.stream(self.admit_stream):
             s = flipmc.System(job_params(job, self.precision), stream=self.admit_stream)
         return self.batches[bi].add(s, job.sweeps), s
 
     def launch(self, quantum_moves):
-        """One time slice of every running job; returns the number of launches."""
         n = 0
         for b in self.batches:
             if b.members:
                 b.run(quantum_moves)
                 n += 1
-        # spread jobs: the next slice of each job whose previous one is done
-        for rec in self.spread_jobs.values():
-            s, left, M, ev = rec
-            if left == 0 or (ev is not None and not ev.query()):
-                continue
-            k = min(left, max(1, quantum_moves // M))
-            s.sweep(k)
-            rec[1] = left - k
-            ev = self.torch.cuda.Event()
-            ev.record(self.spread_stream)
-            rec[3] = ev
-            n += 1
         return n
 
     def harvest(self):
-        """[(lane, slot, system)] of finished jobs."""
+        """[(batch index, slot, system)] of finished jobs."""
         out = []
         for bi, b in enumerate(self.batches):
             if b.members:
                 out += [(bi, slot, s) for slot, s in b.poll()]
-        for slot in [k for k, r in self.spread_jobs.items() if r[1] == 0 and r[3].query()]:
-            out.append((2, slot, self.spread_jobs.pop(slot)[0]))
         return out
 
     def cancel(self, bi, slot):
-        if bi == 2:
-            self.spread_stream.synchronize()
-            del self.spread_jobs[slot]
-        else:
-            self.batches[bi].cancel(slot)
+        self.batches[bi].cancel(slot)
 
     def result(self, job, s):
         obs = s.observables()

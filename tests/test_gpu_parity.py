@@ -286,8 +286,11 @@ def test_checkpoint_resume_is_exact():
 def test_batch_equals_alone(fp32):
     # one persistent launch over uneven systems gives bitwise the results of
     # running each alone
-    specs = [(64, 3.0, 2, 2, 3), (216, 1.0, 3, 6, 4), (343, 0.8, 3, 6, 5), (216, 2.0, 2, 2, 6)]
-    sweeps = [30, 17, 25, 9]
+    # the last two are beyond one workgroup's LDS: they share the batch's
+    # cooperative launches of the multi-workgroup engine, as they run alone
+    specs = [(64, 3.0, 2, 2, 3), (216, 1.0, 3, 6, 4), (343, 0.8, 3, 6, 5), (216, 2.0, 2, 2, 6),
+             (2197, 1.3, 2, 4, 7), (2744, 2.2, 2, 6, 8)]
+    sweeps = [30, 17, 25, 9, 14, 11]
     alone = []
     for (M, T, k, nc, seed), n in zip(specs, sweeps):
         s = flipmc.System(gparams(M, T, k, nc, fp32=fp32, seed=seed))
