@@ -241,11 +241,12 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
  * MC_EBUSY, and the reading calls first synchronise the batch's stream. */
 int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
 
-/* Enqueue one launch in which each occupied slot runs up to
- * max(1, max_moves_per_slot * f(M) / M) of its remaining sweeps, where
- * f(M) = min(1, 0.25 + 0.75 M / 1000) equalises the time slices of large and
- * small systems (0 = all remaining); systems on the multi-workgroup engine
- * run max(1, max_moves_per_slot / 1000) sweeps.  Launches also stop at each
+/* Enqueue one launch in which each occupied slot runs a time slice of its
+ * remaining sweeps (0 = all remaining): the modelled time of
+ * max_moves_per_slot moves of a 1000-molecule system (k = 2, n_c = 4) on one
+ * workgroup, converted with the same model into sweeps of the slot's system
+ * (at least one); systems on the multi-workgroup engine run
+ * max(1, max_moves_per_slot / 1000) sweeps.  Launches also stop at each
  * system's re-sum / g(r) / C_2 sweeps, whose work follows in a second launch.
  * *n_launched = number of launches enqueued. */
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched);

@@ -80,6 +80,7 @@ struct Geometry {
     bool spread;          // standalone sweeps on the multi-workgroup engine
     uint32_t spread_blocks;
     size_t lds;
+    double sweep_cost;    // modelled cycles of one sweep on one workgroup
 };
 
 // Critical path of one sweep of the resident kernel in cycles (a model fitted
@@ -162,6 +163,7 @@ int geometry(const mc_params* p, Geometry* g)
     g->lds = g->resident ? res.total : lds_layout(fp64, false, p->n_molecules, g->ncell).total;
     g->spread = !g->resident && !(p->flags & MC_FLAG_SINGLE_WORKGROUP);
     g->spread_blocks = 1;
+    g->sweep_cost = cost_estimate(p->n_molecules, g->L, g->reach, k, nc);
     if (g->spread) {
         // one wave per cell of a colour, within one cooperative wave of the device
         uint32_t maxb = 0;
@@ -176,6 +178,18 @@ int geometry(const mc_params* p, Geometry* g)
         }
     }
     return MC_OK;
+}
+
+// Modelled cycles of a time slice of max_moves moves of the 1000-molecule
+// reference system (k = 2, n_c = 4) on one workgroup.
+double slice_time(uint64_t max_moves)
+{
+    static const double ref = [] {
+        const double L = std::cbrt(3.0 * 1000.0 / 1.2);
+        const double reach = std::pow(2.0, 1.0 / 6.0) * 1.1 + 2.0 * bond_star() / std::sqrt(3.0);
+        return cost_estimate(1000, L, reach, 2, 4);
+    }();
+    return (double)max_moves / 1000.0 * ref;
 }
 
 // Workgroups of the multi-workgroup event kernel for M molecules (one
@@ -893,7 +907,6 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
         (void)hipGetLastError();
         b->spread_max = 0;
     }
-    b->spread_max = std::min(b->spread_max, (uint32_t)(kMaxParts / kSpreadWaves));
     *out = b;
     return MC_OK;
 }
@@ -943,12 +956,10 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         }
         uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
         if (max_moves_per_slot) {
-            // equal time slices: a workgroup's moves/s falls for small systems
-            // (fewer independent cells per colour phase)
-            const double M = (double)s->p.n_molecules;
-            const double rate = std::min(1.0, 0.25 + 0.75 * M / 1000.0);
-            const uint64_t cap = (uint64_t)((double)max_moves_per_slot * rate / M);
-            k = std::min<uint64_t>(k, std::max<uint64_t>(1, cap));
+            // equal time slices: the time of max_moves_per_slot moves of the
+            // 1000-molecule reference, in sweeps of this system (modelled)
+            const double cap = slice_time(max_moves_per_slot) / s->g.sweep_cost;
+            k = std::min<uint64_t>(k, std::max<uint64_t>(1, (uint64_t)cap));
         }
         const int cls = s->g.resident ? 0 : 1;
         Slot sl{};

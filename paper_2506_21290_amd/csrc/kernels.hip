@@ -795,27 +795,38 @@ __device__ __forceinline__ PassSum<Real> item_pair_pass(const View<Real>& V, dou
                                                         uint32_t base, uint32_t nit, Real rc2f)
 {
     const uint32_t S = V.stride;
+    const bool two = nit - base > 64u;  // wave-uniform: the second pass has items
     const uint32_t itA = base + (uint32_t)__lane_id(), itB = itA + 64u;
     const bool vA = itA < nit, vB = itB < nit;
     const uint32_t cA = vA ? itA : 0u, cB = vB ? itB : 0u;
     const uint32_t sA = cA / 3u, sB = cB / 3u;
     const uint32_t tA = cA - 3u * sA, tB = cB - 3u * sB;
-    const uint32_t jA = surv[sA], jB = surv[sB];
+    const uint32_t jA = surv[sA];
+    uint32_t jB = 0;
+    if (two) jB = surv[sB];
     const double xA = V.com[jA], yA = V.com[S + jA], zA = V.com[2 * S + jA];
-    const double xB = V.com[jB], yB = V.com[S + jB], zB = V.com[2 * S + jB];
-    const R4<Real> gA = V.site[3u * jA + tA], gB = V.site[3u * jB + tB];
+    const R4<Real> gA = V.site[3u * jA + tA];
+    double xB = 0.0, yB = 0.0, zB = 0.0;
+    R4<Real> gB{};
+    if (two) {
+        xB = V.com[jB]; yB = V.com[S + jB]; zB = V.com[2 * S + jB];
+        gB = V.site[3u * jB + tB];
+    }
     __builtin_amdgcn_sched_barrier(0);
     Real sa = Real(0), sb = Real(0);
     uint32_t terms = 0;
-    const Real da = item_terms<kMove, kLog>(mv, L, invL, xA, yA, zA, gA, vA, rc2f, sa, terms);
-    const Real db = item_terms<kMove, kLog>(mv, L, invL, xB, yB, zB, gB, vB, rc2f, sb, terms);
-    return PassSum<Real>{da + db, sa + sb, terms};
+    Real d = item_terms<kMove, kLog>(mv, L, invL, xA, yA, zA, gA, vA, rc2f, sa, terms);
+    if (two) d += item_terms<kMove, kLog>(mv, L, invL, xB, yB, zB, gB, vB, rc2f, sb, terms);
+    return PassSum<Real>{d, sa + sb, terms};
 }
 
 // Per-phase constants of the trial loop.
 struct PhaseConst {
     double half_w, reach_box, step;
-    float prune2;
+    float prune2;        // largest prune radius squared (3e38 when pruning is off)
+    float pr_base, pr_step;  // radius = pr_base + pr_step * (own translation + same cell)
+    float box_in;        // |relative centre| per axis below which an entry is in the cell
+    bool prune_on;
     bool logging;
 };
 
@@ -836,6 +847,13 @@ __device__ __forceinline__ PhaseConst phase_const(const Ctx<Real, kRes>& C, uint
     // (and FP16 keeps the rounding below the 0.02 margin only up to |r| < 16)
     const bool prune_ok = P.half_w + (double)prune_r + P.step < fmin(0.5 * C.L - 1e-3, 16.0);
     P.prune2 = prune_ok ? prune_r * prune_r : 3.0e38f;
+    P.prune_on = prune_ok;
+    // the margins a trial needs: its own move when it translates the
+    // molecule, and the moves made earlier in this cell by molecules of the
+    // cell (no other molecule within reach moves during the colour phase)
+    P.pr_base = (float)(reach + 0.02);
+    P.pr_step = (float)P.step;
+    P.box_in = (float)(P.half_w + 0.05);
     return P;
 }
 
@@ -1095,11 +1113,17 @@ __device__ void cell_trials(const Ctx<Real, kRes>& C, const View<Real>& Vn, cons
             // 2. prune and compact the survivors
             if (!overflow) {
                 uint32_t nsurv = 0;
+                const float r_far = P.pr_base + (move == 0u ? P.pr_step : 0.f);
+                const float r_near = r_far + P.pr_step;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const float px = nr.x[c] - tmx, py = nr.y[c] - tmy, pz = nr.z[c] - tmz;
+                    const bool in_cell = fabsf(nr.x[c]) <= P.box_in && fabsf(nr.y[c]) <= P.box_in &&
+                                         fabsf(nr.z[c]) <= P.box_in;
+                    const float rr = in_cell ? r_near : r_far;
+                    const float lim = P.prune_on ? rr * rr : P.prune2;
                     const bool keep = nr.j[c] != kNoMolecule && nr.j[c] != mloc &&
-                                      px * px + py * py + pz * pz < P.prune2;
+                                      px * px + py * py + pz * pz < lim;
                     const uint64_t bm = __ballot(keep);
                     if (keep) W.surv[nsurv + rank_below(bm)] = (uint16_t)nr.j[c];
                     nsurv += (uint32_t)__popcll(bm);
@@ -1710,15 +1734,16 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                                                    nr, overflow, nseg, total, S.own, W, wc);
                 }
             }
+            if (col == max_colours - 1 && run) {
+                // the wave's accepted dE of the sweep, for the sum in wave order
+                if (lane == 0) C.gpart[gw] = wc.e;
+                wc.e = 0.0;
+                ++sweep;
+            }
             grid.sync();
         }
-        // accepted dE of the sweep, added in wave order; E/M samples
-        if (run) {
-            if (lane == 0) C.gpart[gw] = wc.e;
-            wc.e = 0.0;
-            ++sweep;
-        }
-        grid.sync();
+        // E_acc += the sweep's dE in wave order; E/M samples (the next
+        // sweep's steps touch neither)
         if (run && bid == 0 && tid == 0) {
             for (uint32_t w = 0; w < NW; ++w) e_acc += C.gpart[w];
             const uint64_t t = sweep - origin;
