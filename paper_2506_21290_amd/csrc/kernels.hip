@@ -568,6 +568,53 @@ __device__ void gofr_frame(const Ctx<Real, kRes>& C, uint32_t m0, uint32_t mstep
     if (threadIdx.x == 0 && !shared_out) C.stats->n_gofr += 1;
 }
 
+// Ascending molecule index inside every cell of cells c0, c0 + cstep, ...,
+// one wave per cell and a lane per molecule: its new place is the number of
+// smaller indices in the cell.  Up to 8 cells of a wave have their loads in
+// flight together; a cell of more than 64 molecules is sorted by one lane.
+__device__ void sort_cells(uint16_t* list, const uint32_t* cellb, uint32_t c0, uint32_t cstep,
+                           uint32_t ncell)
+{
+    const uint32_t lane = (uint32_t)__lane_id();
+    for (uint32_t cg = c0; cg < ncell; cg += 8u * cstep) {
+        uint32_t b[8], n[8], v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint32_t c = cg + (uint32_t)r * cstep;
+            b[r] = 0;
+            n[r] = 0;
+            if (c < ncell) {
+                b[r] = cellb[c];
+                n[r] = cellb[c + 1] - b[r];
+            }
+            b[r] = (uint32_t)__builtin_amdgcn_readfirstlane((int)b[r]);
+            n[r] = (uint32_t)__builtin_amdgcn_readfirstlane((int)n[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = lane < n[r] && n[r] <= 64u ? list[b[r] + lane] : 0xFFFFu;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (n[r] <= 1u) continue;
+            if (n[r] <= 64u) {
+                uint32_t rank = 0;
+                for (uint32_t q = 0; q < n[r]; ++q) rank += rl_u(v[r], (int)q) < v[r] ? 1u : 0u;
+                if (lane < n[r]) list[b[r] + rank] = (uint16_t)v[r];
+            } else if (lane == 0) {
+                const uint32_t lo = b[r], hi = b[r] + n[r];
+                for (uint32_t i = lo + 1; i < hi; ++i) {
+                    const uint16_t x = list[i];
+                    uint32_t q = i;
+                    while (q > lo && list[q - 1] > x) {
+                        list[q] = list[q - 1];
+                        --q;
+                    }
+                    list[q] = x;
+                }
+            }
+        }
+    }
+}
+
 // Cell grid of one sweep: counting sort of molecules by cell.
 template <typename Real, bool kRes>
 __device__ void build_cells(const Ctx<Real, kRes>& C, double hx, double hy, double hz,
@@ -592,19 +639,7 @@ __device__ void build_cells(const Ctx<Real, kRes>& C, double hx, double hy, doub
         C.list[pos] = (uint16_t)m;
     }
     __syncthreads();
-    // ascending molecule index inside every cell
-    for (uint32_t c = threadIdx.x; c < ncell; c += kThreads) {
-        const uint32_t b = C.cellb[c], e = C.cellb[c + 1];
-        for (uint32_t i = b + 1; i < e; ++i) {
-            const uint16_t v = C.list[i];
-            uint32_t q = i;
-            while (q > b && C.list[q - 1] > v) {
-                C.list[q] = C.list[q - 1];
-                --q;
-            }
-            C.list[q] = v;
-        }
-    }
+    sort_cells(C.list, C.cellb, threadIdx.x >> 6, kWaves, ncell);
     __syncthreads();
 }
 
@@ -881,16 +916,33 @@ __device__ __forceinline__ NearRegs near_regs(const NearEntry* near, uint32_t nn
     return r;
 }
 
+// Where the multi-workgroup engine stages a cell's neighbourhood (per-wave
+// LDS): centres, sites, the molecule of each slot and the slot of each of the
+// cell's own molecules.
+template <typename Real>
+struct StageLds {
+    double* com;     // [3][kCellListCap] centres
+    R4<Real>* site;  // [3 * kCellListCap] site offsets + sigma
+    uint16_t* gid;   // molecule of each slot
+    uint16_t* own;   // slot of the cell's q-th molecule
+};
+
 // Molecules whose centre is within reach of the box of a cell centred at
-// (bx0, by0, bz0), from the stencil segments of the cell list: their indices
-// and relative centres go to near[]; returns the count (overflow set when it
-// exceeds the list capacity).  Two molecules per lane and step, loads issued
-// before arithmetic.
-template <typename Real, bool kRes>
-__device__ uint32_t build_near(const Ctx<Real, kRes>& C, const PhaseConst& P, int nseg,
-                               uint32_t total, double bx0, double by0, double bz0,
-                               const WaveLds<Real>& W, bool& overflow)
+// (bx0, by0, bz0), from the stencil segments of the cell list, into the near
+// list (index and FP16 relative centre; returns the count, sets overflow past
+// the list capacity).  The lanes are split evenly over the segments and take
+// kPer molecules each per step, loads issued before arithmetic; the list order
+// (step, then molecule rank within the step, then lane) is the same in both
+// engines.  With kStage the molecules are also copied to S (centres, sites) and
+// the list holds their slots; the cell's own molecules (list positions
+// cbeg .. cbeg + ccnt) get their slots in S.own.
+template <typename Real, bool kRes, bool kStage>
+__device__ uint32_t gather_near(const Ctx<Real, kRes>& C, const PhaseConst& P, int nseg,
+                                uint32_t total, double bx0, double by0, double bz0, uint32_t cbeg,
+                                uint32_t ccnt, const WaveLds<Real>& W, const StageLds<Real>& S,
+                                bool& overflow)
 {
+    constexpr int kPer = 4;
     const int lane = __lane_id();
     const uint32_t M = C.M;
     const int per = 64 / nseg;  // lanes per segment (nseg <= 50)
@@ -905,48 +957,88 @@ __device__ uint32_t build_near(const Ctx<Real, kRes>& C, const PhaseConst& P, in
 #pragma unroll
     for (int o = 32; o; o >>= 1) longest = max(longest, (uint32_t)__shfl_xor(longest, o));
     const bool seg_ok = my_seg < nseg;
-    const uint32_t step2 = 2u * (uint32_t)per;
+    const uint32_t step = (uint32_t)(kPer * per);
     uint32_t nnear = 0;
     overflow = false;
-    for (uint32_t t0 = 0; t0 < longest; t0 += step2) {
-        const uint32_t tA = t0 + (uint32_t)my_sub, tB = tA + (uint32_t)per;
-        const bool vA = seg_ok && tA < my_len, vB = seg_ok && tB < my_len;
-        const uint32_t jA = C.list[vA ? my_lo + tA : 0u];
-        const uint32_t jB = C.list[vB ? my_lo + tB : 0u];
-        const double xA = C.com[jA], yA = C.com[M + jA], zA = C.com[2 * M + jA];
-        const double xB = C.com[jB], yB = C.com[M + jB], zB = C.com[2 * M + jB];
+    for (uint32_t t0 = 0; t0 < longest; t0 += step) {
+        uint32_t li[kPer], jj[kPer];
+        bool vv[kPer];
+        double xx[kPer], yy[kPer], zz[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const uint32_t t = t0 + (uint32_t)(my_sub + u * per);
+            vv[u] = seg_ok && t < my_len;
+            li[u] = vv[u] ? my_lo + t : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) jj[u] = C.list[li[u]];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            xx[u] = C.com[jj[u]];
+            yy[u] = C.com[M + jj[u]];
+            zz[u] = C.com[2 * M + jj[u]];
+        }
         __builtin_amdgcn_sched_barrier(0);
-        const double rxA = min_image(xA - bx0, C.L, C.invL), ryA = min_image(yA - by0, C.L, C.invL),
-                     rzA = min_image(zA - bz0, C.L, C.invL);
-        const double rxB = min_image(xB - bx0, C.L, C.invL), ryB = min_image(yB - by0, C.L, C.invL),
-                     rzB = min_image(zB - bz0, C.L, C.invL);
-        const double exA = fmax(fabs(rxA) - P.half_w, 0.0), eyA = fmax(fabs(ryA) - P.half_w, 0.0),
-                     ezA = fmax(fabs(rzA) - P.half_w, 0.0);
-        const double exB = fmax(fabs(rxB) - P.half_w, 0.0), eyB = fmax(fabs(ryB) - P.half_w, 0.0),
-                     ezB = fmax(fabs(rzB) - P.half_w, 0.0);
-        const bool keepA = vA && exA * exA + eyA * eyA + ezA * ezA < P.reach_box;
-        const bool keepB = vB && exB * exB + eyB * eyB + ezB * ezB < P.reach_box;
-        const uint64_t bmA = __ballot(keepA), bmB = __ballot(keepB);
-        const uint32_t npA = (uint32_t)__popcll(bmA), npB = (uint32_t)__popcll(bmB);
-        if (nnear + npA + npB > kListCap) {
+        float fx[kPer], fy[kPer], fz[kPer];
+        uint64_t bm[kPer];
+        uint32_t base[kPer + 1];
+        base[0] = nnear;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const double rx = min_image(xx[u] - bx0, C.L, C.invL);
+            const double ry = min_image(yy[u] - by0, C.L, C.invL);
+            const double rz = min_image(zz[u] - bz0, C.L, C.invL);
+            const double ex = fmax(fabs(rx) - P.half_w, 0.0), ey = fmax(fabs(ry) - P.half_w, 0.0),
+                         ez = fmax(fabs(rz) - P.half_w, 0.0);
+            vv[u] = vv[u] && ex * ex + ey * ey + ez * ez < P.reach_box;
+            bm[u] = __ballot(vv[u]);
+            base[u + 1] = base[u] + (uint32_t)__popcll(bm[u]);
+            fx[u] = (float)rx; fy[u] = (float)ry; fz[u] = (float)rz;
+        }
+        if (base[kPer] > kListCap) {
             overflow = true;
             break;
         }
-        if (keepA) {
-            NearEntry e;
-            e.j = (uint16_t)jA;
-            e.rx = (__fp16)(float)rxA; e.ry = (__fp16)(float)ryA; e.rz = (__fp16)(float)rzA;
-            W.near[nnear + rank_below(bmA)] = e;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (vv[u]) {
+                const uint32_t slot = base[u] + rank_below(bm[u]);
+                NearEntry e;
+                e.j = (uint16_t)(kStage ? slot : jj[u]);
+                e.rx = (__fp16)fx[u]; e.ry = (__fp16)fy[u]; e.rz = (__fp16)fz[u];
+                W.near[slot] = e;
+                if (kStage) {
+                    S.com[slot] = xx[u];
+                    S.com[kListCap + slot] = yy[u];
+                    S.com[2 * kListCap + slot] = zz[u];
+                    S.gid[slot] = (uint16_t)jj[u];
+                    const uint32_t q = li[u] - cbeg;
+                    if (q < ccnt && q < kListCap) S.own[q] = (uint16_t)slot;
+                }
+            }
         }
-        if (keepB) {
-            NearEntry e;
-            e.j = (uint16_t)jB;
-            e.rx = (__fp16)(float)rxB; e.ry = (__fp16)(float)ryB; e.rz = (__fp16)(float)rzB;
-            W.near[nnear + npA + rank_below(bmB)] = e;
-        }
-        nnear += npA + npB;
+        nnear = base[kPer];
     }
     wave_lds_sync();
+    if (kStage && !overflow) {
+        // the staged molecules' sites, three slots per lane, loads first
+        R4<Real> st[9];
+        uint32_t sl[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sl[c] = (uint32_t)lane + 64u * c;
+            const uint32_t g = sl[c] < nnear ? (uint32_t)S.gid[sl[c]] : 0u;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) st[3 * c + t] = C.site[3 * g + t];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (sl[c] < nnear)
+#pragma unroll
+                for (int t = 0; t < 3; ++t) S.site[3 * sl[c] + t] = st[3 * c + t];
+        wave_lds_sync();
+    }
     return nnear;
 }
 
@@ -1241,7 +1333,8 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
         uint32_t total;
         const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
         bool overflow;
-        const uint32_t nnear = build_near(C, P, nseg, total, bx0, by0, bz0, W, overflow);
+        const uint32_t nnear = gather_near<Real, kRes, false>(C, P, nseg, total, bx0, by0, bz0, 0u, 0u,
+                                                             W, StageLds<Real>{}, overflow);
         const NearRegs nr = near_regs(W.near, nnear, overflow);
         cell_trials<Real, kRes, false>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0, nr,
                                        overflow, nseg, total, nullptr, W, wc);
@@ -1480,107 +1573,6 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
 // exactly as in the single-workgroup engine, so the decisions are the same.
 
 // The staged neighbourhood of the cell a wave is working on.
-template <typename Real>
-struct StageLds {
-    double* com;     // [3][kCellListCap] centres
-    R4<Real>* site;  // [3 * kCellListCap] site offsets + sigma
-    uint16_t* gid;   // molecule of each slot
-    uint16_t* own;   // slot of the cell's q-th molecule
-};
-
-// Stage the molecules within reach of the box of the cell centred at
-// (bx0, by0, bz0): centres, sites, near list (slots and FP16 relative centres)
-// and the slots of the cell's own molecules.  Returns the number of slots; sets
-// overflow when the stencil or the neighbourhood is larger than the staging
-// area (the cell then runs on the HBM state).
-template <typename Real>
-__device__ uint32_t stage_cell(const Ctx<Real, false>& C, const PhaseConst& P, int nseg,
-                               uint32_t total, double bx0, double by0, double bz0, uint32_t cbeg,
-                               uint32_t ccnt, const WaveLds<Real>& W, const StageLds<Real>& S,
-                               bool& overflow)
-{
-    const int lane = __lane_id();
-    const uint32_t M = C.M;
-    overflow = total > 64u * kSpreadPerLane || ccnt > kListCap;
-    if (overflow) return 0;
-    uint32_t li[kSpreadPerLane], jj[kSpreadPerLane];
-    bool vv[kSpreadPerLane];
-#pragma unroll
-    for (int r = 0; r < kSpreadPerLane; ++r) {
-        const uint32_t idx = (uint32_t)lane + 64u * r;
-        vv[r] = idx < total;
-        li[r] = 0;
-        if (64u * r < total && vv[r]) {
-            int lo = 0, hi = nseg;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if ((uint32_t)W.segoff[mid] <= idx) lo = mid; else hi = mid;
-            }
-            li[r] = (uint32_t)W.seglo[lo] + (idx - (uint32_t)W.segoff[lo]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < kSpreadPerLane; ++r) jj[r] = C.list[li[r]];
-    double xx[kSpreadPerLane], yy[kSpreadPerLane], zz[kSpreadPerLane];
-#pragma unroll
-    for (int r = 0; r < kSpreadPerLane; ++r) {
-        xx[r] = C.com[jj[r]];
-        yy[r] = C.com[M + jj[r]];
-        zz[r] = C.com[2 * M + jj[r]];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    uint32_t n = 0;
-#pragma unroll
-    for (int r = 0; r < kSpreadPerLane; ++r) {
-        if (64u * r >= total) break;
-        const double rx = min_image(xx[r] - bx0, C.L, C.invL);
-        const double ry = min_image(yy[r] - by0, C.L, C.invL);
-        const double rz = min_image(zz[r] - bz0, C.L, C.invL);
-        const double ex = fmax(fabs(rx) - P.half_w, 0.0), ey = fmax(fabs(ry) - P.half_w, 0.0),
-                     ez = fmax(fabs(rz) - P.half_w, 0.0);
-        const bool keep = vv[r] && ex * ex + ey * ey + ez * ez < P.reach_box;
-        const uint64_t bm = __ballot(keep);
-        const uint32_t np = (uint32_t)__popcll(bm);
-        if (n + np > kListCap) {
-            overflow = true;
-            break;
-        }
-        if (keep) {
-            const uint32_t slot = n + rank_below(bm);
-            S.com[slot] = xx[r];
-            S.com[kListCap + slot] = yy[r];
-            S.com[2 * kListCap + slot] = zz[r];
-            S.gid[slot] = (uint16_t)jj[r];
-            NearEntry e;
-            e.j = (uint16_t)slot;
-            e.rx = (__fp16)(float)rx; e.ry = (__fp16)(float)ry; e.rz = (__fp16)(float)rz;
-            W.near[slot] = e;
-            if (li[r] - cbeg < ccnt) S.own[li[r] - cbeg] = (uint16_t)slot;
-        }
-        n += np;
-    }
-    if (overflow) return 0;
-    wave_lds_sync();
-    // the staged molecules' sites, three slots per lane, loads first
-    R4<Real> st[9];
-    uint32_t sl[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        sl[c] = (uint32_t)lane + 64u * c;
-        const uint32_t g = sl[c] < n ? (uint32_t)S.gid[sl[c]] : 0u;
-#pragma unroll
-        for (int t = 0; t < 3; ++t) st[3 * c + t] = C.site[3 * g + t];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        if (sl[c] < n)
-#pragma unroll
-            for (int t = 0; t < 3; ++t) S.site[3 * sl[c] + t] = st[3 * c + t];
-    wave_lds_sync();
-    return n;
-}
-
 // One launch can advance several systems: slot i owns workgroups
 // [first_block, first_block + n_blocks) and runs n_sweeps sweeps; every
 // workgroup takes part in every grid barrier (max_sweeps sweeps of max_colours
@@ -1694,19 +1686,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
         grid.sync();
         // ascending molecule index inside every cell
         if (run) {
-            for (uint32_t c = gtid; c < ncell; c += GT) {
-                const uint32_t b = C.cellb[c], e = C.cellb[c + 1];
-                for (uint32_t i = b + 1; i < e; ++i) {
-                    const uint16_t v = C.list[i];
-                    uint32_t q = i;
-                    while (q > b && C.list[q - 1] > v) {
-                        C.list[q] = C.list[q - 1];
-                        --q;
-                    }
-                    C.list[q] = v;
-                }
-                fill[c] = 0;
-            }
+            sort_cells(C.list, C.cellb, gw, NW, ncell);
+            for (uint32_t c = gtid; c < ncell; c += GT) fill[c] = 0;
         }
         grid.sync();
 
@@ -1727,8 +1708,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                     uint32_t total;
                     const int nseg = stencil_segments(C, cx, cy, cz, W.seglo, W.segoff, &total);
                     bool overflow;
-                    const uint32_t ns =
-                        stage_cell(C, P, nseg, total, bx0, by0, bz0, cbeg, ccnt, W, S, overflow);
+                    const uint32_t ns = gather_near<Real, false, true>(C, P, nseg, total, bx0, by0, bz0,
+                                                                       cbeg, ccnt, W, S, overflow);
                     const NearRegs nr = near_regs(W.near, ns, overflow);
                     cell_trials<Real, false, true>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0,
                                                    nr, overflow, nseg, total, S.own, W, wc);

@@ -133,6 +133,36 @@ def test_spread_engine_many_workgroups(fp32):
     run_parity(gp, oparams(1728, 0.9, 2, 6, seed=21), 4, fp32)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_engines_make_identical_decisions(fp32):
+    # the same system on the LDS engine, on one workgroup with the state in
+    # HBM and on the multi-workgroup engine: the same near lists in the same
+    # order, so the same dE bits, decisions and states
+    n = 12
+    runs = []
+    for flags, engine in [(0, flipmc.MC_ENGINE_LDS),
+                          (flipmc.MC_FLAG_HBM_STATE | flipmc.MC_FLAG_SINGLE_WORKGROUP,
+                           flipmc.MC_ENGINE_HBM),
+                          (flipmc.MC_FLAG_HBM_STATE, flipmc.MC_ENGINE_SPREAD)]:
+        gp = gparams(1000, 0.9, 2, 4, fp32=fp32, seed=31, flags=flags, resum_interval=0,
+                     obs_interval=0, gofr_interval=0)
+        assert flipmc.mc_engine(gp)[0] == engine
+        g = flipmc.System(gp)
+        g.decision_log(n)
+        g.sweep(n)
+        runs.append((g.read_log(), g.get_state()))
+    (l0, s0) = runs[0]
+    assert int(l0["accepted"].sum()) > 0
+    for lg, sg in runs[1:]:
+        assert np.array_equal(lg["delta_e"], l0["delta_e"])
+        assert np.array_equal(lg["accepted"], l0["accepted"])
+        assert np.array_equal(lg["pair_terms"], l0["pair_terms"])
+        assert np.array_equal(sg["com"], s0["com"])
+        assert np.array_equal(sg["quat"], s0["quat"])
+        assert np.array_equal(sg["types"], s0["types"])
+        assert abs(sg["e_acc"] - s0["e_acc"]) <= 1e-12 * (abs(s0["e_acc"]) + 1.0)
+
+
 def test_spread_engine_full_size_8000_sampled():
     # the 8000-molecule configuration (T = 1.1, FP32 dE) on its first sweeps,
     # with the engine's own decomposition, every trial checked
