@@ -161,8 +161,8 @@ int mc_placement(const mc_params* p, int* resident, size_t* lds_bytes);
 
 /* The engine mc_sweep uses for a system with these parameters (MC_ENGINE_*)
  * and, for MC_ENGINE_SPREAD, the number of workgroups of its launches
- * (*workgroups = 1 otherwise).  Systems inside a batch always run on one
- * workgroup each.  Either output may be NULL. */
+ * (*workgroups = 1 otherwise).  Inside a batch the engine is chosen per run
+ * (see mc_batch_run).  Either output may be NULL. */
 int mc_engine(const mc_params* p, int* engine, uint32_t* workgroups);
 
 /* Bytes of device memory mc_init_system needs for these parameters. */
@@ -224,14 +224,17 @@ const char* mc_last_error(void);
 
 /* ---- batches: many systems in one persistent launch ---------------------- */
 
-/* A batch holds up to max_slots systems of one precision.  mc_batch_run
- * advances systems that fit one workgroup's LDS (and those flagged
- * MC_FLAG_SINGLE_WORKGROUP) in one persistent launch, one workgroup per
- * system; larger systems share one cooperative launch of the multi-workgroup
- * engine on a second stream the batch creates, each on the workgroups it
- * uses alone (as many as the device holds at once, the first one rotating
- * from run to run).  A system gives bitwise the same results in a batch as
- * alone. */
+/* A batch holds up to max_slots systems of one precision.  Each
+ * mc_batch_run gives every system one workgroup; the workgroups left over
+ * (up to the batch's workgroup limit, one per compute unit by default) go to
+ * the systems beyond one workgroup's LDS with the most remaining work, which
+ * then run on the multi-workgroup engine, each on up to the workgroups it
+ * uses alone.  Systems on one workgroup share one persistent launch per
+ * placement class (state in LDS / in HBM); systems on the multi-workgroup
+ * engine share one cooperative launch on a second stream the batch creates.
+ * All engines make the same decisions and sum the energy in the same order,
+ * so a system gives bitwise the same results in a batch as alone, whichever
+ * engines its runs used. */
 int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc_batch** out);
 
 /* Put an initialised system into a free slot with n_sweeps of work; the
@@ -241,15 +244,21 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
  * MC_EBUSY, and the reading calls first synchronise the batch's stream. */
 int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
 
-/* Enqueue one launch in which each occupied slot runs a time slice of its
+/* Enqueue one run in which each occupied slot runs a time slice of its
  * remaining sweeps (0 = all remaining): the modelled time of
  * max_moves_per_slot moves of a 1000-molecule system (k = 2, n_c = 4) on one
  * workgroup, converted with the same model into sweeps of the slot's system
- * (at least one); systems on the multi-workgroup engine run
- * max(1, max_moves_per_slot / 1000) sweeps.  Launches also stop at each
- * system's re-sum / g(r) / C_2 sweeps, whose work follows in a second launch.
- * *n_launched = number of launches enqueued. */
+ * (at least one); a system on the multi-workgroup engine runs
+ * max(1, max_moves_per_slot / 1000) sweeps scaled by the fraction of its own
+ * workgroup count it got.  Slices also stop at each system's re-sum / g(r) /
+ * C_2 sweeps, whose work follows in a second launch.  *n_launched = number of
+ * sweep launches enqueued. */
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched);
+
+/* At most max_workgroups workgroups of the batch's runs at once (0 = one per
+ * compute unit of the current device, the default): fewer leaves compute units
+ * to other work and moves fewer systems onto the multi-workgroup engine. */
+int mc_batch_set_workgroups(mc_batch* b, uint32_t max_workgroups);
 
 /* Synchronise, then report (and free) the slots whose work is complete:
  * their slot indices and systems. */

@@ -202,7 +202,7 @@ uint32_t event_blocks(uint32_t M)
 
 struct BufLayout {
     size_t sys, stats, com, quat, types, u0, kref, esamp, dsamp, gall, ginter, c2, c2s;
-    size_t props, gpart, gsite, gcell, gcellid, glist, gcnt, total;
+    size_t props, gpart, gsite, gcell, gcellid, glist, gcnt, gecell, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -234,6 +234,7 @@ BufLayout buf_layout(const mc_params* p, const Geometry& g)
         b.gcellid = o; o = al(o + M * sizeof(uint16_t));
         b.glist = o;   o = al(o + M * sizeof(uint16_t));
         b.gcnt = o;    o = al(o + 2 * size_t(g.ncell) * sizeof(uint32_t));
+        b.gecell = o;  o = al(o + size_t(g.ncell) * sizeof(double));
     }
     b.total = o;
     return b;
@@ -280,7 +281,7 @@ struct mc_batch {
     hipEvent_t copied2[2];
     bool pending2[2];
     uint32_t spread_max;              // co-resident workgroups of the cooperative launch
-    uint32_t rr;                      // rotation of the first system considered
+    uint32_t wg_limit;                // workgroups that run at once (compute units)
 };
 
 namespace {
@@ -630,6 +631,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
         D.g_cellid = (uint16_t*)(b + lay.gcellid);
         D.g_list = (uint16_t*)(b + lay.glist);
         D.g_cnt = (uint32_t*)(b + lay.gcnt);
+        D.g_ecell = (double*)(b + lay.gecell);
     }
     s->dev = (SysDev*)(b + lay.sys);
 
@@ -870,7 +872,7 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
     b->stream2 = nullptr;
     b->go = b->done = nullptr;
     b->spread_max = 0;
-    b->rr = 0;
+    b->wg_limit = 0;
     for (int i = 0; i < 2; ++i) {
         b->dev_slots[i] = nullptr;
         b->host_slots[i] = nullptr;
@@ -907,6 +909,13 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
         (void)hipGetLastError();
         b->spread_max = 0;
     }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        mc_batch_destroy(b);
+        return fail(MC_EDEVICE, "could not query the device");
+    }
+    b->wg_limit = (uint32_t)ncu;
     *out = b;
     return MC_OK;
 }
@@ -928,6 +937,19 @@ int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot)
     return fail(MC_EBUSY, "no free slot");
 }
 
+int mc_batch_set_workgroups(mc_batch* b, uint32_t max_workgroups)
+{
+    if (!b) return fail(MC_EINVAL, "null batch");
+    if (max_workgroups == 0) {
+        int dev = 0, ncu = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        max_workgroups = (uint32_t)ncu;
+    }
+    b->wg_limit = max_workgroups;
+    return MC_OK;
+}
+
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
 {
     if (!b) return fail(MC_EINVAL, "null batch");
@@ -944,83 +966,99 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
     Slot* hs = b->host_slots[par];
     const uint32_t S = b->max_slots;
     const bool fp64 = b->precision == MC_FP64;
-    uint32_t n[3] = {0, 0, 0};
-    size_t lds[2] = {0, 0};
-    std::vector<uint32_t> spread;  // slots of systems on the multi-workgroup engine
+
+    // Engine of every system for this run.  Each system needs one workgroup;
+    // the workgroups left over (up to the batch's limit) go to the systems
+    // that can run on the multi-workgroup engine, most remaining work first,
+    // each up to its own workgroup count.  The engines make the same
+    // decisions, so a system may change engine from run to run.
+    std::vector<uint32_t> active;
+    std::vector<std::pair<double, uint32_t>> cand;  // (-remaining moves, slot)
     for (uint32_t i = 0; i < S; ++i) {
         mc_system* s = b->sys[i];
         if (!s || b->remaining[i] == 0) continue;
-        if (s->g.spread && s->g.spread_blocks <= b->spread_max) {
-            spread.push_back(i);
-            continue;
-        }
-        uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
-        if (max_moves_per_slot) {
-            // equal time slices: the time of max_moves_per_slot moves of the
-            // 1000-molecule reference, in sweeps of this system (modelled)
-            const double cap = slice_time(max_moves_per_slot) / s->g.sweep_cost;
-            k = std::min<uint64_t>(k, std::max<uint64_t>(1, (uint64_t)cap));
-        }
-        const int cls = s->g.resident ? 0 : 1;
-        Slot sl{};
-        sl.sys = s->dev;
-        sl.n_sweeps = k;
-        hs[cls * S + n[cls]++] = sl;
-        lds[cls] = std::max(lds[cls], s->g.lds);
-        b->remaining[i] -= k;
-        s->sweep += k;
-        const uint32_t f = events_at(s, s->sweep);
-        if (f) {
-            Slot ev{};
-            ev.sys = s->dev;
-            ev.flags = f;
-            hs[2 * S + n[2]++] = ev;
-        }
+        active.push_back(i);
+        if (s->g.spread && b->spread_max >= 2)
+            cand.emplace_back(-(double)b->remaining[i] * (double)s->p.n_molecules, i);
+    }
+    std::sort(cand.begin(), cand.end());
+    std::vector<uint32_t> nblk(S, 0);
+    uint32_t spare = b->wg_limit > active.size() ? b->wg_limit - (uint32_t)active.size() : 0u;
+    uint32_t coop = 0;
+    for (const auto& c : cand) {
+        const mc_system* s = b->sys[c.second];
+        const uint32_t nb = std::min({s->g.spread_blocks, spare + 1u, b->spread_max - coop});
+        if (nb < 2) break;
+        nblk[c.second] = nb;
+        spare -= nb - 1;
+        coop += nb;
     }
 
-    // multi-workgroup systems: as many as fit in one cooperative launch, the
-    // first one rotating from run to run; a slice is as many sweeps as a
-    // 1000-molecule system of the batch gets (a sweep of these systems takes
-    // about as long)
+    uint32_t n[3] = {0, 0, 0};
+    size_t lds[2] = {0, 0};
     uint32_t ns = 0, ne = 0, blocks = 0;
     uint64_t max_sw = 0;
     int max_col = 0;
     SpreadSlot* hsp = b->host_spread[par];
     Slot* hev = b->host_ev2[par];
-    std::vector<std::pair<mc_system*, uint32_t>> parts;  // event work of the launch
-    for (size_t j = 0; j < spread.size(); ++j) {
-        const uint32_t i = spread[(b->rr + j) % spread.size()];
+    // the O(M^2) event work of large systems goes to the event kernel over
+    // many workgroups, whatever engine ran the sweeps
+    std::vector<std::pair<mc_system*, uint32_t>> parts1, parts2;
+    auto event_slot = [&](mc_system* s, uint32_t f, std::vector<std::pair<mc_system*, uint32_t>>& parts) {
+        Slot ev{};
+        ev.sys = s->dev;
+        ev.flags = f;
+        const uint32_t nbp = event_blocks(s->p.n_molecules);
+        if (nbp > 1 && (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic | kFlagGofr))) {
+            parts.emplace_back(s, f);
+            ev.flags = f | kFlagParts;
+            ev.pad = nbp;
+        }
+        return ev;
+    };
+    for (uint32_t i : active) {
         mc_system* s = b->sys[i];
-        const uint32_t nb = s->g.spread_blocks;
-        if (blocks + nb > b->spread_max) continue;
         uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
-        if (max_moves_per_slot) k = std::min<uint64_t>(k, std::max<uint64_t>(1, max_moves_per_slot / 1000));
-        SpreadSlot sl{};
-        sl.sys = s->dev;
-        sl.n_sweeps = k;
-        sl.first_block = blocks;
-        sl.n_blocks = nb;
-        hsp[ns++] = sl;
-        blocks += nb;
-        max_sw = std::max(max_sw, k);
-        max_col = std::max(max_col, (int)(s->g.k * s->g.k * s->g.k));
+        if (nblk[i]) {
+            // a slice of as many sweeps as a 1000-molecule system of the batch
+            // gets (a sweep on the system's own workgroup count takes about as
+            // long), fewer when it has fewer workgroups
+            if (max_moves_per_slot) {
+                const double q = (double)(max_moves_per_slot / 1000) * nblk[i] / s->g.spread_blocks;
+                k = std::min<uint64_t>(k, std::max<uint64_t>(1, (uint64_t)q));
+            }
+            SpreadSlot sl{};
+            sl.sys = s->dev;
+            sl.n_sweeps = k;
+            sl.first_block = blocks;
+            sl.n_blocks = nblk[i];
+            hsp[ns++] = sl;
+            blocks += nblk[i];
+            max_sw = std::max(max_sw, k);
+            max_col = std::max(max_col, (int)(s->g.k * s->g.k * s->g.k));
+        } else {
+            if (max_moves_per_slot) {
+                // equal time slices: the time of max_moves_per_slot moves of the
+                // 1000-molecule reference, in sweeps of this system (modelled)
+                const double cap = slice_time(max_moves_per_slot) / s->g.sweep_cost;
+                k = std::min<uint64_t>(k, std::max<uint64_t>(1, (uint64_t)cap));
+            }
+            const int cls = s->g.resident ? 0 : 1;
+            Slot sl{};
+            sl.sys = s->dev;
+            sl.n_sweeps = k;
+            hs[cls * S + n[cls]++] = sl;
+            lds[cls] = std::max(lds[cls], s->g.lds);
+        }
         b->remaining[i] -= k;
         s->sweep += k;
         const uint32_t f = events_at(s, s->sweep);
         if (f) {
-            Slot ev{};
-            ev.sys = s->dev;
-            ev.flags = f;
-            const uint32_t nbp = event_blocks(s->p.n_molecules);
-            if (nbp > 1 && (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic | kFlagGofr))) {
-                parts.emplace_back(s, f);
-                ev.flags = f | kFlagParts;
-                ev.pad = nbp;
-            }
-            hev[ne++] = ev;
+            if (nblk[i]) hev[ne++] = event_slot(s, f, parts2);
+            else hs[2 * S + n[2]++] = event_slot(s, f, parts1);
         }
     }
-    if (!spread.empty()) b->rr = (b->rr + 1) % (uint32_t)spread.size();
+
     if (ns) {
         HIPCHK(hipEventRecord(b->go, b->stream));
         HIPCHK(hipStreamWaitEvent(b->stream2, b->go, 0));
@@ -1033,7 +1071,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         b->pending2[par] = true;
         SpreadSlot none{};
         HIPCHK(launch_spread(fp64, b->dev_spread[par], ns, none, max_sw, max_col, blocks, b->stream2));
-        for (const auto& pe : parts) {
+        for (const auto& pe : parts2) {
             Slot one{};
             one.sys = pe.first->dev;
             one.flags = pe.second;
@@ -1044,7 +1082,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         HIPCHK(hipEventRecord(b->done, b->stream2));
     }
 
-    if (n[0] + n[1]) {
+    if (n[0] + n[1] + n[2]) {
         HIPCHK(hipMemcpyAsync(b->dev_slots[par], hs, 3 * sizeof(Slot) * S, hipMemcpyHostToDevice,
                               b->stream));
         HIPCHK(hipEventRecord(b->copied[par], b->stream));
@@ -1054,6 +1092,12 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             if (n[cls])
                 HIPCHK(launch_sweeps(fp64, cls == 0, b->dev_slots[par] + cls * S, none, n[cls],
                                      lds[cls], b->stream));
+        for (const auto& pe : parts1) {
+            Slot one{};
+            one.sys = pe.first->dev;
+            one.flags = pe.second;
+            HIPCHK(launch_event_parts(one, event_blocks(pe.first->p.n_molecules), b->stream));
+        }
         if (n[2]) HIPCHK(launch_events(b->dev_slots[par] + 2 * S, none, n[2], b->stream));
     }
     // later work on the batch stream (the next run, poll, reads) follows the

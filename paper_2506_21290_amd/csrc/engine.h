@@ -87,7 +87,8 @@ struct SysDev {
     uint16_t* g_list;    // [M] molecules sorted by cell, ascending inside a cell
     void* props;         // [M] proposals of the current sweep (48 bytes each)
     uint32_t* g_cnt;     // [2 * ncell] cell counts and fill cursors (multi-workgroup engine)
-    double* g_part;      // [kMaxParts] per-wave / per-workgroup partial sums
+    double* g_part;      // [kMaxParts] per-workgroup partial sums of the event kernel
+    double* g_ecell;     // [ncell] accepted dE of each cell in the current sweep (HBM state)
     // decision log
     void* log;
     uint64_t log_sweep0;
@@ -122,8 +123,8 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 
 // LDS carve-up, shared by the host (launch size) and the kernel (pointers).
 struct LdsLayout {
-    size_t surv, seglo, segoff, near, wpart, misc, trial;
-    size_t com, site, cell, cellid, list, total;
+    size_t surv, seglo, segoff, near, misc, trial;
+    size_t com, site, cell, cellid, list, ecell, total;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(bool fp64, bool resident, uint32_t M,
@@ -135,7 +136,6 @@ __host__ __device__ inline LdsLayout lds_layout(bool fp64, bool resident, uint32
     l.seglo = o;  o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
     l.segoff = o; o = align16(o + kWaves * kMaxSeg * sizeof(uint16_t));
     l.near = o;   o = align16(o + kWaves * kCellListCap * 8);
-    l.wpart = o;  o = align16(o + kWaves * sizeof(double));
     l.misc = o;   o = align16(o + 16 * sizeof(double));
     l.trial = o;  o = align16(o + kWaves * trial_bytes(fp64));
     if (resident) {
@@ -144,6 +144,7 @@ __host__ __device__ inline LdsLayout lds_layout(bool fp64, bool resident, uint32
         l.cell = o;   o = align16(o + (size_t(ncell) + 1) * sizeof(uint32_t));
         l.cellid = o; o = align16(o + size_t(M) * sizeof(uint16_t));
         l.list = o;   o = align16(o + size_t(M) * sizeof(uint16_t));
+        l.ecell = o;  o = align16(o + size_t(ncell) * sizeof(double));
     }
     l.total = o;
     return l;

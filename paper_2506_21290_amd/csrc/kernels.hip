@@ -125,6 +125,17 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
     return __longlong_as_double((long long)((hi << 32) | lo));
 }
 
+// The accepted dE of a sweep from the per-cell sums (each in its cell's trial
+// order): lane l adds cells l, l + 64, ... in turn, then the DPP sum.  Every
+// engine reduces the same way, so E_acc does not depend on how the cells were
+// spread over waves and workgroups.  Call with a whole wave.
+__device__ __forceinline__ double sweep_energy(const double* ecell, uint32_t ncell)
+{
+    double a = 0.0;
+    for (uint32_t c = (uint32_t)__lane_id(); c < ncell; c += 64u) a += ecell[c];
+    return wave_sum_dpp(a);
+}
+
 // Exclusive prefix sum over the wave; *total gets the wave total.
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
 {
@@ -292,7 +303,7 @@ struct Ctx {
     uint16_t* cellid;
     uint16_t* list;
     double* red;
-    double* wpart;
+    double* ecell;  // accepted dE of each cell in the current sweep
     uint32_t* bins;
     double* misc;
 };
@@ -1326,7 +1337,10 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
         const int cx = kx + k * (a % na), cy = ky + k * ((a / na) % na), cz = kz + k * (a / (na * na));
         const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
         const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
-        if (ccnt == 0) continue;
+        if (ccnt == 0) {
+            if (__lane_id() == 0) C.ecell[cell] = 0.0;
+            continue;
+        }
         const double bx0 = hx + ((double)cx + 0.5) * C.w;
         const double by0 = hy + ((double)cy + 0.5) * C.w;
         const double bz0 = hz + ((double)cz + 0.5) * C.w;
@@ -1336,8 +1350,10 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
         const uint32_t nnear = gather_near<Real, kRes, false>(C, P, nseg, total, bx0, by0, bz0, 0u, 0u,
                                                              W, StageLds<Real>{}, overflow);
         const NearRegs nr = near_regs(W.near, nnear, overflow);
+        wc.e = 0.0;
         cell_trials<Real, kRes, false>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0, nr,
                                        overflow, nseg, total, nullptr, W, wc);
+        if (__lane_id() == 0) C.ecell[cell] = wc.e;
     }
 }
 
@@ -1384,7 +1400,6 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
     const LdsLayout L = lds_layout(fp64, kRes, C.M, C.ncell);
     C.red = nullptr;
     C.bins = nullptr;
-    C.wpart = (double*)(smem + L.wpart);
     C.misc = (double*)(smem + L.misc);
     if (kRes) {
         C.com = (double*)(smem + L.com);
@@ -1392,12 +1407,14 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
         C.cellb = (uint32_t*)(smem + L.cell);
         C.cellid = (uint16_t*)(smem + L.cellid);
         C.list = (uint16_t*)(smem + L.list);
+        C.ecell = (double*)(smem + L.ecell);
     } else {
         C.com = C.gcom;
         C.site = (R4<Real>*)g_site;
         C.cellb = g_cell;
         C.cellid = g_cellid;
         C.list = g_list;
+        C.ecell = Dp->g_ecell;
     }
     WaveLds<Real> W;
     W.surv = (uint16_t*)(smem + L.surv) + wave * kCellListCap;
@@ -1438,15 +1455,14 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
             run_phase(C, props, col, sweep, hx, hy, hz, W, wc);
             __syncthreads();
         }
-        // accumulated energy in a fixed wave order; E/M samples
-        if (lane == 0) C.wpart[wave] = wc.e;
-        wc.e = 0.0;
+        // E_acc += the sweep's dE (sweep_energy); E/M samples
         ++sweep;
-        __syncthreads();
+        if (wave == 0) {
+            const double e = C.misc[0] + sweep_energy(C.ecell, C.ncell);
+            if (lane == 0) C.misc[0] = e;
+        }
         if (tid == 0) {
-            double e = C.misc[0];
-            for (int w = 0; w < kWaves; ++w) e += C.wpart[w];
-            C.misc[0] = e;
+            const double e = C.misc[0];
             const uint64_t t = sweep - origin;
             if (t >= C.obs_start && C.obs_interval && t % C.obs_interval == 0) {
                 const double em = e / (double)M;
@@ -1494,7 +1510,7 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
     C.red = red;
     C.misc = misc;
     C.bins = bins;
-    C.wpart = nullptr;
+    C.ecell = nullptr;
     C.site = nullptr;
     C.cellb = nullptr;
     C.cellid = nullptr;
@@ -1622,7 +1638,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
     C.list = Dp->g_list;
     C.red = nullptr;
     C.bins = nullptr;
-    C.wpart = nullptr;
+    C.ecell = Dp->g_ecell;
     uint32_t* cnt = Dp->g_cnt;
     uint32_t* fill = cnt + C.ncell;
     PropRec* props = (PropRec*)Dp->props;
@@ -1701,7 +1717,10 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                               cz = kz + k * (int)(a / (na * na));
                     const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
                     const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
-                    if (ccnt == 0) continue;
+                    if (ccnt == 0) {
+                        if (lane == 0) C.ecell[cell] = 0.0;
+                        continue;
+                    }
                     const double bx0 = hx + ((double)cx + 0.5) * C.w;
                     const double by0 = hy + ((double)cy + 0.5) * C.w;
                     const double bz0 = hz + ((double)cz + 0.5) * C.w;
@@ -1711,22 +1730,22 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                     const uint32_t ns = gather_near<Real, false, true>(C, P, nseg, total, bx0, by0, bz0,
                                                                        cbeg, ccnt, W, S, overflow);
                     const NearRegs nr = near_regs(W.near, ns, overflow);
+                    wc.e = 0.0;
                     cell_trials<Real, false, true>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0,
                                                    nr, overflow, nseg, total, S.own, W, wc);
+                    if (lane == 0) C.ecell[cell] = wc.e;
                 }
             }
-            if (col == max_colours - 1 && run) {
-                // the wave's accepted dE of the sweep, for the sum in wave order
-                if (lane == 0) C.gpart[gw] = wc.e;
-                wc.e = 0.0;
-                ++sweep;
-            }
+            if (col == max_colours - 1 && run) ++sweep;
             grid.sync();
         }
-        // E_acc += the sweep's dE in wave order; E/M samples (the next
+        // E_acc += the sweep's dE (sweep_energy); E/M samples (the next
         // sweep's steps touch neither)
+        if (run && bid == 0 && wave == 0) {
+            const double de = sweep_energy(C.ecell, C.ncell);
+            e_acc += de;
+        }
         if (run && bid == 0 && tid == 0) {
-            for (uint32_t w = 0; w < NW; ++w) e_acc += C.gpart[w];
             const uint64_t t = sweep - origin;
             if (t >= C.obs_start && C.obs_interval && t % C.obs_interval == 0) {
                 const double em = e_acc / (double)M;
@@ -1768,7 +1787,7 @@ __global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
     C.red = red;
     C.misc = misc;
     C.bins = bins;
-    C.wpart = nullptr;
+    C.ecell = nullptr;
     C.site = nullptr;
     C.cellb = nullptr;
     C.cellid = nullptr;

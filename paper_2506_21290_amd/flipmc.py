@@ -32,6 +32,7 @@ EXPORTED = [
     "mc_set_state", "mc_decision_log", "mc_timing_enable", "mc_timing_read", "mc_destroy",
     "mc_last_error", "mc_batch_create",
     "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
+    "mc_batch_set_workgroups",
 ]
 
 
@@ -152,6 +153,7 @@ def lib():
         L.mc_batch_run.argtypes = [vp, C.c_uint64, u32p]
         L.mc_batch_poll.argtypes = [vp, u32p, C.POINTER(vp), C.c_size_t, szp]
         L.mc_batch_cancel.argtypes = [vp, C.c_uint32]
+        L.mc_batch_set_workgroups.argtypes = [vp, C.c_uint32]
         L.mc_batch_destroy.argtypes = [vp]
         L.mc_batch_destroy.restype = None
         _lib = L
@@ -342,7 +344,8 @@ class System:
 
 
 class Batch:
-    """Several systems advanced by one persistent launch per call."""
+    """Several systems advanced together, one time slice per run: one workgroup
+    each, spare workgroups to the large systems with the most work left."""
 
     def __init__(self, max_slots, precision=MC_FP32_DE, stream=None):
         self._stream_handle, self.stream = _stream_handle(stream)
@@ -363,6 +366,10 @@ class Batch:
         _check(lib().mc_batch_add(self.h, system.h, int(n_sweeps), C.byref(slot)))
         self.members[slot.value] = system
         return slot.value
+
+    def set_workgroups(self, max_workgroups=0):
+        """At most max_workgroups workgroups at once (0 = one per compute unit)."""
+        _check(lib().mc_batch_set_workgroups(self.h, int(max_workgroups)))
 
     def run(self, max_moves_per_slot=0) -> int:
         n = C.c_uint32()

@@ -2,12 +2,13 @@
 
 Requests are sampling jobs (M molecules at temperature T for S sweeps).  Their
 configurations stay resident in HBM for the job's life; a job is admitted as
-soon as a slot and enough of the memory budget are free, and every launch
+soon as a slot and enough of the memory budget are free, and every run
 advances all admitted jobs by one time slice, so jobs that arrive while others
-run join the next launch and their work overlaps on the device.  Systems whose
-working set fits one workgroup's LDS share one persistent batched launch;
-larger ones share cooperative launches of the multi-workgroup engine (each on
-its own workgroups), on a second stream, side by side with the first batch.
+run join the next run and their work overlaps on the device.  Every job gets
+one workgroup per run (systems whose working set fits one workgroup's LDS keep
+it there); the workgroups left over go to the large jobs with the most work
+left, which then run on the multi-workgroup engine in a cooperative launch
+beside the others.
 
 The time slice is given in attempted moves per job; the engine scales it by
 its model of per-workgroup throughput against system size (small systems run
@@ -74,27 +75,27 @@ def gofr_normalised(obs, n_sites, box):
 
 
 class GpuBackend:
-    """Jobs as flipmc systems in two batches on two streams: batch 0 holds the
-    jobs whose state fits one workgroup's LDS (one persistent launch, one
-    workgroup per job), batch 1 the larger ones, which the batch advances
-    together in one cooperative launch of the multi-workgroup engine (each job
-    on its own workgroups; as many as fit, in rotation)."""
+    """Jobs as flipmc systems in one batch: every run gives each job one
+    workgroup and the spare workgroups of the device to the large jobs with the
+    most work left (multi-workgroup engine); the engines make the same
+    decisions, so a job's result does not depend on how it was run."""
 
-    def __init__(self, precision=flipmc.MC_FP32_DE, max_slots=1024):
+    def __init__(self, precision=flipmc.MC_FP32_DE, max_slots=1024, max_workgroups=0):
         import torch
 
         self.torch = torch
         self.precision = precision
-        self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        self.streams = [torch.cuda.Stream()]
         self.admit_stream = torch.cuda.Stream()
         self.batches = [flipmc.Batch(max_slots, precision, stream=s) for s in self.streams]
+        for b in self.batches:
+            b.set_workgroups(max_workgroups)
         self.max_slots = max_slots
 
     def size(self, job):
         """(bytes of device memory, batch index)"""
         p = job_params(job, self.precision)
-        engine, _ = flipmc.mc_engine(p)
-        return flipmc.mc_required_bytes(p), 0 if engine == flipmc.MC_ENGINE_LDS else 1
+        return flipmc.mc_required_bytes(p), 0
 
     def free_slots(self, bi):
         return self.max_slots - len(self.batches[bi].members)
