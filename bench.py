@@ -6,7 +6,9 @@ equilibrated temperature of the paper), density 1.2, seeded lattice start,
 checkerboard sweeps with FP32 energy differences and an FP64 re-sum every 100
 sweeps; a step is 100 sweeps (one re-sum window) including the cell builds,
 the re-sum, E/M samples, the g(r) frame and C_2 samples.  The same run in
-plain FP64 is timed beside it.  Prints one JSON line.
+plain FP64 is timed beside it, then the first 200 jobs of the serving stream
+give the p50/p99 request latency ("serving"), then the CPU oracle runs on a
+bounded sample ("cpu_baseline").  Prints one JSON line.
 
 Other workloads (--workload): c2 (8000 molecules), c3 (256 uneven replicas in
 one persistent launch) and c4 (the serving loop).
@@ -182,6 +184,11 @@ def bench_c1(args, flipmc, torch):
         "max_abs_drift_per_window": f32["max_abs_drift_per_window"],
         "sweeps_done": f32["sweeps_done"],
     }
+    if args.serving_jobs > 0:
+        # the request latency of the metric: the serving stream, first jobs
+        sv = bench_c4(args, flipmc, torch, n_jobs=args.serving_jobs)
+        out["serving"] = {k: sv[k] for k in ("workload", "completed", "p50_latency_s", "p99_latency_s",
+                                              "moves_per_s", "wall_s", "peak_concurrent_jobs")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, k=cpu_k, nc=cpu_nc)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
@@ -286,11 +293,11 @@ def bench_c3(args, flipmc, torch):
     }
 
 
-def bench_c4(args, flipmc, torch):
+def bench_c4(args, flipmc, torch, n_jobs=None):
     """Poisson stream of sampling jobs served with continuous batching."""
     from paper_2506_21290_amd import serve, workloads
 
-    jobs = workloads.serving_stream(n_jobs=args.jobs, rate=200.0, seed=1, m_max=args.m_max,
+    jobs = workloads.serving_stream(n_jobs=n_jobs or args.jobs, rate=200.0, seed=1, m_max=args.m_max,
                                     s_max=args.s_max)
     srv = serve.Server(memory_budget=args.budget, backend=serve.GpuBackend(flipmc.MC_FP32_DE),
                        quantum_moves=args.quantum)
@@ -342,7 +349,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "copy"])
-    ap.add_argument("--jobs", type=int, default=2000)
+    ap.add_argument("--jobs", type=int, default=200)
+    ap.add_argument("--serving-jobs", type=int, default=200,
+                    help="jobs of the serving stream run after the c1 line's own work (0: none)")
     ap.add_argument("--m-max", type=int, default=27000)
     ap.add_argument("--s-max", type=int, default=10000)
     ap.add_argument("--budget", type=int, default=4 << 30)
