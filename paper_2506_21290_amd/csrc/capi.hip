@@ -205,7 +205,7 @@ uint32_t event_blocks(uint32_t M)
 
 struct BufLayout {
     size_t sys, stats, com, quat, types, u0, kref, esamp, dsamp, gall, ginter, c2, c2s;
-    size_t props, gpart, gsite, gcell, gcellid, glist, gcnt, gecell, total;
+    size_t props, gpart, gsite, gcell, gcellid, glist, gcnt, gecell, gbar, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -238,6 +238,7 @@ BufLayout buf_layout(const mc_params* p, const Geometry& g)
         b.glist = o;   o = al(o + M * sizeof(uint16_t));
         b.gcnt = o;    o = al(o + 2 * size_t(g.ncell) * sizeof(uint32_t));
         b.gecell = o;  o = al(o + size_t(g.ncell) * sizeof(double));
+        b.gbar = o;    o = al(o + sizeof(uint32_t));
     }
     b.total = o;
     return b;
@@ -284,7 +285,8 @@ struct mc_batch {
     hipEvent_t copied2[2];
     bool pending2[2];
     uint32_t spread_max;              // co-resident workgroups of the cooperative launch
-    uint32_t wg_limit;                // workgroups that run at once (compute units)
+    uint32_t ncu;                     // compute units of the device
+    uint32_t wg_limit;                // compute units the batch's runs use at once
 };
 
 namespace {
@@ -406,6 +408,7 @@ int advance(mc_system* s, uint64_t n)
         const uint64_t chunk = std::min<uint64_t>(n, next_event(s) - s->sweep);
         one.n_sweeps = chunk;
         one.flags = 0;
+        if (s->g.spread) HIPCHK(hipMemsetAsync(s->host.g_bar, 0, sizeof(uint32_t), s->stream));
         hipEvent_t t0 = timing_start(s);
         if (s->g.spread) {
             SpreadSlot sl{};
@@ -413,8 +416,8 @@ int advance(mc_system* s, uint64_t n)
             sl.n_sweeps = chunk;
             sl.first_block = 0;
             sl.n_blocks = s->g.spread_blocks;
-            HIPCHK(launch_spread(s->p.precision == MC_FP64, nullptr, 1, sl, chunk,
-                                 (int)(s->g.k * s->g.k * s->g.k), s->g.spread_blocks, s->stream));
+            HIPCHK(launch_spread(s->p.precision == MC_FP64, nullptr, 1, sl, s->g.spread_blocks,
+                                 s->stream));
         }
         else
             HIPCHK(launch_sweeps(s->p.precision == MC_FP64, s->g.resident, nullptr, one, 1,
@@ -436,6 +439,9 @@ int read_stats(mc_system* s, Stats* st)
     if (int rc = sync_owner(s)) return rc;
     HIPCHK(hipMemcpyAsync(st, s->host.stats, sizeof(Stats), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (st->fault)
+        return fail(MC_EDEVICE, "a workgroup barrier of the multi-workgroup engine timed out: "
+                                "the system's state is invalid");
     return MC_OK;
 }
 
@@ -635,6 +641,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
         D.g_list = (uint16_t*)(b + lay.glist);
         D.g_cnt = (uint32_t*)(b + lay.gcnt);
         D.g_ecell = (double*)(b + lay.gecell);
+        D.g_bar = (uint32_t*)(b + lay.gbar);
     }
     s->dev = (SysDev*)(b + lay.sys);
 
@@ -875,6 +882,7 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
     b->stream2 = nullptr;
     b->go = b->done = nullptr;
     b->spread_max = 0;
+    b->ncu = 1;
     b->wg_limit = 0;
     for (int i = 0; i < 2; ++i) {
         b->dev_slots[i] = nullptr;
@@ -918,6 +926,7 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
         mc_batch_destroy(b);
         return fail(MC_EDEVICE, "could not query the device");
     }
+    b->ncu = (uint32_t)ncu;
     b->wg_limit = (uint32_t)ncu;
     *out = b;
     return MC_OK;
@@ -943,13 +952,7 @@ int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot)
 int mc_batch_set_workgroups(mc_batch* b, uint32_t max_workgroups)
 {
     if (!b) return fail(MC_EINVAL, "null batch");
-    if (max_workgroups == 0) {
-        int dev = 0, ncu = 0;
-        HIPCHK(hipGetDevice(&dev));
-        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        max_workgroups = (uint32_t)ncu;
-    }
-    b->wg_limit = max_workgroups;
+    b->wg_limit = max_workgroups ? max_workgroups : b->ncu;
     return MC_OK;
 }
 
@@ -986,43 +989,43 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
     }
     std::sort(cand.begin(), cand.end());
     std::vector<uint32_t> nblk(S, 0);
-    const uint32_t spare = b->wg_limit > active.size() ? b->wg_limit - (uint32_t)active.size() : 0u;
     {
-        // the spare workgroups shared in proportion to the remaining work
-        // (each system up to its own workgroup count, the whole cooperative
-        // launch up to what the device holds at once); what the caps and the
+        // the spare compute units shared in proportion to the remaining work,
+        // each system up to its own workgroup count (bpc workgroups of the
+        // multi-workgroup engine fit on one compute unit), the cooperative
+        // launch up to what the device holds at once; what the caps and the
         // rounding leave goes to the systems with the most work, in order
+        const uint32_t spare = b->wg_limit > active.size() ? b->wg_limit - (uint32_t)active.size() : 0u;
+        const uint32_t bpc = std::max(1u, b->spread_max / std::max(1u, b->ncu));
         double total = 0.0;
         for (const auto& c : cand) total -= c.first;
         uint32_t left = spare, coop = 0;
+        auto cus = [&](uint32_t nb) { return (nb + bpc - 1) / bpc; };
         for (const auto& c : cand) {
             const mc_system* s = b->sys[c.second];
             const uint32_t share = total > 0.0 ? (uint32_t)((double)spare * (-c.first) / total) : 0u;
-            uint32_t nb = std::min({s->g.spread_blocks, 1u + std::min(share, left), b->spread_max - coop});
+            const uint32_t nb = std::min({s->g.spread_blocks, (1u + std::min(share, left)) * bpc,
+                                          b->spread_max - coop});
             if (nb < 2) continue;
             nblk[c.second] = nb;
-            left -= nb - 1;
+            left -= cus(nb) - 1;
             coop += nb;
         }
         for (const auto& c : cand) {
             if (left == 0 || coop >= b->spread_max) break;
             const mc_system* s = b->sys[c.second];
-            const uint32_t have = nblk[c.second] ? nblk[c.second] : 1u;
-            const uint32_t add = std::min({s->g.spread_blocks - std::min(have, s->g.spread_blocks), left,
-                                           b->spread_max - coop - (nblk[c.second] ? 0u : 1u)});
-            if (add == 0 || have + add < 2) continue;
-            if (!nblk[c.second]) coop += 1;
-            nblk[c.second] = have + add;
-            left -= add;
-            coop += add;
+            const uint32_t have = nblk[c.second];
+            const uint32_t want = std::min({s->g.spread_blocks, (cus(std::max(have, 1u)) + left) * bpc,
+                                            b->spread_max - coop + have});
+            if (want <= std::max(have, 1u) || want < 2) continue;
+            left -= cus(want) - (have ? cus(have) : 1u);
+            coop += want - have;
+            nblk[c.second] = want;
         }
     }
-
     uint32_t n[3] = {0, 0, 0};
     size_t lds[2] = {0, 0};
     uint32_t ns = 0, ne = 0, blocks = 0;
-    uint64_t max_sw = 0;
-    int max_col = 0;
     SpreadSlot* hsp = b->host_spread[par];
     Slot* hev = b->host_ev2[par];
     // the O(M^2) event work of large systems goes to the event kernel over
@@ -1058,8 +1061,6 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             sl.n_blocks = nblk[i];
             hsp[ns++] = sl;
             blocks += nblk[i];
-            max_sw = std::max(max_sw, k);
-            max_col = std::max(max_col, (int)(s->g.k * s->g.k * s->g.k));
         } else {
             if (max_moves_per_slot) {
                 // equal time slices: the time of max_moves_per_slot moves of the
@@ -1094,7 +1095,8 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         HIPCHK(hipEventRecord(b->copied2[par], b->stream2));
         b->pending2[par] = true;
         SpreadSlot none{};
-        HIPCHK(launch_spread(fp64, b->dev_spread[par], ns, none, max_sw, max_col, blocks, b->stream2));
+        HIPCHK(launch_zero_barriers(b->dev_spread[par], ns, b->stream2));
+        HIPCHK(launch_spread(fp64, b->dev_spread[par], ns, none, blocks, b->stream2));
         for (const auto& pe : parts2) {
             Slot one{};
             one.sys = pe.first->dev;

@@ -54,6 +54,8 @@ struct Stats {
     uint32_t n_drift;
     uint32_t n_gofr;
     uint32_t n_c2;
+    uint32_t fault;          // nonzero: a workgroup barrier of the multi-workgroup engine timed out
+    uint32_t pad;
 };
 
 // Everything a workgroup needs about its system; lives in the system's device
@@ -89,6 +91,7 @@ struct SysDev {
     uint32_t* g_cnt;     // [2 * ncell] cell counts and fill cursors (multi-workgroup engine)
     double* g_part;      // [kMaxParts] per-workgroup partial sums of the event kernel
     double* g_ecell;     // [ncell] accepted dE of each cell in the current sweep (HBM state)
+    uint32_t* g_bar;     // barrier counter of the system's workgroups (multi-workgroup engine)
     // decision log
     void* log;
     uint64_t log_sweep0;
@@ -192,11 +195,12 @@ struct SpreadSlot {
 
 // Cooperative launch of the multi-workgroup engine over n_blocks workgroups:
 // the systems of dev_slots[0 .. n_slots) (device array), or `one` when
-// dev_slots is null; max_sweeps / max_colours bound every slot's sweeps and
-// colours per sweep.
+// dev_slots is null.  The workgroups of each system synchronise among
+// themselves only (each system's g_bar must be zero at launch).
 hipError_t launch_spread(bool fp64, const SpreadSlot* dev_slots, uint32_t n_slots,
-                         const SpreadSlot& one, uint64_t max_sweeps, int max_colours,
-                         uint32_t n_blocks, hipStream_t stream);
+                         const SpreadSlot& one, uint32_t n_blocks, hipStream_t stream);
+// Zero the barrier counters of the systems of dev_slots[0 .. n_slots).
+hipError_t launch_zero_barriers(const SpreadSlot* dev_slots, uint32_t n_slots, hipStream_t stream);
 // Largest cooperative grid of the spread kernel on the current device.
 hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks);
 // The O(M^2) part of an event (re-sum partial energies into g_part, g(r)

@@ -24,9 +24,7 @@
 // run is reproducible regardless of how systems are batched.
 #include "engine.h"
 
-#include <hip/hip_cooperative_groups.h>
 
-namespace cg = cooperative_groups;
 
 namespace flipmc {
 namespace {
@@ -1589,17 +1587,58 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
 // exactly as in the single-workgroup engine, so the decisions are the same.
 
 // The staged neighbourhood of the cell a wave is working on.
+// Barrier of the workgroups of one system inside a cooperative launch (which
+// keeps every workgroup resident): a counter in the system's buffer, zero at
+// launch, that each workgroup raises once per barrier; a workgroup passes the
+// n-th barrier when the counter reaches n x (workgroups of the system).  The
+// wait is bounded: past the bound the system is marked faulted (Stats::fault)
+// and the workgroup stops waiting, at this and every later barrier, so that
+// the launch still ends.
+constexpr uint32_t kBarrierSpins = 1u << 23;  // seconds of waiting
+
+struct SysBarrier {
+    uint32_t* count;
+    uint32_t nblk;
+    uint32_t epoch;
+    bool broken;
+};
+
+__device__ void sys_sync(SysBarrier& B, uint32_t* fault, uint32_t* flag)
+{
+    __syncthreads();
+    ++B.epoch;
+    if (threadIdx.x == 0) {
+        uint32_t bad = 0;
+        if (!B.broken) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(B.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t target = B.epoch * B.nblk;
+            uint32_t spins = 0;
+            while (__hip_atomic_load(B.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins == kBarrierSpins) {
+                    bad = 1;
+                    __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        *flag = bad;
+    }
+    __syncthreads();
+    if (*flag) B.broken = true;
+}
+
 // One launch can advance several systems: slot i owns workgroups
-// [first_block, first_block + n_blocks) and runs n_sweeps sweeps; every
-// workgroup takes part in every grid barrier (max_sweeps sweeps of max_colours
-// colours), idle where its own system has fewer.
+// [first_block, first_block + n_blocks) and runs n_sweeps sweeps; the
+// workgroups of a system synchronise among themselves (sys_sync), so systems
+// of one launch run at their own pace.
 template <typename Real>
 __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __restrict__ slots,
-                                                           uint32_t n_slots, SpreadSlot one,
-                                                           uint64_t max_sweeps, int max_colours)
+                                                           uint32_t n_slots, SpreadSlot one)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    cg::grid_group grid = cg::this_grid();
     constexpr bool fp64 = sizeof(Real) == 8;
     constexpr uint32_t kCap = kListCap;
     SpreadSlot sl = one;
@@ -1612,6 +1651,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
             }
         }
     }
+    if (sl.sys == nullptr || sl.n_blocks == 0) return;  // a workgroup of no system
     SysDev* __restrict__ Dp = sl.sys;
     const uint32_t bid = blockIdx.x - sl.first_block, nblk = sl.n_blocks;
     Ctx<Real, false> C;
@@ -1662,10 +1702,13 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
     double e_acc = st->e_acc;
     uint64_t sweep = st->sweep;
     const uint64_t origin = st->obs_origin;
-    grid.sync();
+    SysBarrier B{Dp->g_bar, nblk, 0u, false};
+    uint32_t* bflag = (uint32_t*)(C.misc + 15);
+    auto sync = [&]() { sys_sync(B, &st->fault, bflag); };
+    sync();
 
-    for (uint64_t it = 0; it < max_sweeps; ++it) {
-        const bool run = it < sl.n_sweeps;
+    for (uint64_t it = 0; it < sl.n_sweeps; ++it) {
+        constexpr bool run = true;
         const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, C.seed_lo,
                               C.seed_hi);
         const double hx = C.w * unit_open(g.x), hy = C.w * unit_open(g.y),
@@ -1682,7 +1725,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                 props[m] = propose(C, m, sweep, hx, hy, hz, ix, iy, iz);
             }
         }
-        grid.sync();
+        sync();
         // cell starts (exclusive scan of the counts); counts cleared for the
         // next sweep
         if (run && bid == 0) {
@@ -1692,25 +1735,25 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
             if (tid == 0) C.cellb[ncell] = M;
             for (uint32_t c = tid; c < ncell; c += kSpreadThreads) cnt[c] = 0;
         }
-        grid.sync();
+        sync();
         if (run) {
             for (uint32_t m = gtid; m < M; m += GT) {
                 const uint32_t c = C.cellid[m];
                 C.list[C.cellb[c] + atomicAdd(&fill[c], 1u)] = (uint16_t)m;
             }
         }
-        grid.sync();
+        sync();
         // ascending molecule index inside every cell
         if (run) {
             sort_cells(C.list, C.cellb, gw, NW, ncell);
             for (uint32_t c = gtid; c < ncell; c += GT) fill[c] = 0;
         }
-        grid.sync();
+        sync();
 
         const PhaseConst P = phase_const(C, sweep);
         const View<Real> V{S.com, S.site, kCap};
-        for (int col = 0; col < max_colours; ++col) {
-            if (run && col < ncol) {
+        for (int col = 0; col < ncol; ++col) {
+            if (run) {
                 const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
                 for (uint32_t a = gw; a < nact; a += NW) {
                     const int cx = kx + k * (int)(a % na), cy = ky + k * (int)((a / na) % na),
@@ -1736,8 +1779,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                     if (lane == 0) C.ecell[cell] = wc.e;
                 }
             }
-            if (col == max_colours - 1 && run) ++sweep;
-            grid.sync();
+            if (col == ncol - 1) ++sweep;
+            sync();
         }
         // E_acc += the sweep's dE (sweep_energy); E/M samples (the next
         // sweep's steps touch neither)
@@ -1896,17 +1939,21 @@ hipError_t spread_max_blocks_t(uint32_t* n_blocks)
 
 template <typename Real>
 hipError_t launch_spread_t(const SpreadSlot* dev_slots, uint32_t n_slots, const SpreadSlot& one,
-                           uint64_t max_sweeps, int max_colours, uint32_t n_blocks,
-                           hipStream_t stream)
+                           uint32_t n_blocks, hipStream_t stream)
 {
     hipError_t e = spread_configure<Real>();
     if (e != hipSuccess) return e;
     SpreadSlot o = one;
-    void* args[] = {(void*)&dev_slots, (void*)&n_slots, (void*)&o, (void*)&max_sweeps,
-                    (void*)&max_colours};
+    void* args[] = {(void*)&dev_slots, (void*)&n_slots, (void*)&o};
     return hipLaunchCooperativeKernel((const void*)&k_spread<Real>, dim3(n_blocks),
                                       dim3(kSpreadThreads), args,
                                       spread_lds_bytes(sizeof(Real) == 8), stream);
+}
+
+__global__ void k_zero_barriers(const SpreadSlot* __restrict__ slots, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *slots[i].sys->g_bar = 0u;
 }
 
 }  // namespace
@@ -1917,13 +1964,16 @@ hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks)
 }
 
 hipError_t launch_spread(bool fp64, const SpreadSlot* dev_slots, uint32_t n_slots,
-                         const SpreadSlot& one, uint64_t max_sweeps, int max_colours,
-                         uint32_t n_blocks, hipStream_t stream)
+                         const SpreadSlot& one, uint32_t n_blocks, hipStream_t stream)
 {
-    return fp64 ? launch_spread_t<double>(dev_slots, n_slots, one, max_sweeps, max_colours,
-                                          n_blocks, stream)
-                : launch_spread_t<float>(dev_slots, n_slots, one, max_sweeps, max_colours,
-                                         n_blocks, stream);
+    return fp64 ? launch_spread_t<double>(dev_slots, n_slots, one, n_blocks, stream)
+                : launch_spread_t<float>(dev_slots, n_slots, one, n_blocks, stream);
+}
+
+hipError_t launch_zero_barriers(const SpreadSlot* dev_slots, uint32_t n_slots, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_barriers, dim3((n_slots + 63) / 64), dim3(64), 0, stream, dev_slots, n_slots);
+    return hipGetLastError();
 }
 
 hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t stream)
