@@ -355,7 +355,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=27000)
     ap.add_argument("--s-max", type=int, default=10000)
     ap.add_argument("--budget", type=int, default=4 << 30)
-    ap.add_argument("--quantum", type=int, default=200_000)
+    ap.add_argument("--quantum", type=int, default=100_000)
     ap.add_argument("--time-limit", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

@@ -245,14 +245,15 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
 int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
 
 /* Enqueue one run in which each occupied slot runs a time slice of its
- * remaining sweeps (0 = all remaining): the modelled time of
- * max_moves_per_slot moves of a 1000-molecule system (k = 2, n_c = 4) on one
- * workgroup, converted with the same model into sweeps of the slot's system
- * (at least one); a system on the multi-workgroup engine runs
- * max(1, max_moves_per_slot / 1000) sweeps scaled by the fraction of its own
- * workgroup count it got.  Slices also stop at each system's re-sum / g(r) /
- * C_2 sweeps, whose work follows in a second launch.  *n_launched = number of
- * sweep launches enqueued. */
+ * remaining sweeps (0 = all remaining).  Every launch of the run is sized to
+ * the time a 1000-molecule system (k = 2, n_c = 4) takes for
+ * max_moves_per_slot moves on one workgroup: each system's slice is that time
+ * over its modelled sweep time (one-workgroup cost model, divided by its
+ * workgroups on the multi-workgroup engine), scaled per engine by the time
+ * per modelled cycle measured on the batch's earlier launches; at least one
+ * sweep.  Slices also stop at each system's re-sum / g(r) / C_2 sweeps, whose
+ * work follows in a second launch.  *n_launched = number of sweep launches
+ * enqueued. */
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched);
 
 /* At most max_workgroups workgroups of the batch's runs at once (0 = one per

@@ -195,6 +195,14 @@ double slice_time(uint64_t max_moves)
     return (double)max_moves / 1000.0 * ref;
 }
 
+// Milliseconds per modelled cycle on an idle device: a sweep of the
+// 1000-molecule reference (k = 2, n_c = 4) takes about 0.31 ms on one
+// workgroup with the state in LDS.
+double ms_per_model_cycle()
+{
+    return 0.31 / slice_time(1000);
+}
+
 // Workgroups of the multi-workgroup event kernel for M molecules (one
 // molecule per thread of the O(M^2) loops), 1 = single-workgroup events.
 uint32_t event_blocks(uint32_t M)
@@ -287,6 +295,12 @@ struct mc_batch {
     uint32_t spread_max;              // co-resident workgroups of the cooperative launch
     uint32_t ncu;                     // compute units of the device
     uint32_t wg_limit;                // compute units the batch's runs use at once
+    // slice calibration per engine class (one workgroup with the state in LDS,
+    // one workgroup with the state in HBM, multi-workgroup): milliseconds per
+    // modelled cycle, learnt from the timed launches of earlier runs
+    double ms_per_cycle[3];
+    double pred[3];                   // modelled cycles of the class's last launch (0: none)
+    hipEvent_t t_beg[3], t_end[3];
 };
 
 namespace {
@@ -884,6 +898,11 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
     b->spread_max = 0;
     b->ncu = 1;
     b->wg_limit = 0;
+    for (int c = 0; c < 3; ++c) {
+        b->ms_per_cycle[c] = ms_per_model_cycle() * (c == 0 ? 1.0 : (c == 1 ? 1.3 : 4.0));
+        b->pred[c] = 0.0;
+        b->t_beg[c] = b->t_end[c] = nullptr;
+    }
     for (int i = 0; i < 2; ++i) {
         b->dev_slots[i] = nullptr;
         b->host_slots[i] = nullptr;
@@ -910,6 +929,11 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
             return fail(MC_EDEVICE, "could not allocate the slot tables");
         }
     }
+    for (int c = 0; c < 3; ++c)
+        if (hipEventCreate(&b->t_beg[c]) != hipSuccess || hipEventCreate(&b->t_end[c]) != hipSuccess) {
+            mc_batch_destroy(b);
+            return fail(MC_EDEVICE, "could not create the timing events");
+        }
     if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->go, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
@@ -972,6 +996,27 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
     Slot* hs = b->host_slots[par];
     const uint32_t S = b->max_slots;
     const bool fp64 = b->precision == MC_FP64;
+
+    // calibration from the launches of the last run that have finished
+    for (int c = 0; c < 3; ++c) {
+        if (b->pred[c] <= 0.0) continue;
+        if (hipEventQuery(b->t_end[c]) != hipSuccess) {
+            (void)hipGetLastError();  // not finished: no sample
+            continue;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->t_beg[c], b->t_end[c]) == hipSuccess && ms > 0.f) {
+            const double f = b->ms_per_cycle[c];
+            const double r = std::min(4.0 * f, std::max(0.25 * f, (double)ms / b->pred[c]));
+            b->ms_per_cycle[c] = 0.5 * f + 0.5 * r;
+        }
+        (void)hipGetLastError();
+        b->pred[c] = 0.0;
+    }
+    // every launch of a run is sized to the time the reference system takes
+    // for max_moves_per_slot moves
+    const double t_slice = slice_time(max_moves_per_slot) * ms_per_model_cycle();
+    double pred[3] = {0.0, 0.0, 0.0};
 
     // Engine of every system for this run.  Each system needs one workgroup;
     // the workgroups left over (up to the batch's limit) go to the systems
@@ -1047,13 +1092,14 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         mc_system* s = b->sys[i];
         uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
         if (nblk[i]) {
-            // a slice of as many sweeps as a 1000-molecule system of the batch
-            // gets (a sweep on the system's own workgroup count takes about as
-            // long), fewer when it has fewer workgroups
+            // modelled cycles of a sweep: the one-workgroup model over the
+            // workgroups (the class calibration absorbs the engine's overheads)
+            const double unit = s->g.sweep_cost / nblk[i];
             if (max_moves_per_slot) {
-                const double q = (double)(max_moves_per_slot / 1000) * nblk[i] / s->g.spread_blocks;
+                const double q = t_slice / (b->ms_per_cycle[2] * unit);
                 k = std::min<uint64_t>(k, std::max<uint64_t>(1, (uint64_t)q));
             }
+            pred[2] = std::max(pred[2], (double)k * unit);
             SpreadSlot sl{};
             sl.sys = s->dev;
             sl.n_sweeps = k;
@@ -1062,13 +1108,14 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             hsp[ns++] = sl;
             blocks += nblk[i];
         } else {
+            const int cls = s->g.resident ? 0 : 1;
             if (max_moves_per_slot) {
                 // equal time slices: the time of max_moves_per_slot moves of the
-                // 1000-molecule reference, in sweeps of this system (modelled)
-                const double cap = slice_time(max_moves_per_slot) / s->g.sweep_cost;
+                // 1000-molecule reference, in sweeps of this system
+                const double cap = t_slice / (b->ms_per_cycle[cls] * s->g.sweep_cost);
                 k = std::min<uint64_t>(k, std::max<uint64_t>(1, (uint64_t)cap));
             }
-            const int cls = s->g.resident ? 0 : 1;
+            pred[cls] = std::max(pred[cls], (double)k * s->g.sweep_cost);
             Slot sl{};
             sl.sys = s->dev;
             sl.n_sweeps = k;
@@ -1096,7 +1143,10 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         b->pending2[par] = true;
         SpreadSlot none{};
         HIPCHK(launch_zero_barriers(b->dev_spread[par], ns, b->stream2));
+        HIPCHK(hipEventRecord(b->t_beg[2], b->stream2));
         HIPCHK(launch_spread(fp64, b->dev_spread[par], ns, none, blocks, b->stream2));
+        HIPCHK(hipEventRecord(b->t_end[2], b->stream2));
+        b->pred[2] = pred[2];
         for (const auto& pe : parts2) {
             Slot one{};
             one.sys = pe.first->dev;
@@ -1115,9 +1165,13 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         b->pending[par] = true;
         Slot none{};
         for (int cls = 0; cls < 2; ++cls)
-            if (n[cls])
+            if (n[cls]) {
+                HIPCHK(hipEventRecord(b->t_beg[cls], b->stream));
                 HIPCHK(launch_sweeps(fp64, cls == 0, b->dev_slots[par] + cls * S, none, n[cls],
                                      lds[cls], b->stream));
+                HIPCHK(hipEventRecord(b->t_end[cls], b->stream));
+                b->pred[cls] = pred[cls];
+            }
         for (const auto& pe : parts1) {
             Slot one{};
             one.sys = pe.first->dev;
@@ -1177,6 +1231,10 @@ void mc_batch_destroy(mc_batch* b)
         if (b->dev_ev2[i]) (void)hipFree(b->dev_ev2[i]);
         if (b->host_ev2[i]) (void)hipHostFree(b->host_ev2[i]);
         if (b->copied2[i]) (void)hipEventDestroy(b->copied2[i]);
+    }
+    for (int c = 0; c < 3; ++c) {
+        if (b->t_beg[c]) (void)hipEventDestroy(b->t_beg[c]);
+        if (b->t_end[c]) (void)hipEventDestroy(b->t_end[c]);
     }
     if (b->go) (void)hipEventDestroy(b->go);
     if (b->done) (void)hipEventDestroy(b->done);

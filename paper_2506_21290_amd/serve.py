@@ -10,10 +10,10 @@ it there); the workgroups left over go to the large jobs with the most work
 left, which then run on the multi-workgroup engine in a cooperative launch
 beside the others.
 
-The time slice is given in attempted moves per job; the engine scales it by
-its model of per-workgroup throughput against system size (small systems run
-fewer moves per second on one workgroup), so every job of a launch gets a
-similar share of time.
+The time slice is given in attempted moves of a 1000-molecule job; the batch
+turns it into a time and gives every job the sweeps it runs in that time on
+its engine (a cost model against size, calibrated on the batch's own timed
+launches), so the launches of a run take about the same time.
 
 Each finished job returns E/M (mean over the second half of its sweeps), g(r)
 (frames over the second half) and C_2(t) (Sec. III, Eq. 3 and Eq. 7).
@@ -137,7 +137,7 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, memory_budget, backend=None, quantum_moves=200_000):
+    def __init__(self, memory_budget, backend=None, quantum_moves=100_000):
         self.backend = backend if backend is not None else GpuBackend()
         self.budget = int(memory_budget)
         self.used = 0
