@@ -1583,10 +1583,10 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
 // taking cells of the colour in turn.  For every cell the wave copies the
 // neighbourhood (molecules within reach of the cell's box) into its LDS and
 // runs the cell's trials on the copy, writing each accepted move through to
-// HBM.  Grid barriers separate the steps; the colours keep the waves apart
-// exactly as in the single-workgroup engine, so the decisions are the same.
+// HBM.  Barriers among the system's workgroups separate the steps; the colours
+// keep the waves apart exactly as in the single-workgroup engine, so the
+// decisions are the same.
 
-// The staged neighbourhood of the cell a wave is working on.
 // Barrier of the workgroups of one system inside a cooperative launch (which
 // keeps every workgroup resident): a counter in the system's buffer, zero at
 // launch, that each workgroup raises once per barrier; a workgroup passes the
