@@ -33,10 +33,15 @@ SWEEPS_PER_STEP = 100
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank lines left out (a
+    change of wording does not change the kernel the counters were taken on)."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "engine.h"):
-        with open(os.path.join(ROOT, "paper_2506_21290_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2506_21290_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
