@@ -45,17 +45,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on another version of the kernel."""
+def measured_counters(name):
+    """The committed rocprofv3 counter summary of a kernel (HBM bytes per
+    launch, VALU busy fraction), or {} when it is missing or was taken on
+    another version of the kernel."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return t.get("bytes_per_launch")
+        return {}
+    return t
+
+
+def measured_traffic(name):
+    return measured_counters(name).get("bytes_per_launch")
 
 
 def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=0, nc=0, seed=1):
@@ -169,6 +174,8 @@ def bench_c1(args, flipmc, torch):
             "frac": achieved / PEAK_TFLOPS["f32"],
             "traffic": traffic,
             "kernel": "k_sweeps<float, resident>",
+            "cus_used": 1,
+            "valu_busy_on_its_cu": measured_counters("k_sweeps_c1").get("valu_busy_on_its_cu"),
             "avg_launch_ms": f32["sweep_kernel_ms"] / launches,
             "flops_per_launch": flops / launches,
             "flop_per_pair_term": FLOP_PER_PAIR_TERM,
