@@ -19,6 +19,11 @@ constexpr int kGofrBins = 256;
 constexpr int kC2Max = 32;
 constexpr int kMaxMolecules = 65535;  // indices are stored as u16 in cell lists
 constexpr int kCellListCap = 192;     // per-wave list of molecules near the current cell
+// The single-workgroup event kernel copies centres, quaternions and types of
+// systems up to this size into LDS for its O(M^2) loops (larger systems use
+// the multi-workgroup event kernel).
+constexpr uint32_t kEventStage = 2047;
+constexpr size_t kEventStageBytes = size_t(kEventStage) * (7 * sizeof(double) + sizeof(uint32_t));
 
 // Work of the event kernel (Slot::flags).
 enum : uint32_t {

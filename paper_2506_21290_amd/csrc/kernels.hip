@@ -454,6 +454,57 @@ __device__ double resum_energy(const Ctx<Real, kRes>& C, uint32_t m0, uint32_t m
     return block_sum(e, C.red);
 }
 
+// The same total from the cell lists of the last sweep (HBM state): a
+// molecule has moved at most sqrt(3) d_max since they were built, so every
+// pair within reach lies within `span` cells per axis of the cell it was
+// sorted into.  Each pair is counted by its lower index, the neighbour cells
+// in a fixed order and the molecules of a cell in ascending index.
+// Requires 2 span + 1 <= n_c.
+template <typename Real, bool kRes>
+__device__ double resum_energy_cells(const Ctx<Real, kRes>& C, uint32_t m0, uint32_t mstep, int span)
+{
+    const uint32_t M = C.M;
+    const int nc = (int)C.nc;
+    double e = 0.0;
+    for (uint32_t m = m0; m < M; m += mstep) {
+        double om[9], sm[3];
+        offsets_f64(C, m, om, sm);
+        const double cx = C.com[m], cy = C.com[M + m], cz = C.com[2 * M + m];
+        const int cid = (int)C.cellid[m];
+        const int ix = cid % nc, iy = (cid / nc) % nc, iz = cid / (nc * nc);
+        for (int oz = -span; oz <= span; ++oz)
+            for (int oy = -span; oy <= span; ++oy)
+                for (int ox = -span; ox <= span; ++ox) {
+                    const int x = (ix + ox + nc) % nc, y = (iy + oy + nc) % nc, z = (iz + oz + nc) % nc;
+                    const uint32_t c = (uint32_t)(x + nc * (y + nc * z));
+                    const uint32_t pe = C.cellb[c + 1];
+                    for (uint32_t p = C.cellb[c]; p < pe; ++p) {
+                        const uint32_t j = C.list[p];
+                        if (j <= m) continue;
+                        const double dx = min_image(C.com[j] - cx, C.L, C.invL);
+                        const double dy = min_image(C.com[M + j] - cy, C.L, C.invL);
+                        const double dz = min_image(C.com[2 * M + j] - cz, C.L, C.invL);
+                        if (dx * dx + dy * dy + dz * dz >= C.reach2) continue;
+                        double oj[9], sj[3];
+                        offsets_f64(C, j, oj, sj);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+#pragma unroll
+                            for (int t = 0; t < 3; ++t) {
+                                const double rx = dx + oj[3 * t] - om[3 * a];
+                                const double ry = dy + oj[3 * t + 1] - om[3 * a + 1];
+                                const double rz = dz + oj[3 * t + 2] - om[3 * a + 2];
+                                const double r2 = rx * rx + ry * ry + rz * rz;
+                                const double sg = 0.5 * (sm[a] + sj[t]);
+                                const double s2 = sg * sg;
+                                if (r2 < C.rc2_factor * s2) e += pair_u(s2, r2);
+                            }
+                    }
+                }
+    }
+    return block_sum(e, C.red);
+}
+
 __device__ __forceinline__ bool is_c2_time(uint64_t t)
 {
     if (t == 0) return false;
@@ -1500,6 +1551,7 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
     __shared__ double red[kWaves];
     __shared__ double misc[16];
     __shared__ uint32_t bins[2 * kGofrBins];
+    extern __shared__ __align__(16) unsigned char ev_stage[];
     const Slot sl = slots ? slots[blockIdx.x] : one;
     if (sl.sys == nullptr || sl.flags == 0) return;
     Ctx<double, false> C;
@@ -1522,8 +1574,23 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
     }
     const uint64_t sweep = st->sweep;
     const double e_acc = st->e_acc;
-    __syncthreads();
     const uint32_t f = sl.flags;
+    const uint32_t M = C.M;
+    if ((f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic | kFlagGofr)) &&
+        !(f & kFlagParts) && M <= kEventStage) {
+        // the O(M^2) loops read centres, orientations and types from an LDS
+        // copy (same values, same order: the same sums)
+        double* scom = (double*)ev_stage;
+        double* squat = scom + 3 * M;
+        uint32_t* stypes = (uint32_t*)(squat + 4 * M);
+        for (uint32_t i = tid; i < 3 * M; i += kThreads) scom[i] = C.gcom[i];
+        for (uint32_t i = tid; i < 4 * M; i += kThreads) squat[i] = C.quat[i];
+        for (uint32_t i = tid; i < M; i += kThreads) stypes[i] = C.types[i];
+        C.com = scom;
+        C.quat = squat;
+        C.types = stypes;
+    }
+    __syncthreads();
     if (f & kFlagObsReset) {
         reset_observables(C);
         __syncthreads();
@@ -1832,9 +1899,9 @@ __global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
     C.bins = bins;
     C.ecell = nullptr;
     C.site = nullptr;
-    C.cellb = nullptr;
-    C.cellid = nullptr;
-    C.list = nullptr;
+    C.cellb = one.sys->g_cell;
+    C.cellid = one.sys->g_cellid;
+    C.list = one.sys->g_list;
     if (threadIdx.x == 0) {
         misc[1] = C.sig0;
         misc[2] = C.sig1;
@@ -1844,7 +1911,11 @@ __global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
     const uint32_t f = one.flags;
     const uint32_t m0 = blockIdx.x * kThreads + threadIdx.x, step = gridDim.x * kThreads;
     if (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) {
-        const double e = resum_energy(C, m0, step);
+        // a scheduled re-sum follows sweeps, whose cell lists are still there
+        const int span = (int)ceil((sqrt(C.reach2) + 2.0 * 1.7320508075688772 * C.dmax + 1e-9) / C.w);
+        const bool cells = (f & (kFlagResumSet | kFlagResumReport)) == 0 && C.cellb != nullptr &&
+                           2 * span + 1 <= (int)C.nc;
+        const double e = cells ? resum_energy_cells(C, m0, step, span) : resum_energy(C, m0, step);
         if (threadIdx.x == 0) C.gpart[blockIdx.x] = e;
         __syncthreads();
     }
@@ -1903,7 +1974,11 @@ hipError_t launch_sweeps(bool fp64, bool resident, const Slot* dev_slots, const 
 hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
                          hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_events, dim3(n_blocks), dim3(kThreads), 0, stream, dev_slots, one);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void*)&k_events, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kEventStageBytes);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_events, dim3(n_blocks), dim3(kThreads), kEventStageBytes, stream,
+                       dev_slots, one);
     return hipGetLastError();
 }
 
