@@ -16,6 +16,7 @@ constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxSeg = 64;        // stencil row segments per cell (k <= 3: <= 50)
 constexpr int kGofrBins = 256;
+constexpr int kGofrQueue = 128;  // per-wave queue of molecule pairs of a g(r) frame
 constexpr int kC2Max = 32;
 constexpr int kMaxMolecules = 65535;  // indices are stored as u16 in cell lists
 constexpr int kCellListCap = 192;     // per-wave list of molecules near the current cell

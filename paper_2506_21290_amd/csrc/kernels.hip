@@ -302,6 +302,7 @@ struct Ctx {
     uint16_t* list;
     double* red;
     double* ecell;  // accepted dE of each cell in the current sweep
+    const double* off;  // FP64 site offsets [9][M] computed up front (event kernel), or null
     uint32_t* bins;
     double* misc;
 };
@@ -404,14 +405,19 @@ __device__ __forceinline__ void offsets_f64(const Ctx<Real, kRes>& C, uint32_t m
                                             double sg[3])
 {
     const uint32_t M = C.M;
-    double r[9];
-    rotation(C.quat[m], C.quat[M + m], C.quat[2 * M + m], C.quat[3 * M + m], r);
+    if (C.off) {
 #pragma unroll
-    for (int s = 0; s < 3; ++s)
+        for (int i = 0; i < 9; ++i) o[i] = C.off[i * M + m];
+    } else {
+        double r[9];
+        rotation(C.quat[m], C.quat[M + m], C.quat[2 * M + m], C.quat[3 * M + m], r);
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            o[3 * s + a] = r[3 * a] * body_at(C, s, 0) + r[3 * a + 1] * body_at(C, s, 1) +
-                           r[3 * a + 2] * body_at(C, s, 2);
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                o[3 * s + a] = r[3 * a] * body_at(C, s, 0) + r[3 * a + 1] * body_at(C, s, 1) +
+                               r[3 * a + 2] * body_at(C, s, 2);
+    }
     const uint32_t ty = C.types[m];
 #pragma unroll
     for (int s = 0; s < 3; ++s) sg[s] = sigma_of(C, (ty >> (8 * s)) & 0xFFu);
@@ -564,64 +570,112 @@ __device__ void reset_observables(const Ctx<Real, kRes>& C)
 
 // One g(r) frame (Eq. 3 numerator): every ordered pair of distinct sites.
 template <typename Real, bool kRes>
-__device__ void gofr_frame(const Ctx<Real, kRes>& C, uint32_t m0, uint32_t mstep, bool shared_out)
+__device__ void gofr_frame(const Ctx<Real, kRes>& C, uint32_t m0, uint32_t mstep, bool shared_out,
+                           uint32_t* queue)
 {
     const uint32_t M = C.M, half = M / 2, nb = C.gofr_nbins;
-    uint32_t* ball = C.bins;
+    uint32_t* bintra = C.bins;  // intramolecular pairs; all = intra + inter at the end
     uint32_t* binter = C.bins + kGofrBins;
+    uint32_t* q = queue + (threadIdx.x >> 6) * kGofrQueue;  // this wave's molecule pairs
+    const uint32_t lane = (uint32_t)__lane_id();
     for (uint32_t b = threadIdx.x; b < 2 * kGofrBins; b += kThreads) C.bins[b] = 0;
     __syncthreads();
     const double dr = C.gofr_dr, rmax = C.gofr_rmax;
     const double cut = rmax + 2.0 * C.radius;
     const double cut2 = cut * cut;
-    for (uint32_t m = m0; m < M; m += mstep) {
-        double om[9], sm[3];
+    const float inv_dr = (float)(1.0 / dr);
+    // bin floor(sqrt(r2) / dr) in FP64; an FP32 estimate decides unless it
+    // lies within 2e-4 of a bin edge (its error stays below 1e-4 up to the last bin)
+    auto bin = [&](double r2) __attribute__((always_inline)) {
+        const float t = sqrtf((float)r2) * inv_dr;
+        const float fl = floorf(t);
+        int b = (int)fl;
+        if (t - fl < 2e-4f || fl + 1.0f - t < 2e-4f) b = (int)floor(sqrt(r2) / dr);
+        return b;
+    };
+    // the nine site pairs of molecules m, j (each with its own nearest image)
+    auto site_pairs = [&](uint32_t m, uint32_t j) __attribute__((always_inline)) {
+        double om[9], sm[3], oj[9], sj[3];
         offsets_f64(C, m, om, sm);
+        offsets_f64(C, j, oj, sj);
+        const double dx = min_image(C.com[j] - C.com[m], C.L, C.invL);
+        const double dy = min_image(C.com[M + j] - C.com[M + m], C.L, C.invL);
+        const double dz = min_image(C.com[2 * M + j] - C.com[2 * M + m], C.L, C.invL);
 #pragma unroll
-        for (int s = 0; s < 3; ++s)
+        for (int t = 0; t < 3; ++t) {
+            const double bx = dx + oj[3 * t], by = dy + oj[3 * t + 1], bz = dz + oj[3 * t + 2];
 #pragma unroll
-            for (int t = s + 1; t < 3; ++t) {
-                const double rx = om[3 * t] - om[3 * s], ry = om[3 * t + 1] - om[3 * s + 1],
-                             rz = om[3 * t + 2] - om[3 * s + 2];
-                const int b = (int)floor(sqrt(rx * rx + ry * ry + rz * rz) / dr);
-                if (b >= 0 && b < (int)nb) atomicAdd(&ball[b], 2u);
-            }
-        const double cx = C.com[m], cy = C.com[M + m], cz = C.com[2 * M + m];
-        for (uint32_t dj = 1; dj <= half; ++dj) {
-            if ((M & 1u) == 0u && dj == half && m >= half) break;
-            uint32_t j = m + dj;
-            if (j >= M) j -= M;
-            const double dx = min_image(C.com[j] - cx, C.L, C.invL);
-            const double dy = min_image(C.com[M + j] - cy, C.L, C.invL);
-            const double dz = min_image(C.com[2 * M + j] - cz, C.L, C.invL);
-            if (dx * dx + dy * dy + dz * dz >= cut2) continue;
-            double oj[9], sj[3];
-            offsets_f64(C, j, oj, sj);
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const double bx = dx + oj[3 * t], by = dy + oj[3 * t + 1], bz = dz + oj[3 * t + 2];
-#pragma unroll
-                for (int s = 0; s < 3; ++s) {
-                    // each site pair takes its own nearest image: r reaches L / 2
-                    const double rx = min_image(bx - om[3 * s], C.L, C.invL);
-                    const double ry = min_image(by - om[3 * s + 1], C.L, C.invL);
-                    const double rz = min_image(bz - om[3 * s + 2], C.L, C.invL);
-                    const int b = (int)floor(sqrt(rx * rx + ry * ry + rz * rz) / dr);
-                    if (b >= 0 && b < (int)nb) {
-                        atomicAdd(&ball[b], 2u);
-                        atomicAdd(&binter[b], 2u);
-                    }
-                }
+            for (int s = 0; s < 3; ++s) {
+                // r reaches L / 2
+                const double rx = min_image(bx - om[3 * s], C.L, C.invL);
+                const double ry = min_image(by - om[3 * s + 1], C.L, C.invL);
+                const double rz = min_image(bz - om[3 * s + 2], C.L, C.invL);
+                const int b = bin(rx * rx + ry * ry + rz * rz);
+                if (b >= 0 && b < (int)nb) atomicAdd(&binter[b], 2u);
             }
         }
+    };
+    // the pairs within reach of the bins are queued per wave and binned 64 at
+    // a time (the counts do not depend on the order)
+    uint32_t qn = 0;
+    auto drain = [&](uint32_t upto) __attribute__((always_inline)) {
+        while (qn >= upto && qn > 0) {
+            const uint32_t take = min(qn, 64u);
+            const uint32_t base = qn - take;
+            if (lane < take) {
+                const uint32_t e = q[base + lane];
+                site_pairs(e & 0xFFFFu, e >> 16);
+            }
+            qn = base;
+        }
+    };
+    // rounds of the wave's first lane (the most of any lane): wave-uniform
+    const uint32_t nrounds = (M + mstep - 1 - min(m0 - lane, M)) / mstep;
+    for (uint32_t r = 0; r < nrounds; ++r) {
+        const uint32_t m = m0 + r * mstep;
+        const bool mine = m < M;
+        if (mine) {
+            double om[9], sm[3];
+            offsets_f64(C, m, om, sm);
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+#pragma unroll
+                for (int t = s + 1; t < 3; ++t) {
+                    const double rx = om[3 * t] - om[3 * s], ry = om[3 * t + 1] - om[3 * s + 1],
+                                 rz = om[3 * t + 2] - om[3 * s + 2];
+                    const int b = bin(rx * rx + ry * ry + rz * rz);
+                    if (b >= 0 && b < (int)nb) atomicAdd(&bintra[b], 2u);
+                }
+        }
+        const double cx = mine ? C.com[m] : 0.0, cy = mine ? C.com[M + m] : 0.0,
+                     cz = mine ? C.com[2 * M + m] : 0.0;
+        for (uint32_t dj = 1; dj <= half; ++dj) {
+            bool keep = mine && !((M & 1u) == 0u && dj == half && m >= half);
+            uint32_t j = m + dj;
+            if (j >= M) j -= M;
+            if (keep) {
+                const double dx = min_image(C.com[j] - cx, C.L, C.invL);
+                const double dy = min_image(C.com[M + j] - cy, C.L, C.invL);
+                const double dz = min_image(C.com[2 * M + j] - cz, C.L, C.invL);
+                keep = dx * dx + dy * dy + dz * dz < cut2;
+            }
+            const uint64_t bm = __ballot(keep);
+            if (keep) q[qn + rank_below(bm)] = m | (j << 16);
+            qn += (uint32_t)__popcll(bm);
+            wave_lds_sync();
+            drain(64u);
+            wave_lds_sync();
+        }
     }
+    drain(1u);
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
+        const uint32_t all = bintra[b] + binter[b];
         if (shared_out) {  // several workgroups add into the histograms
-            if (ball[b]) atomicAdd((unsigned long long*)&C.gofr_all[b], (unsigned long long)ball[b]);
+            if (all) atomicAdd((unsigned long long*)&C.gofr_all[b], (unsigned long long)all);
             if (binter[b]) atomicAdd((unsigned long long*)&C.gofr_inter[b], (unsigned long long)binter[b]);
         } else {
-            C.gofr_all[b] += ball[b];
+            C.gofr_all[b] += all;
             C.gofr_inter[b] += binter[b];
         }
     }
@@ -1457,6 +1511,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
         C.cellid = (uint16_t*)(smem + L.cellid);
         C.list = (uint16_t*)(smem + L.list);
         C.ecell = (double*)(smem + L.ecell);
+        C.off = nullptr;
     } else {
         C.com = C.gcom;
         C.site = (R4<Real>*)g_site;
@@ -1464,6 +1519,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
         C.cellid = g_cellid;
         C.list = g_list;
         C.ecell = Dp->g_ecell;
+        C.off = nullptr;
     }
     WaveLds<Real> W;
     W.surv = (uint16_t*)(smem + L.surv) + wave * kCellListCap;
@@ -1551,6 +1607,7 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
     __shared__ double red[kWaves];
     __shared__ double misc[16];
     __shared__ uint32_t bins[2 * kGofrBins];
+    __shared__ uint32_t gqueue[kWaves * kGofrQueue];
     extern __shared__ __align__(16) unsigned char ev_stage[];
     const Slot sl = slots ? slots[blockIdx.x] : one;
     if (sl.sys == nullptr || sl.flags == 0) return;
@@ -1561,6 +1618,7 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
     C.misc = misc;
     C.bins = bins;
     C.ecell = nullptr;
+    C.off = nullptr;
     C.site = nullptr;
     C.cellb = nullptr;
     C.cellid = nullptr;
@@ -1580,14 +1638,27 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
         !(f & kFlagParts) && M <= kEventStage) {
         // the O(M^2) loops read centres, orientations and types from an LDS
         // copy (same values, same order: the same sums)
+        // (with the site offsets computed once per molecule when they fit)
         double* scom = (double*)ev_stage;
         double* squat = scom + 3 * M;
-        uint32_t* stypes = (uint32_t*)(squat + 4 * M);
+        const bool pre = size_t(M) * (12 * sizeof(double) + sizeof(uint32_t)) <= kEventStageBytes;
+        uint32_t* stypes = (uint32_t*)(squat + (pre ? 9 : 4) * M);
         for (uint32_t i = tid; i < 3 * M; i += kThreads) scom[i] = C.gcom[i];
-        for (uint32_t i = tid; i < 4 * M; i += kThreads) squat[i] = C.quat[i];
         for (uint32_t i = tid; i < M; i += kThreads) stypes[i] = C.types[i];
+        if (pre) {
+            __syncthreads();  // sigma table (misc) before offsets_f64
+            for (uint32_t m = tid; m < M; m += kThreads) {
+                double o[9], sg[3];
+                offsets_f64(C, m, o, sg);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) squat[i * M + m] = o[i];
+            }
+            C.off = squat;
+        } else {
+            for (uint32_t i = tid; i < 4 * M; i += kThreads) squat[i] = C.quat[i];
+            C.quat = squat;
+        }
         C.com = scom;
-        C.quat = squat;
         C.types = stypes;
     }
     __syncthreads();
@@ -1626,7 +1697,7 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
         if (f & kFlagParts) {
             if (tid == 0) st->n_gofr += 1;
         } else {
-            gofr_frame(C, threadIdx.x, kThreads, false);
+            gofr_frame(C, threadIdx.x, kThreads, false, gqueue);
         }
         __syncthreads();
     }
@@ -1746,6 +1817,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
     C.red = nullptr;
     C.bins = nullptr;
     C.ecell = Dp->g_ecell;
+    C.off = nullptr;
     uint32_t* cnt = Dp->g_cnt;
     uint32_t* fill = cnt + C.ncell;
     PropRec* props = (PropRec*)Dp->props;
@@ -1891,6 +1963,7 @@ __global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
     __shared__ double red[kWaves];
     __shared__ double misc[16];
     __shared__ uint32_t bins[2 * kGofrBins];
+    __shared__ uint32_t gqueue[kWaves * kGofrQueue];
     Ctx<double, false> C;
     load_ctx(C, one.sys);
     C.com = C.gcom;
@@ -1898,6 +1971,7 @@ __global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
     C.misc = misc;
     C.bins = bins;
     C.ecell = nullptr;
+    C.off = nullptr;
     C.site = nullptr;
     C.cellb = one.sys->g_cell;
     C.cellid = one.sys->g_cellid;
@@ -1919,7 +1993,7 @@ __global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
         if (threadIdx.x == 0) C.gpart[blockIdx.x] = e;
         __syncthreads();
     }
-    if (f & kFlagGofr) gofr_frame(C, m0, step, true);
+    if (f & kFlagGofr) gofr_frame(C, m0, step, true, gqueue);
 }
 
 __global__ void k_init_lattice(SysDev* Dp, uint32_t n)
