@@ -94,6 +94,11 @@ typedef struct {
     uint32_t max_samples;      /* capacity of the E/M and drift sample arrays        */
     uint32_t flags;            /* MC_FLAG_* bits                                     */
     double   gofr_dr;          /* g(r) bin width; r_max = min(L/2, 5)                */
+    uint32_t barrier_polls;    /* multi-workgroup engine: polls a workgroup waits at
+                                  a barrier of its system before it gives up and the
+                                  system is marked faulted (reads then return
+                                  MC_EDEVICE); 0 = default (about 2^23, seconds)       */
+    uint32_t reserved;         /* 0                                                  */
 } mc_params;
 
 typedef struct mc_system mc_system;

@@ -521,6 +521,8 @@ void mc_params_default(mc_params* p)
     p->obs_start = 0;
     p->max_samples = 4096;
     p->gofr_dr = 0.02;
+    p->barrier_polls = 0;
+    p->reserved = 0;
 }
 
 int mc_geometry(const mc_params* p, double* box, uint32_t* k, uint32_t* nc)
@@ -632,6 +634,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
     if (nb > (uint32_t)kGofrBins) nb = kGofrBins;
     D.gofr_nbins = nb;
     D.gofr_dr = p->gofr_dr;
+    D.barrier_polls = p->barrier_polls ? p->barrier_polls : (1u << 23);
     D.gofr_rmax = rmax;
     D.lds_bytes = (uint32_t)g.lds;
     D.com = (double*)(b + lay.com);

@@ -73,7 +73,7 @@ struct SysDev {
     double body[9];      // body-frame site offsets, row s = site s
     double sigma[3];     // diameters of types A, B, C
     uint32_t resum_interval, obs_interval, gofr_interval, obs_start;
-    uint32_t max_samples, gofr_nbins, lds_bytes, pad0;
+    uint32_t max_samples, gofr_nbins, lds_bytes, barrier_polls;
     double gofr_dr, gofr_rmax;
     // state
     double* com;         // SoA [3][M]

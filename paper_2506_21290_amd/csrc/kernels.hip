@@ -1729,15 +1729,14 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
 // keeps every workgroup resident): a counter in the system's buffer, zero at
 // launch, that each workgroup raises once per barrier; a workgroup passes the
 // n-th barrier when the counter reaches n x (workgroups of the system).  The
-// wait is bounded: past the bound the system is marked faulted (Stats::fault)
-// and the workgroup stops waiting, at this and every later barrier, so that
-// the launch still ends.
-constexpr uint32_t kBarrierSpins = 1u << 23;  // seconds of waiting
-
+// wait is bounded (SysDev::barrier_polls polls, seconds by default): past the
+// bound the system is marked faulted (Stats::fault) and the workgroup stops
+// waiting, at this and every later barrier, so that the launch still ends.
 struct SysBarrier {
     uint32_t* count;
     uint32_t nblk;
     uint32_t epoch;
+    uint32_t polls;
     bool broken;
 };
 
@@ -1754,7 +1753,7 @@ __device__ void sys_sync(SysBarrier& B, uint32_t* fault, uint32_t* flag)
             uint32_t spins = 0;
             while (__hip_atomic_load(B.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins == kBarrierSpins) {
+                if (++spins >= B.polls) {
                     bad = 1;
                     __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
@@ -1841,7 +1840,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
     double e_acc = st->e_acc;
     uint64_t sweep = st->sweep;
     const uint64_t origin = st->obs_origin;
-    SysBarrier B{Dp->g_bar, nblk, 0u, false};
+    SysBarrier B{Dp->g_bar, nblk, 0u, Dp->barrier_polls, false};
     uint32_t* bflag = (uint32_t*)(C.misc + 15);
     auto sync = [&]() { sys_sync(B, &st->fault, bflag); };
     sync();

@@ -64,6 +64,8 @@ class mc_params(C.Structure):
         ("max_samples", C.c_uint32),
         ("flags", C.c_uint32),
         ("gofr_dr", C.c_double),
+        ("barrier_polls", C.c_uint32),
+        ("reserved", C.c_uint32),
     ]
 
 

@@ -163,6 +163,23 @@ def test_engines_make_identical_decisions(fp32):
         assert abs(sg["e_acc"] - s0["e_acc"]) <= 1e-12 * (abs(s0["e_acc"]) + 1.0)
 
 
+def test_barrier_timeout_marks_the_system_faulted():
+    # failure handling forced from the host: a one-poll bound on the waits at
+    # the multi-workgroup engine's barriers.  Workgroups give up instead of
+    # waiting, the launch still ends, and reading the system reports the
+    # fault instead of a corrupt state; another system is unaffected.
+    gp = gparams(2197, 1.3, 2, 6, fp32=True, seed=9, barrier_polls=1, resum_interval=0,
+                 obs_interval=0, gofr_interval=0)
+    assert flipmc.mc_engine(gp) == (flipmc.MC_ENGINE_SPREAD, 7)
+    g = flipmc.System(gp)
+    g.sweep(20)
+    with pytest.raises(flipmc.McError, match="barrier"):
+        g.energy()
+    ok = flipmc.System(gparams(2197, 1.3, 2, 6, fp32=True, seed=9))
+    ok.sweep(3)
+    assert math.isfinite(ok.energy()[0])
+
+
 def test_spread_engine_full_size_8000_sampled():
     # the 8000-molecule configuration (T = 1.1, FP32 dE) on its first sweeps,
     # with the engine's own decomposition, every trial checked
