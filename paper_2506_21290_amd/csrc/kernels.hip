@@ -1730,41 +1730,40 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
 // launch, that each workgroup raises once per barrier; a workgroup passes the
 // n-th barrier when the counter reaches n x (workgroups of the system).  The
 // wait is bounded (SysDev::barrier_polls polls, seconds by default): past the
-// bound the system is marked faulted (Stats::fault) and the workgroup stops
-// waiting, at this and every later barrier, so that the launch still ends.
+// bound the system is marked faulted (Stats::fault) and sys_sync returns
+// false, and the workgroup must leave the kernel at once.  A workgroup thus
+// only goes on past a barrier when every workgroup has finished the work
+// before it, and the others, which then miss its increments, time out too.
 struct SysBarrier {
     uint32_t* count;
     uint32_t nblk;
     uint32_t epoch;
     uint32_t polls;
-    bool broken;
 };
 
-__device__ void sys_sync(SysBarrier& B, uint32_t* fault, uint32_t* flag)
+__device__ bool sys_sync(SysBarrier& B, uint32_t* fault, uint32_t* flag)
 {
     __syncthreads();
     ++B.epoch;
     if (threadIdx.x == 0) {
         uint32_t bad = 0;
-        if (!B.broken) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_fetch_add(B.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t target = B.epoch * B.nblk;
-            uint32_t spins = 0;
-            while (__hip_atomic_load(B.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins >= B.polls) {
-                    bad = 1;
-                    __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(B.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = B.epoch * B.nblk;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(B.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins >= B.polls) {
+                bad = 1;
+                __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *flag = bad;
     }
     __syncthreads();
-    if (*flag) B.broken = true;
+    return *flag == 0u;
 }
 
 // One launch can advance several systems: slot i owns workgroups
@@ -1840,10 +1839,10 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
     double e_acc = st->e_acc;
     uint64_t sweep = st->sweep;
     const uint64_t origin = st->obs_origin;
-    SysBarrier B{Dp->g_bar, nblk, 0u, Dp->barrier_polls, false};
+    SysBarrier B{Dp->g_bar, nblk, 0u, Dp->barrier_polls};
     uint32_t* bflag = (uint32_t*)(C.misc + 15);
-    auto sync = [&]() { sys_sync(B, &st->fault, bflag); };
-    sync();
+    // at every barrier a workgroup that timed out leaves (see sys_sync)
+    if (!sys_sync(B, &st->fault, bflag)) return;
 
     for (uint64_t it = 0; it < sl.n_sweeps; ++it) {
         constexpr bool run = true;
@@ -1863,7 +1862,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                 props[m] = propose(C, m, sweep, hx, hy, hz, ix, iy, iz);
             }
         }
-        sync();
+        if (!sys_sync(B, &st->fault, bflag)) return;
         // cell starts (exclusive scan of the counts); counts cleared for the
         // next sweep
         if (run && bid == 0) {
@@ -1873,20 +1872,20 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
             if (tid == 0) C.cellb[ncell] = M;
             for (uint32_t c = tid; c < ncell; c += kSpreadThreads) cnt[c] = 0;
         }
-        sync();
+        if (!sys_sync(B, &st->fault, bflag)) return;
         if (run) {
             for (uint32_t m = gtid; m < M; m += GT) {
                 const uint32_t c = C.cellid[m];
                 C.list[C.cellb[c] + atomicAdd(&fill[c], 1u)] = (uint16_t)m;
             }
         }
-        sync();
+        if (!sys_sync(B, &st->fault, bflag)) return;
         // ascending molecule index inside every cell
         if (run) {
             sort_cells(C.list, C.cellb, gw, NW, ncell);
             for (uint32_t c = gtid; c < ncell; c += GT) fill[c] = 0;
         }
-        sync();
+        if (!sys_sync(B, &st->fault, bflag)) return;
 
         const PhaseConst P = phase_const(C, sweep);
         const View<Real> V{S.com, S.site, kCap};
@@ -1918,7 +1917,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                 }
             }
             if (col == ncol - 1) ++sweep;
-            sync();
+            if (!sys_sync(B, &st->fault, bflag)) return;
         }
         // E_acc += the sweep's dE (sweep_energy); E/M samples (the next
         // sweep's steps touch neither)
