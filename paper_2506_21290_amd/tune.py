@@ -30,7 +30,10 @@ _table = None
 def candidates(M, precision, per_k=4):
     """Valid (k, n_c) for an M-molecule box at the default density: the
     `per_k` finest grids of each k (coarser grids only lengthen the chains of
-    trials inside a cell)."""
+    trials inside a cell).  When some of them keep the state in one
+    workgroup's LDS, only those: such a system then runs on one workgroup,
+    the most efficient use of a compute unit when many jobs share the device
+    (a finer grid beyond the LDS would be faster alone on many workgroups)."""
     out = []
     for k in (2, 3):
         ok = []
@@ -43,7 +46,13 @@ def candidates(M, precision, per_k=4):
                 continue
             ok.append((k, nc))
         out += ok[-per_k:]
-    return out
+    resident = []
+    for k, nc in out:
+        p = flipmc.mc_params_default(n_molecules=M, precision=precision, colours_per_axis=k,
+                                     cells_per_side=nc)
+        if flipmc.mc_placement(p)[0]:
+            resident.append((k, nc))
+    return resident or out
 
 
 def table():
