@@ -242,7 +242,12 @@ __device__ __forceinline__ float pair_u(float s2, float r2)
 }
 __device__ __forceinline__ double pair_u(double s2, double r2)
 {
-    const double x = s2 / r2;
+    // 1 / r2: the hardware estimate refined by two Newton steps (within an
+    // ulp or two of the quotient; r2 is a normal number here)
+    double y = __builtin_amdgcn_rcp(r2);
+    y = fma(fma(-r2, y, 1.0), y, y);
+    y = fma(fma(-r2, y, 1.0), y, y);
+    const double x = s2 * y;
     const double x3 = x * x * x;
     const double t = fma(2.0, x3, -1.0);
     return t * t;
