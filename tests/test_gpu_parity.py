@@ -190,6 +190,31 @@ def test_spread_engine_full_size_8000_sampled():
     run_parity(gp, oparams(8000, 1.1, k, nc, seed=1), 2, True)
 
 
+def test_largest_lattice_keeps_its_energy():
+    # the largest lattice start within the 16-bit molecule index (40^3 = 64000
+    # molecules, multi-workgroup engine, FP32 dE): too large for the oracle's
+    # trial-by-trial replay, so checked by properties that hold at any size.
+    # The accumulated energy matches a fresh FP64 re-sum (from the lattice's
+    # overlaps, E/M ~ 1e5, down by orders of magnitude in three sweeps) within
+    # the FP32 bound on the accepted moves, and the state stays valid.
+    gp = flipmc.mc_params_default(n_molecules=64000, temperature=1.0, seed=11,
+                                  precision=flipmc.MC_FP32_DE, resum_interval=0,
+                                  obs_interval=0, gofr_interval=0)
+    L, k, nc = flipmc.mc_geometry(gp)
+    assert flipmc.mc_engine(gp)[0] == flipmc.MC_ENGINE_SPREAD
+    g = flipmc.System(gp)
+    e0 = g.get_state()["e_acc"]
+    g.sweep(3)
+    st = g.get_state()
+    e, _, drift = g.energy()
+    assert st["sweep"] == 3 and math.isfinite(e) and e < e0
+    assert abs(drift) <= 3e-5 * (abs(e0) + abs(e))
+    assert np.all((st["com"] >= 0.0) & (st["com"] < L))
+    assert np.allclose(np.linalg.norm(st["quat"], axis=1), 1.0, atol=1e-12)
+    obs = g.observables()
+    assert int(sum(obs["attempts"])) == 3 * 64000 and int(sum(obs["accepts"])) > 0
+
+
 def test_spread_engine_events_match_oracle():
     # 2197 molecules: the re-sum and g(r) run on the multi-workgroup event
     # kernel; both match the oracle on the same states
