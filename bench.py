@@ -374,7 +374,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": f"--gpus {args.gpus}: this engine runs on one GPU; "
-                                   "multi-GPU runs are not part of this build"}))
+                                   "it has no multi-GPU mode"}))
         sys.exit(2)
     import torch
 
