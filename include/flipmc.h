@@ -232,9 +232,11 @@ const char* mc_last_error(void);
 /* A batch holds up to max_slots systems of one precision.  Each
  * mc_batch_run gives every system one workgroup; the workgroups left over
  * (up to the batch's workgroup limit, one per compute unit by default) go to
- * the systems beyond one workgroup's LDS with the most remaining work, which
- * then run on the multi-workgroup engine, each on up to the workgroups it
- * uses alone.  Systems on one workgroup share one persistent launch per
+ * the systems with the most remaining work that can use several (those
+ * beyond one workgroup's LDS, and those within it when enough workgroups are
+ * idle to make them modelled 25 % faster), which then run on the
+ * multi-workgroup engine, each on up to the workgroups its cells allow.
+ * Systems on one workgroup share one persistent launch per
  * placement class (state in LDS / in HBM); systems on the multi-workgroup
  * engine share one cooperative launch on a second stream the batch creates.
  * All engines make the same decisions and sum the energy in the same order,
@@ -258,7 +260,8 @@ int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
  * per modelled cycle measured on the batch's earlier launches; at least one
  * sweep.  Slices also stop at each system's re-sum / g(r) / C_2 sweeps, whose
  * work follows in a second launch.  *n_launched = number of sweep launches
- * enqueued. */
+ * enqueued (one per placement class in use, one for the multi-workgroup
+ * engine). */
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched);
 
 /* At most max_workgroups workgroups of the batch's runs at once (0 = one per

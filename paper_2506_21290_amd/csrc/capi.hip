@@ -78,9 +78,10 @@ struct Geometry {
     uint32_t k, nc, ncell;
     bool resident;
     bool spread;          // standalone sweeps on the multi-workgroup engine
-    uint32_t spread_blocks;
+    uint32_t spread_blocks;  // its workgroups (also of an LDS system a batch may move there)
     size_t lds;
     double sweep_cost;    // modelled cycles of one sweep on one workgroup
+    double spread_cost;   // the same with the state in HBM (the multi-workgroup engine's unit)
 };
 
 // Critical path of one sweep of the resident kernel in cycles (a model fitted
@@ -166,9 +167,13 @@ int geometry(const mc_params* p, Geometry* g)
     // the model is fitted to the LDS state; with the state in HBM a sweep on
     // one workgroup takes about 1.3 times as long (measured 1.1 - 1.4 over
     // 2197 - 27000 molecules)
-    g->sweep_cost = cost_estimate(p->n_molecules, g->L, g->reach, k, nc) * (g->resident ? 1.0 : 1.3);
-    if (g->spread) {
-        // one wave per cell of a colour, within one cooperative wave of the device
+    const double cost = cost_estimate(p->n_molecules, g->L, g->reach, k, nc);
+    g->sweep_cost = cost * (g->resident ? 1.0 : 1.3);
+    g->spread_cost = cost * 1.3;
+    if (!(p->flags & MC_FLAG_SINGLE_WORKGROUP)) {
+        // one wave per cell of a colour, within one cooperative wave of the
+        // device; an LDS system keeps the count for a batch, which may move it
+        // to the multi-workgroup engine when compute units are idle
         uint32_t maxb = 0;
         const hipError_t e = spread_max_blocks(fp64, &maxb);
         if (e != hipSuccess || maxb == 0) {
@@ -238,7 +243,7 @@ BufLayout buf_layout(const mc_params* p, const Geometry& g)
     b.c2s = o;    o = al(o + kC2Max * sizeof(uint64_t));
     b.props = o;  o = al(o + M * 48);
     b.gpart = o;  o = al(o + kMaxParts * sizeof(double));
-    if (!g.resident) {
+    if (!g.resident || g.spread_blocks >= 2) {
         const bool fp64 = p->precision == MC_FP64;
         b.gsite = o;   o = al(o + 3 * M * site_bytes(fp64));
         b.gcell = o;   o = al(o + (size_t(g.ncell) + 1) * sizeof(uint32_t));
@@ -651,7 +656,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
     D.c2_sweep = (uint64_t*)(b + lay.c2s);
     D.props = (void*)(b + lay.props);
     D.g_part = (double*)(b + lay.gpart);
-    if (!g.resident) {
+    if (!g.resident || g.spread_blocks >= 2) {
         D.g_site = (void*)(b + lay.gsite);
         D.g_cell = (uint32_t*)(b + lay.gcell);
         D.g_cellid = (uint16_t*)(b + lay.gcellid);
@@ -955,6 +960,21 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
     }
     b->ncu = (uint32_t)ncu;
     b->wg_limit = (uint32_t)ncu;
+    {
+        // the first launch of a kernel carries one-time set-up costs: run the
+        // sweep kernels once here with no system, so the batch's timing of its
+        // own launches (its engine calibration) does not see them
+        const bool fp64 = precision == MC_FP64;
+        Slot none{};
+        SpreadSlot snone{};
+        hipError_t e = launch_sweeps(fp64, true, nullptr, none, 1, 0, b->stream);
+        if (e == hipSuccess) e = launch_sweeps(fp64, false, nullptr, none, 1, 0, b->stream);
+        if (e == hipSuccess && b->spread_max >= 2) e = launch_spread(fp64, nullptr, 0, snone, 1, b->stream);
+        if (e != hipSuccess) {
+            mc_batch_destroy(b);
+            return fail(MC_EDEVICE, "warm-up launch: %s", hipGetErrorString(e));
+        }
+    }
     *out = b;
     return MC_OK;
 }
@@ -1024,15 +1044,17 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
     // Engine of every system for this run.  Each system needs one workgroup;
     // the workgroups left over (up to the batch's limit) go to the systems
     // that can run on the multi-workgroup engine, most remaining work first,
-    // each up to its own workgroup count.  The engines make the same
-    // decisions, so a system may change engine from run to run.
+    // each up to its own workgroup count; a system whose state fits in LDS
+    // moves there only with enough workgroups to be modelled 25 % faster than
+    // on its own one.  The engines make the same decisions, so a system may
+    // change engine from run to run.
     std::vector<uint32_t> active;
     std::vector<std::pair<double, uint32_t>> cand;  // (-remaining moves, slot)
     for (uint32_t i = 0; i < S; ++i) {
         mc_system* s = b->sys[i];
         if (!s || b->remaining[i] == 0) continue;
         active.push_back(i);
-        if (s->g.spread && b->spread_max >= 2)
+        if ((s->g.spread || (s->g.resident && s->g.spread_blocks >= 2)) && b->spread_max >= 2)
             cand.emplace_back(-(double)b->remaining[i] * (double)s->p.n_molecules, i);
     }
     std::sort(cand.begin(), cand.end());
@@ -1049,12 +1071,16 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         for (const auto& c : cand) total -= c.first;
         uint32_t left = spare, coop = 0;
         auto cus = [&](uint32_t nb) { return (nb + bpc - 1) / bpc; };
+        auto pays = [&](const mc_system* s, uint32_t nb) {
+            return !s->g.resident || (double)nb * s->g.sweep_cost * b->ms_per_cycle[0] >=
+                                         1.25 * s->g.spread_cost * b->ms_per_cycle[2];
+        };
         for (const auto& c : cand) {
             const mc_system* s = b->sys[c.second];
             const uint32_t share = total > 0.0 ? (uint32_t)((double)spare * (-c.first) / total) : 0u;
             const uint32_t nb = std::min({s->g.spread_blocks, (1u + std::min(share, left)) * bpc,
                                           b->spread_max - coop});
-            if (nb < 2) continue;
+            if (nb < 2 || !pays(s, nb)) continue;
             nblk[c.second] = nb;
             left -= cus(nb) - 1;
             coop += nb;
@@ -1065,7 +1091,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             const uint32_t have = nblk[c.second];
             const uint32_t want = std::min({s->g.spread_blocks, (cus(std::max(have, 1u)) + left) * bpc,
                                             b->spread_max - coop + have});
-            if (want <= std::max(have, 1u) || want < 2) continue;
+            if (want <= std::max(have, 1u) || want < 2 || !pays(s, want)) continue;
             left -= cus(want) - (have ? cus(have) : 1u);
             coop += want - have;
             nblk[c.second] = want;
@@ -1097,7 +1123,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         if (nblk[i]) {
             // modelled cycles of a sweep: the one-workgroup model over the
             // workgroups (the class calibration absorbs the engine's overheads)
-            const double unit = s->g.sweep_cost / nblk[i];
+            const double unit = s->g.spread_cost / nblk[i];
             if (max_moves_per_slot) {
                 const double q = t_slice / (b->ms_per_cycle[2] * unit);
                 k = std::min<uint64_t>(k, std::max<uint64_t>(1, (uint64_t)q));
@@ -1186,7 +1212,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
     // later work on the batch stream (the next run, poll, reads) follows the
     // multi-workgroup launch
     if (ns) HIPCHK(hipStreamWaitEvent(b->stream, b->done, 0));
-    if (n_launched) *n_launched = n[0] + n[1] + (ns ? 1u : 0u);
+    if (n_launched) *n_launched = (n[0] ? 1u : 0u) + (n[1] ? 1u : 0u) + (ns ? 1u : 0u);
     return MC_OK;
 }
 

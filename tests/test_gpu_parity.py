@@ -391,6 +391,43 @@ def test_batch_equals_alone(fp32, workgroups):
         assert np.array_equal(st["types"], ref["types"]) and st["e_acc"] == ref["e_acc"]
 
 
+@pytest.mark.parametrize("limit,launches", [(0, 2), (2, 1)])
+def test_batch_moves_lds_system_to_idle_compute_units(limit, launches):
+    # FP32: 1728 molecules (k = 2, n_c = 6) fit one workgroup's LDS; with
+    # compute units idle the batch runs them on 7 workgroups of the
+    # multi-workgroup engine (a second launch beside the LDS launch of the
+    # small system), with a limit of 2 workgroups on one; either way bitwise
+    # the result of running each system alone
+    specs = [(1728, 0.9, 2, 6, 41), (216, 1.5, 3, 6, 42)]
+    sweeps = [12, 20]
+    assert flipmc.mc_engine(gparams(1728, 0.9, 2, 6, fp32=True))[0] == flipmc.MC_ENGINE_LDS
+    alone = []
+    for (M, T, k, nc, seed), n in zip(specs, sweeps):
+        s = flipmc.System(gparams(M, T, k, nc, fp32=True, seed=seed))
+        s.sweep(n)
+        alone.append(s.get_state())
+    b = flipmc.Batch(4, flipmc.MC_FP32_DE)
+    b.set_workgroups(limit)
+    systems = []
+    for (M, T, k, nc, seed), n in zip(specs, sweeps):
+        s = flipmc.System(gparams(M, T, k, nc, fp32=True, seed=seed), stream=b.stream)
+        b.add(s, n)
+        systems.append(s)
+    assert b.run(0) == launches
+    done = b.poll()
+    for _ in range(100):
+        if len(done) == len(specs):
+            break
+        b.run(0)
+        done += b.poll()
+    assert len(done) == len(specs)
+    for s, ref in zip(systems, alone):
+        st = s.get_state()
+        assert st["sweep"] == ref["sweep"]
+        assert np.array_equal(st["com"], ref["com"]) and np.array_equal(st["quat"], ref["quat"])
+        assert np.array_equal(st["types"], ref["types"]) and st["e_acc"] == ref["e_acc"]
+
+
 def test_isolated_molecule():
     gp = flipmc.mc_params_default(n_molecules=1, temperature=0.5, density=0.001,
                                   colours_per_axis=2, cells_per_side=2, precision=flipmc.MC_FP64)
