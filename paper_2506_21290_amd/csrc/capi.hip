@@ -391,20 +391,22 @@ uint32_t events_at(const mc_system* s, uint64_t sweep)
     return f;
 }
 
-// First sweep after s->sweep at which some event work is due.
-uint64_t next_event(const mc_system* s)
+// First sweep after s->sweep at which some event work is due (only g(r)
+// frames when the sweep kernel takes the re-sums and C_2 samples itself).
+uint64_t next_event(const mc_system* s, bool gofr_only = false)
 {
     const mc_params& p = s->p;
     const uint64_t now = s->sweep;
     uint64_t best = UINT64_MAX;
-    if (p.resum_interval) best = std::min(best, (now / p.resum_interval + 1) * p.resum_interval);
+    if (p.resum_interval && !gofr_only)
+        best = std::min(best, (now / p.resum_interval + 1) * p.resum_interval);
     const uint64_t t = now - s->origin;
     if (p.gofr_interval) {
         uint64_t n = (t / p.gofr_interval + 1) * p.gofr_interval;
         if (n < p.obs_start) n = ((p.obs_start + p.gofr_interval - 1) / p.gofr_interval) * p.gofr_interval;
         best = std::min(best, s->origin + n);
     }
-    for (uint64_t dec = 1; dec <= (uint64_t)1e18; dec *= 10) {
+    for (uint64_t dec = 1; !gofr_only && dec <= (uint64_t)1e18; dec *= 10) {
         bool found = false;
         for (uint64_t m : {1ull, 2ull, 5ull}) {
             if (m * dec > t) {
@@ -1119,7 +1121,11 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
     };
     for (uint32_t i : active) {
         mc_system* s = b->sys[i];
-        uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s) - s->sweep);
+        // a system on one workgroup whose events fit the one-workgroup event
+        // kernel takes its scheduled re-sums and C_2 samples inside the sweep
+        // kernel: its slice stops only at g(r) frames
+        const bool inl = !nblk[i] && event_blocks(s->p.n_molecules) == 1;
+        uint64_t k = std::min<uint64_t>(b->remaining[i], next_event(s, inl) - s->sweep);
         if (nblk[i]) {
             // modelled cycles of a sweep: the one-workgroup model over the
             // workgroups (the class calibration absorbs the engine's overheads)
@@ -1148,12 +1154,13 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             Slot sl{};
             sl.sys = s->dev;
             sl.n_sweeps = k;
+            sl.flags = inl ? kFlagInline : 0u;
             hs[cls * S + n[cls]++] = sl;
             lds[cls] = std::max(lds[cls], s->g.lds);
         }
         b->remaining[i] -= k;
         s->sweep += k;
-        const uint32_t f = events_at(s, s->sweep);
+        const uint32_t f = events_at(s, s->sweep) & (inl ? ~(kFlagResumPeriodic | kFlagC2) : ~0u);
         if (f) {
             if (nblk[i]) hev[ne++] = event_slot(s, f, parts2);
             else hs[2 * S + n[2]++] = event_slot(s, f, parts1);

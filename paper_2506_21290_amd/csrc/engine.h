@@ -37,6 +37,9 @@ enum : uint32_t {
     kFlagParts = 64u,         // the re-sum and the g(r) frame were done by the
                               // multi-workgroup event kernel: sum its partial
                               // energies (Slot::pad of them), count the frame
+    kFlagInline = 128u,       // (a sweep slot) the scheduled re-sums and C_2
+                              // samples of its sweeps are taken by the sweep
+                              // kernel itself, as the event kernel takes them
 };
 
 // Device accumulators of one system.

@@ -1582,6 +1582,45 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
                 st->e_sumsq += em * em;
             }
         }
+        if (sl.flags & kFlagInline) {
+            // this sweep's scheduled re-sum and C_2 sample, taken here with the
+            // event kernel's routines and thread mapping (the same sums), so
+            // that a slice need not end at them
+            const bool resum = C.resum_interval && sweep % C.resum_interval == 0;
+            const bool c2 = is_c2_time(sweep - origin);
+            if (resum || c2) {
+                __syncthreads();
+                Ctx<Real, kRes> E = C;
+                E.red = C.misc + 8;
+                if (resum) {
+                    const double e = resum_energy(E, tid, kThreads);
+                    if (tid == 0) {
+                        // re-anchor the accumulated energy: each drift sample
+                        // is the error of one window
+                        const double drift = C.misc[0] - e;
+                        C.misc[0] = e;
+                        st->e_resum = e;
+                        st->drift = drift;
+                        st->resum_sweep = sweep;
+                        st->n_resum += 1;
+                        if (st->n_drift < C.max_samples) C.drift_samples[st->n_drift] = drift;
+                        st->n_drift += 1;
+                        if (sweep > C.resum_interval && fabs(drift) > st->max_abs_drift)
+                            st->max_abs_drift = fabs(drift);
+                    }
+                    __syncthreads();
+                }
+                if (c2) {
+                    const double v = c2_value(E);
+                    if (tid == 0 && st->n_c2 < kC2Max) {
+                        C.c2[st->n_c2] = v;
+                        C.c2_sweep[st->n_c2] = sweep - origin;
+                        st->n_c2 += 1;
+                    }
+                    __syncthreads();
+                }
+            }
+        }
     }
 
     // write back

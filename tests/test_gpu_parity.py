@@ -428,6 +428,44 @@ def test_batch_moves_lds_system_to_idle_compute_units(limit, launches):
         assert np.array_equal(st["types"], ref["types"]) and st["e_acc"] == ref["e_acc"]
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_batch_inline_events_equal_event_kernel(fp32):
+    # in a batch, systems on one workgroup take their scheduled re-sums and
+    # C_2 samples inside the sweep kernel; alone they go to the event kernel.
+    # Time-sliced runs cross several of them: every observable, drift sample
+    # and C_2 sample is bitwise the same (g(r) frames still end a slice)
+    specs = [(216, 1.2, 3, 6, 51), (512, 0.8, 2, 4, 52), (125, 2.5, 2, 2, 53)]
+    sweeps = [230, 170, 260]
+    kw = dict(resum_interval=20, obs_interval=5, gofr_interval=40)
+    alone = []
+    for (M, T, k, nc, seed), n in zip(specs, sweeps):
+        s = flipmc.System(gparams(M, T, k, nc, fp32=fp32, seed=seed, **kw))
+        s.sweep(n)
+        alone.append((s.observables(), s.samples(), s.get_state()))
+    b = flipmc.Batch(4, flipmc.MC_FP32_DE if fp32 else flipmc.MC_FP64)
+    b.set_workgroups(len(specs))  # every system on its own one workgroup
+    systems = []
+    for (M, T, k, nc, seed), n in zip(specs, sweeps):
+        s = flipmc.System(gparams(M, T, k, nc, fp32=fp32, seed=seed, **kw), stream=b.stream)
+        b.add(s, n)
+        systems.append(s)
+    done = []
+    for _ in range(400):
+        b.run(max_moves_per_slot=3000)
+        done += b.poll()
+        if len(done) == len(specs):
+            break
+    assert len(done) == len(specs)
+    for s, (o_ref, (e_ref, d_ref), st_ref) in zip(systems, alone):
+        o, (e, d), st = s.observables(), s.samples(), s.get_state()
+        assert o["n_drift_samples"] == o_ref["n_drift_samples"] >= 8
+        assert len(o["c2"]) == len(o_ref["c2"]) >= 6 and o["n_gofr_frames"] == o_ref["n_gofr_frames"] >= 4
+        for key in o_ref:
+            assert np.array_equal(np.asarray(o[key]), np.asarray(o_ref[key])), key
+        assert np.array_equal(e, e_ref) and np.array_equal(d, d_ref)
+        assert np.array_equal(st["com"], st_ref["com"]) and st["e_acc"] == st_ref["e_acc"]
+
+
 def test_isolated_molecule():
     gp = flipmc.mc_params_default(n_molecules=1, temperature=0.5, density=0.001,
                                   colours_per_axis=2, cells_per_side=2, precision=flipmc.MC_FP64)
