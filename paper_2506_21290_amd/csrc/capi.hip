@@ -969,8 +969,8 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
         const bool fp64 = precision == MC_FP64;
         Slot none{};
         SpreadSlot snone{};
-        hipError_t e = launch_sweeps(fp64, true, nullptr, none, 1, 0, b->stream);
-        if (e == hipSuccess) e = launch_sweeps(fp64, false, nullptr, none, 1, 0, b->stream);
+        hipError_t e = launch_sweeps(fp64, true, nullptr, none, 1, 0, b->stream, true);
+        if (e == hipSuccess) e = launch_sweeps(fp64, false, nullptr, none, 1, 0, b->stream, true);
         if (e == hipSuccess && b->spread_max >= 2) e = launch_spread(fp64, nullptr, 0, snone, 1, b->stream);
         if (e != hipSuccess) {
             mc_batch_destroy(b);
@@ -1204,7 +1204,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             if (n[cls]) {
                 HIPCHK(hipEventRecord(b->t_beg[cls], b->stream));
                 HIPCHK(launch_sweeps(fp64, cls == 0, b->dev_slots[par] + cls * S, none, n[cls],
-                                     lds[cls], b->stream));
+                                     lds[cls], b->stream, true));
                 HIPCHK(hipEventRecord(b->t_end[cls], b->stream));
                 b->pred[cls] = pred[cls];
             }

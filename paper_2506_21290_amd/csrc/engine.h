@@ -189,9 +189,11 @@ __host__ __device__ inline size_t spread_lds_bytes(bool fp64)
     return kSpreadWaves * spread_wave_bytes(fp64) + 16 * sizeof(double);
 }
 
-// Kernel launchers (kernels.hip).
+// Kernel launchers (kernels.hip).  inline_events: the sweep kernel takes the
+// scheduled re-sums and C_2 samples of slots flagged kFlagInline.
 hipError_t launch_sweeps(bool fp64, bool resident, const Slot* dev_slots, const Slot& one,
-                         uint32_t n_blocks, size_t lds_bytes, hipStream_t stream);
+                         uint32_t n_blocks, size_t lds_bytes, hipStream_t stream,
+                         bool inline_events = false);
 hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
                          hipStream_t stream);
 hipError_t launch_init_lattice(SysDev* dev_sys, uint32_t M, hipStream_t stream);

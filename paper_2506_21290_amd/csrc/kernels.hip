@@ -1489,8 +1489,11 @@ __device__ __forceinline__ void load_ctx(Ctx<Real, kRes>& C, const SysDev* __res
 }
 
 // The hot kernel: n checkerboard sweeps of every slot's system, one
-// workgroup per system, with the state resident in LDS when it fits.
-template <typename Real, bool kRes>
+// workgroup per system, with the state resident in LDS when it fits.  The
+// variant with kInl also takes the scheduled re-sums and C_2 samples of slots
+// flagged kFlagInline (a batch's systems); the plain one leaves them to the
+// event kernel.
+template <typename Real, bool kRes, bool kInl>
 __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ slots, Slot one)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1582,7 +1585,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
                 st->e_sumsq += em * em;
             }
         }
-        if (sl.flags & kFlagInline) {
+        if (kInl && (sl.flags & kFlagInline)) {
             // this sweep's scheduled re-sum and C_2 sample, taken here with the
             // event kernel's routines and thread mapping (the same sums), so
             // that a slice need not end at them
@@ -2059,32 +2062,42 @@ __global__ void k_init_lattice(SysDev* Dp, uint32_t n)
     D.types[m] = 0u | (1u << 8) | (2u << 16);
 }
 
-template <typename Real, bool kRes>
+template <typename Real, bool kRes, bool kInl>
 hipError_t launch_one(const Slot* dev_slots, const Slot& one, uint32_t n_blocks, size_t lds,
                       hipStream_t stream)
 {
     static size_t configured = 0;
     if (lds > configured) {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_sweeps<Real, kRes>,
+        hipError_t e = hipFuncSetAttribute((const void*)&k_sweeps<Real, kRes, kInl>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         configured = lds;
     }
-    hipLaunchKernelGGL((k_sweeps<Real, kRes>), dim3(n_blocks), dim3(kThreads), lds, stream,
+    hipLaunchKernelGGL((k_sweeps<Real, kRes, kInl>), dim3(n_blocks), dim3(kThreads), lds, stream,
                        dev_slots, one);
     return hipGetLastError();
+}
+
+template <typename Real, bool kInl>
+hipError_t launch_res(bool resident, const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
+                      size_t lds, hipStream_t stream)
+{
+    return resident ? launch_one<Real, true, kInl>(dev_slots, one, n_blocks, lds, stream)
+                    : launch_one<Real, false, kInl>(dev_slots, one, n_blocks, lds, stream);
 }
 
 }  // namespace
 
 hipError_t launch_sweeps(bool fp64, bool resident, const Slot* dev_slots, const Slot& one,
-                         uint32_t n_blocks, size_t lds_bytes, hipStream_t stream)
+                         uint32_t n_blocks, size_t lds_bytes, hipStream_t stream, bool inline_events)
 {
     if (fp64)
-        return resident ? launch_one<double, true>(dev_slots, one, n_blocks, lds_bytes, stream)
-                        : launch_one<double, false>(dev_slots, one, n_blocks, lds_bytes, stream);
-    return resident ? launch_one<float, true>(dev_slots, one, n_blocks, lds_bytes, stream)
-                    : launch_one<float, false>(dev_slots, one, n_blocks, lds_bytes, stream);
+        return inline_events
+                   ? launch_res<double, true>(resident, dev_slots, one, n_blocks, lds_bytes, stream)
+                   : launch_res<double, false>(resident, dev_slots, one, n_blocks, lds_bytes, stream);
+    return inline_events
+               ? launch_res<float, true>(resident, dev_slots, one, n_blocks, lds_bytes, stream)
+               : launch_res<float, false>(resident, dev_slots, one, n_blocks, lds_bytes, stream);
 }
 
 hipError_t launch_events(const Slot* dev_slots, const Slot& one, uint32_t n_blocks,
