@@ -1278,19 +1278,20 @@ __device__ void cell_trials(const Ctx<Real, kRes>& C, const View<Real>& Vn, cons
                 tr->dl[1] = move == 0u ? (Real)pr.a1 : Real(0);
                 tr->dl[2] = move == 0u ? (Real)pr.a2 : Real(0);
             }
-            wave_lds_sync();
+            // the moved sites, read by every lane once the record is written
             Moved<Real> mv;
+            auto load_moved = [&]() __attribute__((always_inline)) {
 #pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                mv.o[s] = tr->old_site[s];
-                mv.n[s] = tr->new_site[s];
-            }
-            mv.cx = tr->cm[0]; mv.cy = tr->cm[1]; mv.cz = tr->cm[2];
-            mv.dlx = tr->dl[0]; mv.dly = tr->dl[1]; mv.dlz = tr->dl[2];
-            mv.flip = flip;
-            mv.nmv = flip ? 2 : 3;
-            const float tmx = tr->mr[0], tmy = tr->mr[1], tmz = tr->mr[2];
-            __builtin_amdgcn_sched_barrier(0);
+                for (int s = 0; s < 3; ++s) {
+                    mv.o[s] = tr->old_site[s];
+                    mv.n[s] = tr->new_site[s];
+                }
+                mv.cx = tr->cm[0]; mv.cy = tr->cm[1]; mv.cz = tr->cm[2];
+                mv.dlx = tr->dl[0]; mv.dly = tr->dl[1]; mv.dlz = tr->dl[2];
+                mv.flip = flip;
+                mv.nmv = flip ? 2 : 3;
+                __builtin_amdgcn_sched_barrier(0);
+            };
 
             Real acc = Real(0), accs = Real(0);
             uint32_t terms = 0, tests = 0;
@@ -1321,8 +1322,11 @@ __device__ void cell_trials(const Ctx<Real, kRes>& C, const View<Real>& Vn, cons
                 }
             };
 
-            // 2. prune and compact the survivors
+            // 2. prune and compact the survivors (the prune needs only the
+            // molecule's relative centre, taken from the lane that holds it
+            // while that lane's record is still being written)
             if (!overflow) {
+                const float tmx = rl_f(mrx, i), tmy = rl_f(mry, i), tmz = rl_f(mrz, i);
                 uint32_t nsurv = 0;
                 const float r_far = P.pr_base + (move == 0u ? P.pr_step : 0.f);
                 const float r_near = r_far + P.pr_step;
@@ -1339,8 +1343,12 @@ __device__ void cell_trials(const Ctx<Real, kRes>& C, const View<Real>& Vn, cons
                     if (keep) W.surv[nsurv + rank_below(bm)] = (uint16_t)nr.j[c];
                     nsurv += (uint32_t)__popcll(bm);
                 }
+                wave_lds_sync();  // the record and the survivors
+                load_moved();
                 if (nsurv) eval_items(3u * nsurv);
             } else {
+                wave_lds_sync();
+                load_moved();
                 // list overflow: every stencil molecule, 64 at a time
                 for (uint32_t base = 0; base < total; base += 64u) {
                     const uint32_t idx = base + (uint32_t)lane;
