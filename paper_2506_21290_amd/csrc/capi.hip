@@ -104,6 +104,20 @@ double cost_estimate(uint32_t M, double L, double reach, uint32_t k, uint32_t nc
     return (double)k * k * k * (cells_per_wave * (t_list + std::max(1.0, per_cell) * t_trial) + 300.0);
 }
 
+// Initial milliseconds per modelled cycle of the engine classes (one
+// workgroup with the state in LDS, in HBM; the multi-workgroup engine per
+// workgroup), relative to the LDS class; a batch then measures its own.
+constexpr double kCycleRatio[3] = {1.0, 1.3, 4.0};
+
+// Whether the multi-workgroup engine on nb workgroups is modelled at least
+// 25 % faster than the system's own engine on one workgroup, with ms_one and
+// ms_multi the milliseconds per modelled cycle of the two (always, for a
+// system beyond one workgroup's LDS).
+bool spread_pays(const Geometry& g, uint32_t nb, double ms_one, double ms_multi)
+{
+    return !g.resident || (double)nb * g.sweep_cost * ms_one >= 1.25 * g.spread_cost * ms_multi;
+}
+
 int geometry(const mc_params* p, Geometry* g)
 {
     if (!p) return fail(MC_EINVAL, "null parameters");
@@ -172,8 +186,10 @@ int geometry(const mc_params* p, Geometry* g)
     g->spread_cost = cost * 1.3;
     if (!(p->flags & MC_FLAG_SINGLE_WORKGROUP)) {
         // one wave per cell of a colour, within one cooperative wave of the
-        // device; an LDS system keeps the count for a batch, which may move it
-        // to the multi-workgroup engine when compute units are idle
+        // device.  A system whose state fits one workgroup's LDS runs alone on
+        // the multi-workgroup engine too when that is modelled faster (many
+        // cells per colour); otherwise it keeps the count for a batch, which
+        // may move it there when compute units are idle
         uint32_t maxb = 0;
         const hipError_t e = spread_max_blocks(fp64, &maxb);
         if (e != hipSuccess || maxb == 0) {
@@ -183,6 +199,9 @@ int geometry(const mc_params* p, Geometry* g)
             const uint32_t na = nc / k;
             const uint32_t want = (na * na * na + kSpreadWaves - 1) / kSpreadWaves;
             g->spread_blocks = std::max(1u, std::min({want, maxb, (uint32_t)(kMaxParts / kSpreadWaves)}));
+            if (g->resident && g->spread_blocks >= 2 &&
+                spread_pays(*g, g->spread_blocks, kCycleRatio[0], kCycleRatio[2]))
+                g->spread = true;
         }
     }
     return MC_OK;
@@ -558,7 +577,7 @@ int mc_engine(const mc_params* p, int* engine, uint32_t* workgroups)
     Geometry g;
     const int rc = geometry(p, &g);
     if (rc) return rc;
-    if (engine) *engine = g.resident ? MC_ENGINE_LDS : (g.spread ? MC_ENGINE_SPREAD : MC_ENGINE_HBM);
+    if (engine) *engine = g.spread ? MC_ENGINE_SPREAD : (g.resident ? MC_ENGINE_LDS : MC_ENGINE_HBM);
     if (workgroups) *workgroups = g.spread ? g.spread_blocks : 1u;
     return MC_OK;
 }
@@ -909,7 +928,7 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
     b->ncu = 1;
     b->wg_limit = 0;
     for (int c = 0; c < 3; ++c) {
-        b->ms_per_cycle[c] = ms_per_model_cycle() * (c == 0 ? 1.0 : (c == 1 ? 1.3 : 4.0));
+        b->ms_per_cycle[c] = ms_per_model_cycle() * kCycleRatio[c];
         b->pred[c] = 0.0;
         b->t_beg[c] = b->t_end[c] = nullptr;
     }
@@ -1056,7 +1075,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         mc_system* s = b->sys[i];
         if (!s || b->remaining[i] == 0) continue;
         active.push_back(i);
-        if ((s->g.spread || (s->g.resident && s->g.spread_blocks >= 2)) && b->spread_max >= 2)
+        if (s->g.spread_blocks >= 2 && b->spread_max >= 2)
             cand.emplace_back(-(double)b->remaining[i] * (double)s->p.n_molecules, i);
     }
     std::sort(cand.begin(), cand.end());
@@ -1074,8 +1093,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         uint32_t left = spare, coop = 0;
         auto cus = [&](uint32_t nb) { return (nb + bpc - 1) / bpc; };
         auto pays = [&](const mc_system* s, uint32_t nb) {
-            return !s->g.resident || (double)nb * s->g.sweep_cost * b->ms_per_cycle[0] >=
-                                         1.25 * s->g.spread_cost * b->ms_per_cycle[2];
+            return spread_pays(s->g, nb, b->ms_per_cycle[0], b->ms_per_cycle[2]);
         };
         for (const auto& c : cand) {
             const mc_system* s = b->sys[c.second];

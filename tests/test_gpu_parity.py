@@ -263,10 +263,18 @@ def test_fp32_hbm_state_path():
 
 
 @pytest.mark.parametrize("fp32", [False, True])
-def test_full_size_1000_molecules_sampled(fp32):
-    # the bench configuration (M = 1000, T = 0.75, k = 3, n_c = 9) on its
-    # first sweeps, every trial checked
-    run_parity(gparams(1000, 0.75, 3, 9, fp32=fp32), oparams(1000, 0.75, 3, 9), 3, fp32)
+@pytest.mark.parametrize("decomp", ["bench", (3, 9)])
+def test_full_size_1000_molecules_sampled(fp32, decomp):
+    # the 1000-molecule configuration at T = 0.75 on its first sweeps, every
+    # trial checked: with the decomposition the bench runs (the engine's
+    # table, one LDS workgroup) and with k = 3, n_c = 9 (27 cells per colour:
+    # the multi-workgroup engine in FP32)
+    if decomp == "bench":
+        _, k, nc = flipmc.mc_geometry(gparams(1000, 0.75, 0, 0, fp32=fp32))
+        assert flipmc.mc_engine(gparams(1000, 0.75, k, nc, fp32=fp32))[0] == flipmc.MC_ENGINE_LDS
+    else:
+        k, nc = decomp
+    run_parity(gparams(1000, 0.75, k, nc, fp32=fp32), oparams(1000, 0.75, k, nc), 3, fp32)
 
 
 def test_energy_invariant_and_drift():
@@ -400,7 +408,9 @@ def test_batch_moves_lds_system_to_idle_compute_units(limit, launches):
     # the result of running each system alone
     specs = [(1728, 0.9, 2, 6, 41), (216, 1.5, 3, 6, 42)]
     sweeps = [12, 20]
-    assert flipmc.mc_engine(gparams(1728, 0.9, 2, 6, fp32=True))[0] == flipmc.MC_ENGINE_LDS
+    assert flipmc.mc_placement(gparams(1728, 0.9, 2, 6, fp32=True))[0] == 1
+    # alone it takes the multi-workgroup engine too (27 cells per colour)
+    assert flipmc.mc_engine(gparams(1728, 0.9, 2, 6, fp32=True)) == (flipmc.MC_ENGINE_SPREAD, 7)
     alone = []
     for (M, T, k, nc, seed), n in zip(specs, sweeps):
         s = flipmc.System(gparams(M, T, k, nc, fp32=True, seed=seed))
