@@ -4,8 +4,7 @@ For a system size M and a precision, every valid (k, n_c) is a correct
 sampler with its own trajectory; they differ in speed (colour phases, cells per
 wave, neighbour-list length, and for the multi-workgroup engine the number of
 workgroups, one wave per cell of a colour).  The tuner times each candidate on
-the engine mc_sweep picks for the size (one workgroup with the state in LDS
-when it fits, else the multi-workgroup engine) and records the fastest in
+the engine mc_sweep picks for it (mc_engine) and records the fastest in
 ``tuned.json`` next to this file.  ``choose`` reads the table (falling back to
 the engine's own model when a size is missing), so a job's decomposition is a
 fixed function of (M, precision) and can be reproduced by the oracle.
