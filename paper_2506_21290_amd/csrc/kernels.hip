@@ -1049,10 +1049,10 @@ struct StageLds {
 // Molecules whose centre is within reach of the box of a cell centred at
 // (bx0, by0, bz0), from the stencil segments of the cell list, into the near
 // list (index and FP16 relative centre; returns the count, sets overflow past
-// the list capacity).  The lanes are split evenly over the segments and take
-// kPer molecules each per step, loads issued before arithmetic; the list order
-// (step, then molecule rank within the step, then lane) is the same in both
-// engines.  With kStage the molecules are also copied to S (centres, sites) and
+// the list capacity).  The lanes are split over the segments in proportion to
+// their molecules and take kPer molecules each per step, loads issued before
+// arithmetic; the list order (step, then molecule rank within the step, then
+// lane) is the same in all engines.  With kStage the molecules are also copied to S (centres, sites) and
 // the list holds their slots; the cell's own molecules (list positions
 // cbeg .. cbeg + ccnt) get their slots in S.own.
 template <typename Real, bool kRes, bool kStage>
@@ -1064,29 +1064,42 @@ __device__ uint32_t gather_near(const Ctx<Real, kRes>& C, const PhaseConst& P, i
     constexpr int kPer = 4;
     const int lane = __lane_id();
     const uint32_t M = C.M;
-    const int per = 64 / nseg;  // lanes per segment (nseg <= 50)
-    const int my_seg = lane / per, my_sub = lane - my_seg * per;
-    uint32_t my_lo = 0, my_len = 0;
-    if (my_seg < nseg) {
-        my_lo = W.seglo[my_seg];
-        const uint32_t end = my_seg + 1 < nseg ? (uint32_t)W.segoff[my_seg + 1] : total;
-        my_len = end - (uint32_t)W.segoff[my_seg];
-    }
-    uint32_t longest = my_len;
+    // lanes per segment (nseg <= 50): one each, and the other 64 - nseg in
+    // proportion to the segment's molecules.  Segment s starts at lane
+    // s + (64 - nseg) * segoff[s] / total; lane l serves the segment whose
+    // start is the last one at or below l (the starts are distinct).
+    uint64_t starts = 0;
+    if (lane < nseg)
+        starts = 1ull << ((uint32_t)lane +
+                          (uint32_t)(64 - nseg) * (uint32_t)W.segoff[lane] / max(total, 1u));
 #pragma unroll
-    for (int o = 32; o; o >>= 1) longest = max(longest, (uint32_t)__shfl_xor(longest, o));
-    const bool seg_ok = my_seg < nseg;
-    const uint32_t step = (uint32_t)(kPer * per);
+    for (int o = 32; o; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)starts, o), hi = __shfl_xor((uint32_t)(starts >> 32), o);
+        starts |= ((uint64_t)hi << 32) | lo;
+    }
+    const uint64_t upto = starts & ((2ull << lane) - 1ull);  // starts at or below this lane
+    const int my_seg = __popcll(upto) - 1;
+    const int first = 63 - __clzll(upto);
+    const uint64_t above = starts & ~((2ull << lane) - 1ull);
+    const uint32_t nl = (uint32_t)((above ? __ffsll((long long)above) - 1 : 64) - first);
+    const uint32_t my_sub = (uint32_t)(lane - first);
+    const uint32_t my_lo = W.seglo[my_seg];
+    const uint32_t end = my_seg + 1 < nseg ? (uint32_t)W.segoff[my_seg + 1] : total;
+    const uint32_t my_len = end - (uint32_t)W.segoff[my_seg];
+    const uint32_t step = (uint32_t)kPer * nl;  // this lane's segment per step
+    uint32_t nstep = (my_len + step - 1) / step;
+#pragma unroll
+    for (int o = 32; o; o >>= 1) nstep = max(nstep, (uint32_t)__shfl_xor(nstep, o));
     uint32_t nnear = 0;
     overflow = false;
-    for (uint32_t t0 = 0; t0 < longest; t0 += step) {
+    for (uint32_t k = 0; k < nstep; ++k) {
         uint32_t li[kPer], jj[kPer];
         bool vv[kPer];
         double xx[kPer], yy[kPer], zz[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            const uint32_t t = t0 + (uint32_t)(my_sub + u * per);
-            vv[u] = seg_ok && t < my_len;
+            const uint32_t t = k * step + (uint32_t)u * nl + my_sub;
+            vv[u] = t < my_len;
             li[u] = vv[u] ? my_lo + t : 0u;
         }
 #pragma unroll
