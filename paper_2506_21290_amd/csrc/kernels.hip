@@ -1454,15 +1454,42 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
                           double hx, double hy, double hz, const WaveLds<Real>& W, WaveCount& wc)
 {
     const int wave = threadIdx.x >> 6;
+    const int lane = __lane_id();
     const int k = (int)C.k, nc = (int)C.nc, na = nc / k;
     const int nact = na * na * na;
     const int kx = col % k, ky = (col / k) % k, kz = col / (k * k);
-    const int ncw = nact > wave ? (nact - 1 - wave) / kWaves + 1 : 0;
     const PhaseConst P = phase_const(C, sweep);
     const View<Real> V{C.com, C.site, C.M};
+    // With at most one cell per wave, the colour's cells go to the waves in
+    // order of decreasing molecule count: the lower waves of each SIMD, whose
+    // instructions issue first, take the larger cells, so the two waves of a
+    // SIMD tend to finish together.  Otherwise wave w takes cells
+    // w + kWaves ci.  Cells of a colour do not interact, so any assignment
+    // gives the same results.
+    const bool ranked = nact <= kWaves;
+    uint32_t rank = 0;
+    if (ranked) {
+        uint32_t cnt = 0;
+        if (lane < nact) {
+            const int cx = kx + k * (lane % na), cy = ky + k * ((lane / na) % na),
+                      cz = kz + k * (lane / (na * na));
+            const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
+            cnt = C.cellb[cell + 1] - C.cellb[cell];
+        }
+        for (int j = 0; j < nact; ++j) {
+            const uint32_t cj = rl_u(cnt, j);
+            rank += (cj > cnt || (cj == cnt && j < lane)) ? 1u : 0u;
+        }
+    }
+    const int ncw = (nact + kWaves - 1) / kWaves;
 
     for (int ci = 0; ci < ncw; ++ci) {
-        const int a = wave + kWaves * ci;
+        int a = wave + kWaves * ci;
+        if (ranked) {
+            const uint64_t bm = __ballot(lane < nact && rank == (uint32_t)wave);
+            a = bm ? __ffsll((long long)bm) - 1 : nact;
+        }
+        if (a >= nact) continue;
         const int cx = kx + k * (a % na), cy = ky + k * ((a / na) % na), cz = kz + k * (a / (na * na));
         const uint32_t cell = (uint32_t)(cx + nc * (cy + nc * cz));
         const uint32_t cbeg = C.cellb[cell], ccnt = C.cellb[cell + 1] - cbeg;
