@@ -1153,22 +1153,17 @@ __device__ uint32_t gather_near(const Ctx<Real, kRes>& C, const PhaseConst& P, i
     }
     wave_lds_sync();
     if (kStage && !overflow) {
-        // the staged molecules' sites, three slots per lane, loads first
-        R4<Real> st[9];
-        uint32_t sl[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            sl[c] = (uint32_t)lane + 64u * c;
-            const uint32_t g = sl[c] < nnear ? (uint32_t)S.gid[sl[c]] : 0u;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) st[3 * c + t] = C.site[3 * g + t];
+        // the staged molecules' sites, a slot per lane at a time with its
+        // three loads in flight (nine at once did not fit the registers and
+        // went through scratch memory one load at a time)
+#pragma unroll 1
+        for (uint32_t sl = (uint32_t)lane; sl < nnear; sl += 64u) {
+            const uint32_t g = S.gid[sl];
+            const R4<Real> a0 = C.site[3 * g], a1 = C.site[3 * g + 1], a2 = C.site[3 * g + 2];
+            S.site[3 * sl] = a0;
+            S.site[3 * sl + 1] = a1;
+            S.site[3 * sl + 2] = a2;
         }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (sl[c] < nnear)
-#pragma unroll
-                for (int t = 0; t < 3; ++t) S.site[3 * sl[c] + t] = st[3 * c + t];
         wave_lds_sync();
     }
     return nnear;
