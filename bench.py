@@ -232,6 +232,10 @@ def bench_c2(args, flipmc, torch):
     o1 = s.observables()
     terms = int(o1["pair_terms"] - o0["pair_terms"])
     kern_s = tm["sweep_ms"] / 1e3
+    # HBM bytes of one 100-sweep launch from the committed counter summary
+    # (null when it was taken on other kernel sources)
+    traffic = measured_traffic("k_spread_c2")
+    _, wg = flipmc.mc_engine(p)
     achieved = terms * FLOP_PER_PAIR_TERM / kern_s / 1e12
     return {
         "workload": "c2: 8000 molecules, T=1.1, FP32 dE + FP64 re-sum every 100 sweeps, 1000 timed sweeps",
@@ -241,7 +245,10 @@ def bench_c2(args, flipmc, torch):
         "candidate_pair_tests_per_s": int(o1["pair_tests"] - o0["pair_tests"]) / (ms / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
-                     "traffic": measured_traffic("k_sweeps_c2")},
+                     "traffic": traffic, "kernel": "k_spread<float>",
+                     "cus_used": wg,
+                     "valu_busy_on_its_cus": measured_counters("k_spread_c2").get("valu_busy_on_its_cus"),
+                     "hbm_gb_per_s": (traffic * n_sweeps / 100 / kern_s / 1e9) if traffic else None},
         "ms": ms,
     }
 
