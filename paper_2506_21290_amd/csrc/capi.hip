@@ -107,7 +107,10 @@ double cost_estimate(uint32_t M, double L, double reach, uint32_t k, uint32_t nc
 // Initial milliseconds per modelled cycle of the engine classes (one
 // workgroup with the state in LDS, in HBM; the multi-workgroup engine per
 // workgroup), relative to the LDS class; a batch then measures its own.
-constexpr double kCycleRatio[3] = {1.0, 1.3, 4.0};
+// The multi-workgroup engine moves about 2.9 times fewer molecules per
+// workgroup than an LDS workgroup (1728 molecules on 7 workgroups, 8000 on
+// 32), 2.2 per modelled cycle of its HBM cost; 2.5 keeps a margin.
+constexpr double kCycleRatio[3] = {1.0, 1.3, 2.5};
 
 // Whether the multi-workgroup engine on nb workgroups is modelled at least
 // 25 % faster than the system's own engine on one workgroup, with ms_one and
