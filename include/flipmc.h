@@ -99,6 +99,9 @@ typedef struct {
                                   system is marked faulted (reads then return
                                   MC_EDEVICE); 0 = default (about 2^23, seconds)       */
     uint32_t reserved;         /* 0                                                  */
+    double   fs_q;             /* |q| of F_s(q, t) over the sites (Sec. III.B: 7.4,
+                                  the first peak of the structure factor)             */
+    double   fs_q_cm;          /* |q| of F_s^cm(q, t) over the centres (5.1)         */
 } mc_params;
 
 typedef struct mc_system mc_system;
@@ -147,6 +150,12 @@ typedef struct {
     uint32_t pad;
     uint64_t c2_sweep[MC_C2_MAX];          /* sweeps after the observable origin   */
     double   c2[MC_C2_MAX];                /* C_2(t) (Sec. III.B, Eq. 7, l = 2)    */
+    double   fs[MC_C2_MAX];                /* F_s(q, t) of the sites at the same sweeps
+                                              (Sec. III.B, Eq. 5; averaged over all
+                                              directions of q: mean of sin(q d)/(q d)
+                                              over the site displacements d since the
+                                              observable origin, centres unwrapped)   */
+    double   fs_cm[MC_C2_MAX];             /* F_s^cm(q, t) of the centres (Eq. 6)     */
 } mc_obs;
 
 /* ---- single system ------------------------------------------------------ */
@@ -209,7 +218,8 @@ int mc_reset_observables(mc_system* s);
 /* Read / overwrite the state (host arrays in the layouts of mc_init_system;
  * any output pointer may be NULL).  mc_set_state also sets the sweep counter
  * (which keys the random numbers) and the accumulated energy; e_acc NaN means
- * "re-sum it". */
+ * "re-sum it".  It also clears the periodic-image counts that unwrap the
+ * centres for F_s, so F_s needs a new origin (mc_reset_observables) after it. */
 int mc_get_state(mc_system* s, double* com, double* quat, uint8_t* types, uint64_t* sweep,
                  double* e_acc);
 int mc_set_state(mc_system* s, const double* com, const double* quat, const uint8_t* types,

@@ -50,6 +50,7 @@ struct or_system {
     double*   quat;       /* 4 M, (w, x, y, z) */
     uint8_t*  type;       /* 3 M */
     double*   site;       /* 9 M: site positions c + R(q) b, refreshed on change */
+    int32_t*  img;        /* 3 M: periodic images crossed by accepted translations */
     uint64_t  sweep;
     double    e_acc;
     uint64_t  attempts[3], accepts[3], exits, pair_terms;
@@ -254,6 +255,7 @@ or_system* or_create(const or_params* p, char* err)
     s->quat = (double*)calloc(4 * M, sizeof(double));
     s->type = (uint8_t*)calloc(3 * M, 1);
     s->site = (double*)calloc(9 * M, sizeof(double));
+    s->img = (int32_t*)calloc(3 * M, sizeof(int32_t));
     for (size_t m = 0; m < M; ++m) {
         s->quat[4 * m] = 1.0;
         s->type[3 * m + 0] = 0; s->type[3 * m + 1] = 1; s->type[3 * m + 2] = 2;
@@ -264,7 +266,7 @@ or_system* or_create(const or_params* p, char* err)
 void or_destroy(or_system* s)
 {
     if (!s) return;
-    free(s->com); free(s->quat); free(s->type); free(s->site); free(s);
+    free(s->com); free(s->quat); free(s->type); free(s->site); free(s->img); free(s);
 }
 
 double or_box(const or_system* s) { return s->L; }
@@ -297,6 +299,7 @@ int or_init_lattice(or_system* s)
         s->type[3 * m + 0] = 0; s->type[3 * m + 1] = 1; s->type[3 * m + 2] = 2;
         refresh_sites(s, m);
     }
+    memset(s->img, 0, 3 * sizeof(int32_t) * M);
     s->sweep = 0;
     s->e_acc = or_energy(s);
     memset(s->attempts, 0, sizeof s->attempts);
@@ -313,6 +316,7 @@ int or_set_state(or_system* s, const double* com, const double* quat, const uint
     memcpy(s->quat, quat, 4 * sizeof(double) * M);
     memcpy(s->type, types, 3 * (size_t)M);
     for (uint32_t m = 0; m < M; ++m) refresh_sites(s, m);
+    memset(s->img, 0, 3 * sizeof(int32_t) * M);
     s->sweep = sweep;
     s->e_acc = e_acc;
     return 0;
@@ -332,6 +336,26 @@ void or_get_state(const or_system* s, double* com, double* quat, uint8_t* types,
 void or_sites(const or_system* s, double* xyz)
 {
     memcpy(xyz, s->site, 9 * sizeof(double) * s->p.n_molecules);
+}
+
+void or_unwrapped(const or_system* s, double* com, double* site)
+{
+    /* Positions followed through the periodic boundaries: the centre plus
+     * the box lengths its accepted translations crossed, and each site index
+     * at that centre plus R(q) b_k.  A flip exchanges types only, so it moves
+     * no site index (Sec. III.B). */
+    for (uint32_t m = 0; m < s->p.n_molecules; ++m) {
+        double c[3], r[9];
+        for (int a = 0; a < 3; ++a) c[a] = s->com[3 * m + a] + s->L * (double)s->img[3 * m + a];
+        if (com) memcpy(&com[3 * m], c, sizeof c);
+        if (!site) continue;
+        or_rotation_matrix(&s->quat[4 * m], r);
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a)
+                site[9 * m + 3 * k + a] = c[a] + (r[3 * a + 0] * s->body[3 * k + 0] +
+                                                  r[3 * a + 1] * s->body[3 * k + 1] +
+                                                  r[3 * a + 2] * s->body[3 * k + 2]);
+    }
 }
 
 void or_counters(const or_system* s, uint64_t attempts[3], uint64_t accepts[3], uint64_t* exits,
@@ -451,6 +475,7 @@ static void trial(or_system* s, uint32_t m, uint32_t slot, const double* h, or_r
     memcpy(ty_new, &s->type[3 * m], 3);
     unsigned mask = 7u;
     int axis = 255;
+    int32_t crossed[3] = {0, 0, 0};
 
     rec->sweep = sweep; rec->molecule = m; rec->slot = slot; rec->move = (uint8_t)move;
     rec->accepted = 0; rec->exited = 0; rec->axis = 255; rec->pair_terms = 0;
@@ -460,8 +485,11 @@ static void trial(or_system* s, uint32_t m, uint32_t slot, const double* h, or_r
 
     if (move == OR_TRANSLATE) {
         double p[3] = {p0, p1, p2};
-        for (int a = 0; a < 3; ++a)
-            c_new[a] = wrap(c_old[a] + s->p.max_displacement * (2.0 * p[a] - 1.0), s->L);
+        for (int a = 0; a < 3; ++a) {
+            double x = c_old[a] + s->p.max_displacement * (2.0 * p[a] - 1.0);
+            c_new[a] = wrap(x, s->L);
+            crossed[a] = (int32_t)floor(x / s->L);  /* the box lengths wrap removed */
+        }
         if (h) {
             int nc = (int)s->p.cells_per_side;
             int old_cell = cell_axis(s, c_old[0], h[0]) +
@@ -516,6 +544,7 @@ static void trial(or_system* s, uint32_t m, uint32_t slot, const double* h, or_r
         memcpy(&s->com[3 * m], c_new, sizeof c_new);
         memcpy(&s->quat[4 * m], q_new, sizeof q_new);
         memcpy(&s->type[3 * m], ty_new, 3);
+        for (int a = 0; a < 3; ++a) s->img[3 * m + a] += crossed[a];
         refresh_sites(s, m);
         s->e_acc += de;
         s->accepts[move]++;

@@ -113,6 +113,12 @@ void or_gofr_accumulate(const or_system* s, double dr, int nbins,
 void   or_orientation_ref(const or_system* s, double* u0, uint8_t* kref);
 double or_c2(const or_system* s, const double* u0, const uint8_t* kref);
 
+/* Unwrapped positions for F_s(q, t) and F_s^cm(q, t) (Sec. III.B, Eqs. 5 and
+ * 6): com (3 M) = wrapped centre + L * images crossed by accepted
+ * translations since the last or_init_lattice / or_set_state; site (9 M) =
+ * that centre + R(q) b_k for site index k.  Either pointer may be NULL. */
+void   or_unwrapped(const or_system* s, double* com, double* site);
+
 #ifdef __cplusplus
 }
 #endif

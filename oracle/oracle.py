@@ -160,6 +160,7 @@ def lib():
         L.or_orientation_ref.argtypes = [C.c_void_p, dp, u8p]
         L.or_c2.restype = C.c_double
         L.or_c2.argtypes = [C.c_void_p, dp, u8p]
+        L.or_unwrapped.argtypes = [C.c_void_p, dp, dp]
         _lib = L
     return _lib
 
@@ -350,3 +351,28 @@ class System:
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         kref = np.ascontiguousarray(kref, dtype=np.uint8)
         return lib().or_c2(self.h, _p(u0, C.c_double), _p(kref, C.c_uint8))
+
+    def unwrapped(self):
+        """(centres (M, 3), sites (3M, 3)) followed through the periodic
+        boundaries since the last lattice start or set_state."""
+        com = np.zeros(3 * self.M)
+        site = np.zeros(9 * self.M)
+        lib().or_unwrapped(self.h, _p(com, C.c_double), _p(site, C.c_double))
+        return com.reshape(self.M, 3), site.reshape(3 * self.M, 3)
+
+    def fs(self, ref, q=7.4, q_cm=5.1):
+        """(F_s(q, t), F_s^cm(q_cm, t)) from the reference ``ref`` =
+        ``unwrapped()`` at t = 0; see ``fs_isotropic``."""
+        com, site = self.unwrapped()
+        return fs_isotropic(site - ref[1], q), fs_isotropic(com - ref[0], q_cm)
+
+
+def fs_isotropic(d, q):
+    """Self-intermediate scattering function (Sec. III.B, Eqs. 5 and 6) of the
+    displacements d (n, 3), averaged over every direction of a wavevector of
+    modulus q: the mean over a sphere of exp(i q . d) is sin(q |d|) / (q |d|),
+    so F_s is the mean of that over the n particles.  The paper averages over
+    wavevectors whose modulus is near q; the full spherical average at exactly
+    q is the reading taken here."""
+    x = q * np.sqrt(np.sum(np.asarray(d, dtype=np.float64) ** 2, axis=1))
+    return float(np.mean(np.sinc(x / np.pi)))

@@ -137,6 +137,7 @@ int geometry(const mc_params* p, Geometry* g)
     if (!(p->max_displacement >= 0) || !(p->max_rotation >= 0))
         return fail(MC_EINVAL, "step sizes must be non-negative");
     if (!(p->gofr_dr > 0)) return fail(MC_EINVAL, "gofr_dr must be positive");
+    if (!(p->fs_q >= 0) || !(p->fs_q_cm >= 0)) return fail(MC_EINVAL, "fs_q and fs_q_cm must be >= 0");
     g->L = std::cbrt(3.0 * (double)p->n_molecules / p->density);
     g->bond = p->bond_length > 0 ? p->bond_length : bond_star();
     g->radius = g->bond / std::sqrt(3.0);
@@ -240,6 +241,7 @@ uint32_t event_blocks(uint32_t M)
 
 struct BufLayout {
     size_t sys, stats, com, quat, types, u0, kref, esamp, dsamp, gall, ginter, c2, c2s;
+    size_t img, r0, o0, fs, fscm;
     size_t props, gpart, gsite, gcell, gcellid, glist, gcnt, gecell, gbar, total;
 };
 
@@ -263,6 +265,11 @@ BufLayout buf_layout(const mc_params* p, const Geometry& g)
     b.ginter = o; o = al(o + kGofrBins * sizeof(uint64_t));
     b.c2 = o;     o = al(o + kC2Max * sizeof(double));
     b.c2s = o;    o = al(o + kC2Max * sizeof(uint64_t));
+    b.img = o;    o = al(o + 3 * M * sizeof(int32_t));
+    b.r0 = o;     o = al(o + 3 * M * sizeof(double));
+    b.o0 = o;     o = al(o + 9 * M * sizeof(double));
+    b.fs = o;     o = al(o + kC2Max * sizeof(double));
+    b.fscm = o;   o = al(o + kC2Max * sizeof(double));
     b.props = o;  o = al(o + M * 48);
     b.gpart = o;  o = al(o + kMaxParts * sizeof(double));
     if (!g.resident || g.spread_blocks >= 2) {
@@ -551,6 +558,8 @@ void mc_params_default(mc_params* p)
     p->max_samples = 4096;
     p->gofr_dr = 0.02;
     p->barrier_polls = 0;
+    p->fs_q = 7.4;     // first peak of the site structure factor (Sec. III.B)
+    p->fs_q_cm = 5.1;  // first peak of the centres' structure factor
     p->reserved = 0;
 }
 
@@ -678,6 +687,13 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
     D.gofr_inter = (uint64_t*)(b + lay.ginter);
     D.c2 = (double*)(b + lay.c2);
     D.c2_sweep = (uint64_t*)(b + lay.c2s);
+    D.img = (int32_t*)(b + lay.img);
+    D.r0 = (double*)(b + lay.r0);
+    D.o0 = (double*)(b + lay.o0);
+    D.fs = (double*)(b + lay.fs);
+    D.fs_cm = (double*)(b + lay.fscm);
+    D.fs_q = p->fs_q;
+    D.fs_q_cm = p->fs_q_cm;
     D.props = (void*)(b + lay.props);
     D.g_part = (double*)(b + lay.gpart);
     if (!g.resident || g.spread_blocks >= 2) {
@@ -768,6 +784,8 @@ int mc_observables(mc_system* s, mc_obs* o)
     HIPCHK(hipMemcpyAsync(o->gofr_all, s->host.gofr_all, sizeof o->gofr_all, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(o->gofr_inter, s->host.gofr_inter, sizeof o->gofr_inter, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(o->c2, s->host.c2, sizeof o->c2, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->fs, s->host.fs, sizeof o->fs, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->fs_cm, s->host.fs_cm, sizeof o->fs_cm, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(o->c2_sweep, s->host.c2_sweep, sizeof o->c2_sweep, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return MC_OK;
@@ -834,6 +852,8 @@ int mc_set_state(mc_system* s, const double* com, const double* quat, const uint
     if (s->batch) return fail(MC_EBUSY, "system is in a batch");
     int rc = upload_state(s, com, quat, types);
     if (rc) return rc;
+    // the new state has crossed no periodic images yet
+    HIPCHK(hipMemsetAsync(s->host.img, 0, 3 * sizeof(int32_t) * s->p.n_molecules, s->stream));
     Stats st;
     if ((rc = read_stats(s, &st))) return rc;
     st.sweep = sweep;

@@ -78,6 +78,7 @@ struct SysDev {
     uint32_t resum_interval, obs_interval, gofr_interval, obs_start;
     uint32_t max_samples, gofr_nbins, lds_bytes, barrier_polls;
     double gofr_dr, gofr_rmax;
+    double fs_q, fs_q_cm;  // wavenumbers of F_s (sites) and F_s^cm (centres)
     // state
     double* com;         // SoA [3][M]
     double* quat;        // SoA [4][M], (w, x, y, z)
@@ -91,6 +92,11 @@ struct SysDev {
     uint64_t* gofr_inter;
     double* c2;
     uint64_t* c2_sweep;
+    int32_t* img;        // SoA [3][M] periodic images crossed by accepted translations
+    double* r0;          // SoA [3][M] unwrapped centres at the observable origin
+    double* o0;          // SoA [9][M] site offsets at the observable origin
+    double* fs;          // [kC2Max] F_s(q, t) at the C_2 sample sweeps
+    double* fs_cm;       // [kC2Max] F_s^cm(q, t) at the same sweeps
     // HBM copies of the work arrays of non-resident systems
     void* g_site;        // Real4 [3M]: offset xyz + sigma of the site's type
     uint32_t* g_cell;    // [ncell + 1] cell starts

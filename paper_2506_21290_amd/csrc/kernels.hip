@@ -284,11 +284,17 @@ struct Ctx {
     double bR, bH;            // body frame: site 0 at (bR, 0, 0), sites 1, 2 at (-bR/2, +-bH, 0)
     double sig0, sig1, sig2;  // diameters of types A, B, C
     double gofr_dr, gofr_rmax;
+    double fs_q, fs_q_cm;
     double* gcom;
     double* quat;
     uint32_t* types;
     double* u0;
     uint8_t* kref;
+    int32_t* img;
+    double* r0;
+    double* o0;
+    double* fs;
+    double* fs_cm;
     Stats* stats;
     double* e_samples;
     double* drift_samples;
@@ -544,11 +550,55 @@ __device__ double c2_value(const Ctx<Real, kRes>& C)
     return block_sum(v, C.red) / (double)M;
 }
 
+// sin(x) / x, with its Taylor value near 0.
+__device__ __forceinline__ double sinc(double x)
+{
+    return x < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x;
+}
+
+// The self-intermediate scattering functions (Sec. III.B) of the sites,
+// F_s(q, t), and of the centres, F_s^cm(q, t), averaged over all directions
+// of the wavevector at |q| = C.fs_q and C.fs_q_cm: the mean of
+// sin(q d) / (q d) over the displacements d since the observable origin.
+// Centres are unwrapped with the image counts of the accepted translations;
+// a site keeps its index through a flip, so a flip moves no site.
+template <typename Real, bool kRes>
+__device__ void fs_values(const Ctx<Real, kRes>& C, double& fs, double& fs_cm)
+{
+    const uint32_t M = C.M;
+    double a = 0.0, b = 0.0;
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            d[k] = (C.com[k * M + m] + C.L * (double)C.img[k * M + m]) - C.r0[k * M + m];
+        b += sinc(C.fs_q_cm * sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+        double o[9], sg[3];
+        offsets_f64(C, m, o, sg);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const double ex = d[0] + (o[3 * t] - C.o0[(3 * t) * M + m]);
+            const double ey = d[1] + (o[3 * t + 1] - C.o0[(3 * t + 1) * M + m]);
+            const double ez = d[2] + (o[3 * t + 2] - C.o0[(3 * t + 2) * M + m]);
+            a += sinc(C.fs_q * sqrt(ex * ex + ey * ey + ez * ez));
+        }
+    }
+    fs = block_sum(a, C.red) / (3.0 * (double)M);
+    fs_cm = block_sum(b, C.red) / (double)M;
+}
+
 template <typename Real, bool kRes>
 __device__ void reset_observables(const Ctx<Real, kRes>& C)
 {
     const uint32_t M = C.M;
     for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
+        // F_s references: unwrapped centre and site offsets
+        double o[9], sg[3];
+        offsets_f64(C, m, o, sg);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) C.o0[i * M + m] = o[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) C.r0[k * M + m] = C.com[k * M + m] + C.L * (double)C.img[k * M + m];
         const uint32_t ty = C.types[m];
         int k = 0;
         for (int s = 0; s < 3; ++s)
@@ -1390,8 +1440,14 @@ __device__ void cell_trials(const Ctx<Real, kRes>& C, const View<Real>& Vn, cons
                     R4<Real>* sp = V.site + 3 * ml;
                     R4<Real>* gp = C.site + 3 * mi;
                     if (move == 0u) {
-                        const double nx = wrap(cmx + pr.a0, C.L), ny = wrap(cmy + pr.a1, C.L),
-                                     nz = wrap(cmz + pr.a2, C.L);
+                        const double tx = cmx + pr.a0, ty = cmy + pr.a1, tz = cmz + pr.a2;
+                        const double nx = wrap(tx, C.L), ny = wrap(ty, C.L), nz = wrap(tz, C.L);
+                        // periodic images crossed (the shifts wrap takes off)
+                        const int ix = (int)floor(tx / C.L), iy = (int)floor(ty / C.L),
+                                  iz = (int)floor(tz / C.L);
+                        if (ix) atomicAdd(&C.img[mi], ix);
+                        if (iy) atomicAdd(&C.img[M + mi], iy);
+                        if (iz) atomicAdd(&C.img[2 * M + mi], iz);
                         V.com[ml] = nx; V.com[S + ml] = ny; V.com[2 * S + ml] = nz;
                         if (staged) {
                             C.com[mi] = nx; C.com[M + mi] = ny; C.com[2 * M + mi] = nz;
@@ -1524,6 +1580,8 @@ __device__ __forceinline__ void load_ctx(Ctx<Real, kRes>& C, const SysDev* __res
     C.sig0 = Dp->sigma[0]; C.sig1 = Dp->sigma[1]; C.sig2 = Dp->sigma[2];
     C.gofr_dr = Dp->gofr_dr; C.gofr_rmax = Dp->gofr_rmax;
     C.gcom = Dp->com; C.quat = Dp->quat; C.types = Dp->types; C.u0 = Dp->u0; C.kref = Dp->kref;
+    C.img = Dp->img; C.r0 = Dp->r0; C.o0 = Dp->o0; C.fs = Dp->fs; C.fs_cm = Dp->fs_cm;
+    C.fs_q = Dp->fs_q; C.fs_q_cm = Dp->fs_q_cm;
     C.stats = Dp->stats; C.e_samples = Dp->e_samples; C.drift_samples = Dp->drift_samples;
     C.gofr_all = Dp->gofr_all; C.gofr_inter = Dp->gofr_inter; C.c2 = Dp->c2;
     C.c2_sweep = Dp->c2_sweep;
@@ -1658,8 +1716,12 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
                 }
                 if (c2) {
                     const double v = c2_value(E);
+                    double fs, fs_cm;
+                    fs_values(E, fs, fs_cm);
                     if (tid == 0 && st->n_c2 < kC2Max) {
                         C.c2[st->n_c2] = v;
+                        C.fs[st->n_c2] = fs;
+                        C.fs_cm[st->n_c2] = fs_cm;
                         C.c2_sweep[st->n_c2] = sweep - origin;
                         st->n_c2 += 1;
                     }
@@ -1793,8 +1855,12 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
     }
     if (f & kFlagC2) {
         const double c2 = c2_value(C);
+        double fs, fs_cm;
+        fs_values(C, fs, fs_cm);
         if (tid == 0 && st->n_c2 < kC2Max) {
             C.c2[st->n_c2] = c2;
+            C.fs[st->n_c2] = fs;
+            C.fs_cm[st->n_c2] = fs_cm;
             C.c2_sweep[st->n_c2] = sweep - st->obs_origin;
             st->n_c2 += 1;
         }

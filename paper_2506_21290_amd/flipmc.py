@@ -66,6 +66,8 @@ class mc_params(C.Structure):
         ("gofr_dr", C.c_double),
         ("barrier_polls", C.c_uint32),
         ("reserved", C.c_uint32),
+        ("fs_q", C.c_double),
+        ("fs_q_cm", C.c_double),
     ]
 
 
@@ -96,6 +98,8 @@ class mc_obs(C.Structure):
         ("pad", C.c_uint32),
         ("c2_sweep", C.c_uint64 * MC_C2_MAX),
         ("c2", C.c_double * MC_C2_MAX),
+        ("fs", C.c_double * MC_C2_MAX),
+        ("fs_cm", C.c_double * MC_C2_MAX),
     ]
 
 
@@ -283,6 +287,8 @@ class System:
             "gofr_inter": np.array(o.gofr_inter[:nb], dtype=np.uint64),
             "c2_sweep": np.array(o.c2_sweep[: o.n_c2], dtype=np.uint64),
             "c2": np.array(o.c2[: o.n_c2]),
+            "fs": np.array(o.fs[: o.n_c2]),
+            "fs_cm": np.array(o.fs_cm[: o.n_c2]),
         }
 
     def samples(self, cap=None):

@@ -345,6 +345,43 @@ def test_observables_match_oracle():
     np.testing.assert_allclose(e_samples, energies, rtol=1e-9, atol=1e-9)
 
 
+@pytest.mark.parametrize("engine", ["lds", "spread"])
+def test_fs_matches_oracle(engine):
+    # F_s(q, t) of the sites and F_s^cm(q, t) of the centres (Sec. III.B,
+    # Eqs. 5 and 6) at the C_2 sample sweeps.  "lds": 64 molecules at a very
+    # high temperature with long steps, so centres cross the periodic boundary
+    # many times; "spread": 1000 molecules on the multi-workgroup engine.
+    if engine == "lds":
+        M, T, k, nc, seed, n = 64, 1e6, 2, 2, 5, 60
+        kw = dict(p_flip=0.1, p_translate=0.8, max_displacement=0.35)
+        flags, want_engine = 0, flipmc.MC_ENGINE_LDS
+    else:
+        M, T, k, nc, seed, n = 1000, 0.9, 2, 4, 31, 25
+        kw = {}
+        flags, want_engine = flipmc.MC_FLAG_HBM_STATE, flipmc.MC_ENGINE_SPREAD
+    gp = gparams(M, T, k, nc, seed=seed, flags=flags, **kw)
+    assert flipmc.mc_engine(gp)[0] == want_engine
+    g = flipmc.System(gp)
+    g.sweep(n)
+    obs = g.observables()
+    sweeps = [int(t) for t in obs["c2_sweep"]]
+    assert len(sweeps) >= 5 and sweeps[-1] <= n
+    o = oracle.System(oparams(M, T, k, nc, seed=seed, **kw))
+    ref = o.unwrapped()
+    want = {}
+    for t in range(1, n + 1):
+        o.sweep_checkerboard(1)
+        if t in sweeps:
+            want[t] = o.fs(ref, q=gp.fs_q, q_cm=gp.fs_q_cm)
+    assert np.array_equal(g.get_state()["com"], o.get_state()["com"])
+    np.testing.assert_allclose(obs["fs"], [want[t][0] for t in sweeps], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(obs["fs_cm"], [want[t][1] for t in sweeps], rtol=0, atol=1e-12)
+    assert obs["fs"][-1] < 0.99
+    if engine == "lds":
+        com_u = o.unwrapped()[0]
+        assert np.sum(np.abs(com_u - o.get_state()["com"]) > 1.0) >= 5  # boundary crossings
+
+
 def test_checkpoint_resume_is_exact():
     gp = gparams(216, 1.0, 3, 6, seed=13)
     a = flipmc.System(gp)
