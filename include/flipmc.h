@@ -156,6 +156,15 @@ typedef struct {
                                               over the site displacements d since the
                                               observable origin, centres unwrapped)   */
     double   fs_cm[MC_C2_MAX];             /* F_s^cm(q, t) of the centres (Eq. 6)     */
+    /* Moments of the per-particle contributions (Sec. V.A) at the same sweeps,
+     * from which the self parts of the four-point susceptibilities (Sec. V.B,
+     * chi_4^self = mean of squares - square of the mean) and the Pearson
+     * coefficient of Eq. 13 follow.  C_2^i = P_2(u_i(t).u_i(0)); F_s^cm,i and
+     * F_s^i are the direction-averaged sin(q d)/(q d) of one centre or site. */
+    double   c2_sq[MC_C2_MAX];             /* mean over molecules of (C_2^i)^2        */
+    double   fs_cm_sq[MC_C2_MAX];          /* mean over molecules of (F_s^cm,i)^2     */
+    double   c2_fs_cm[MC_C2_MAX];          /* mean over molecules of C_2^i F_s^cm,i   */
+    double   fs_sq[MC_C2_MAX];             /* mean over sites of (F_s^i)^2            */
 } mc_obs;
 
 /* ---- single system ------------------------------------------------------ */

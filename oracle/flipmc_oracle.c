@@ -693,6 +693,17 @@ void or_orientation_ref(const or_system* s, double* u0, uint8_t* kref)
     }
 }
 
+void or_c2_terms(const or_system* s, const double* u0, const uint8_t* kref, double* c2i)
+{
+    /* Contribution of each molecule to C_2 (Sec. V.A): P_2(u(t) . u(0)). */
+    for (uint32_t m = 0; m < s->p.n_molecules; ++m) {
+        double u[3];
+        orientation(s, m, kref[m], u);
+        double dot = u[0] * u0[3 * m] + u[1] * u0[3 * m + 1] + u[2] * u0[3 * m + 2];
+        c2i[m] = 0.5 * (3.0 * dot * dot - 1.0);
+    }
+}
+
 double or_c2(const or_system* s, const double* u0, const uint8_t* kref)
 {
     /* Eq. (7) with l = 2: mean of P_2(u(t) . u(0)) over molecules. */

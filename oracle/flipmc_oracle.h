@@ -112,6 +112,8 @@ void or_gofr_accumulate(const or_system* s, double dr, int nbins,
  * filled by or_orientation_ref from the current state (Sec. III.B, Eq. 7). */
 void   or_orientation_ref(const or_system* s, double* u0, uint8_t* kref);
 double or_c2(const or_system* s, const double* u0, const uint8_t* kref);
+/* Per-molecule contributions C_2^i = P_2(u_i(t) . u_i(0)) (Sec. V.A), M values. */
+void   or_c2_terms(const or_system* s, const double* u0, const uint8_t* kref, double* c2i);
 
 /* Unwrapped positions for F_s(q, t) and F_s^cm(q, t) (Sec. III.B, Eqs. 5 and
  * 6): com (3 M) = wrapped centre + L * images crossed by accepted

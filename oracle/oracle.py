@@ -161,6 +161,7 @@ def lib():
         L.or_c2.restype = C.c_double
         L.or_c2.argtypes = [C.c_void_p, dp, u8p]
         L.or_unwrapped.argtypes = [C.c_void_p, dp, dp]
+        L.or_c2_terms.argtypes = [C.c_void_p, dp, u8p, dp]
         _lib = L
     return _lib
 
@@ -367,6 +368,53 @@ class System:
         return fs_isotropic(site - ref[1], q), fs_isotropic(com - ref[0], q_cm)
 
 
+    def c2_terms(self, u0, kref):
+        out = np.zeros(self.M)
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        kref = np.ascontiguousarray(kref, dtype=np.uint8)
+        lib().or_c2_terms(self.h, _p(u0, C.c_double), _p(kref, C.c_uint8), _p(out, C.c_double))
+        return out
+
+    def particle_terms(self, ref, u0, kref, q=7.4, q_cm=5.1):
+        """Per-particle contributions (Sec. V.A) since the reference
+        (``ref`` = unwrapped(), ``u0, kref`` = orientation_ref() at t = 0):
+        C_2^i per molecule, F_s^cm,i per molecule and F_s^i per site, the
+        last two direction-averaged like ``fs_isotropic``."""
+        com, site = self.unwrapped()
+        return (self.c2_terms(u0, kref), sinc_terms(com - ref[0], q_cm),
+                sinc_terms(site - ref[1], q))
+
+
+def sinc_terms(d, q):
+    """sin(q |d|) / (q |d|) of each row of d: the mean of exp(i q . d) over
+    all directions of a wavevector of modulus q."""
+    x = q * np.sqrt(np.sum(np.asarray(d, dtype=np.float64) ** 2, axis=1))
+    return np.sinc(x / np.pi)
+
+
+def chi4_self(c_i):
+    """Self part of the four-point susceptibility (Sec. V.B, Eq. 11): the
+    variance of the per-particle contributions."""
+    c_i = np.asarray(c_i, dtype=np.float64)
+    return float(np.mean(c_i ** 2) - np.mean(c_i) ** 2)
+
+
+def pearson(c2_i, fcm_i):
+    """Pearson coefficient of Eq. 13 between C_2^i and F_s^cm,i."""
+    c2_i = np.asarray(c2_i, dtype=np.float64)
+    fcm_i = np.asarray(fcm_i, dtype=np.float64)
+    cov = np.mean(c2_i * fcm_i) - np.mean(c2_i) * np.mean(fcm_i)
+    return float(cov / np.sqrt(chi4_self(c2_i) * chi4_self(fcm_i)))
+
+
+def chi4(c_hat, n):
+    """Four-point susceptibility (Sec. V.B, Eq. 10) from the instantaneous
+    values c_hat of one correlation in independent runs: n times their
+    variance, n = M for a molecular correlation, 3M for sites."""
+    c_hat = np.asarray(c_hat, dtype=np.float64)
+    return float(n * (np.mean(c_hat ** 2) - np.mean(c_hat) ** 2))
+
+
 def fs_isotropic(d, q):
     """Self-intermediate scattering function (Sec. III.B, Eqs. 5 and 6) of the
     displacements d (n, 3), averaged over every direction of a wavevector of
@@ -374,5 +422,4 @@ def fs_isotropic(d, q):
     so F_s is the mean of that over the n particles.  The paper averages over
     wavevectors whose modulus is near q; the full spherical average at exactly
     q is the reading taken here."""
-    x = q * np.sqrt(np.sum(np.asarray(d, dtype=np.float64) ** 2, axis=1))
-    return float(np.mean(np.sinc(x / np.pi)))
+    return float(np.mean(sinc_terms(d, q)))

@@ -241,7 +241,7 @@ uint32_t event_blocks(uint32_t M)
 
 struct BufLayout {
     size_t sys, stats, com, quat, types, u0, kref, esamp, dsamp, gall, ginter, c2, c2s;
-    size_t img, r0, o0, fs, fscm;
+    size_t img, r0, o0, fs, fscm, mom;
     size_t props, gpart, gsite, gcell, gcellid, glist, gcnt, gecell, gbar, total;
 };
 
@@ -270,6 +270,7 @@ BufLayout buf_layout(const mc_params* p, const Geometry& g)
     b.o0 = o;     o = al(o + 9 * M * sizeof(double));
     b.fs = o;     o = al(o + kC2Max * sizeof(double));
     b.fscm = o;   o = al(o + kC2Max * sizeof(double));
+    b.mom = o;    o = al(o + 4 * kC2Max * sizeof(double));
     b.props = o;  o = al(o + M * 48);
     b.gpart = o;  o = al(o + kMaxParts * sizeof(double));
     if (!g.resident || g.spread_blocks >= 2) {
@@ -692,6 +693,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
     D.o0 = (double*)(b + lay.o0);
     D.fs = (double*)(b + lay.fs);
     D.fs_cm = (double*)(b + lay.fscm);
+    D.mom = (double*)(b + lay.mom);
     D.fs_q = p->fs_q;
     D.fs_q_cm = p->fs_q_cm;
     D.props = (void*)(b + lay.props);
@@ -786,6 +788,10 @@ int mc_observables(mc_system* s, mc_obs* o)
     HIPCHK(hipMemcpyAsync(o->c2, s->host.c2, sizeof o->c2, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(o->fs, s->host.fs, sizeof o->fs, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(o->fs_cm, s->host.fs_cm, sizeof o->fs_cm, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->c2_sq, s->host.mom, sizeof o->c2_sq, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->fs_cm_sq, s->host.mom + kC2Max, sizeof o->fs_cm_sq, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->c2_fs_cm, s->host.mom + 2 * kC2Max, sizeof o->c2_fs_cm, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(o->fs_sq, s->host.mom + 3 * kC2Max, sizeof o->fs_sq, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(o->c2_sweep, s->host.c2_sweep, sizeof o->c2_sweep, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return MC_OK;

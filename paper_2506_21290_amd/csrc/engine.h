@@ -97,6 +97,7 @@ struct SysDev {
     double* o0;          // SoA [9][M] site offsets at the observable origin
     double* fs;          // [kC2Max] F_s(q, t) at the C_2 sample sweeps
     double* fs_cm;       // [kC2Max] F_s^cm(q, t) at the same sweeps
+    double* mom;         // [4][kC2Max] per-particle moments at the same sweeps
     // HBM copies of the work arrays of non-resident systems
     void* g_site;        // Real4 [3M]: offset xyz + sigma of the site's type
     uint32_t* g_cell;    // [ncell + 1] cell starts

@@ -295,6 +295,7 @@ struct Ctx {
     double* o0;
     double* fs;
     double* fs_cm;
+    double* mom;
     Stats* stats;
     double* e_samples;
     double* drift_samples;
@@ -529,62 +530,81 @@ __device__ __forceinline__ bool is_c2_time(uint64_t t)
     return t == 1 || t == 2 || t == 5;
 }
 
-template <typename Real, bool kRes>
-__device__ double c2_value(const Ctx<Real, kRes>& C)
-{
-    const uint32_t M = C.M;
-    double v = 0.0;
-    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
-        double r[9];
-        rotation(C.quat[m], C.quat[M + m], C.quat[2 * M + m], C.quat[3 * M + m], r);
-        const int k = C.kref[m];
-        double dot = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double u = (r[3 * a] * body_at(C, k, 0) + r[3 * a + 1] * body_at(C, k, 1) +
-                              r[3 * a + 2] * body_at(C, k, 2)) / C.radius;
-            dot += u * C.u0[a * M + m];
-        }
-        v += 0.5 * (3.0 * dot * dot - 1.0);
-    }
-    return block_sum(v, C.red) / (double)M;
-}
-
 // sin(x) / x, with its Taylor value near 0.
 __device__ __forceinline__ double sinc(double x)
 {
     return x < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x;
 }
 
-// The self-intermediate scattering functions (Sec. III.B) of the sites,
-// F_s(q, t), and of the centres, F_s^cm(q, t), averaged over all directions
-// of the wavevector at |q| = C.fs_q and C.fs_q_cm: the mean of
-// sin(q d) / (q d) over the displacements d since the observable origin.
-// Centres are unwrapped with the image counts of the accepted translations;
-// a site keeps its index through a flip, so a flip moves no site.
+// The time correlations of one sample (Sec. III.B) and the moments of their
+// per-particle contributions (Sec. V.A) that the four-point susceptibilities
+// and the Pearson coefficient (Sec. V.B and V.C) are built from:
+//   C_2^i    = P_2(u_i(t) . u_i(0)), u following the site that held type B
+//              at the observable origin (Eq. 7, l = 2),
+//   F_s^cm,i = sin(q d)/(q d) at |q| = C.fs_q_cm, d the displacement of the
+//              unwrapped centre (Eq. 6 averaged over all directions of q),
+//   F_s^i    = the same over each site index at |q| = C.fs_q (Eq. 5); a
+//              site keeps its index through a flip, so a flip moves no site.
+// Centres are unwrapped with the image counts of the accepted translations.
+// d[0..6] = means of C_2^i, (C_2^i)^2, F_s^cm,i, (F_s^cm,i)^2, C_2^i F_s^cm,i
+// over molecules and of F_s^i, (F_s^i)^2 over sites.
+constexpr int kDyn = 7;
+
 template <typename Real, bool kRes>
-__device__ void fs_values(const Ctx<Real, kRes>& C, double& fs, double& fs_cm)
+__device__ void dyn_values(const Ctx<Real, kRes>& C, double d[kDyn])
 {
     const uint32_t M = C.M;
-    double a = 0.0, b = 0.0;
-    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
-        double d[3];
+    double a[kDyn];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            d[k] = (C.com[k * M + m] + C.L * (double)C.img[k * M + m]) - C.r0[k * M + m];
-        b += sinc(C.fs_q_cm * sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+    for (int j = 0; j < kDyn; ++j) a[j] = 0.0;
+    for (uint32_t m = threadIdx.x; m < M; m += kThreads) {
         double o[9], sg[3];
         offsets_f64(C, m, o, sg);
+        const int k = C.kref[m];
+        double dot = 0.0;
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            const double okx = k == 0 ? o[x] : (k == 1 ? o[3 + x] : o[6 + x]);
+            dot += (okx / C.radius) * C.u0[x * M + m];
+        }
+        const double c2 = 0.5 * (3.0 * dot * dot - 1.0);
+        double dc[3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+            dc[x] = (C.com[x * M + m] + C.L * (double)C.img[x * M + m]) - C.r0[x * M + m];
+        const double fcm = sinc(C.fs_q_cm * sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]));
+        a[0] += c2; a[1] += c2 * c2; a[2] += fcm; a[3] += fcm * fcm; a[4] += c2 * fcm;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-            const double ex = d[0] + (o[3 * t] - C.o0[(3 * t) * M + m]);
-            const double ey = d[1] + (o[3 * t + 1] - C.o0[(3 * t + 1) * M + m]);
-            const double ez = d[2] + (o[3 * t + 2] - C.o0[(3 * t + 2) * M + m]);
-            a += sinc(C.fs_q * sqrt(ex * ex + ey * ey + ez * ez));
+            const double ex = dc[0] + (o[3 * t] - C.o0[(3 * t) * M + m]);
+            const double ey = dc[1] + (o[3 * t + 1] - C.o0[(3 * t + 1) * M + m]);
+            const double ez = dc[2] + (o[3 * t + 2] - C.o0[(3 * t + 2) * M + m]);
+            const double f = sinc(C.fs_q * sqrt(ex * ex + ey * ey + ez * ez));
+            a[5] += f; a[6] += f * f;
         }
     }
-    fs = block_sum(a, C.red) / (3.0 * (double)M);
-    fs_cm = block_sum(b, C.red) / (double)M;
+#pragma unroll
+    for (int j = 0; j < kDyn; ++j) d[j] = block_sum(a[j], C.red) / ((j < 5 ? 1.0 : 3.0) * (double)M);
+}
+
+// One sample of the time correlations at the current sweep.
+template <typename Real, bool kRes>
+__device__ void store_dyn(const Ctx<Real, kRes>& C, Stats* st, uint64_t t)
+{
+    double d[kDyn];
+    dyn_values(C, d);
+    if (threadIdx.x == 0 && st->n_c2 < kC2Max) {
+        const uint32_t n = st->n_c2;
+        C.c2[n] = d[0];
+        C.fs_cm[n] = d[2];
+        C.fs[n] = d[5];
+        C.mom[n] = d[1];
+        C.mom[kC2Max + n] = d[3];
+        C.mom[2 * kC2Max + n] = d[4];
+        C.mom[3 * kC2Max + n] = d[6];
+        C.c2_sweep[n] = t;
+        st->n_c2 = n + 1;
+    }
 }
 
 template <typename Real, bool kRes>
@@ -1580,7 +1600,7 @@ __device__ __forceinline__ void load_ctx(Ctx<Real, kRes>& C, const SysDev* __res
     C.sig0 = Dp->sigma[0]; C.sig1 = Dp->sigma[1]; C.sig2 = Dp->sigma[2];
     C.gofr_dr = Dp->gofr_dr; C.gofr_rmax = Dp->gofr_rmax;
     C.gcom = Dp->com; C.quat = Dp->quat; C.types = Dp->types; C.u0 = Dp->u0; C.kref = Dp->kref;
-    C.img = Dp->img; C.r0 = Dp->r0; C.o0 = Dp->o0; C.fs = Dp->fs; C.fs_cm = Dp->fs_cm;
+    C.img = Dp->img; C.r0 = Dp->r0; C.o0 = Dp->o0; C.fs = Dp->fs; C.fs_cm = Dp->fs_cm; C.mom = Dp->mom;
     C.fs_q = Dp->fs_q; C.fs_q_cm = Dp->fs_q_cm;
     C.stats = Dp->stats; C.e_samples = Dp->e_samples; C.drift_samples = Dp->drift_samples;
     C.gofr_all = Dp->gofr_all; C.gofr_inter = Dp->gofr_inter; C.c2 = Dp->c2;
@@ -1715,16 +1735,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
                     __syncthreads();
                 }
                 if (c2) {
-                    const double v = c2_value(E);
-                    double fs, fs_cm;
-                    fs_values(E, fs, fs_cm);
-                    if (tid == 0 && st->n_c2 < kC2Max) {
-                        C.c2[st->n_c2] = v;
-                        C.fs[st->n_c2] = fs;
-                        C.fs_cm[st->n_c2] = fs_cm;
-                        C.c2_sweep[st->n_c2] = sweep - origin;
-                        st->n_c2 += 1;
-                    }
+                    store_dyn(E, st, sweep - origin);
                     __syncthreads();
                 }
             }
@@ -1853,18 +1864,7 @@ __global__ void __launch_bounds__(kThreads) k_events(const Slot* __restrict__ sl
         }
         __syncthreads();
     }
-    if (f & kFlagC2) {
-        const double c2 = c2_value(C);
-        double fs, fs_cm;
-        fs_values(C, fs, fs_cm);
-        if (tid == 0 && st->n_c2 < kC2Max) {
-            C.c2[st->n_c2] = c2;
-            C.fs[st->n_c2] = fs;
-            C.fs_cm[st->n_c2] = fs_cm;
-            C.c2_sweep[st->n_c2] = sweep - st->obs_origin;
-            st->n_c2 += 1;
-        }
-    }
+    if (f & kFlagC2) store_dyn(C, st, sweep - st->obs_origin);
 }
 
 // ----------------------------------------------------- multi-workgroup --

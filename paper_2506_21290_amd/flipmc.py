@@ -100,6 +100,10 @@ class mc_obs(C.Structure):
         ("c2", C.c_double * MC_C2_MAX),
         ("fs", C.c_double * MC_C2_MAX),
         ("fs_cm", C.c_double * MC_C2_MAX),
+        ("c2_sq", C.c_double * MC_C2_MAX),
+        ("fs_cm_sq", C.c_double * MC_C2_MAX),
+        ("c2_fs_cm", C.c_double * MC_C2_MAX),
+        ("fs_sq", C.c_double * MC_C2_MAX),
     ]
 
 
@@ -289,6 +293,10 @@ class System:
             "c2": np.array(o.c2[: o.n_c2]),
             "fs": np.array(o.fs[: o.n_c2]),
             "fs_cm": np.array(o.fs_cm[: o.n_c2]),
+            "c2_sq": np.array(o.c2_sq[: o.n_c2]),
+            "fs_cm_sq": np.array(o.fs_cm_sq[: o.n_c2]),
+            "c2_fs_cm": np.array(o.c2_fs_cm[: o.n_c2]),
+            "fs_sq": np.array(o.fs_sq[: o.n_c2]),
         }
 
     def samples(self, cap=None):

@@ -114,3 +114,44 @@ def test_unwrapped_centres_follow_every_translation(oracle_mod):
     ref_u = s.unwrapped()
     fs, fs_cm = s.fs(ref_u)
     assert (fs, fs_cm) == (1.0, 1.0)
+
+
+def test_moment_helpers_are_library_statistics(oracle_mod):
+    rng = np.random.default_rng(3)
+    x, y = rng.normal(size=500), rng.normal(size=500)
+    y = 0.6 * x + 0.8 * y
+    assert oracle_mod.chi4_self(x) == pytest.approx(np.var(x), rel=1e-12)
+    assert oracle_mod.pearson(x, y) == pytest.approx(np.corrcoef(x, y)[0, 1], rel=1e-12)
+    assert oracle_mod.chi4(x, 64) == pytest.approx(64 * np.var(x), rel=1e-12)
+
+
+@pytest.mark.parametrize("same", [True, False])
+def test_two_populations_closed_forms(oracle_mod, same):
+    # Even molecules turned by theta about the triangle's normal; odd ones (or,
+    # when `same`, the even ones too) moved by delta.  Each contribution then
+    # takes two values, so the per-particle variance is (a - b)^2 / 4 and the
+    # Pearson coefficient of Eq. 13 is +1 (same molecules rotate and move) or
+    # -1 (the movers are the molecules that did not rotate).
+    M = 64
+    p = oracle_mod.Params(n_molecules=M, temperature=3.0, colours_per_axis=2, cells_per_side=2)
+    s = oracle_mod.System(p)
+    st = s.get_state()
+    ident = np.tile([1.0, 0, 0, 0], (M, 1))
+    s.set_state(st["com"], ident, st["types"], 0)
+    ref = s.unwrapped()
+    u0, kref = s.orientation_ref()
+    theta, delta = 0.8, np.array([0.2, 0.1, -0.3])
+    even = np.arange(M) % 2 == 0
+    quat = ident.copy()
+    quat[even] = [math.cos(theta / 2), 0, 0, math.sin(theta / 2)]
+    com = st["com"].copy()
+    com[even if same else ~even] += delta
+    s.set_state(com, quat, st["types"], 0)
+    c2_i, fcm_i, fs_i = s.particle_terms(ref, u0, kref, q=7.4, q_cm=5.1)
+    p2 = 0.5 * (3 * math.cos(theta) ** 2 - 1)
+    x = 5.1 * np.linalg.norm(delta)
+    fd = math.sin(x) / x
+    assert oracle_mod.chi4_self(c2_i) == pytest.approx((1 - p2) ** 2 / 4, abs=1e-14)
+    assert oracle_mod.chi4_self(fcm_i) == pytest.approx((1 - fd) ** 2 / 4, abs=1e-14)
+    assert oracle_mod.pearson(c2_i, fcm_i) == pytest.approx(1.0 if same else -1.0, abs=1e-12)
+    assert len(fs_i) == 3 * M and np.all(fs_i <= 1.0)

@@ -352,11 +352,11 @@ def test_fs_matches_oracle(engine):
     # high temperature with long steps, so centres cross the periodic boundary
     # many times; "spread": 1000 molecules on the multi-workgroup engine.
     if engine == "lds":
-        M, T, k, nc, seed, n = 64, 1e6, 2, 2, 5, 60
+        M, T, k, nc, seed, n = 64, 1e6, 2, 2, 5, 50
         kw = dict(p_flip=0.1, p_translate=0.8, max_displacement=0.35)
         flags, want_engine = 0, flipmc.MC_ENGINE_LDS
     else:
-        M, T, k, nc, seed, n = 1000, 0.9, 2, 4, 31, 25
+        M, T, k, nc, seed, n = 1000, 0.9, 2, 4, 31, 20
         kw = {}
         flags, want_engine = flipmc.MC_FLAG_HBM_STATE, flipmc.MC_ENGINE_SPREAD
     gp = gparams(M, T, k, nc, seed=seed, flags=flags, **kw)
@@ -365,17 +365,29 @@ def test_fs_matches_oracle(engine):
     g.sweep(n)
     obs = g.observables()
     sweeps = [int(t) for t in obs["c2_sweep"]]
-    assert len(sweeps) >= 5 and sweeps[-1] <= n
+    assert len(sweeps) >= 5 and sweeps[-1] == n
     o = oracle.System(oparams(M, T, k, nc, seed=seed, **kw))
     ref = o.unwrapped()
+    u0, kref = o.orientation_ref()
     want = {}
     for t in range(1, n + 1):
         o.sweep_checkerboard(1)
         if t in sweeps:
-            want[t] = o.fs(ref, q=gp.fs_q, q_cm=gp.fs_q_cm)
+            c2_i, fcm_i, fs_i = o.particle_terms(ref, u0, kref, q=gp.fs_q, q_cm=gp.fs_q_cm)
+            want[t] = {"fs": fs_i.mean(), "fs_cm": fcm_i.mean(), "c2": c2_i.mean(),
+                       "c2_sq": np.mean(c2_i ** 2), "fs_cm_sq": np.mean(fcm_i ** 2),
+                       "c2_fs_cm": np.mean(c2_i * fcm_i), "fs_sq": np.mean(fs_i ** 2)}
+            assert want[t]["fs"] == pytest.approx(o.fs(ref, gp.fs_q, gp.fs_q_cm)[0], abs=1e-14)
     assert np.array_equal(g.get_state()["com"], o.get_state()["com"])
-    np.testing.assert_allclose(obs["fs"], [want[t][0] for t in sweeps], rtol=0, atol=1e-12)
-    np.testing.assert_allclose(obs["fs_cm"], [want[t][1] for t in sweeps], rtol=0, atol=1e-12)
+    for key in ("fs", "fs_cm", "c2", "c2_sq", "fs_cm_sq", "c2_fs_cm", "fs_sq"):
+        np.testing.assert_allclose(obs[key], [want[t][key] for t in sweeps], rtol=0, atol=1e-12,
+                                   err_msg=key)
+    # the Pearson coefficient of Eq. 13 from the device's moments at the last sample
+    var_c2 = obs["c2_sq"][-1] - obs["c2"][-1] ** 2
+    var_f = obs["fs_cm_sq"][-1] - obs["fs_cm"][-1] ** 2
+    rho = (obs["c2_fs_cm"][-1] - obs["c2"][-1] * obs["fs_cm"][-1]) / math.sqrt(var_c2 * var_f)
+    c2_i, fcm_i, _ = o.particle_terms(ref, u0, kref, q=gp.fs_q, q_cm=gp.fs_q_cm)
+    assert rho == pytest.approx(oracle.pearson(c2_i, fcm_i), abs=1e-9)
     assert obs["fs"][-1] < 0.99
     if engine == "lds":
         com_u = o.unwrapped()[0]
