@@ -11,12 +11,15 @@ give the p50/p99 request latency ("serving"), then the CPU oracle runs on a
 bounded sample ("cpu_baseline").  Prints one JSON line.
 
 Other workloads (--workload): c2 (8000 molecules), c3 (256 uneven replicas in
-one persistent launch) and c4 (the serving loop).
+one persistent launch), c4 (the serving loop) and tau (relaxation times of flip
+MC against local MC, with the four-point susceptibility and the Pearson
+coefficient of the same runs).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
+import math
 import numpy as np
 import json
 import os
@@ -253,6 +256,82 @@ def bench_c2(args, flipmc, torch):
     }
 
 
+def crossing_time(t, c, level=math.exp(-1.0)):
+    """First time at which the correlation c(t) falls to `level`, linear in
+    log t between the two samples around the crossing; None if it never does."""
+    for i in range(1, len(t)):
+        if c[i] <= level < c[i - 1]:
+            x0, x1 = math.log(t[i - 1]), math.log(t[i])
+            return math.exp(x0 + (x1 - x0) * (c[i - 1] - level) / (c[i - 1] - c[i]))
+    return None
+
+
+def bench_tau(args, flipmc, torch):
+    """Relaxation of flip MC (p_flip = 0.2) and of local MC (p_flip = 0, the
+    same translation to rotation ratio) for replicas of the 1000-molecule
+    system at one temperature: each replica is equilibrated from its own
+    lattice start, then samples F_s(7.4, t), F_s^cm(5.1, t) and C_2(t) at
+    t in {1, 2, 5} x 10^j sweeps.  tau is where the replica mean crosses 1/e
+    (Sec. III.C); chi_4 (Eq. 10) is M (or 3M) times the variance of the
+    replicas' values and chi_4^self (Eq. 11) the mean per-replica variance of
+    the per-particle terms; rho (Eq. 13) is the replica mean of the Pearson
+    coefficient.  All replicas of both dynamics run in one batch."""
+    M, T, R = 1000, args.tau_temperature, args.tau_replicas
+    b = flipmc.Batch(2 * R, flipmc.MC_FP32_DE)
+    runs = {}
+    for kind, pf in (("flip", 0.2), ("local", 0.0)):
+        runs[kind] = []
+        for r in range(R):
+            p = flipmc.mc_params_default(n_molecules=M, temperature=T, precision=flipmc.MC_FP32_DE,
+                                         seed=r + 1, p_flip=pf, p_translate=(1.0 - pf) / 2,
+                                         resum_interval=1000, obs_interval=0, gofr_interval=0)
+            s = flipmc.System(p, stream=b.stream)
+            runs[kind].append(s)
+
+    def run_all(n):
+        for ss in runs.values():
+            for s in ss:
+                b.add(s, n)
+        done = 0
+        while done < 2 * R:
+            b.run(0)
+            done += len(b.poll())
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_all(args.tau_equilibration)
+    for ss in runs.values():
+        for s in ss:
+            s.reset_observables()
+    run_all(args.tau_sweeps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"workload": f"tau: {R} replicas x 2 dynamics of {M} molecules, T={T}, FP32 dE, "
+                       f"{args.tau_equilibration} + {args.tau_sweeps} sweeps each",
+           "wall_s": wall,
+           "moves_per_s": 2 * R * M * (args.tau_equilibration + args.tau_sweeps) / wall}
+    for kind, ss in runs.items():
+        obs = [s.observables() for s in ss]
+        t = [int(x) for x in obs[0]["c2_sweep"]]
+        res = {"t": t}
+        for key, n_part, sq in (("fs", 3 * M, "fs_sq"), ("fs_cm", M, "fs_cm_sq"), ("c2", M, "c2_sq")):
+            c = np.array([o[key] for o in obs])  # replicas x samples
+            mean = c.mean(axis=0)
+            chi4 = n_part * c.var(axis=0)
+            chi4_self = np.mean([o[sq] - o[key] ** 2 for o in obs], axis=0)
+            res[key] = {"mean": mean.tolist(), "tau": crossing_time(t, mean),
+                        "chi4_over_self_peak": float(np.max(chi4 / np.maximum(chi4_self, 1e-300)))}
+        rho = np.mean([(o["c2_fs_cm"] - o["c2"] * o["fs_cm"]) /
+                       np.sqrt(np.maximum((o["c2_sq"] - o["c2"] ** 2) * (o["fs_cm_sq"] - o["fs_cm"] ** 2),
+                                          1e-300)) for o in obs], axis=0)
+        res["pearson_peak"] = float(np.max(rho))
+        out[kind] = res
+    out["speedup"] = {key: (out["local"][key]["tau"] / out["flip"][key]["tau"]
+                            if out["local"][key]["tau"] and out["flip"][key]["tau"] else None)
+                      for key in ("fs", "fs_cm", "c2")}
+    return out
+
+
 def bench_c3(args, flipmc, torch):
     """256 independent replicas, M in {216, 512, 1000, 1728}, T over the
     paper's range, FP32 dE, 1000 sweeps each, all advanced by one batch."""
@@ -367,7 +446,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "copy"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "tau", "copy"])
+    ap.add_argument("--tau-temperature", type=float, default=2.2)
+    ap.add_argument("--tau-replicas", type=int, default=8)
+    ap.add_argument("--tau-equilibration", type=int, default=2000)
+    ap.add_argument("--tau-sweeps", type=int, default=50000)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--serving-jobs", type=int, default=200,
                     help="jobs of the serving stream run after the c1 line's own work (0: none)")
@@ -393,7 +476,7 @@ def main():
     if args.workload == "c1":
         out = bench_c1(args, flipmc, torch)
     else:
-        out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
+        out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "tau": bench_tau,
                "copy": bench_copy}[args.workload](args, flipmc, torch)
     print(json.dumps(out), flush=True)
 
