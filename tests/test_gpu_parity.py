@@ -525,6 +525,33 @@ def test_batch_inline_events_equal_event_kernel(fp32):
         assert np.array_equal(st["com"], st_ref["com"]) and st["e_acc"] == st_ref["e_acc"]
 
 
+def test_new_observable_origin_after_a_batch_run():
+    # the relaxation-time workflow: equilibrate in a batch, take a new
+    # observable origin, run again in the batch; C_2, F_s, F_s^cm and their
+    # moments equal those of the same system advanced alone
+    gp = gparams(216, 2.0, 3, 6, fp32=True, seed=12, max_displacement=0.2)
+    alone = flipmc.System(gp)
+    alone.sweep(30)
+    alone.reset_observables()
+    alone.sweep(50)
+    ref = alone.observables()
+    b = flipmc.Batch(2, flipmc.MC_FP32_DE)
+    s = flipmc.System(gp, stream=b.stream)
+    for n, reset in ((30, False), (50, True)):
+        if reset:
+            s.reset_observables()
+        b.add(s, n)
+        for _ in range(100):
+            b.run(max_moves_per_slot=2000)
+            if b.poll():
+                break
+    obs = s.observables()
+    assert list(obs["c2_sweep"]) == [1, 2, 5, 10, 20, 50]
+    for key in ("c2", "fs", "fs_cm", "c2_sq", "fs_cm_sq", "c2_fs_cm", "fs_sq"):
+        assert np.array_equal(obs[key], ref[key]), key
+    assert obs["fs_cm"][-1] < 1.0
+
+
 def test_isolated_molecule():
     gp = flipmc.mc_params_default(n_molecules=1, temperature=0.5, density=0.001,
                                   colours_per_axis=2, cells_per_side=2, precision=flipmc.MC_FP64)
