@@ -90,6 +90,7 @@ def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=0, nc=
     tm = s.timing_read()
     o1 = s.observables()
     e, em, drift = s.energy()
+    s.close()
     moves = steps * SWEEPS_PER_STEP * M
     att = [int(o1["attempts"][i] - o0["attempts"][i]) for i in range(3)]
     acc = [int(o1["accepts"][i] - o0["accepts"][i]) for i in range(3)]
@@ -103,6 +104,7 @@ def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=0, nc=
         "pair_terms": int(o1["pair_terms"] - o0["pair_terms"]),
         "pair_tests": int(o1["pair_tests"] - o0["pair_tests"]),
         "exits": int(o1["exits"] - o0["exits"]),
+        "near_overflows": int(o1["near_overflows"] - o0["near_overflows"]),
         "accept_rate": {kind: (acc[i] / att[i] if att[i] else None)
                         for i, kind in enumerate(["translate", "rotate", "flip"])},
         "energy_per_molecule": em,
@@ -114,12 +116,35 @@ def run_system(flipmc, torch, precision, steps, warmup, M=1000, T=0.75, k=0, nc=
     }
 
 
-def cpu_baseline(seconds, M=1000, T=0.75, k=2, nc=4):
+LIQUID = os.path.join(ROOT, "tests", "golden", "liquid_1000_T0.75_sweep500.npz")
+
+
+def host_cpu():
+    """(logical CPUs visible to this process, model name of the host CPU)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return n, model
+
+
+def _oracle_replica(seconds, seed_offset=0):
+    """Sweeps of the oracle on the 1000-molecule workload from its liquid
+    state at sweep 500 (the warm-up the GPU leg also runs), for `seconds`;
+    returns (attempted moves, elapsed s).  One replica per process."""
+    import numpy as np
     from oracle import oracle
 
-    oracle.build()
-    s = oracle.System(oracle.Params(n_molecules=M, temperature=T, colours_per_axis=k,
-                                    cells_per_side=nc, seed=1))
+    f = np.load(LIQUID)
+    s = oracle.System(oracle.Params(n_molecules=1000, temperature=0.75, colours_per_axis=2,
+                                    cells_per_side=4, seed=1 + seed_offset), lattice=False)
+    s.set_state(f["com"], f["quat"], f["types"], int(f["sweep"]))
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -127,14 +152,36 @@ def cpu_baseline(seconds, M=1000, T=0.75, k=2, nc=4):
         n += 1
         dt = time.perf_counter() - t0
         if dt >= seconds:
-            break
+            return n * 1000, dt
+
+
+def cpu_baseline(seconds, max_procs=16):
+    """The serial FP64 oracle on the host: one replica on one core, then one
+    replica process per core (up to max_procs) at once."""
+    import multiprocessing as mp
+    from oracle import oracle
+
+    oracle.build()
+    moves, dt = _oracle_replica(seconds)
+    one = moves / dt
+    ncpu, model = host_cpu()
+    procs = max(1, min(ncpu, max_procs))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.starmap(_oracle_replica, [(seconds, r + 1) for r in range(procs)])
+    allc = sum(m / t for m, t in res)
     return {
-        "value": n * M / dt,
+        "value": one,
         "unit": "molecule-moves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{n} checkerboard sweeps ({n * M} attempted moves) of the same 1000-molecule "
-                  f"system from its lattice start, serial FP64 oracle, {dt:.1f} s",
+        "sample": f"{moves} attempted moves ({moves // 1000} checkerboard sweeps) of the 1000-molecule "
+                  f"T=0.75 system from its liquid state at sweep 500 (the GPU leg's warm-up), "
+                  f"serial FP64 oracle, {dt:.1f} s",
+        "all_cores": {"value": allc, "processes": procs, "cores": procs,
+                      "sample": f"{procs} oracle replicas (seeds 2-{procs + 1}), one process each, "
+                                f"{seconds:.0f} s each"},
+        "nproc": ncpu,
+        "cpu_model": model,
     }
 
 
@@ -146,7 +193,6 @@ def bench_c1(args, flipmc, torch):
     kern_s = f32["sweep_kernel_ms"] / 1e3
     achieved = flops / kern_s / 1e12
     traffic = measured_traffic("k_sweeps_c1")
-    cpu_k, cpu_nc = f32["k"], f32["n_c"]
     out = {
         "metric": METRIC,
         "value": f32["moves_per_s"],
@@ -195,6 +241,7 @@ def bench_c1(args, flipmc, torch):
         "candidate_pair_tests_per_s": f32["pair_tests"] / (f32["ms"] / 1e3),
         "accept_rate": f32["accept_rate"],
         "exits_per_move": f32["exits"] / f32["moves"],
+        "near_overflows": f32["near_overflows"],
         "energy_per_molecule": f32["energy_per_molecule"],
         "max_abs_drift_per_window": f32["max_abs_drift_per_window"],
         "sweeps_done": f32["sweeps_done"],
@@ -204,9 +251,15 @@ def bench_c1(args, flipmc, torch):
         sv = bench_c4(args, flipmc, torch, n_jobs=args.serving_jobs)
         out["serving"] = {k: sv[k] for k in ("workload", "completed", "p50_latency_s", "p99_latency_s",
                                               "moves_per_s", "wall_s", "peak_concurrent_jobs")}
+    if not args.no_sub:
+        # the 8000-molecule system and the 256-replica batch, each with the
+        # roofline of its own dominant kernel
+        out["c2"] = bench_c2(args, flipmc, torch)
+        out["c3"] = bench_c3(args, flipmc, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, k=cpu_k, nc=cpu_nc)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
+        out["gpu_over_cpu_all_cores"] = out["value"] / out["cpu_baseline"]["all_cores"]["value"]
     return out
 
 
@@ -234,7 +287,10 @@ def bench_c2(args, flipmc, torch):
     tm = s.timing_read()
     o1 = s.observables()
     terms = int(o1["pair_terms"] - o0["pair_terms"])
+    overflows = int(o1["near_overflows"] - o0["near_overflows"])
     kern_s = tm["sweep_ms"] / 1e3
+    launches = max(1, tm["sweep_launches"])
+    s.close()
     # HBM bytes of one 100-sweep launch from the committed counter summary
     # (null when it was taken on other kernel sources)
     traffic = measured_traffic("k_spread_c2")
@@ -251,19 +307,12 @@ def bench_c2(args, flipmc, torch):
                      "traffic": traffic, "kernel": "k_spread<float>",
                      "cus_used": wg,
                      "valu_busy_on_its_cus": measured_counters("k_spread_c2").get("valu_busy_on_its_cus"),
-                     "hbm_gb_per_s": (traffic * n_sweeps / 100 / kern_s / 1e9) if traffic else None},
+                     "hbm_gb_per_s": (traffic * n_sweeps / 100 / kern_s / 1e9) if traffic else None,
+                     "avg_launch_ms": tm["sweep_ms"] / launches,
+                     "flops_per_launch": terms * FLOP_PER_PAIR_TERM / launches},
+        "near_overflows": overflows,
         "ms": ms,
     }
-
-
-def crossing_time(t, c, level=math.exp(-1.0)):
-    """First time at which the correlation c(t) falls to `level`, linear in
-    log t between the two samples around the crossing; None if it never does."""
-    for i in range(1, len(t)):
-        if c[i] <= level < c[i - 1]:
-            x0, x1 = math.log(t[i - 1]), math.log(t[i])
-            return math.exp(x0 + (x1 - x0) * (c[i - 1] - level) / (c[i - 1] - c[i]))
-    return None
 
 
 def bench_tau(args, flipmc, torch):
@@ -311,20 +360,15 @@ def bench_tau(args, flipmc, torch):
            "wall_s": wall,
            "moves_per_s": 2 * R * M * (args.tau_equilibration + args.tau_sweeps) / wall}
     for kind, ss in runs.items():
-        obs = [s.observables() for s in ss]
-        t = [int(x) for x in obs[0]["c2_sweep"]]
-        res = {"t": t}
-        for key, n_part, sq in (("fs", 3 * M, "fs_sq"), ("fs_cm", M, "fs_cm_sq"), ("c2", M, "c2_sq")):
-            c = np.array([o[key] for o in obs])  # replicas x samples
-            mean = c.mean(axis=0)
-            chi4 = n_part * c.var(axis=0)
-            chi4_self = np.mean([o[sq] - o[key] ** 2 for o in obs], axis=0)
-            res[key] = {"mean": mean.tolist(), "tau": crossing_time(t, mean),
-                        "chi4_over_self_peak": float(np.max(chi4 / np.maximum(chi4_self, 1e-300)))}
-        rho = np.mean([(o["c2_fs_cm"] - o["c2"] * o["fs_cm"]) /
-                       np.sqrt(np.maximum((o["c2_sq"] - o["c2"] ** 2) * (o["fs_cm_sq"] - o["fs_cm"] ** 2),
-                                          1e-300)) for o in obs], axis=0)
-        res["pearson_peak"] = float(np.max(rho))
+        # means, chi_4 (Eq. 10), chi_4^self (Eq. 11), rho (Eq. 13) and the 1/e
+        # times (Sec. III.C), formed by the library from the runs' observables
+        d = flipmc.mc_dynamics([s.obs_struct() for s in ss], M)
+        res = {"t": [int(x) for x in d["t"]]}
+        for key in ("fs", "fs_cm", "c2"):
+            ratio = d["chi4_" + key] / np.maximum(d["chi4s_" + key], 1e-300)
+            res[key] = {"mean": d[key].tolist(), "tau": d["tau_" + key],
+                        "chi4_over_self_peak": float(np.max(ratio))}
+        res["pearson_peak"] = float(np.max(d["rho"]))
         out[kind] = res
     out["speedup"] = {key: (out["local"][key]["tau"] / out["flip"][key]["tau"]
                             if out["local"][key]["tau"] and out["flip"][key]["tau"] else None)
@@ -359,8 +403,15 @@ def bench_c3(args, flipmc, torch):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     moves = sum(j.n_molecules * j.sweeps for j in jobs)
+    obs = [s.observables() for s in systems]
+    terms = sum(int(o["pair_terms"]) for o in obs)
+    overflows = sum(int(o["near_overflows"]) for o in obs)
+    achieved = terms * FLOP_PER_PAIR_TERM / (ms / 1e3) / 1e12
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    for s in systems:
+        s.close()
+    b.close()
     # the same kind of replica alone, plain FP64: a stratified sample of 8
-    sample = [j for size in workloads.REPLICA_SIZES for j in jobs if j.n_molecules == size][:0]
     by_size = {}
     for j in jobs:
         by_size.setdefault(j.n_molecules, []).append(j)
@@ -380,12 +431,26 @@ def bench_c3(args, flipmc, torch):
         torch.cuda.synchronize()
         t_seq += a.elapsed_time(z) / 1e3
         m_seq += j.n_molecules * j.sweeps
+        s.close()
     return {
         "workload": "c3: 256 replicas, M in {216,512,1000,1728}, T in [0.75,3], FP32 dE, 1000 sweeps each",
         "moves_per_s": moves / (ms / 1e3),
         "ms": ms,
         "moves": moves,
         "launches": launches,
+        "pair_interactions_per_s": terms / (ms / 1e3),
+        "near_overflows": overflows,
+        # the batch's run is one launch of the one-workgroup sweep kernel (all
+        # 256 replicas, re-sums and C_2 samples inside it): its time is the
+        # timed region, measured with events on the batch's stream
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
+                     "traffic": measured_traffic("k_sweeps_c3"),
+                     "kernel": "k_sweeps<float, resident, inline events>",
+                     "cus_used": min(ncu, len(jobs)),
+                     "valu_busy": measured_counters("k_sweeps_c3").get("valu_busy"),
+                     "avg_launch_ms": ms / max(1, launches),
+                     "flops_per_launch": terms * FLOP_PER_PAIR_TERM / max(1, launches)},
         "fp64_one_by_one_moves_per_s": m_seq / t_seq,
         "fp64_sample": f"{len(sample)} replicas (2 per size) run alone in FP64",
     }
@@ -460,7 +525,8 @@ def main():
     ap.add_argument("--quantum", type=int, default=100_000)
     ap.add_argument("--time-limit", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-sub", action="store_true", help="leave out the c2 and c3 sub-objects")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": f"--gpus {args.gpus}: this engine runs on one GPU; "

@@ -11,10 +11,13 @@
  * Conventions for every call:
  *   - Return value: MC_OK (0) or a negative MC_E* code; mc_last_error() then
  *     returns a thread-local message.  No call aborts or throws.
- *   - Device memory is owned by the caller: mc_init_system() carves its
- *     state out of one caller-provided device buffer of at least
- *     mc_required_bytes() bytes, which must outlive the system.  The library
- *     owns only the opaque handles and small host mirrors.
+ *   - Device memory and streams are owned by the caller: mc_init_system()
+ *     carves a system out of one caller-provided device buffer of at least
+ *     mc_required_bytes() bytes, mc_batch_create() its slot tables out of one
+ *     of at least mc_batch_required_bytes(); each buffer must outlive its
+ *     system or batch.  The library owns only the opaque handles, small host
+ *     mirrors, the pinned host staging of a batch's slot tables and HIP
+ *     events; it never allocates device memory and never creates a stream.
  *   - All GPU work of a system is enqueued on the HIP stream given at
  *     mc_init_system() (NULL = the null stream).  mc_sweep() and
  *     mc_batch_run() only enqueue; calls that return host data (mc_energy,
@@ -65,8 +68,11 @@ enum { MC_ENGINE_LDS = 0, MC_ENGINE_HBM = 1, MC_ENGINE_SPREAD = 2 };
 #define MC_GOFR_MAX_BINS 256
 #define MC_C2_MAX 32
 
-/* Parameters of one system.  mc_params_default() fills the paper's values
- * (Sec. II.A: sigma = 0.9 / 1.0 / 1.1, density 1.2; Sec. II.B: p_flip = 0.2). */
+/* Parameters of one system: the model of Sec. II.A (three atom sizes, the WCA
+ * potential of Eq. 1 between sites of different molecules, number density
+ * N / V in a cubic periodic box) and the flip MC of Sec. II.B (flip
+ * probability, step sizes, NVT at temperature T).  mc_params_default() fills
+ * the paper's values (sigma = 0.9 / 1.0 / 1.1, density 1.2, p_flip = 0.2). */
 typedef struct {
     uint32_t n_molecules;      /* M (>= 1, <= 65535)                                 */
     uint32_t precision;        /* MC_FP64 or MC_FP32_DE                              */
@@ -107,7 +113,8 @@ typedef struct {
 typedef struct mc_system mc_system;
 typedef struct mc_batch mc_batch;
 
-/* One attempted move, written by the device when a decision log is enabled. */
+/* One attempted move of Sec. II.B (trial, Metropolis test), written by the
+ * device when a decision log is enabled (mc_decision_log). */
 typedef struct {
     double   delta_e;    /* E_m(new) - E_m(old) over the moved sites, as computed  */
     double   scale;      /* E_m(new) + E_m(old) over the moved sites               */
@@ -130,6 +137,8 @@ typedef struct {
     uint64_t exits;              /* translations rejected for leaving their cell   */
     uint64_t pair_terms;         /* interacting site-pair terms evaluated          */
     uint64_t pair_tests;         /* candidate site-pair distance tests             */
+    uint64_t near_overflows;     /* cells whose list of nearby molecules overflowed
+                                    (then every stencil molecule is a candidate)  */
     double   e_acc;              /* E_0 + sum of accepted dE (FP64)                */
     double   e_resum;            /* last FP64 re-sum                               */
     double   drift;              /* e_acc - e_resum at the last re-sum: the error
@@ -165,15 +174,25 @@ typedef struct {
     double   fs_cm_sq[MC_C2_MAX];          /* mean over molecules of (F_s^cm,i)^2     */
     double   c2_fs_cm[MC_C2_MAX];          /* mean over molecules of C_2^i F_s^cm,i   */
     double   fs_sq[MC_C2_MAX];             /* mean over sites of (F_s^i)^2            */
+    /* Eq. (3) normalised: counts / (frames N rho (4 pi / 3)(r_{b+1}^3 - r_b^3)),
+     * N = 3 M, rho = N / L^3; bin b covers [b dr, (b + 1) dr).  0 without frames. */
+    double   gofr_norm_all[MC_GOFR_MAX_BINS];
+    double   gofr_norm_inter[MC_GOFR_MAX_BINS];
 } mc_obs;
 
 /* ---- single system ------------------------------------------------------ */
 
-/* Fill *p with the paper's model values and this engine's defaults. */
+/* Fill *p with the paper's model values (Sec. II.A sizes and density,
+ * Sec. II.B p_flip) and this engine's defaults (move mixture 0.2 flip / 0.4
+ * translation / 0.4 rotation, steps 0.1 and 0.2 rad, re-sum every 100 sweeps,
+ * F_s at q = 7.4 and 5.1 as in Sec. III.B).  Never fails. */
 void mc_params_default(mc_params* p);
 
-/* Box side L = (3 M / density)^(1/3) and the decomposition the engine will
- * use (k, n_c) for these parameters (after "choose" defaults). */
+/* Box side L = (3 M / density)^(1/3) (Sec. II.A: rho = N / V, N = 3 M) and
+ * the checkerboard decomposition (k, n_c) the engine will use (after "choose"
+ * defaults).  MC_EGEOM when the box is below 2 (W + 2 d_max), W the reach of
+ * a molecule (largest cut-off + 2 circumradii), or when (k - 1) L / n_c < W.
+ * Any output may be NULL. */
 int mc_geometry(const mc_params* p, double* box, uint32_t* colours_per_axis,
                 uint32_t* cells_per_side);
 
@@ -192,40 +211,56 @@ int mc_placement(const mc_params* p, int* resident, size_t* lds_bytes);
  * mc_batch_run).  Either output may be NULL. */
 int mc_engine(const mc_params* p, int* engine, uint32_t* workgroups);
 
-/* Bytes of device memory mc_init_system needs for these parameters. */
+/* Bytes of device memory mc_init_system needs for these parameters (state of
+ * Sec. II.A's M molecules, observable accumulators of Sec. III and the
+ * engine's work arrays, 256-byte aligned regions).  Host only. */
 int mc_required_bytes(const mc_params* p, size_t* bytes);
 
-/* Create a system in device_buf (>= mc_required_bytes).  With com, quat and
- * types all NULL the start is the seeded simple-cubic lattice (M = n^3,
- * random uniform orientations, types A, B, C on sites 0, 1, 2); otherwise
- * they are host arrays com[3M] (xyz per molecule), quat[4M] (w, x, y, z,
- * unit) and types[3M] (0 = A, 1 = B, 2 = C, a permutation per molecule).
- * Computes E_0 by an FP64 re-sum; fails with MC_ENONFINITE if it is not
- * finite.  hip_stream is a hipStream_t (NULL = null stream). */
+/* Create a system of the model of Sec. II.A (M molecules, density, box) in
+ * device_buf (caller-owned, 256-byte aligned, >= mc_required_bytes, must
+ * outlive the system).  With com, quat and types all NULL the start is the
+ * seeded simple-cubic lattice (M = n^3, random uniform orientations, types
+ * A, B, C on sites 0, 1, 2); otherwise they are host arrays com[3M] (xyz per
+ * molecule), quat[4M] (w, x, y, z, unit) and types[3M] (0 = A, 1 = B,
+ * 2 = C, a permutation per molecule), copied at once.  Computes E_0 (Eq. 1
+ * summed over site pairs of distinct molecules) by an FP64 re-sum; fails with
+ * MC_ENONFINITE if it is not finite, MC_ENOMEM if the buffer is too small,
+ * MC_EINVAL for a bad argument.  hip_stream is a hipStream_t (NULL = null
+ * stream).  Synchronises the stream before returning. */
 int mc_init_system(const mc_params* p, const double* com, const double* quat,
                    const uint8_t* types, void* device_buf, size_t buf_bytes,
                    void* hip_stream, mc_system** out);
 
-/* Enqueue n checkerboard sweeps (each attempts every molecule once). */
+/* Enqueue n Monte Carlo timesteps (Sec. II.B: a timestep is N attempted
+ * moves; here each of the M molecules is attempted once per sweep, in the
+ * checkerboard order).  Asynchronous on the system's stream; MC_EBUSY inside
+ * a batch. */
 int mc_sweep(mc_system* s, uint64_t n_sweeps);
 
-/* FP64 total inter-molecular energy now (a fresh re-sum), E/M, and the drift
- * e_acc - e_total.  Synchronises. Any output pointer may be NULL. */
+/* FP64 total energy now (Eq. 1 over site pairs of distinct molecules, a fresh
+ * re-sum), E/M, and the drift e_acc - e_total of the accumulated energy.
+ * Synchronises.  Any output pointer may be NULL.  MC_ENONFINITE if E is not
+ * finite, MC_EBUSY inside a batch. */
 int mc_energy(mc_system* s, double* e_total, double* e_per_molecule, double* drift);
 
-/* Copy the accumulators to *out.  Synchronises. */
+/* Copy the accumulators to *out (host): move counters, E/M moments, g(r) of
+ * Eq. 3 as counts and normalised, C_2 of Eq. 7 and F_s, F_s^cm of Eqs. 5-6
+ * with their per-particle moments (Sec. V).  Synchronises (the batch's
+ * stream first inside a batch). */
 int mc_observables(mc_system* s, mc_obs* out);
 
-/* Copy up to cap E/M samples and drift samples (NULL to skip either). */
+/* Copy up to cap E/M samples and drift samples to host arrays (NULL to skip
+ * either); *n_energy / *n_drift get the counts copied.  Synchronises. */
 int mc_samples(mc_system* s, double* energy, double* drift, size_t cap, size_t* n_energy,
                size_t* n_drift);
 
-/* Clear the observable accumulators and take the current state as the
- * reference of C_2 and the origin of sampling times. */
+/* Clear the observable accumulators and take the current state as the time
+ * origin of C_2 (Eq. 7) and F_s (Eqs. 5-6): the reference orientation and
+ * unwrapped positions.  Asynchronous; MC_EBUSY inside a batch. */
 int mc_reset_observables(mc_system* s);
 
-/* Read / overwrite the state (host arrays in the layouts of mc_init_system;
- * any output pointer may be NULL).  mc_set_state also sets the sweep counter
+/* Read / overwrite the state of Sec. II.A (host arrays in the layouts of
+ * mc_init_system; any output pointer may be NULL).  Both synchronise.  mc_set_state also sets the sweep counter
  * (which keys the random numbers) and the accumulated energy; e_acc NaN means
  * "re-sum it".  It also clears the periodic-image counts that unwrap the
  * centres for F_s, so F_s needs a new origin (mc_reset_observables) after it. */
@@ -234,25 +269,66 @@ int mc_get_state(mc_system* s, double* com, double* quat, uint8_t* types, uint64
 int mc_set_state(mc_system* s, const double* com, const double* quat, const uint8_t* types,
                  uint64_t sweep, double e_acc);
 
-/* Record every attempted move of the next sweeps into a caller-owned DEVICE
- * array of capacity records: record (sweep - first_sweep) * M + molecule.
- * Sweeps beyond capacity / M are not recorded.  records = NULL disables. */
+/* Record every attempted move (Sec. II.B trial and Metropolis decision) of
+ * the next sweeps into a caller-owned DEVICE array of capacity records:
+ * record (sweep - first_sweep) * M + molecule.  Sweeps beyond capacity / M
+ * are not recorded.  records = NULL disables.  Stays in force when the system
+ * joins a batch; MC_EBUSY when called inside one. */
 int mc_decision_log(mc_system* s, void* device_records, size_t capacity);
 
-/* Time every launch of the sweep kernel and of the event kernel of this system
- * with HIP events recorded on its stream (enable = 0 stops and clears). */
+/* Measurement (not part of the method): time every launch of the sweep kernel
+ * and of the event kernel of this system with HIP events recorded on its
+ * stream (enable = 0 stops and clears).  The events are the library's. */
 int mc_timing_enable(mc_system* s, int enable);
 
-/* Sum of the recorded launch durations (ms) and launch counts.  Synchronises. */
+/* Sum of the recorded launch durations (ms) and launch counts.  Synchronises.
+ * Any output pointer may be NULL. */
 int mc_timing_read(mc_system* s, double* sweep_ms, uint64_t* sweep_launches, double* event_ms,
                    uint64_t* event_launches);
 
+/* Release a system's handle after waiting for its stream (and its batch's
+ * streams when it is in one); its device buffer is the caller's to free
+ * afterwards.  NULL is ignored. */
 void mc_destroy(mc_system* s);
+/* Message of the last failing call of this thread (never NULL). */
 const char* mc_last_error(void);
+
+/* ---- analysis of independent runs ------------------------------------------ */
+
+/* Time correlations of n independent runs of one system (same M, same sample
+ * sweeps), formed from what mc_observables returns.  Per sample time t_j:
+ *   c2, fs, fs_cm  the ensemble means of C_2 (Eq. 7), F_s (Eq. 5), F_s^cm (Eq. 6);
+ *   chi4_*         Eq. 10: M (3 M for the sites' F_s) times the variance over
+ *                  runs of the run's value;
+ *   chi4s_*        Eq. 11: mean over runs and particles of C_i^2 minus the
+ *                  square of the ensemble mean (the self part);
+ *   rho            Eq. 13: (mean of C_2^i F_s^cm,i - C_2 F_s^cm) over the
+ *                  square root of the product of the two self parts;
+ * and the relaxation times of Sec. III.C: the first time each mean falls to
+ * 1/e, linear in ln t between the two samples around the crossing (NaN when
+ * it does not fall that far).  Host only; MC_EINVAL when the runs do not
+ * share their sample sweeps. */
+typedef struct {
+    uint32_t n_times;
+    uint32_t n_runs;
+    uint64_t t[MC_C2_MAX];          /* sweeps after the observable origin        */
+    double   c2[MC_C2_MAX], fs[MC_C2_MAX], fs_cm[MC_C2_MAX];
+    double   chi4_c2[MC_C2_MAX], chi4_fs[MC_C2_MAX], chi4_fs_cm[MC_C2_MAX];
+    double   chi4s_c2[MC_C2_MAX], chi4s_fs[MC_C2_MAX], chi4s_fs_cm[MC_C2_MAX];
+    double   rho[MC_C2_MAX];
+    double   tau_c2, tau_fs, tau_fs_cm;
+} mc_dyn;
+
+int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn* out);
 
 /* ---- batches: many systems in one persistent launch ---------------------- */
 
-/* A batch holds up to max_slots systems of one precision.  Each
+/* The batched and served patterns of this engine (not from the paper, which
+ * runs independent samples, Sec. III.B): many independent Markov chains of
+ * the same model, each with its own size, temperature and sweep count, share
+ * persistent launches.
+ *
+ * A batch holds up to max_slots systems of one precision.  Each
  * mc_batch_run gives every system one workgroup; the workgroups left over
  * (up to the batch's workgroup limit, one per compute unit by default) go to
  * the systems with the most remaining work that can use several (those
@@ -265,7 +341,20 @@ const char* mc_last_error(void);
  * All engines make the same decisions and sum the energy in the same order,
  * so a system gives bitwise the same results in a batch as alone, whichever
  * engines its runs used. */
-int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc_batch** out);
+/* Bytes of caller-owned device memory a batch of max_slots slots needs (its
+ * double-buffered slot tables).  MC_EINVAL when max_slots is 0 or above
+ * 65536. */
+int mc_batch_required_bytes(uint32_t max_slots, size_t* bytes);
+
+/* Create a batch whose slot tables live in device_buf (caller-owned, 256-byte
+ * aligned, >= mc_batch_required_bytes(max_slots), must outlive the batch).
+ * Systems on one workgroup run on hip_stream; the multi-workgroup launches
+ * run on hip_stream_aux (a second caller stream, so both overlap) or, when it
+ * is NULL, on hip_stream after them.  The batch keeps pinned host staging of
+ * its slot tables and a few HIP events of its own.  MC_ENOMEM when the
+ * buffer is too small. */
+int mc_batch_create(uint32_t max_slots, uint32_t precision, void* device_buf, size_t buf_bytes,
+                    void* hip_stream, void* hip_stream_aux, mc_batch** out);
 
 /* Put an initialised system into a free slot with n_sweeps of work; the
  * system must use the batch's precision.  MC_EBUSY when no slot is free.
@@ -299,6 +388,8 @@ int mc_batch_poll(mc_batch* b, uint32_t* slots, mc_system** systems, size_t cap,
 /* Remove a system from its slot before its work is done. */
 int mc_batch_cancel(mc_batch* b, uint32_t slot);
 
+/* Wait for the batch's streams and release its handle; its systems leave it
+ * and stay valid.  NULL is ignored. */
 void mc_batch_destroy(mc_batch* b);
 
 #ifdef __cplusplus

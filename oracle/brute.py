@@ -111,6 +111,41 @@ def energy(com, quat, types, box, bond, sigma=(0.9, 1.0, 1.1)):
     return 0.5 * float(u[other].sum())
 
 
+def interacting_pairs(com, quat, types, box, bond, m, moved, sigma=(0.9, 1.0, 1.1)):
+    """Number of (moved site of molecule m, site of another molecule) pairs
+    closer than their cut-off 2^(1/6) sigma_ij (Eq. 1), nearest image per
+    site pair."""
+    pos = sites(com, quat, bond)
+    sg = np.asarray(sigma)
+    ty = np.asarray(types)
+    others = np.array([j for j in range(len(com)) if j != m], dtype=int)
+    n = 0
+    for a in moved:
+        d = pos[others].reshape(-1, 3) - pos[m, a]
+        d -= box * np.round(d / box)
+        r2 = (d * d).sum(-1)
+        sij = 0.5 * (sg[ty[m, a]] + sg[ty[others].reshape(-1)])
+        n += int(np.count_nonzero(r2 < (2.0 ** (1.0 / 3.0)) * sij * sij))
+    return n
+
+
+def lattice_quaternions(n_molecules, seed):
+    """Orientations of the lattice start: Shoemake's uniform unit quaternion
+    (Graphics Gems III, 1992) from the three uniforms (u1, u2, u3) of the
+    Philox block (m, 2^32 - 1, 2^32 - 1, 2) of molecule m:
+    (sqrt(u1) cos 2 pi u3, sqrt(1 - u1) sin 2 pi u2, sqrt(1 - u1) cos 2 pi u2,
+    sqrt(u1) sin 2 pi u3)."""
+    m = np.arange(n_molecules, dtype=np.uint64)
+    ctr = np.stack([m, np.full_like(m, 0xFFFFFFFF), np.full_like(m, 0xFFFFFFFF),
+                    np.full_like(m, 2)], axis=1)
+    key = np.tile(np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint64), (n_molecules, 1))
+    g = philox4x32_10(ctr, key)
+    u1, u2, u3 = (uniform_open(g[:, i]) for i in range(3))
+    return np.stack([np.sqrt(u1) * np.cos(2 * np.pi * u3), np.sqrt(1 - u1) * np.sin(2 * np.pi * u2),
+                     np.sqrt(1 - u1) * np.cos(2 * np.pi * u2), np.sqrt(u1) * np.sin(2 * np.pi * u3)],
+                    axis=1)
+
+
 class Replayer:
     """Replays the oracle's decision log step by step from the definitions."""
 
@@ -135,6 +170,7 @@ class Replayer:
         return (self.box / self.p.cells_per_side) * uniform_open(g[:3])
 
     def propose(self, com, quat, types, m, slot, sweep, restricted):
+        """(move kind, new state or None for a cell exit, u_acc, moved sites)"""
         b0 = self.draw(slot, sweep, 0)
         b1 = self.draw(slot, sweep, 1)
         u_acc = uniform53(b0[0], b0[1])
@@ -147,13 +183,15 @@ class Replayer:
             a = min(int(3 * pr[0]), 2)
             s1, s2 = (a + 1) % 3, (a + 2) % 3
             types2[m, s1], types2[m, s2] = types[m, s2], types[m, s1]
+            moved = (s1, s2)
         elif u_type < p.p_flip + p.p_translate:
             move = 0
             com2[m] = np.mod(com[m] + p.max_displacement * (2 * pr - 1), self.box)
             if restricted:
                 h = self.shift(sweep)
                 if self.cell(com2[m], h) != self.cell(com[m], h):
-                    return move, None, u_acc
+                    return move, None, u_acc, ()
+            moved = (0, 1, 2)
         else:
             move = 1
             z = 2 * pr[0] - 1
@@ -168,7 +206,11 @@ class Replayer:
                 *(d[0] * q[1:] + q[0] * d[1:] + np.cross(d[1:], q[1:])),
             ])
             quat2[m] = prod / np.linalg.norm(prod)
-        return move, (com2, quat2, types2), u_acc
+            moved = (0, 1, 2)
+        return move, (com2, quat2, types2), u_acc, moved
 
     def energy(self, com, quat, types):
         return energy(com, quat, types, self.box, self.bond, self.p.sigma)
+
+    def pairs(self, com, quat, types, m, moved):
+        return interacting_pairs(com, quat, types, self.box, self.bond, m, moved, self.p.sigma)

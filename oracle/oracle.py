@@ -232,6 +232,18 @@ def gofr_bins(box, dr=0.02):
     return n, rm.value
 
 
+def gofr_normalise(counts, frames, n_sites, box, dr):
+    """Eq. (3): g(r_b) = counts_b / (frames N rho (4 pi / 3)(r_{b+1}^3 - r_b^3)),
+    rho = N / L^3, bin b = [b dr, (b + 1) dr); zeros without frames."""
+    counts = np.asarray(counts, dtype=np.float64)
+    if frames == 0:
+        return np.zeros_like(counts)
+    r = np.arange(len(counts) + 1) * dr
+    shell = 4.0 * np.pi / 3.0 * (r[1:] ** 3 - r[:-1] ** 3)
+    rho = n_sites / box ** 3
+    return counts / (frames * n_sites * rho * shell)
+
+
 class System:
     """One oracle Markov chain."""
 
@@ -413,6 +425,17 @@ def chi4(c_hat, n):
     variance, n = M for a molecular correlation, 3M for sites."""
     c_hat = np.asarray(c_hat, dtype=np.float64)
     return float(n * (np.mean(c_hat ** 2) - np.mean(c_hat) ** 2))
+
+
+def relaxation_time(t, c, level=float(np.exp(-1.0))):
+    """Sec. III.C: the time at which a correlation c(t), sampled at times t,
+    first falls to `level` (1/e), linear in ln t between the two samples
+    around the crossing; None if it never falls that far."""
+    for i in range(1, len(t)):
+        if c[i] <= level < c[i - 1]:
+            x0, x1 = np.log(float(t[i - 1])), np.log(float(t[i]))
+            return float(np.exp(x0 + (x1 - x0) * (c[i - 1] - level) / (c[i - 1] - c[i])))
+    return None
 
 
 def fs_isotropic(d, q):

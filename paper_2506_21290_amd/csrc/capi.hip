@@ -144,8 +144,12 @@ int geometry(const mc_params* p, Geometry* g)
     const double smax = std::max(p->sigma[0], std::max(p->sigma[1], p->sigma[2]));
     const double rcmax = std::pow(2.0, 1.0 / 6.0) * smax;
     g->reach = rcmax + 2.0 * g->radius;
-    if (g->L < 2.0 * (rcmax + 2.0 * p->max_displacement))
-        return fail(MC_EGEOM, "box side %.4f too small for the minimum-image convention", g->L);
+    // Pair terms are formed from the nearest image of the two centres plus the
+    // site offsets.  That is the nearest image of every interacting site pair
+    // only when no molecule reaches another through two images: L >= 2 reach.
+    if (g->L < 2.0 * (g->reach + 2.0 * p->max_displacement))
+        return fail(MC_EGEOM, "box side %.4f below twice the interaction reach %.4f (minimum image)",
+                    g->L, g->reach + 2.0 * p->max_displacement);
     uint32_t k = p->colours_per_axis, nc = p->cells_per_side;
     if (k == 0 && nc == 0) {
         double best = std::numeric_limits<double>::infinity();
@@ -319,7 +323,7 @@ struct mc_batch {
     int parity;
     // systems on the multi-workgroup engine: one cooperative launch per run on
     // stream2, overlapping the batch stream's launches
-    hipStream_t stream2;
+    hipStream_t stream2;              // caller's second stream (or the batch stream)
     hipEvent_t go, done;              // stream2 waits for go (stream), stream for done (stream2)
     SpreadSlot* dev_spread[2];        // per parity: [systems | (events as Slot)] x max_slots
     SpreadSlot* host_spread[2];
@@ -450,13 +454,16 @@ uint64_t next_event(const mc_system* s, bool gofr_only = false)
     return best;
 }
 
+constexpr uint64_t kMaxSweepsPerLaunch = 1u << 16;
+
 // Enqueue n sweeps of one system, split at event sweeps.
 int advance(mc_system* s, uint64_t n)
 {
     Slot one{};
     one.sys = s->dev;
     while (n > 0) {
-        const uint64_t chunk = std::min<uint64_t>(n, next_event(s) - s->sweep);
+        // at most kMaxSweepsPerLaunch sweeps per launch (a bounded kernel time)
+        const uint64_t chunk = std::min<uint64_t>({n, next_event(s) - s->sweep, kMaxSweepsPerLaunch});
         one.n_sweeps = chunk;
         one.flags = 0;
         if (s->g.spread) HIPCHK(hipMemsetAsync(s->host.g_bar, 0, sizeof(uint32_t), s->stream));
@@ -754,6 +761,27 @@ int mc_energy(mc_system* s, double* e_total, double* e_per_molecule, double* dri
     return MC_OK;
 }
 
+namespace {
+
+// Eq. (3): g(r) = counts / (frames N rho (4 pi / 3) (r_{b+1}^3 - r_b^3)) with
+// N = 3 M sites, rho = N / L^3 and the exact shell volume of bin b.
+void gofr_normalise(const mc_system* s, mc_obs* o)
+{
+    const double N = 3.0 * (double)s->p.n_molecules;
+    const double rho = N / (s->g.L * s->g.L * s->g.L);
+    const double frames = (double)o->n_gofr_frames;
+    const double dr = o->gofr_dr;
+    for (uint32_t b = 0; b < o->gofr_nbins && frames > 0.0; ++b) {
+        const double r0 = dr * (double)b, r1 = dr * (double)(b + 1);
+        const double shell = 4.0 * M_PI / 3.0 * (r1 * r1 * r1 - r0 * r0 * r0);
+        const double ideal = frames * N * rho * shell;
+        o->gofr_norm_all[b] = (double)o->gofr_all[b] / ideal;
+        o->gofr_norm_inter[b] = (double)o->gofr_inter[b] / ideal;
+    }
+}
+
+}  // namespace
+
 int mc_observables(mc_system* s, mc_obs* o)
 {
     if (!s || !o) return fail(MC_EINVAL, "null argument");
@@ -769,6 +797,7 @@ int mc_observables(mc_system* s, mc_obs* o)
     o->exits = st.exits;
     o->pair_terms = st.pair_terms;
     o->pair_tests = st.pair_tests;
+    o->near_overflows = st.near_overflows;
     o->e_acc = st.e_acc;
     o->e_resum = st.e_resum;
     o->drift = st.drift;
@@ -794,6 +823,7 @@ int mc_observables(mc_system* s, mc_obs* o)
     HIPCHK(hipMemcpyAsync(o->fs_sq, s->host.mom + 3 * kC2Max, sizeof o->fs_sq, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(o->c2_sweep, s->host.c2_sweep, sizeof o->c2_sweep, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    gofr_normalise(s, o);
     return MC_OK;
 }
 
@@ -926,7 +956,13 @@ int mc_timing_read(mc_system* s, double* sweep_ms, uint64_t* sweep_launches, dou
 void mc_destroy(mc_system* s)
 {
     if (!s) return;
-    if (!s->ev_sweep.empty() || !s->ev_event.empty()) (void)hipStreamSynchronize(s->stream);
+    // no kernel of the system may still run when the caller frees its buffer:
+    // wait for its own stream and, inside a batch, for the batch's streams
+    (void)hipStreamSynchronize(s->stream);
+    if (s->batch) {
+        (void)hipStreamSynchronize(s->batch->stream);
+        if (s->batch->stream2) (void)hipStreamSynchronize(s->batch->stream2);
+    }
     for (auto& pr : s->ev_sweep) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
     for (auto& pr : s->ev_event) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
@@ -938,12 +974,122 @@ void mc_destroy(mc_system* s)
     delete s;
 }
 
+// ------------------------------------------------- analysis of several runs --
+
+namespace {
+
+// First time the samples c[0..n) fall to `level`: linear in ln t between the
+// two samples around the crossing; NaN when they never do.
+double crossing_time(const uint64_t* t, const double* c, uint32_t n, double level)
+{
+    for (uint32_t j = 1; j < n; ++j) {
+        if (c[j] <= level && level < c[j - 1]) {
+            const double x0 = std::log((double)t[j - 1]), x1 = std::log((double)t[j]);
+            return std::exp(x0 + (x1 - x0) * (c[j - 1] - level) / (c[j - 1] - c[j]));
+        }
+    }
+    return std::numeric_limits<double>::quiet_NaN();
+}
+
+}  // namespace
+
+int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn* out)
+{
+    if (!runs || !out || n_runs == 0 || n_molecules == 0) return fail(MC_EINVAL, "bad arguments");
+    std::memset(out, 0, sizeof *out);
+    const uint32_t n = runs[0].n_c2;
+    if (n > MC_C2_MAX) return fail(MC_EINVAL, "n_c2 above %d", MC_C2_MAX);
+    for (size_t r = 1; r < n_runs; ++r) {
+        if (runs[r].n_c2 != n) return fail(MC_EINVAL, "run %zu has %u samples, run 0 %u", r, runs[r].n_c2, n);
+        for (uint32_t j = 0; j < n; ++j)
+            if (runs[r].c2_sweep[j] != runs[0].c2_sweep[j])
+                return fail(MC_EINVAL, "run %zu samples other sweeps than run 0", r);
+    }
+    out->n_times = n;
+    out->n_runs = (uint32_t)n_runs;
+    const double R = (double)n_runs, M = (double)n_molecules;
+    for (uint32_t j = 0; j < n; ++j) {
+        out->t[j] = runs[0].c2_sweep[j];
+        double m[3] = {0, 0, 0}, m2[3] = {0, 0, 0}, sq[3] = {0, 0, 0}, cross = 0.0;
+        for (size_t r = 0; r < n_runs; ++r) {
+            const mc_obs& o = runs[r];
+            const double v[3] = {o.c2[j], o.fs[j], o.fs_cm[j]};
+            const double q[3] = {o.c2_sq[j], o.fs_sq[j], o.fs_cm_sq[j]};
+            for (int a = 0; a < 3; ++a) {
+                m[a] += v[a];
+                m2[a] += v[a] * v[a];
+                sq[a] += q[a];
+            }
+            cross += o.c2_fs_cm[j];
+        }
+        double chi[3], self[3];
+        const double npart[3] = {M, 3.0 * M, M};
+        for (int a = 0; a < 3; ++a) {
+            m[a] /= R;
+            chi[a] = npart[a] * (m2[a] / R - m[a] * m[a]);
+            self[a] = sq[a] / R - m[a] * m[a];
+        }
+        out->c2[j] = m[0]; out->fs[j] = m[1]; out->fs_cm[j] = m[2];
+        out->chi4_c2[j] = chi[0]; out->chi4_fs[j] = chi[1]; out->chi4_fs_cm[j] = chi[2];
+        out->chi4s_c2[j] = self[0]; out->chi4s_fs[j] = self[1]; out->chi4s_fs_cm[j] = self[2];
+        out->rho[j] = (cross / R - m[0] * m[2]) / std::sqrt(self[0] * self[2]);
+    }
+    const double e1 = std::exp(-1.0);
+    out->tau_c2 = crossing_time(out->t, out->c2, n, e1);
+    out->tau_fs = crossing_time(out->t, out->fs, n, e1);
+    out->tau_fs_cm = crossing_time(out->t, out->fs_cm, n, e1);
+    return MC_OK;
+}
+
 // ------------------------------------------------------------------ batches --
 
-int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc_batch** out)
+namespace {
+
+// The batch's device slot tables in the caller's buffer, double-buffered:
+// per parity [resident | non-resident | events] x max_slots Slots, max_slots
+// SpreadSlots, max_slots Slots of the multi-workgroup engine's events.
+struct BatchLayout {
+    size_t slots[2], spread[2], ev2[2], total;
+};
+
+BatchLayout batch_layout(uint32_t max_slots)
 {
-    if (!out || max_slots == 0) return fail(MC_EINVAL, "bad arguments");
+    BatchLayout l{};
+    size_t o = 0;
+    for (int i = 0; i < 2; ++i) {
+        l.slots[i] = o;  o = al(o + 3 * sizeof(Slot) * max_slots);
+        l.spread[i] = o; o = al(o + sizeof(SpreadSlot) * max_slots);
+        l.ev2[i] = o;    o = al(o + sizeof(Slot) * max_slots);
+    }
+    l.total = o;
+    return l;
+}
+
+constexpr uint32_t kMaxBatchSlots = 1u << 16;
+
+}  // namespace
+
+int mc_batch_required_bytes(uint32_t max_slots, size_t* bytes)
+{
+    if (!bytes || max_slots == 0 || max_slots > kMaxBatchSlots)
+        return fail(MC_EINVAL, "max_slots must be in [1, %u] and bytes non-null", kMaxBatchSlots);
+    *bytes = batch_layout(max_slots).total;
+    return MC_OK;
+}
+
+int mc_batch_create(uint32_t max_slots, uint32_t precision, void* device_buf, size_t buf_bytes,
+                    void* hip_stream, void* hip_stream_aux, mc_batch** out)
+{
+    if (!out) return fail(MC_EINVAL, "null output handle");
+    *out = nullptr;
+    if (max_slots == 0 || max_slots > kMaxBatchSlots)
+        return fail(MC_EINVAL, "max_slots must be in [1, %u]", kMaxBatchSlots);
     if (precision != MC_FP64 && precision != MC_FP32_DE) return fail(MC_EINVAL, "bad precision");
+    if (!device_buf) return fail(MC_EINVAL, "null device buffer");
+    if (((uintptr_t)device_buf & 255u) != 0) return fail(MC_EINVAL, "device buffer must be 256-byte aligned");
+    const BatchLayout lay = batch_layout(max_slots);
+    if (buf_bytes < lay.total)
+        return fail(MC_ENOMEM, "device buffer of %zu bytes, %zu needed", buf_bytes, lay.total);
     mc_batch* b = new mc_batch();
     b->max_slots = max_slots;
     b->precision = precision;
@@ -973,18 +1119,20 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
         b->copied2[i] = nullptr;
         b->pending2[i] = false;
     }
+    uint8_t* dbuf = (uint8_t*)device_buf;
     for (int i = 0; i < 2; ++i) {
-        // slot tables: one per residency class, double-buffered
-        if (hipMalloc((void**)&b->dev_slots[i], 3 * sizeof(Slot) * max_slots) != hipSuccess ||
-            hipHostMalloc((void**)&b->host_slots[i], 3 * sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        // slot tables: one per residency class, double-buffered; the device
+        // copies in the caller's buffer, their pinned host staging owned here
+        b->dev_slots[i] = (Slot*)(dbuf + lay.slots[i]);
+        b->dev_spread[i] = (SpreadSlot*)(dbuf + lay.spread[i]);
+        b->dev_ev2[i] = (Slot*)(dbuf + lay.ev2[i]);
+        if (hipHostMalloc((void**)&b->host_slots[i], 3 * sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&b->copied[i], hipEventDisableTiming) != hipSuccess ||
-            hipMalloc((void**)&b->dev_spread[i], sizeof(SpreadSlot) * max_slots) != hipSuccess ||
             hipHostMalloc((void**)&b->host_spread[i], sizeof(SpreadSlot) * max_slots, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&b->dev_ev2[i], sizeof(Slot) * max_slots) != hipSuccess ||
             hipHostMalloc((void**)&b->host_ev2[i], sizeof(Slot) * max_slots, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&b->copied2[i], hipEventDisableTiming) != hipSuccess) {
             mc_batch_destroy(b);
-            return fail(MC_EDEVICE, "could not allocate the slot tables");
+            return fail(MC_EDEVICE, "could not allocate the host staging of the slot tables");
         }
     }
     for (int c = 0; c < 3; ++c)
@@ -992,11 +1140,11 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* hip_stream, mc
             mc_batch_destroy(b);
             return fail(MC_EDEVICE, "could not create the timing events");
         }
-    if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->go, hipEventDisableTiming) != hipSuccess ||
+    b->stream2 = hip_stream_aux ? (hipStream_t)hip_stream_aux : b->stream;
+    if (hipEventCreateWithFlags(&b->go, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
         mc_batch_destroy(b);
-        return fail(MC_EDEVICE, "could not create the second stream");
+        return fail(MC_EDEVICE, "could not create the stream events");
     }
     if (spread_max_blocks(precision == MC_FP64, &b->spread_max) != hipSuccess) {
         (void)hipGetLastError();
@@ -1306,12 +1454,9 @@ void mc_batch_destroy(mc_batch* b)
         if (s) s->batch = nullptr;
     if (b->stream2) (void)hipStreamSynchronize(b->stream2);
     for (int i = 0; i < 2; ++i) {
-        if (b->dev_slots[i]) (void)hipFree(b->dev_slots[i]);
         if (b->host_slots[i]) (void)hipHostFree(b->host_slots[i]);
         if (b->copied[i]) (void)hipEventDestroy(b->copied[i]);
-        if (b->dev_spread[i]) (void)hipFree(b->dev_spread[i]);
         if (b->host_spread[i]) (void)hipHostFree(b->host_spread[i]);
-        if (b->dev_ev2[i]) (void)hipFree(b->dev_ev2[i]);
         if (b->host_ev2[i]) (void)hipHostFree(b->host_ev2[i]);
         if (b->copied2[i]) (void)hipEventDestroy(b->copied2[i]);
     }
@@ -1321,7 +1466,6 @@ void mc_batch_destroy(mc_batch* b)
     }
     if (b->go) (void)hipEventDestroy(b->go);
     if (b->done) (void)hipEventDestroy(b->done);
-    if (b->stream2) (void)hipStreamDestroy(b->stream2);
     delete b;
 }
 

@@ -57,6 +57,7 @@ struct Stats {
     uint64_t exits;
     uint64_t pair_terms;
     uint64_t pair_tests;
+    uint64_t near_overflows;  // cells whose near list overflowed (every stencil molecule evaluated)
     double e_sum;
     double e_sumsq;
     uint32_t n_e;

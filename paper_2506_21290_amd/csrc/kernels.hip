@@ -834,7 +834,7 @@ __device__ void build_cells(const Ctx<Real, kRes>& C, double hx, double hy, doub
 
 // Per-wave counters, kept in registers for the whole launch.
 struct WaveCount {
-    uint32_t att0, att1, att2, acc0, acc1, acc2, exits;
+    uint32_t att0, att1, att2, acc0, acc1, acc2, exits, overflows;
     uint64_t terms, tests;
     double e;  // accepted dE of the current sweep, in trial order
 };
@@ -1577,6 +1577,7 @@ __device__ void run_phase(const Ctx<Real, kRes>& C, const PropRec* props, int co
         const uint32_t nnear = gather_near<Real, kRes, false>(C, P, nseg, total, bx0, by0, bz0, 0u, 0u,
                                                              W, StageLds<Real>{}, overflow);
         const NearRegs nr = near_regs(W.near, nnear, overflow);
+        wc.overflows += overflow ? 1u : 0u;
         wc.e = 0.0;
         cell_trials<Real, kRes, false>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0, nr,
                                        overflow, nseg, total, nullptr, W, wc);
@@ -1755,6 +1756,8 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
         if (wc.exits) atomicAdd((unsigned long long*)&st->exits, (unsigned long long)wc.exits);
         if (wc.terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)wc.terms);
         if (wc.tests) atomicAdd((unsigned long long*)&st->pair_tests, (unsigned long long)wc.tests);
+        if (wc.overflows)
+            atomicAdd((unsigned long long*)&st->near_overflows, (unsigned long long)wc.overflows);
     }
     __syncthreads();
     if (tid == 0) {
@@ -1905,9 +1908,12 @@ __device__ bool sys_sync(SysBarrier& B, uint32_t* fault, uint32_t* flag)
         uint32_t bad = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(B.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the counter may wrap in a long launch: compare the signed distance
+        // (the workgroups are never 2^31 increments apart)
         const uint32_t target = B.epoch * B.nblk;
         uint32_t spins = 0;
-        while (__hip_atomic_load(B.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while ((int32_t)(__hip_atomic_load(B.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                         target) < 0) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins >= B.polls) {
                 bad = 1;
@@ -2066,6 +2072,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
                     const uint32_t ns = gather_near<Real, false, true>(C, P, nseg, total, bx0, by0, bz0,
                                                                        cbeg, ccnt, W, S, overflow);
                     const NearRegs nr = near_regs(W.near, ns, overflow);
+                    wc.overflows += overflow ? 1u : 0u;
                     wc.e = 0.0;
                     cell_trials<Real, false, true>(C, V, props, sweep, P, cbeg, ccnt, bx0, by0, bz0,
                                                    nr, overflow, nseg, total, S.own, W, wc);
@@ -2103,6 +2110,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
         if (wc.exits) atomicAdd((unsigned long long*)&st->exits, (unsigned long long)wc.exits);
         if (wc.terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)wc.terms);
         if (wc.tests) atomicAdd((unsigned long long*)&st->pair_tests, (unsigned long long)wc.tests);
+        if (wc.overflows)
+            atomicAdd((unsigned long long*)&st->near_overflows, (unsigned long long)wc.overflows);
     }
     if (bid == 0 && tid == 0) {
         st->sweep = sweep;

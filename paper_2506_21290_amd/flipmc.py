@@ -7,9 +7,11 @@ a handle plus its torch buffer.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import weakref
 
 import numpy as np
 
@@ -30,9 +32,9 @@ EXPORTED = [
     "mc_init_system", "mc_sweep",
     "mc_energy", "mc_observables", "mc_samples", "mc_reset_observables", "mc_get_state",
     "mc_set_state", "mc_decision_log", "mc_timing_enable", "mc_timing_read", "mc_destroy",
-    "mc_last_error", "mc_batch_create",
+    "mc_last_error", "mc_batch_required_bytes", "mc_batch_create",
     "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
-    "mc_batch_set_workgroups",
+    "mc_batch_set_workgroups", "mc_dynamics",
 ]
 
 
@@ -79,6 +81,7 @@ class mc_obs(C.Structure):
         ("exits", C.c_uint64),
         ("pair_terms", C.c_uint64),
         ("pair_tests", C.c_uint64),
+        ("near_overflows", C.c_uint64),
         ("e_acc", C.c_double),
         ("e_resum", C.c_double),
         ("drift", C.c_double),
@@ -104,6 +107,24 @@ class mc_obs(C.Structure):
         ("fs_cm_sq", C.c_double * MC_C2_MAX),
         ("c2_fs_cm", C.c_double * MC_C2_MAX),
         ("fs_sq", C.c_double * MC_C2_MAX),
+        ("gofr_norm_all", C.c_double * MC_GOFR_MAX_BINS),
+        ("gofr_norm_inter", C.c_double * MC_GOFR_MAX_BINS),
+    ]
+
+
+class mc_dyn(C.Structure):
+    _fields_ = [
+        ("n_times", C.c_uint32),
+        ("n_runs", C.c_uint32),
+        ("t", C.c_uint64 * MC_C2_MAX),
+        ("c2", C.c_double * MC_C2_MAX), ("fs", C.c_double * MC_C2_MAX),
+        ("fs_cm", C.c_double * MC_C2_MAX),
+        ("chi4_c2", C.c_double * MC_C2_MAX), ("chi4_fs", C.c_double * MC_C2_MAX),
+        ("chi4_fs_cm", C.c_double * MC_C2_MAX),
+        ("chi4s_c2", C.c_double * MC_C2_MAX), ("chi4s_fs", C.c_double * MC_C2_MAX),
+        ("chi4s_fs_cm", C.c_double * MC_C2_MAX),
+        ("rho", C.c_double * MC_C2_MAX),
+        ("tau_c2", C.c_double), ("tau_fs", C.c_double), ("tau_fs_cm", C.c_double),
     ]
 
 
@@ -158,7 +179,8 @@ def lib():
         L.mc_destroy.argtypes = [vp]
         L.mc_destroy.restype = None
         L.mc_last_error.restype = C.c_char_p
-        L.mc_batch_create.argtypes = [C.c_uint32, C.c_uint32, vp, C.POINTER(vp)]
+        L.mc_batch_required_bytes.argtypes = [C.c_uint32, szp]
+        L.mc_batch_create.argtypes = [C.c_uint32, C.c_uint32, vp, C.c_size_t, vp, vp, C.POINTER(vp)]
         L.mc_batch_add.argtypes = [vp, vp, C.c_uint64, u32p]
         L.mc_batch_run.argtypes = [vp, C.c_uint64, u32p]
         L.mc_batch_poll.argtypes = [vp, u32p, C.POINTER(vp), C.c_size_t, szp]
@@ -166,6 +188,7 @@ def lib():
         L.mc_batch_set_workgroups.argtypes = [vp, C.c_uint32]
         L.mc_batch_destroy.argtypes = [vp]
         L.mc_batch_destroy.restype = None
+        L.mc_dynamics.argtypes = [C.POINTER(mc_obs), C.c_size_t, C.c_uint32, C.POINTER(mc_dyn)]
         _lib = L
     return _lib
 
@@ -173,6 +196,34 @@ def lib():
 def _check(rc):
     if rc != MC_OK:
         raise McError(rc, lib().mc_last_error().decode())
+
+
+# Systems and batches still open at interpreter exit are closed by one atexit
+# hook, registered after torch is imported (atexit runs last-in first-out, so
+# the hook runs before torch's own and before the HIP runtime is torn down):
+# batches first, then systems, newest first.  Each object holds its own
+# reference to the library, so closing never depends on module globals that
+# interpreter shutdown may already have cleared.
+_live = []
+_hook = []
+
+
+def _track(obj):
+    if not _hook:
+        atexit.register(_close_all)
+        _hook.append(True)
+    _live.append(weakref.ref(obj))
+
+
+def _close_all():
+    objs = [r() for r in reversed(_live)]
+    for o in objs:
+        if isinstance(o, Batch):
+            o.close()
+    for o in objs:
+        if isinstance(o, System):
+            o.close()
+    _live.clear()
 
 
 def _ptr(a, ct):
@@ -218,6 +269,23 @@ def mc_required_bytes(p: mc_params) -> int:
     return n.value
 
 
+def mc_dynamics(runs, n_molecules) -> dict:
+    """Ensemble means, chi_4 (Eq. 10), chi_4^self (Eq. 11), rho (Eq. 13) and
+    the 1/e relaxation times of independent runs (mc_obs structures)."""
+    arr = (mc_obs * len(runs))(*runs)
+    d = mc_dyn()
+    _check(lib().mc_dynamics(arr, len(runs), int(n_molecules), C.byref(d)))
+    n = d.n_times
+    out = {"t": np.array(d.t[:n], dtype=np.uint64), "n_runs": d.n_runs}
+    for k in ("c2", "fs", "fs_cm", "chi4_c2", "chi4_fs", "chi4_fs_cm", "chi4s_c2", "chi4s_fs",
+              "chi4s_fs_cm", "rho"):
+        out[k] = np.array(getattr(d, k)[:n])
+    for k in ("tau_c2", "tau_fs", "tau_fs_cm"):
+        v = getattr(d, k)
+        out[k] = None if math.isnan(v) else v
+    return out
+
+
 def _stream_handle(stream):
     import torch
 
@@ -245,16 +313,24 @@ class System:
             quat = np.ascontiguousarray(quat, dtype=np.float64).reshape(-1)
             types = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
             args = (_ptr(com, C.c_double), _ptr(quat, C.c_double), _ptr(types, C.c_uint8))
-        _check(lib().mc_init_system(C.byref(params), *args, C.c_void_p(self.buffer.data_ptr()),
-                                    nbytes, self._stream_handle, C.byref(h)))
+        self._lib = lib()
+        _check(self._lib.mc_init_system(C.byref(params), *args, C.c_void_p(self.buffer.data_ptr()),
+                                        nbytes, self._stream_handle, C.byref(h)))
         self.h = h
+        self._log = None
+        _track(self)
+
+    def close(self):
+        """Wait for the system's kernels, release its handle, then its buffer."""
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self._lib.mc_destroy(h)  # synchronises its stream (and its batch's)
+        self.h = None
+        self.buffer = None
         self._log = None
 
     def __del__(self):
-        h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().mc_destroy(h)
-            self.h = None
+        self.close()
 
     def sweep(self, n=1):
         _check(lib().mc_sweep(self.h, int(n)))
@@ -264,9 +340,14 @@ class System:
         _check(lib().mc_energy(self.h, C.byref(e), C.byref(em), C.byref(d)))
         return e.value, em.value, d.value
 
-    def observables(self) -> dict:
+    def obs_struct(self) -> mc_obs:
+        """The accumulators as the C structure (the input of mc_dynamics)."""
         o = mc_obs()
-        _check(lib().mc_observables(self.h, C.byref(o)))
+        _check(self._lib.mc_observables(self.h, C.byref(o)))
+        return o
+
+    def observables(self) -> dict:
+        o = self.obs_struct()
         nb = o.gofr_nbins
         return {
             "sweep": o.sweep,
@@ -275,6 +356,7 @@ class System:
             "exits": o.exits,
             "pair_terms": o.pair_terms,
             "pair_tests": o.pair_tests,
+            "near_overflows": o.near_overflows,
             "e_acc": o.e_acc,
             "e_resum": o.e_resum,
             "drift": o.drift,
@@ -289,6 +371,8 @@ class System:
             "gofr_rmax": o.gofr_rmax,
             "gofr_all": np.array(o.gofr_all[:nb], dtype=np.uint64),
             "gofr_inter": np.array(o.gofr_inter[:nb], dtype=np.uint64),
+            "gofr_norm_all": np.array(o.gofr_norm_all[:nb]),
+            "gofr_norm_inter": np.array(o.gofr_norm_inter[:nb]),
             "c2_sweep": np.array(o.c2_sweep[: o.n_c2], dtype=np.uint64),
             "c2": np.array(o.c2[: o.n_c2]),
             "fs": np.array(o.fs[: o.n_c2]),
@@ -363,19 +447,38 @@ class Batch:
     """Several systems advanced together, one time slice per run: one workgroup
     each, spare workgroups to the large systems with the most work left."""
 
-    def __init__(self, max_slots, precision=MC_FP32_DE, stream=None):
+    def __init__(self, max_slots, precision=MC_FP32_DE, stream=None, aux_stream=None,
+                 device="cuda"):
+        import torch
+
         self._stream_handle, self.stream = _stream_handle(stream)
+        # the multi-workgroup launches overlap the others on a second stream
+        # (default priority, like every stream here)
+        self.aux_stream = aux_stream if aux_stream is not None else torch.cuda.Stream()
+        self._lib = lib()
+        n = C.c_size_t()
+        _check(self._lib.mc_batch_required_bytes(int(max_slots), C.byref(n)))
+        self.buffer = torch.empty(n.value, dtype=torch.uint8, device=device)
         h = C.c_void_p()
-        _check(lib().mc_batch_create(int(max_slots), int(precision), self._stream_handle, C.byref(h)))
+        _check(self._lib.mc_batch_create(int(max_slots), int(precision),
+                                         C.c_void_p(self.buffer.data_ptr()), n.value,
+                                         self._stream_handle, C.c_void_p(self.aux_stream.cuda_stream),
+                                         C.byref(h)))
         self.h = h
         self.max_slots = max_slots
         self.members = {}
+        _track(self)
 
-    def __del__(self):
+    def close(self):
+        """Wait for the batch's streams and release it (its systems stay open)."""
         h = getattr(self, "h", None)
         if h is not None and h.value:
-            lib().mc_batch_destroy(h)
-            self.h = None
+            self._lib.mc_batch_destroy(h)
+        self.h = None
+        self.buffer = None
+
+    def __del__(self):
+        self.close()
 
     def add(self, system: System, n_sweeps) -> int:
         slot = C.c_uint32()

@@ -25,7 +25,6 @@ any object that offers the same few methods.
 from __future__ import annotations
 
 import collections
-import math
 import time
 from dataclasses import dataclass, field
 
@@ -60,18 +59,6 @@ def job_params(job, precision):
         seed=job.seed, colours_per_axis=k, cells_per_side=nc, resum_interval=100,
         obs_interval=10, gofr_interval=gofr_every, obs_start=S // 2,
         max_samples=max(16, S // 10 + 2))
-
-
-def gofr_normalised(obs, n_sites, box):
-    """Eq. (3): counts / (frames N rho 4 pi r^2 dr) with the exact shell volume."""
-    nb = len(obs["gofr_all"])
-    dr = obs["gofr_dr"]
-    r = np.arange(nb + 1) * dr
-    shell = 4.0 * math.pi / 3.0 * (r[1:] ** 3 - r[:-1] ** 3)
-    rho = n_sites / box ** 3
-    frames = max(1, obs["n_gofr_frames"])
-    g = obs["gofr_all"] / (frames * n_sites * rho * shell)
-    return 0.5 * (r[1:] + r[:-1]), g
 
 
 class GpuBackend:
@@ -126,8 +113,8 @@ class GpuBackend:
 
     def result(self, job, s):
         obs = s.observables()
-        box = flipmc.mc_geometry(s.params)[0]
-        r, g = gofr_normalised(obs, 3 * job.n_molecules, box)
+        g = obs["gofr_norm_all"]  # Eq. (3), normalised by the library
+        r = (np.arange(len(g)) + 0.5) * obs["gofr_dr"]
         n_e = max(1, obs["n_energy_samples"])
         att, acc = obs["attempts"], obs["accepts"]
         return dict(energy_per_molecule=obs["energy_sum"] / n_e, gofr_r=r, gofr=g,

@@ -87,3 +87,22 @@ def test_required_bytes_grows_with_state():
     c = flipmc.mc_required_bytes(flipmc.mc_params_default(n_molecules=8000))
     assert a < b < c
     assert a < 1 << 20
+
+
+def test_box_must_hold_twice_the_reach():
+    # The engine forms pair terms from the nearest image of two centres plus
+    # the site offsets; that is every site pair's nearest image only when
+    # L >= 2 (W + 2 d_max), W = 2^(1/6) 1.1 + 2 b*/sqrt(3).  27 molecules at
+    # density 1.2 (L = 4.07, which k = 3, n_c = 3 would otherwise accept) and
+    # 48 (L = 4.93) are rejected; 56 (L = 5.19) and 64 (L = 5.43) are not.
+    W = 2 ** (1 / 6) * 1.1 + 2 * 0.9608971989592554 / 3 ** 0.5
+    for M, ok in [(27, False), (48, False), (56, True), (64, True)]:
+        L = (3 * M / 1.2) ** (1 / 3)
+        assert (L >= 2 * (W + 0.2)) == ok
+        p = flipmc.mc_params_default(n_molecules=M, colours_per_axis=3, cells_per_side=3)
+        if ok:
+            assert flipmc.mc_geometry(p)[0] == pytest.approx(L, rel=1e-14)
+        else:
+            with pytest.raises(flipmc.McError) as e:
+                flipmc.mc_geometry(p)
+            assert e.value.code == flipmc.MC_EGEOM

@@ -1,0 +1,82 @@
+"""Statistical parity: the FP32 engine samples the oracle's distribution.
+
+64 molecules at T = 3 (the highest temperature the paper studies), 16
+independent seeds on each side: the engine with FP32 energy differences
+(seeds 1 - 16) and the serial FP64 oracle (seeds 101 - 116), so the two sides
+are independent chains.  Each runs 200 sweeps from its lattice start, takes
+the observable origin there and runs 1000 more: E/M every 10 sweeps, g(r)
+(Eq. 3, intermolecular pairs) every 50, C_2 (Eq. 7) at t = 1, 2, 5, ... after
+the origin.  The means over seeds of E/M, of g(r) over the first-peak window
+r in [0.9, 1.3) and of C_2 at t = 20 agree within twice the standard error of
+their difference.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle  # noqa: E402
+from paper_2506_21290_amd import flipmc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+M, T, K, NC = 64, 3.0, 2, 2
+EQ, PROD, DR = 200, 1000, 0.02
+PEAK = (0.9, 1.3)
+T_C2 = 20
+
+
+def _window(g, dr):
+    r = (np.arange(len(g)) + 0.5) * dr
+    sel = (r >= PEAK[0]) & (r < PEAK[1])
+    return float(np.mean(g[sel]))
+
+
+def engine_run(seed):
+    p = flipmc.mc_params_default(n_molecules=M, temperature=T, colours_per_axis=K, cells_per_side=NC,
+                                 seed=seed, precision=flipmc.MC_FP32_DE, resum_interval=100,
+                                 obs_interval=10, gofr_interval=50, obs_start=0, gofr_dr=DR,
+                                 max_samples=256)
+    s = flipmc.System(p)
+    s.sweep(EQ)
+    s.reset_observables()
+    s.sweep(PROD)
+    o = s.observables()
+    em = o["energy_sum"] / o["n_energy_samples"]
+    c2 = dict(zip([int(t) for t in o["c2_sweep"]], o["c2"]))
+    return em, _window(o["gofr_norm_inter"], DR), c2[T_C2]
+
+
+def oracle_run(seed):
+    o = oracle.System(oracle.Params(n_molecules=M, temperature=T, colours_per_axis=K,
+                                    cells_per_side=NC, seed=seed))
+    o.sweep_checkerboard(EQ)
+    u0, kref = o.orientation_ref()
+    nb, _ = oracle.gofr_bins(o.box, DR)
+    ca = np.zeros(nb, dtype=np.uint64)
+    ci = np.zeros(nb, dtype=np.uint64)
+    es, frames, c2 = [], 0, None
+    for t in range(1, PROD + 1):
+        o.sweep_checkerboard(1)
+        if t % 10 == 0:
+            es.append(o.energy() / M)
+        if t % 50 == 0:
+            o.gofr_accumulate(ca, ci, dr=DR)
+            frames += 1
+        if t == T_C2:
+            c2 = o.c2(u0, kref)
+    g = oracle.gofr_normalise(ci, frames, 3 * M, o.box, DR)
+    return float(np.mean(es)), _window(g, DR), c2
+
+
+def test_fp32_engine_matches_oracle_within_two_sigma():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eng = np.array([engine_run(seed) for seed in range(1, 17)])
+    ora = np.array([oracle_run(seed) for seed in range(101, 117)])
+    for i, name in enumerate(["E/M", "g(r) first peak", "C_2(20)"]):
+        a, b = eng[:, i], ora[:, i]
+        se = np.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+        diff = a.mean() - b.mean()
+        print(f"{name}: engine {a.mean():.5f} oracle {b.mean():.5f} diff {diff:.2e} se {se:.2e}", flush=True)
+        assert se > 0 and abs(diff) <= 2.0 * se, name

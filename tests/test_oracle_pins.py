@@ -161,6 +161,8 @@ def test_lattice_start(oracle_mod):
     assert np.array_equal(st["com"], expect)
     q = st["quat"]
     assert np.allclose((q * q).sum(1), 1.0, atol=1e-15)
+    # the exact map from the tag-2 Philox draws, rebuilt by the numpy code
+    assert np.allclose(q, brute.lattice_quaternions(1000, 1), rtol=0, atol=1e-15)
     # Haar measure: each quaternion component has E[q_i^2] = 1/4, and a rotated
     # axis is uniform on the sphere (mean 0, second moment 1/3).
     assert np.allclose((q * q).mean(0), 0.25, atol=0.03)
@@ -224,8 +226,8 @@ def _replay(oracle_mod, p, n_sweeps, schedule="checkerboard"):
             if schedule == "random":
                 g = rp.draw(int(rec["slot"]), sw, 4)
                 assert m == min(int(p.n_molecules * brute.uniform53_left(g[0], g[1])), p.n_molecules - 1)
-            move, new, u_acc = rp.propose(com, quat, types, m, int(rec["slot"]), sw,
-                                          schedule == "checkerboard")
+            move, new, u_acc, moved = rp.propose(com, quat, types, m, int(rec["slot"]), sw,
+                                                 schedule == "checkerboard")
             assert rec["move"] == move
             assert rec["t_log_u"] == pytest.approx(p.temperature * math.log(u_acc), rel=1e-14)
             if new is None:
@@ -234,6 +236,9 @@ def _replay(oracle_mod, p, n_sweeps, schedule="checkerboard"):
             assert rec["exited"] == 0
             e_new = rp.energy(*new)
             de = e_new - e
+            # the interacting site-pair terms the trial evaluated: moved sites
+            # against all other sites, before and after the move
+            assert rec["pair_terms"] == rp.pairs(com, quat, types, m, moved) + rp.pairs(*new, m, moved)
             scale = abs(rec["scale"]) + abs(e) * 1e-3
             assert abs(rec["delta_e"] - de) <= 1e-10 * scale + 1e-10, (sw, m, move)
             accept = de <= 0 or p.temperature * math.log(u_acc) < -de
@@ -430,10 +435,8 @@ def test_ideal_gas_limit(oracle_mod):
     for _ in range(frames):
         s.sweep_checkerboard(5)
         s.gofr_accumulate(ca, ci, dr=0.05)
-    N, rho = 3 * 216, 1.2
+    g = oracle_mod.gofr_normalise(ci, frames, 3 * 216, s.box, 0.05)
     r = np.arange(nb + 1) * 0.05
-    shell = 4 * np.pi / 3 * (r[1:] ** 3 - r[:-1] ** 3)
-    g = ci / (frames * N * rho * shell)
     sel = r[:-1] >= 1.0
     assert abs(g[sel].mean() - 1.0) < 0.03
     # intramolecular pairs: 6 ordered pairs per molecule per frame at r = b*
@@ -516,3 +519,14 @@ def test_invalid_parameters_are_rejected(oracle_mod):
     with pytest.raises(ValueError):  # not a cube: no lattice start
         oracle_mod.System(oracle_mod.Params(n_molecules=100, temperature=3.0,
                                             colours_per_axis=2, cells_per_side=2))
+
+
+def test_gofr_normalisation_of_a_uniform_histogram(oracle_mod):
+    # counts equal to frames * N * rho * shell volume give g = 1 (Eq. 3);
+    # no frames give zeros
+    box, n_sites, frames, dr, nb = 10.0, 300, 4, 0.05, 100
+    r = np.arange(nb + 1) * dr
+    shell = 4 * np.pi / 3 * (r[1:] ** 3 - r[:-1] ** 3)
+    counts = frames * n_sites * (n_sites / box ** 3) * shell
+    assert np.allclose(oracle_mod.gofr_normalise(counts, frames, n_sites, box, dr), 1.0, rtol=1e-14)
+    assert not oracle_mod.gofr_normalise(counts, 0, n_sites, box, dr).any()

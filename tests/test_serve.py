@@ -116,14 +116,3 @@ def test_replica_set():
     assert len(jobs) == 256 and {j.n_molecules for j in jobs} == set(workloads.REPLICA_SIZES)
     assert [j.seed for j in jobs] == list(range(1, 257))
     assert all(0.75 <= j.temperature <= 3.0 for j in jobs)
-
-
-def test_gofr_normalisation_of_a_uniform_histogram():
-    # counts equal to frames * N * rho * shell volume give g = 1
-    box, n_sites, frames, dr, nb = 10.0, 300, 4, 0.05, 100
-    r = np.arange(nb + 1) * dr
-    shell = 4 * np.pi / 3 * (r[1:] ** 3 - r[:-1] ** 3)
-    counts = frames * n_sites * (n_sites / box ** 3) * shell
-    obs = {"gofr_all": counts, "gofr_dr": dr, "n_gofr_frames": frames}
-    rr, g = serve.gofr_normalised(obs, n_sites, box)
-    assert np.allclose(g, 1.0) and rr[0] == pytest.approx(dr / 2)
