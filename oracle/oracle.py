@@ -16,6 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "flipmc_oracle.c")
+SOURCES = [SRC_PATH, os.path.join(HERE, "flex_oracle.c")]
 
 TRANSLATE, ROTATE, FLIP = 0, 1, 2
 
@@ -41,13 +42,14 @@ assert RECORD_DTYPE.itemsize == 56
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (serial, FP64, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH) or (
-        os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)
-    ):
+    stale = not os.path.exists(LIB_PATH) or any(
+        os.path.getmtime(LIB_PATH) < os.path.getmtime(f)
+        for f in SOURCES + [os.path.join(HERE, "flipmc_oracle.h"), os.path.join(HERE, "flex_oracle.h")])
+    if force or stale:
         subprocess.check_call(
             [
                 "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                "-fPIC", "-shared", SRC_PATH, "-o", LIB_PATH, "-lm",
+                "-fPIC", "-shared", *SOURCES, "-o", LIB_PATH, "-lm",
             ]
         )
     return LIB_PATH

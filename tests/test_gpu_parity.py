@@ -348,11 +348,13 @@ def test_observables_match_oracle():
 @pytest.mark.parametrize("engine", ["lds", "spread"])
 def test_fs_matches_oracle(engine):
     # F_s(q, t) of the sites and F_s^cm(q, t) of the centres (Sec. III.B,
-    # Eqs. 5 and 6) at the C_2 sample sweeps.  "lds": 64 molecules at a very
-    # high temperature with long steps, so centres cross the periodic boundary
-    # many times; "spread": 1000 molecules on the multi-workgroup engine.
+    # Eqs. 5 and 6) at the C_2 sample sweeps.  "lds": 125 molecules (the
+    # smallest lattice whose box holds twice the reach plus two long steps) at
+    # a very high temperature with long steps, so centres cross the periodic
+    # boundary many times; "spread": 1000 molecules on the multi-workgroup
+    # engine.
     if engine == "lds":
-        M, T, k, nc, seed, n = 64, 1e6, 2, 2, 5, 50
+        M, T, k, nc, seed, n = 125, 1e6, 2, 2, 5, 50
         kw = dict(p_flip=0.1, p_translate=0.8, max_displacement=0.35)
         flags, want_engine = 0, flipmc.MC_ENGINE_LDS
     else:
