@@ -293,6 +293,117 @@ void mc_destroy(mc_system* s);
 /* Message of the last failing call of this thread (never NULL). */
 const char* mc_last_error(void);
 
+/* ---- flexible molecules: the paper's own model and other bodies ----------- */
+
+/* The paper's molecule is not rigid (Sec. II.A): atoms A, B, C of diameters
+ * 0.9, 1, 1.1 joined by FENE bonds (Eq. 2) that cannot reach 1.5 sigma_ij,
+ * with the WCA potential of Eq. 1 between every pair of atoms, those of one
+ * molecule included.  Its outlook (Sec. VII) names squares and tetrahedra as
+ * further bodies for intramolecular swap moves; they are the same model with
+ * four atoms: a ring of four bonds, or all six pairs bonded, and four types of
+ * diameters evenly spaced over [0.9, 1.1].
+ *
+ * Monte Carlo (Sec. II.B): a timestep is N = n M attempts, here every atom
+ * once per sweep in a checkerboard over atom cells (a random shift of the
+ * grid per sweep, colours in order, ascending atom index in a cell).  An
+ * attempt is a flip of the atom's molecule with probability p_flip -- a
+ * permutation of its types at fixed positions, uniform over the 180 degree
+ * rotations of the ideal body (triangle: the median through atom q; square:
+ * the diagonal through atom 0, the one through atom 1, the bisector of edge
+ * 01, the bisector of edge 12; tetrahedron: the axes through the midpoints of
+ * edges 01, 02, 03) -- otherwise a translation of the atom, uniform in
+ * [-d, d)^3 and rejected when it leaves the atom's cell.  A bond reaching
+ * 1.5 sigma_ij has infinite energy: such a move is rejected.  All arithmetic
+ * is FP64.  The energy and E/M include the intramolecular terms. */
+enum { MC_TRIANGLE = 0, MC_SQUARE = 1, MC_TETRAHEDRON = 2 };
+
+typedef struct {
+    uint32_t geometry;         /* MC_TRIANGLE, MC_SQUARE or MC_TETRAHEDRON          */
+    uint32_t n_molecules;      /* M; the lattice start needs M = n^3               */
+    double   density;          /* atoms per unit volume, N / V, N = n M            */
+    double   temperature;      /* T > 0                                            */
+    double   sigma[4];         /* diameter of each type (3 used by triangles)      */
+    double   bond_length;      /* side of the ideal body at the lattice start;
+                                  <= 0 picks b*, the minimum of WCA + FENE of a
+                                  sigma_ij = 1 bond                                 */
+    double   p_flip;           /* probability that an attempt is a flip           */
+    double   max_displacement; /* translation: uniform in [-d, d) per component   */
+    uint64_t seed;             /* Philox4x32-10 key                                */
+    uint32_t colours_per_axis; /* k (>= 2); 0 = choose                             */
+    uint32_t cells_per_side;   /* n_c, multiple of k; 0 = choose                   */
+    uint32_t resum_interval;   /* sweeps between FP64 re-sums (0 = never)          */
+    uint32_t obs_interval;     /* sweeps between E/M samples (0 = never)           */
+    uint32_t gofr_interval;    /* sweeps between g(r) frames (0 = never)           */
+    uint32_t obs_start;        /* samples from this sweep after the origin on      */
+    uint32_t max_samples;      /* capacity of the E/M and drift sample arrays      */
+    uint32_t reserved;         /* 0                                                */
+    double   gofr_dr;          /* g(r) bin width; r_max = min(L/2, 5)              */
+    double   fs_q;             /* |q| of F_s over the atoms (Sec. III.B: 7.4)      */
+    double   fs_q_cm;          /* |q| of F_s^cm over the centres of mass (5.1)     */
+} mcf_params;
+
+typedef struct mcf_system mcf_system;
+
+/* Fill *p with the paper's values for `geometry` (Sec. II.A sizes and
+ * density 1.2, Sec. II.B p_flip = 0.2) and this engine's defaults (step 0.1,
+ * re-sum every 100 sweeps).  Never fails. */
+void mcf_params_default(mcf_params* p, uint32_t geometry);
+
+/* Box side L = (n M / density)^(1/3) and the decomposition (k, n_c): same-
+ * colour cells must be (k - 1) L / n_c >= 2 D + r_c apart (D the farthest two
+ * atoms of one molecule can be: one bond of at most 1.5 sigma_ij, two for the
+ * square's diagonal; r_c the largest WCA cut-off), cells at least r_c wide.
+ * MC_EGEOM when no decomposition fits or the box is below
+ * 2 (max(D, r_c) + 2 d).  Any output may be NULL. */
+int mcf_geometry(const mcf_params* p, double* box, uint32_t* colours_per_axis,
+                 uint32_t* cells_per_side);
+
+/* Bytes of device memory mcf_init_system needs.  Host only. */
+int mcf_required_bytes(const mcf_params* p, size_t* bytes);
+
+/* Create a system in device_buf (caller-owned, 256-byte aligned,
+ * >= mcf_required_bytes, must outlive the system).  pos and types NULL: the
+ * seeded lattice start (ideal bodies of side bond_length at simple-cubic
+ * sites, uniformly random orientations, types 0, 1, ... on atoms 0, 1, ...);
+ * otherwise host arrays pos[3 N] (xyz of atom n m + s) and types[N] (a
+ * permutation of 0 .. n-1 per molecule).  MC_ENONFINITE when a bond is
+ * stretched to its limit or atoms coincide; synchronises the stream. */
+int mcf_init_system(const mcf_params* p, const double* pos, const uint8_t* types, void* device_buf,
+                    size_t buf_bytes, void* hip_stream, mcf_system** out);
+
+/* Enqueue n timesteps of N attempts (Sec. II.B).  Asynchronous. */
+int mcf_sweep(mcf_system* s, uint64_t n_sweeps);
+
+/* FP64 total energy now (Eq. 1 over all atom pairs + Eq. 2 over the bonds, a
+ * fresh re-sum), E/M and the drift e_acc - E.  Synchronises. */
+int mcf_energy(mcf_system* s, double* e_total, double* e_per_molecule, double* drift);
+
+/* Accumulators as in mc_observables: attempts / accepts of translations
+ * (index MC_TRANSLATE) and flips (MC_FLIP), exits, pair terms, E/M moments,
+ * g(r) over atoms (Eq. 3, counts and normalised), C_2 (Eq. 7, the vector from
+ * the centre of mass to the atom that was of type B at the origin), F_s over
+ * atoms and F_s^cm over centres of mass (Eqs. 5-6).  The per-particle moments
+ * are not computed (zero).  Synchronises. */
+int mcf_observables(mcf_system* s, mc_obs* out);
+
+/* New observable origin (C_2 reference, unwrapped positions).  Asynchronous. */
+int mcf_reset_observables(mcf_system* s);
+
+/* Read / overwrite the state: host pos[3 N], types[N] as in mcf_init_system
+ * (NULL outputs skipped), the sweep counter and the accumulated energy (NaN =
+ * re-sum it).  Both synchronise. */
+int mcf_get_state(mcf_system* s, double* pos, uint8_t* types, uint64_t* sweep, double* e_acc);
+int mcf_set_state(mcf_system* s, const double* pos, const uint8_t* types, uint64_t sweep,
+                  double e_acc);
+
+/* Record every attempt of the next sweeps into a caller-owned DEVICE array of
+ * mc_move_record (record (sweep - first) * N + atom; `molecule` holds the
+ * atom, `axis` the flip's rotation, delta_e = +inf at a bond's limit). */
+int mcf_decision_log(mcf_system* s, void* device_records, size_t capacity);
+
+/* Wait for the system's stream and release its handle.  NULL is ignored. */
+void mcf_destroy(mcf_system* s);
+
 /* ---- analysis of independent runs ------------------------------------------ */
 
 /* Time correlations of n independent runs of one system (same M, same sample

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "capi.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "capi.hip", "flex.hip")]
 OUT = os.path.join(HERE, "libflipmc.so")
 
 HIPCC_FLAGS = [

@@ -33,6 +33,20 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
+}  // namespace
+
+namespace flipmc {
+
+int api_error(int code, const char* msg)
+{
+    g_err = msg;
+    return code;
+}
+
+}  // namespace flipmc
+
+namespace {
+
 #define HIPCHK(x)                                                                       \
     do {                                                                                \
         hipError_t e_ = (x);                                                            \

@@ -227,4 +227,7 @@ hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks);
 // launch_events(flags | kFlagParts, pad = n_blocks).
 hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t stream);
 
+// Record msg as the calling thread's last error (mc_last_error) and return code.
+int api_error(int code, const char* msg);
+
 }  // namespace flipmc

@@ -1,0 +1,1322 @@
+// flex.hip -- flip Monte Carlo of FLEXIBLE molecules on gfx950: the paper's
+// own model (Simon, Barrat & Berthier, Sec. II.A: three atoms A, B, C joined
+// by FENE bonds, Eq. 2, with the WCA potential of Eq. 1 between every pair of
+// atoms, intramolecular pairs included) and the other bodies of its outlook
+// (Sec. VII): squares (a ring of four bonds) and tetrahedra (six bonds).
+//
+// The moving unit is the atom.  A sweep attempts every atom once (a Monte
+// Carlo timestep of N attempts, Sec. II.B): with probability p_flip a flip of
+// the atom's molecule -- a permutation of the types of its atoms at fixed
+// positions, one of the 180 degree rotations of the ideal body -- otherwise a
+// translation of the atom, uniform in [-d, d)^3 and confined to its cell.
+//
+// Execution: one workgroup of 8 wave64s per system, the state in HBM (it stays
+// in L2).  Per sweep a random shift of a cubic cell grid over the atoms, a
+// counting sort into cells (ascending atom index inside each cell), then the
+// k^3 colours in order; the waves take the cells of a colour, and a wave runs
+// its cell's attempts one after another.  Same-colour cells are at least
+// (k - 1) w >= 2 D + r_c apart (D the largest distance two atoms of one
+// molecule can reach, r_c the largest cut-off), so no two attempts of a
+// colour touch the same pair term.  Per attempt the 64 lanes take the atoms of
+// the stencil cells (radius 1 for a translation, enough for the flipped
+// molecule's reach for a flip) and the lane-0 partial carries the
+// intramolecular terms; a DPP reduction in FP64 gives dE in a fixed order.  A
+// bond stretched to 1.5 sigma_ij or beyond makes dE infinite: the move is
+// rejected.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "flipmc.h"
+#include "wave.h"
+
+namespace flipmc {
+namespace {
+
+constexpr int kFxThreads = 512;
+constexpr int kFxWaves = kFxThreads / 64;
+constexpr int kFxSeg = 64;          // stencil row segments per attempt (radius <= 2: <= 50)
+constexpr uint32_t kFxParts = 1024;  // workgroups of the event kernel
+
+// Everything a workgroup needs about one system; in the system's buffer.
+struct FxDev {
+    uint32_t geometry, n, M, N;
+    uint32_t k, nc, ncell, nflip;
+    uint32_t seed_lo, seed_hi, r_trans, r_flip;
+    uint32_t bonded;  // bit 4 i + j: atoms i, j of a molecule are bonded
+    uint32_t resum_interval, obs_interval, gofr_interval, obs_start, max_samples, gofr_nbins;
+    uint32_t pad;
+    double L, invL, w, T, p_flip, dmax, rc2f;
+    double sigma[4];
+    double gofr_dr, gofr_rmax, fs_q, fs_q_cm;
+    uint8_t flips[4][4];  // new type of atom s = old type of atom flips[q][s]
+    double* pos;          // SoA [3][N], wrapped into [0, L)
+    uint8_t* type;        // [N]
+    int32_t* img;         // SoA [3][N] periodic images crossed by accepted translations
+    Stats* stats;
+    double* e_samples;
+    double* drift_samples;
+    uint64_t* gofr_all;
+    uint64_t* gofr_inter;
+    double* c2;
+    uint64_t* c2_sweep;
+    double* fs;
+    double* fs_cm;
+    double* u0;           // [3][M] orientation at the observable origin
+    uint8_t* kref;        // [M] atom the orientation follows
+    double* r0;           // [3][N] unwrapped atoms at the origin
+    double* rcm0;         // [3][M] unwrapped centres at the origin
+    uint32_t* cell_start; // [ncell + 1]
+    uint32_t* cell_list;  // [N] atoms sorted by cell, ascending inside a cell
+    uint32_t* cell_id;    // [N]
+    double* ecell;        // [ncell] accepted dE of each cell in the current sweep
+    double* part;         // [kFxParts] partial energies of the event kernel
+    MoveRecord* log;
+    uint64_t log_sweep0, log_sweeps;
+};
+
+__device__ __forceinline__ double fx_wrap(double x, double L) { return x - L * floor(x / L); }
+__device__ __forceinline__ double fx_mi(double d, double L, double invL) { return d - L * rint(d * invL); }
+
+__device__ __forceinline__ int fx_axis(double x, double h, const FxDev& D)
+{
+    int c = (int)floor(fx_wrap(x - h, D.L) / D.w);
+    c = c < 0 ? 0 : c;
+    return c >= (int)D.nc ? (int)D.nc - 1 : c;
+}
+
+__device__ __forceinline__ uint32_t fx_cell(double x, double y, double z, const double h[3], const FxDev& D)
+{
+    const uint32_t nc = D.nc;
+    return (uint32_t)fx_axis(x, h[0], D) +
+           nc * ((uint32_t)fx_axis(y, h[1], D) + nc * (uint32_t)fx_axis(z, h[2], D));
+}
+
+// Eq. (1) as (2 (s/r)^6 - 1)^2 below the cut-off, FP64 with a true division.
+__device__ __forceinline__ double fx_wca(double s2, double r2, double rc2f)
+{
+    if (!(r2 < rc2f * s2)) return 0.0;
+    const double x = s2 / r2;
+    const double t = 2.0 * x * x * x - 1.0;
+    return t * t;
+}
+
+// Eq. (2), infinite at or beyond 1.5 sigma_ij.
+__device__ __forceinline__ double fx_fene(double sig, double r2)
+{
+    const double lim2 = 2.25 * sig * sig;
+    if (!(r2 < lim2)) return __builtin_inf();
+    return -33.75 * log(1.0 - r2 / lim2);
+}
+
+struct FxCount {
+    uint32_t att_t, att_f, acc_t, acc_f, exits;
+    uint64_t terms;
+    double e;  // accepted dE of the current cell, in attempt order
+};
+
+// Per-wave LDS: the stencil's row segments.
+struct FxWaveLds {
+    uint32_t* seglo;
+    uint32_t* segoff;
+};
+
+// Row segments of the cells within radius r of cell (cx, cy, cz): rows along
+// x of one or two contiguous cell ranges (every cell once when the stencil
+// covers the whole axis).  Returns the number of segments; *total = atoms.
+__device__ int fx_segments(const FxDev& D, int cx, int cy, int cz, int r, const FxWaveLds& W,
+                           uint32_t* total)
+{
+    const int lane = __lane_id();
+    const int nc = (int)D.nc;
+    const bool full = 2 * r + 1 >= nc;
+    const int nrow = full ? nc : 2 * r + 1;
+    int xa0, xb0, xa1 = 0, xb1 = -1;
+    if (full) {
+        xa0 = 0; xb0 = nc - 1;
+    } else if (cx - r < 0) {
+        xa0 = cx - r + nc; xb0 = nc - 1; xa1 = 0; xb1 = cx + r;
+    } else if (cx + r >= nc) {
+        xa0 = cx - r; xb0 = nc - 1; xa1 = 0; xb1 = cx + r - nc;
+    } else {
+        xa0 = cx - r; xb0 = cx + r;
+    }
+    const int nxr = xb1 >= xa1 ? 2 : 1;
+    const int nseg = nrow * nrow * nxr;
+    uint32_t cnt = 0, lo = 0;
+    if (lane < nseg) {
+        const int ixr = lane % nxr, iy = (lane / nxr) % nrow, iz = lane / (nxr * nrow);
+        const int y = full ? iy : (cy - r + iy + nc) % nc;
+        const int z = full ? iz : (cz - r + iz + nc) % nc;
+        const int xa = ixr ? xa1 : xa0, xb = ixr ? xb1 : xb0;
+        const uint32_t row = (uint32_t)(nc * (y + nc * z));
+        lo = D.cell_start[row + xa];
+        cnt = D.cell_start[row + xb + 1] - lo;
+    }
+    const uint32_t off = wave_excl_scan(cnt, total);
+    if (lane < nseg) {
+        W.seglo[lane] = lo;
+        W.segoff[lane] = off;
+    }
+    wave_lds_sync();
+    return nseg;
+}
+
+__device__ __forceinline__ uint32_t fx_stencil_atom(const FxDev& D, const FxWaveLds& W, int nseg, uint32_t idx)
+{
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (W.segoff[mid] <= idx) lo = mid; else hi = mid;
+    }
+    return D.cell_list[W.seglo[lo] + (idx - W.segoff[lo])];
+}
+
+template <typename T>
+__device__ __forceinline__ T fx_pick(const T v[4], uint32_t i)
+{
+    return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
+}
+
+// One attempt on atom a (Sec. II.B) by a whole wave.  `cell` is the atom's
+// cell for the sweep's shift h: a translation that leaves it is rejected.
+__device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const double h[3], uint32_t cell,
+                           bool logging, const FxWaveLds& W, FxCount& wc)
+{
+    const int lane = __lane_id();
+    const uint32_t n = D.n, N = D.N;
+    const uint32_t slo = (uint32_t)sweep, shi = (uint32_t)(sweep >> 32);
+    const U4 b0 = philox10(a, slo, shi, 0u, D.seed_lo, D.seed_hi);
+    const U4 b1 = philox10(a, slo, shi, 1u, D.seed_lo, D.seed_hi);
+    const double uacc = unit_53(b0.x, b0.y), ut = unit_open(b0.z);
+    const double p0 = unit_open(b1.x), p1 = unit_open(b1.y), p2 = unit_open(b1.z);
+    const double thr = D.T * log(uacc);
+    const bool flip = ut < D.p_flip;
+    const uint32_t base = n * (a / n), sa = a - base;
+    const uint32_t cx = cell % D.nc, cy = (cell / D.nc) % D.nc, cz = cell / (D.nc * D.nc);
+
+    // the molecule's atoms before and after (wave-uniform)
+    double ox[4], oy[4], oz[4], nx[4], ny[4], nz[4];
+    uint32_t ot[4], nt[4];
+#pragma unroll
+    for (uint32_t s = 0; s < 4; ++s) {
+        const uint32_t at = base + (s < n ? s : 0u);
+        ox[s] = nx[s] = D.pos[at];
+        oy[s] = ny[s] = D.pos[N + at];
+        oz[s] = nz[s] = D.pos[2 * N + at];
+        ot[s] = nt[s] = D.type[at];
+    }
+    uint32_t changed = 0;  // bit s: atom base + s moves or changes type
+    uint32_t kind = 255;
+    bool exited = false;
+    double tx = 0.0, ty = 0.0, tz = 0.0;
+    if (flip) {
+        uint32_t q = (uint32_t)((double)D.nflip * p0);
+        q = q >= D.nflip ? D.nflip - 1 : q;
+        kind = q;
+#pragma unroll
+        for (uint32_t s = 0; s < 4; ++s) {
+            if (s >= n) continue;
+            nt[s] = fx_pick(ot, D.flips[q][s]);
+            if (nt[s] != ot[s]) changed |= 1u << s;
+        }
+    } else {
+        tx = fx_pick(ox, sa) + D.dmax * (2.0 * p0 - 1.0);
+        ty = fx_pick(oy, sa) + D.dmax * (2.0 * p1 - 1.0);
+        tz = fx_pick(oz, sa) + D.dmax * (2.0 * p2 - 1.0);
+        const double wx = fx_wrap(tx, D.L), wy = fx_wrap(ty, D.L), wz = fx_wrap(tz, D.L);
+#pragma unroll
+        for (uint32_t s = 0; s < 4; ++s)
+            if (s == sa) {
+                nx[s] = wx;
+                ny[s] = wy;
+                nz[s] = wz;
+            }
+        exited = fx_cell(wx, wy, wz, h, D) != cell;
+        changed = 1u << sa;
+    }
+    if (flip) wc.att_f += 1; else wc.att_t += 1;
+    if (exited) {
+        wc.exits += 1;
+        if (logging && lane == 0) {
+            MoveRecord rec;
+            rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = thr; rec.sweep = sweep;
+            rec.molecule = a; rec.move = MC_TRANSLATE; rec.accepted = 0; rec.exited = 1;
+            rec.axis = 255; rec.pair_terms = 0; rec.pad = 0;
+            D.log[(sweep - D.log_sweep0) * N + a] = rec;
+        }
+        return;
+    }
+
+    double de = 0.0, sc = 0.0;
+    uint32_t terms = 0;
+    // intramolecular pairs touching a changed atom: lane 0's partial
+    if (lane == 0) {
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+            for (uint32_t j = i + 1; j < 4; ++j) {
+                if (j >= n || !(((changed >> i) | (changed >> j)) & 1u)) continue;
+                const bool bonded = (D.bonded >> (4 * i + j)) & 1u;
+                const double dxo = fx_mi(ox[i] - ox[j], D.L, D.invL), dyo = fx_mi(oy[i] - oy[j], D.L, D.invL),
+                             dzo = fx_mi(oz[i] - oz[j], D.L, D.invL);
+                const double dxn = fx_mi(nx[i] - nx[j], D.L, D.invL), dyn = fx_mi(ny[i] - ny[j], D.L, D.invL),
+                             dzn = fx_mi(nz[i] - nz[j], D.L, D.invL);
+                const double r2o = dxo * dxo + dyo * dyo + dzo * dzo;
+                const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
+                const double so = 0.5 * (D.sigma[ot[i]] + D.sigma[ot[j]]);
+                const double sn = 0.5 * (D.sigma[nt[i]] + D.sigma[nt[j]]);
+                double uo = fx_wca(so * so, r2o, D.rc2f), un = fx_wca(sn * sn, r2n, D.rc2f);
+                terms += (r2o < D.rc2f * so * so ? 1u : 0u) + (r2n < D.rc2f * sn * sn ? 1u : 0u);
+                if (bonded) {
+                    const double fo = fx_fene(so, r2o), fn = fx_fene(sn, r2n);
+                    uo += fo;
+                    un += fn;
+                    terms += (fo < __builtin_inf() ? 1u : 0u) + (fn < __builtin_inf() ? 1u : 0u);
+                }
+                de += un - uo;
+                sc += un + uo;
+            }
+    }
+    // intermolecular pairs: the atoms of the stencil cells, a lane each
+    uint32_t total;
+    const int nseg = fx_segments(D, (int)cx, (int)cy, (int)cz, flip ? (int)D.r_flip : (int)D.r_trans,
+                                 W, &total);
+    for (uint32_t b = 0; b < total; b += 64u) {
+        const uint32_t idx = b + (uint32_t)lane;
+        uint32_t j = 0xFFFFFFFFu;
+        if (idx < total) j = fx_stencil_atom(D, W, nseg, idx);
+        const bool valid = j != 0xFFFFFFFFu && j / n != a / n;
+        double xj = 0.0, yj = 0.0, zj = 0.0;
+        uint32_t tj = 0;
+        if (valid) {
+            xj = D.pos[j]; yj = D.pos[N + j]; zj = D.pos[2 * N + j];
+            tj = D.type[j];
+        }
+        const double sj = D.sigma[tj];
+#pragma unroll
+        for (uint32_t s = 0; s < 4; ++s) {
+            if (!((changed >> s) & 1u)) continue;  // wave-uniform
+            const double dxo = fx_mi(ox[s] - xj, D.L, D.invL), dyo = fx_mi(oy[s] - yj, D.L, D.invL),
+                         dzo = fx_mi(oz[s] - zj, D.L, D.invL);
+            const double r2o = valid ? dxo * dxo + dyo * dyo + dzo * dzo : 1e30;
+            double r2n = r2o;
+            if (!flip) {
+                const double dxn = fx_mi(nx[s] - xj, D.L, D.invL), dyn = fx_mi(ny[s] - yj, D.L, D.invL),
+                             dzn = fx_mi(nz[s] - zj, D.L, D.invL);
+                r2n = valid ? dxn * dxn + dyn * dyn + dzn * dzn : 1e30;
+            }
+            const double so = 0.5 * (D.sigma[ot[s]] + sj);
+            const double sn = 0.5 * (D.sigma[nt[s]] + sj);
+            const double uo = fx_wca(so * so, r2o, D.rc2f), un = fx_wca(sn * sn, r2n, D.rc2f);
+            de += un - uo;
+            sc += un + uo;
+            terms += (uint32_t)__popcll(__ballot(r2o < D.rc2f * so * so)) +
+                     (uint32_t)__popcll(__ballot(r2n < D.rc2f * sn * sn));
+        }
+    }
+    // lane 0 holds the intramolecular counts plus the ballots' (wave totals)
+    terms = (uint32_t)__builtin_amdgcn_readlane((int)terms, 0);
+    const double dE = wave_sum_dpp(de);
+    const double S = logging ? wave_sum_dpp(sc) : 0.0;
+    const bool accept = (dE <= 0.0) || (thr < -dE);
+    wc.terms += terms;
+    if (accept) {
+        if (flip) wc.acc_f += 1; else wc.acc_t += 1;
+        wc.e += dE;
+    }
+    if (lane == 0) {
+        if (accept) {
+            if (flip) {
+#pragma unroll
+                for (uint32_t s = 0; s < 4; ++s)
+                    if ((changed >> s) & 1u) D.type[base + s] = (uint8_t)nt[s];
+            } else {
+                D.pos[a] = fx_pick(nx, sa);
+                D.pos[N + a] = fx_pick(ny, sa);
+                D.pos[2 * N + a] = fx_pick(nz, sa);
+                // periodic images crossed (the shifts the wrap took off)
+                const int ix = (int)floor(tx / D.L), iy = (int)floor(ty / D.L), iz = (int)floor(tz / D.L);
+                if (ix) D.img[a] += ix;
+                if (iy) D.img[N + a] += iy;
+                if (iz) D.img[2 * N + a] += iz;
+            }
+        }
+        if (logging) {
+            MoveRecord rec;
+            rec.delta_e = dE; rec.scale = S; rec.t_log_u = thr; rec.sweep = sweep;
+            rec.molecule = a; rec.move = flip ? MC_FLIP : MC_TRANSLATE; rec.accepted = accept ? 1 : 0;
+            rec.exited = 0; rec.axis = (uint8_t)kind; rec.pair_terms = terms; rec.pad = 0;
+            D.log[(sweep - D.log_sweep0) * N + a] = rec;
+        }
+    }
+    wave_lds_sync();
+}
+
+// Ascending atom index inside every cell of c0, c0 + cstep, ...: one wave per
+// cell, a lane per atom whose place is the number of smaller indices (a cell
+// of more than 64 atoms is sorted by one lane).
+__device__ void fx_sort_cells(uint32_t* list, const uint32_t* start, uint32_t c0, uint32_t cstep,
+                              uint32_t ncell)
+{
+    const uint32_t lane = (uint32_t)__lane_id();
+    for (uint32_t c = c0; c < ncell; c += cstep) {
+        const uint32_t b = start[c], cnt = start[c + 1] - b;
+        if (cnt <= 1u) continue;
+        if (cnt <= 64u) {
+            const uint32_t v = lane < cnt ? list[b + lane] : 0xFFFFFFFFu;
+            uint32_t rank = 0;
+            for (uint32_t q = 0; q < cnt; ++q) rank += (uint32_t)__builtin_amdgcn_readlane((int)v, (int)q) < v;
+            wave_lds_sync();
+            if (lane < cnt) list[b + rank] = v;
+        } else if (lane == 0) {
+            for (uint32_t i = b + 1; i < b + cnt; ++i) {
+                const uint32_t x = list[i];
+                uint32_t q = i;
+                while (q > b && list[q - 1] > x) {
+                    list[q] = list[q - 1];
+                    --q;
+                }
+                list[q] = x;
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+// The hot kernel: n sweeps of one system on one workgroup.
+__global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp, uint64_t n_sweeps)
+{
+    __shared__ uint32_t seg[kFxWaves][2][kFxSeg];
+    __shared__ uint32_t scratch[kFxWaves];
+    __shared__ double misc[2];
+    const FxDev& D = *Dp;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    FxWaveLds W{seg[wave][0], seg[wave][1]};
+    Stats* st = D.stats;
+    const uint32_t N = D.N, ncell = D.ncell, nc = D.nc, k = D.k;
+    const uint32_t na = nc / k, nact = na * na * na;
+    uint64_t sweep = st->sweep;
+    const uint64_t origin = st->obs_origin;
+    if (tid == 0) misc[0] = st->e_acc;
+    FxCount wc{};
+    for (uint64_t it = 0; it < n_sweeps; ++it) {
+        const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, D.seed_lo, D.seed_hi);
+        const double h[3] = {D.w * unit_open(g.x), D.w * unit_open(g.y), D.w * unit_open(g.z)};
+        // counting sort of the atoms by cell
+        for (uint32_t c = tid; c <= ncell; c += kFxThreads) D.cell_start[c] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < N; i += kFxThreads) {
+            const uint32_t c = fx_cell(D.pos[i], D.pos[N + i], D.pos[2 * N + i], h, D);
+            D.cell_id[i] = c;
+            atomicAdd(&D.cell_start[c + 1], 1u);
+        }
+        __syncthreads();
+        block_excl_scan_t<kFxThreads>(D.cell_start + 1, ncell, scratch);
+        for (uint32_t i = tid; i < N; i += kFxThreads)
+            D.cell_list[atomicAdd(&D.cell_start[D.cell_id[i] + 1], 1u)] = i;
+        __syncthreads();
+        fx_sort_cells(D.cell_list, D.cell_start, (uint32_t)wave, kFxWaves, ncell);
+        __syncthreads();
+        const bool logging = D.log != nullptr && sweep - D.log_sweep0 < D.log_sweeps;
+        for (uint32_t col = 0; col < k * k * k; ++col) {
+            const uint32_t kx = col % k, ky = (col / k) % k, kz = col / (k * k);
+            for (uint32_t ci = (uint32_t)wave; ci < nact; ci += kFxWaves) {
+                const uint32_t cell = (kx + k * (ci % na)) + nc * ((ky + k * ((ci / na) % na)) +
+                                                                  nc * (kz + k * (ci / (na * na))));
+                wc.e = 0.0;
+                const uint32_t b = D.cell_start[cell], e = D.cell_start[cell + 1];
+                for (uint32_t q = b; q < e; ++q)
+                    fx_attempt(D, D.cell_list[q], sweep, h, cell, logging, W, wc);
+                if (lane == 0) D.ecell[cell] = wc.e;
+            }
+            __syncthreads();
+        }
+        ++sweep;
+        // E_acc += the sweep's dE, the cells in a fixed order; E/M samples
+        if (wave == 0) {
+            const double e = misc[0] + sweep_energy(D.ecell, ncell);
+            if (lane == 0) misc[0] = e;
+        }
+        if (tid == 0) {
+            const uint64_t t = sweep - origin;
+            if (t >= D.obs_start && D.obs_interval && t % D.obs_interval == 0) {
+                const double em = misc[0] / (double)D.M;
+                if (st->n_e < D.max_samples) D.e_samples[st->n_e] = em;
+                st->n_e += 1;
+                st->e_sum += em;
+                st->e_sumsq += em * em;
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        if (wc.att_t) atomicAdd((unsigned long long*)&st->attempts[MC_TRANSLATE], (unsigned long long)wc.att_t);
+        if (wc.att_f) atomicAdd((unsigned long long*)&st->attempts[MC_FLIP], (unsigned long long)wc.att_f);
+        if (wc.acc_t) atomicAdd((unsigned long long*)&st->accepts[MC_TRANSLATE], (unsigned long long)wc.acc_t);
+        if (wc.acc_f) atomicAdd((unsigned long long*)&st->accepts[MC_FLIP], (unsigned long long)wc.acc_f);
+        if (wc.exits) atomicAdd((unsigned long long*)&st->exits, (unsigned long long)wc.exits);
+        if (wc.terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)wc.terms);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        st->sweep = sweep;
+        st->e_acc = misc[0];
+    }
+}
+
+// Event work, the O(N^2) part: each workgroup's partial energy (every pair of
+// atoms once, Eq. 1, plus Eq. 2 over the bonds) into D.part and one g(r)
+// frame (Eq. 3 numerator, every ordered pair) into the histograms.
+__global__ void __launch_bounds__(kFxThreads) k_fx_event_parts(FxDev* __restrict__ Dp, uint32_t flags)
+{
+    __shared__ double red[kFxWaves];
+    __shared__ uint32_t bins[2][kGofrBins];
+    const FxDev& D = *Dp;
+    const uint32_t N = D.N, n = D.n, half = N / 2;
+    const uint32_t i = blockIdx.x * kFxThreads + threadIdx.x;
+    if (flags & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) {
+        double e = 0.0;
+        if (i < N) {
+            const double xi = D.pos[i], yi = D.pos[N + i], zi = D.pos[2 * N + i];
+            const double si = D.sigma[D.type[i]];
+            for (uint32_t dj = 1; dj <= half; ++dj) {
+                if ((N & 1u) == 0u && dj == half && i >= half) break;
+                uint32_t j = i + dj;
+                if (j >= N) j -= N;
+                const double dx = fx_mi(D.pos[j] - xi, D.L, D.invL), dy = fx_mi(D.pos[N + j] - yi, D.L, D.invL),
+                             dz = fx_mi(D.pos[2 * N + j] - zi, D.L, D.invL);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double s = 0.5 * (si + D.sigma[D.type[j]]);
+                e += fx_wca(s * s, r2, D.rc2f);
+                if (i / n == j / n) {
+                    const uint32_t a = i % n, b = j % n;
+                    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    if ((D.bonded >> (4 * lo + hi)) & 1u) e += fx_fene(s, r2);
+                }
+            }
+        }
+        // fixed-order sum over the workgroup
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        e = wave_sum_dpp(e);
+        if (lane == 0) red[wave] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kFxWaves; ++w) t += red[w];
+            D.part[blockIdx.x] = t;
+        }
+    }
+    if (flags & kFlagGofr) {
+        for (uint32_t b = threadIdx.x; b < 2 * kGofrBins; b += kFxThreads) (&bins[0][0])[b] = 0;
+        __syncthreads();
+        if (i < N) {
+            const double xi = D.pos[i], yi = D.pos[N + i], zi = D.pos[2 * N + i];
+            for (uint32_t j = 0; j < N; ++j) {
+                if (j == i) continue;
+                const double dx = fx_mi(D.pos[j] - xi, D.L, D.invL), dy = fx_mi(D.pos[N + j] - yi, D.L, D.invL),
+                             dz = fx_mi(D.pos[2 * N + j] - zi, D.L, D.invL);
+                const int b = (int)floor(sqrt(dx * dx + dy * dy + dz * dz) / D.gofr_dr);
+                if (b >= 0 && b < (int)D.gofr_nbins) {
+                    atomicAdd(&bins[0][b], 1u);
+                    if (i / n != j / n) atomicAdd(&bins[1][b], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < D.gofr_nbins; b += kFxThreads) {
+            if (bins[0][b]) atomicAdd((unsigned long long*)&D.gofr_all[b], (unsigned long long)bins[0][b]);
+            if (bins[1][b]) atomicAdd((unsigned long long*)&D.gofr_inter[b], (unsigned long long)bins[1][b]);
+        }
+    }
+}
+
+// Centre of mass of molecule m (equal masses): atom 0 plus the mean of the
+// nearest-image offsets of the molecule's atoms from it (wrapped positions).
+__device__ void fx_centre(const FxDev& D, uint32_t m, double c[3])
+{
+    const uint32_t N = D.N, base = D.n * m;
+    for (int d = 0; d < 3; ++d) {
+        const double x0 = D.pos[d * N + base];
+        double acc = 0.0;
+        for (uint32_t s = 0; s < D.n; ++s) acc += fx_mi(D.pos[d * N + base + s] - x0, D.L, D.invL);
+        c[d] = x0 + acc / (double)D.n;
+    }
+}
+
+__device__ double fx_sinc(double x) { return x < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x; }
+
+// Event work on one workgroup: the re-sum from the partial energies (drift,
+// re-anchoring), the frame count, the observable origin, a C_2 / F_s sample.
+__global__ void __launch_bounds__(kFxThreads) k_fx_events(FxDev* __restrict__ Dp, uint32_t flags, uint32_t nparts)
+{
+    __shared__ double red[kFxWaves];
+    const FxDev& D = *Dp;
+    Stats* st = D.stats;
+    const uint32_t N = D.N, M = D.M, n = D.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    auto block_sum = [&](double v) {
+        v = wave_sum_dpp(v);
+        __syncthreads();
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < kFxWaves; ++w) t += red[w];
+        return t;
+    };
+    const uint64_t sweep = st->sweep;
+    if (flags & kFlagObsReset) {
+        for (uint32_t i = tid; i < N; i += kFxThreads)
+            for (int d = 0; d < 3; ++d) D.r0[d * N + i] = D.pos[d * N + i] + D.L * (double)D.img[d * N + i];
+        for (uint32_t m = tid; m < M; m += kFxThreads) {
+            double c[3];
+            fx_centre(D, m, c);
+            const uint32_t base = n * m;
+            uint32_t kb = 0;
+            for (uint32_t s = 0; s < n; ++s)
+                if (D.type[base + s] == 1u) kb = s;
+            D.kref[m] = (uint8_t)kb;
+            double u[3], nrm = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                u[d] = fx_mi(D.pos[d * N + base + kb] - c[d], D.L, D.invL);
+                nrm += u[d] * u[d];
+                // unwrapped centre: unwrapped atom 0 plus the offsets
+                D.rcm0[d * M + m] = c[d] - D.pos[d * N + base] + D.pos[d * N + base] +
+                                    D.L * (double)D.img[d * N + base];
+            }
+            nrm = sqrt(nrm);
+            for (int d = 0; d < 3; ++d) D.u0[d * M + m] = u[d] / nrm;
+        }
+        for (uint32_t b = tid; b < kGofrBins; b += kFxThreads) {
+            D.gofr_all[b] = 0;
+            D.gofr_inter[b] = 0;
+        }
+        if (tid == 0) {
+            st->obs_origin = sweep;
+            st->n_e = st->n_drift = st->n_gofr = st->n_c2 = 0;
+            st->e_sum = st->e_sumsq = 0.0;
+            st->max_abs_drift = 0.0;
+        }
+        __syncthreads();
+    }
+    if (flags & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) {
+        if (tid == 0) {
+            double e = 0.0;
+            for (uint32_t b = 0; b < nparts; ++b) e += D.part[b];
+            const double acc = (flags & kFlagResumSet) ? e : st->e_acc;
+            if (flags & (kFlagResumSet | kFlagResumPeriodic)) st->e_acc = e;
+            const double drift = acc - e;
+            st->e_resum = e;
+            st->drift = drift;
+            st->resum_sweep = sweep;
+            if (flags & kFlagResumPeriodic) {
+                st->n_resum += 1;
+                if (st->n_drift < D.max_samples) D.drift_samples[st->n_drift] = drift;
+                st->n_drift += 1;
+                if (sweep > D.resum_interval && fabs(drift) > st->max_abs_drift) st->max_abs_drift = fabs(drift);
+            }
+        }
+        __syncthreads();
+    }
+    if ((flags & kFlagGofr) && tid == 0) st->n_gofr += 1;
+    if (flags & kFlagC2) {
+        double a2 = 0.0, afs = 0.0, acm = 0.0;
+        for (uint32_t m = tid; m < M; m += kFxThreads) {
+            double c[3], u[3], nrm = 0.0, dot = 0.0, dc2 = 0.0;
+            fx_centre(D, m, c);
+            const uint32_t base = n * m, kb = D.kref[m];
+            for (int d = 0; d < 3; ++d) {
+                u[d] = fx_mi(D.pos[d * N + base + kb] - c[d], D.L, D.invL);
+                nrm += u[d] * u[d];
+                const double cu = c[d] + D.L * (double)D.img[d * N + base];
+                const double dd = cu - D.rcm0[d * M + m];
+                dc2 += dd * dd;
+            }
+            nrm = sqrt(nrm);
+            for (int d = 0; d < 3; ++d) dot += (u[d] / nrm) * D.u0[d * M + m];
+            a2 += 0.5 * (3.0 * dot * dot - 1.0);
+            acm += fx_sinc(D.fs_q_cm * sqrt(dc2));
+        }
+        for (uint32_t i = tid; i < N; i += kFxThreads) {
+            double d2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double dd = D.pos[d * N + i] + D.L * (double)D.img[d * N + i] - D.r0[d * N + i];
+                d2 += dd * dd;
+            }
+            afs += fx_sinc(D.fs_q * sqrt(d2));
+        }
+        const double c2 = block_sum(a2) / (double)M;
+        const double fcm = block_sum(acm) / (double)M;
+        const double fs = block_sum(afs) / (double)N;
+        if (tid == 0 && st->n_c2 < kC2Max) {
+            const uint32_t j = st->n_c2;
+            D.c2[j] = c2;
+            D.fs_cm[j] = fcm;
+            D.fs[j] = fs;
+            D.c2_sweep[j] = sweep - st->obs_origin;
+            st->n_c2 = j + 1;
+        }
+    }
+}
+
+__global__ void k_fx_init_lattice(FxDev* __restrict__ Dp, uint32_t nl, double side)
+{
+    const FxDev& D = *Dp;
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= D.M) return;
+    const uint32_t N = D.N, n = D.n;
+    const double a = D.L / (double)nl;
+    const double c[3] = {((double)(m % nl) + 0.5) * a, ((double)((m / nl) % nl) + 0.5) * a,
+                         ((double)(m / (nl * nl)) + 0.5) * a};
+    const U4 g = philox10(m, 0xFFFFFFFFu, 0xFFFFFFFFu, 2u, D.seed_lo, D.seed_hi);
+    const double u1 = unit_open(g.x), u2 = unit_open(g.y), u3 = unit_open(g.z);
+    const double r1 = sqrt(1.0 - u1), r2 = sqrt(u1);
+    const double qw = r2 * cos(kTwoPi * u3), qx = r1 * sin(kTwoPi * u2), qy = r1 * cos(kTwoPi * u2),
+                 qz = r2 * sin(kTwoPi * u3);
+    const double R[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
+                         2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                         2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
+    // the ideal body of side `side` around its centre, atom s in row s
+    double b[12] = {0};
+    if (D.geometry == MC_TRIANGLE) {
+        const double r = side / sqrt(3.0);
+        b[0] = r;
+        b[3] = -0.5 * r; b[4] = 0.5 * side;
+        b[6] = -0.5 * r; b[7] = -0.5 * side;
+    } else if (D.geometry == MC_SQUARE) {
+        const double hs = 0.5 * side;
+        b[0] = hs;  b[1] = hs;
+        b[3] = -hs; b[4] = hs;
+        b[6] = -hs; b[7] = -hs;
+        b[9] = hs;  b[10] = -hs;
+    } else {
+        const double t = side / (2.0 * sqrt(2.0));
+        const double v[12] = {1, 1, 1, 1, -1, -1, -1, 1, -1, -1, -1, 1};
+        for (int i = 0; i < 12; ++i) b[i] = t * v[i];
+    }
+    for (uint32_t s = 0; s < n; ++s) {
+        const uint32_t at = n * m + s;
+        for (int d = 0; d < 3; ++d) {
+            const double v = c[d] + (R[3 * d] * b[3 * s] + R[3 * d + 1] * b[3 * s + 1] + R[3 * d + 2] * b[3 * s + 2]);
+            D.pos[d * N + at] = fx_wrap(v, D.L);
+            D.img[d * N + at] = 0;
+        }
+        D.type[at] = (uint8_t)s;
+    }
+}
+
+}  // namespace
+}  // namespace flipmc
+
+// ------------------------------------------------------------------ host --
+
+namespace {
+
+using namespace flipmc;
+
+int fx_fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return api_error(code, buf);
+}
+
+#define FXCHK(x)                                                                       \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) return fx_fail(MC_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kBondsOf[3][6][2] = {
+    {{0, 1}, {1, 2}, {0, 2}, {-1, -1}, {-1, -1}, {-1, -1}},
+    {{0, 1}, {1, 2}, {2, 3}, {0, 3}, {-1, -1}, {-1, -1}},
+    {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}},
+};
+constexpr int kGraphDiam[3] = {1, 2, 1};
+// new type of atom s = old type of atom perm[s]: the 180 degree rotations of
+// the ideal body (triangle: about the median through atom q; square: the
+// diagonal through atom 0, the one through atom 1, the bisector of edge 01,
+// the bisector of edge 12; tetrahedron: the axes through the midpoints of
+// edges 01, 02, 03 and of the opposite edges)
+constexpr uint8_t kPerm[3][4][4] = {
+    {{0, 2, 1, 3}, {2, 1, 0, 3}, {1, 0, 2, 3}, {0, 1, 2, 3}},
+    {{0, 3, 2, 1}, {2, 1, 0, 3}, {1, 0, 3, 2}, {3, 2, 1, 0}},
+    {{1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}, {0, 1, 2, 3}},
+};
+constexpr uint32_t kNPerm[3] = {3, 4, 3};
+
+// Side of the ideal body at the lattice start: the minimum of WCA + FENE of a
+// sigma_ij = 1 bond, by Newton's method on the slope.
+double fx_bond_star()
+{
+    auto slope = [](double x) {
+        return -48.0 * std::pow(x, -13.0) + 24.0 * std::pow(x, -7.0) + 30.0 * x / (1.0 - x * x / 2.25);
+    };
+    auto curv = [](double x) {
+        const double d = 1.0 - x * x / 2.25;
+        return 624.0 * std::pow(x, -14.0) - 168.0 * std::pow(x, -8.0) + 30.0 / d +
+               30.0 * x * (2.0 * x / 2.25) / (d * d);
+    };
+    double x = 0.96;
+    for (int it = 0; it < 100; ++it) {
+        const double nx = x - slope(x) / curv(x);
+        if (nx == x) break;
+        x = nx;
+    }
+    return x;
+}
+
+struct FxGeom {
+    uint32_t n, N, k, nc, ncell, r_trans, r_flip;
+    double L, w, D, rc, reach;
+};
+
+uint32_t segments_of(uint32_t r, uint32_t nc)
+{
+    const bool full = 2 * r + 1 >= nc;
+    const uint32_t nrow = full ? nc : 2 * r + 1;
+    return nrow * nrow * (full ? 1u : 2u);
+}
+
+// Is (k, nc) a valid decomposition?  Fills the stencil radii.
+bool fx_valid(const FxGeom& g0, uint32_t k, uint32_t nc, FxGeom* out)
+{
+    if (k < 2 || nc < 2 || nc % k != 0) return false;
+    const double w = g0.L / (double)nc;
+    if ((double)(k - 1) * w < g0.reach) return false;  // same-colour cells independent
+    if (w < g0.rc) return false;                       // a translation's partners in +-1 cells
+    const uint32_t rf = (uint32_t)std::ceil((g0.D + g0.rc) / w);
+    if (segments_of(rf, nc) > (uint32_t)kFxSeg || segments_of(1, nc) > (uint32_t)kFxSeg) return false;
+    if ((double)nc * nc * nc > 16777216.0) return false;
+    if (out) {
+        *out = g0;
+        out->k = k;
+        out->nc = nc;
+        out->ncell = nc * nc * nc;
+        out->w = w;
+        out->r_trans = 1;
+        out->r_flip = rf;
+    }
+    return true;
+}
+
+int fx_geometry(const mcf_params* p, FxGeom* gout)
+{
+    if (!p) return fx_fail(MC_EINVAL, "null parameters");
+    if (p->geometry > MC_TETRAHEDRON) return fx_fail(MC_EINVAL, "unknown geometry %u", p->geometry);
+    const uint32_t n = p->geometry == MC_TRIANGLE ? 3u : 4u;
+    if (p->n_molecules < 1 || (uint64_t)p->n_molecules * n > (1u << 24))
+        return fx_fail(MC_EINVAL, "n_molecules must be in [1, 2^24 / %u]", n);
+    if (!(p->density > 0) || !(p->temperature > 0))
+        return fx_fail(MC_EINVAL, "density and temperature must be positive");
+    if (!(p->p_flip >= 0) || p->p_flip > 1.0 || !(p->max_displacement >= 0))
+        return fx_fail(MC_EINVAL, "p_flip or max_displacement out of range");
+    for (uint32_t t = 0; t < n; ++t)
+        if (!(p->sigma[t] > 0)) return fx_fail(MC_EINVAL, "sigma must be positive");
+    if (!(p->gofr_dr > 0)) return fx_fail(MC_EINVAL, "gofr_dr must be positive");
+    FxGeom g{};
+    g.n = n;
+    g.N = n * p->n_molecules;
+    g.L = std::cbrt((double)g.N / p->density);
+    double smax = 0.0, bmax = 0.0;
+    for (uint32_t i = 0; i < n; ++i) {
+        smax = std::max(smax, p->sigma[i]);
+        for (uint32_t j = i + 1; j < n; ++j) bmax = std::max(bmax, 1.5 * 0.5 * (p->sigma[i] + p->sigma[j]));
+    }
+    g.rc = std::pow(2.0, 1.0 / 6.0) * smax;
+    g.D = kGraphDiam[p->geometry] * bmax;
+    g.reach = (2.0 * g.D + g.rc) * (1.0 + 1e-12);
+    const double need = 2.0 * (std::max(g.D, g.rc) + 2.0 * p->max_displacement);
+    if (g.L < need)
+        return fx_fail(MC_EGEOM, "box side %.4f below %.4f (minimum image)", g.L, need);
+    uint32_t k = p->colours_per_axis, nc = p->cells_per_side;
+    if (k == 0 && nc == 0) {
+        // most cells per colour, then fewest colours
+        double best = -1.0;
+        for (uint32_t kk = 2; kk <= 8; ++kk)
+            for (uint32_t cc = kk; cc <= 256; cc += kk) {
+                if (!fx_valid(g, kk, cc, nullptr)) continue;
+                const double act = std::pow((double)(cc / kk), 3.0);
+                if (act > best) {
+                    best = act;
+                    k = kk;
+                    nc = cc;
+                }
+            }
+        if (best < 0) return fx_fail(MC_EGEOM, "no checkerboard fits a box of side %.4f", g.L);
+    } else if (k == 0 || nc == 0) {
+        return fx_fail(MC_EINVAL, "give both colours_per_axis and cells_per_side, or neither");
+    }
+    if (!fx_valid(g, k, nc, gout))
+        return fx_fail(MC_EGEOM, "k = %u, n_c = %u: cells of %.4f need (k-1) w >= %.4f, w >= %.4f and a "
+                                 "flip stencil of at most %d row segments", k, nc, g.L / nc, g.reach, g.rc,
+                       kFxSeg);
+    return MC_OK;
+}
+
+}  // namespace
+
+namespace {
+
+size_t fx_al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct FxLayout {
+    size_t dev, stats, pos, type, img, esamp, dsamp, gall, ginter, c2, c2s, fs, fscm, u0, kref, r0, rcm0;
+    size_t cstart, clist, cid, ecell, part, total;
+};
+
+FxLayout fx_layout(const mcf_params* p, const FxGeom& g)
+{
+    FxLayout l{};
+    const size_t N = g.N, M = p->n_molecules;
+    size_t o = 0;
+    l.dev = o;    o = fx_al(o + sizeof(FxDev));
+    l.stats = o;  o = fx_al(o + sizeof(Stats));
+    l.pos = o;    o = fx_al(o + 3 * N * sizeof(double));
+    l.type = o;   o = fx_al(o + N);
+    l.img = o;    o = fx_al(o + 3 * N * sizeof(int32_t));
+    l.esamp = o;  o = fx_al(o + size_t(p->max_samples) * sizeof(double));
+    l.dsamp = o;  o = fx_al(o + size_t(p->max_samples) * sizeof(double));
+    l.gall = o;   o = fx_al(o + kGofrBins * sizeof(uint64_t));
+    l.ginter = o; o = fx_al(o + kGofrBins * sizeof(uint64_t));
+    l.c2 = o;     o = fx_al(o + kC2Max * sizeof(double));
+    l.c2s = o;    o = fx_al(o + kC2Max * sizeof(uint64_t));
+    l.fs = o;     o = fx_al(o + kC2Max * sizeof(double));
+    l.fscm = o;   o = fx_al(o + kC2Max * sizeof(double));
+    l.u0 = o;     o = fx_al(o + 3 * M * sizeof(double));
+    l.kref = o;   o = fx_al(o + M);
+    l.r0 = o;     o = fx_al(o + 3 * N * sizeof(double));
+    l.rcm0 = o;   o = fx_al(o + 3 * M * sizeof(double));
+    l.cstart = o; o = fx_al(o + (size_t(g.ncell) + 1) * sizeof(uint32_t));
+    l.clist = o;  o = fx_al(o + N * sizeof(uint32_t));
+    l.cid = o;    o = fx_al(o + N * sizeof(uint32_t));
+    l.ecell = o;  o = fx_al(o + size_t(g.ncell) * sizeof(double));
+    l.part = o;   o = fx_al(o + kFxParts * sizeof(double));
+    l.total = o;
+    return l;
+}
+
+bool fx_c2_time(uint64_t t)
+{
+    if (t == 0) return false;
+    while (t % 10 == 0) t /= 10;
+    return t == 1 || t == 2 || t == 5;
+}
+
+}  // namespace
+
+struct mcf_system {
+    mcf_params p;
+    FxGeom g;
+    FxLayout lay;
+    FxDev host;
+    FxDev* dev;
+    hipStream_t stream;
+    uint64_t sweep, origin;
+};
+
+namespace {
+
+uint32_t fx_parts(const mcf_system* s) { return (s->g.N + kFxThreads - 1) / kFxThreads; }
+
+int fx_events(mcf_system* s, uint32_t flags)
+{
+    const uint32_t np = fx_parts(s);
+    if (np > kFxParts) return fx_fail(MC_EINVAL, "too many atoms for the event kernel");
+    if (flags & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic | kFlagGofr)) {
+        hipLaunchKernelGGL(k_fx_event_parts, dim3(np), dim3(kFxThreads), 0, s->stream, s->dev, flags);
+        FXCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_fx_events, dim3(1), dim3(kFxThreads), 0, s->stream, s->dev, flags, np);
+    FXCHK(hipGetLastError());
+    return MC_OK;
+}
+
+uint32_t fx_events_at(const mcf_system* s, uint64_t sweep)
+{
+    uint32_t f = 0;
+    const mcf_params& p = s->p;
+    if (p.resum_interval && sweep % p.resum_interval == 0) f |= kFlagResumPeriodic;
+    const uint64_t t = sweep - s->origin;
+    if (p.gofr_interval && t >= p.obs_start && t % p.gofr_interval == 0) f |= kFlagGofr;
+    if (fx_c2_time(t)) f |= kFlagC2;
+    return f;
+}
+
+uint64_t fx_next_event(const mcf_system* s)
+{
+    const mcf_params& p = s->p;
+    const uint64_t now = s->sweep, t = now - s->origin;
+    uint64_t best = now + (1u << 16);  // bounded launches
+    if (p.resum_interval) best = std::min(best, (now / p.resum_interval + 1) * p.resum_interval);
+    if (p.gofr_interval) {
+        uint64_t nx = (t / p.gofr_interval + 1) * p.gofr_interval;
+        if (nx < p.obs_start) nx = ((p.obs_start + p.gofr_interval - 1) / p.gofr_interval) * p.gofr_interval;
+        best = std::min(best, s->origin + nx);
+    }
+    for (uint64_t dec = 1; dec <= (uint64_t)1e18; dec *= 10) {
+        bool found = false;
+        for (uint64_t m : {1ull, 2ull, 5ull})
+            if (m * dec > t) {
+                best = std::min(best, s->origin + m * dec);
+                found = true;
+                break;
+            }
+        if (found) break;
+    }
+    return best;
+}
+
+int fx_read_stats(mcf_system* s, Stats* st)
+{
+    FXCHK(hipMemcpyAsync(st, s->host.stats, sizeof(Stats), hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+int fx_upload_desc(mcf_system* s)
+{
+    FXCHK(hipMemcpyAsync(s->dev, &s->host, sizeof(FxDev), hipMemcpyHostToDevice, s->stream));
+    FXCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+int fx_upload_state(mcf_system* s, const double* pos, const uint8_t* types)
+{
+    const uint32_t N = s->g.N, n = s->g.n;
+    std::vector<double> x(3 * (size_t)N);
+    for (uint32_t i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double v = pos[3 * i + d];
+            if (!std::isfinite(v)) return fx_fail(MC_EINVAL, "position of atom %u is not finite", i);
+            x[(size_t)d * N + i] = v - s->g.L * std::floor(v / s->g.L);
+        }
+    for (uint32_t m = 0; m < s->p.n_molecules; ++m) {
+        uint32_t seen = 0;
+        for (uint32_t t = 0; t < n; ++t) {
+            const uint32_t ty = types[n * m + t];
+            if (ty >= n || (seen >> ty) & 1u)
+                return fx_fail(MC_EINVAL, "types of molecule %u are not a permutation of 0..%u", m, n - 1);
+            seen |= 1u << ty;
+        }
+    }
+    FXCHK(hipMemcpyAsync(s->host.pos, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    FXCHK(hipMemcpyAsync(s->host.type, types, N, hipMemcpyHostToDevice, s->stream));
+    FXCHK(hipMemsetAsync(s->host.img, 0, 3 * sizeof(int32_t) * N, s->stream));
+    FXCHK(hipStreamSynchronize(s->stream));
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mcf_params_default(mcf_params* p, uint32_t geometry)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->geometry = geometry;
+    p->n_molecules = 1000;
+    p->density = 1.2;
+    p->temperature = 3.0;
+    if (geometry == MC_TRIANGLE) {
+        p->sigma[0] = 0.9; p->sigma[1] = 1.0; p->sigma[2] = 1.1;
+    } else {
+        for (int t = 0; t < 4; ++t) p->sigma[t] = 0.9 + 0.2 * t / 3.0;
+    }
+    p->bond_length = 0.0;
+    p->p_flip = 0.2;
+    p->max_displacement = 0.1;
+    p->seed = 1;
+    p->resum_interval = 100;
+    p->obs_interval = 10;
+    p->gofr_interval = 100;
+    p->max_samples = 4096;
+    p->gofr_dr = 0.02;
+    p->fs_q = 7.4;
+    p->fs_q_cm = 5.1;
+}
+
+int mcf_geometry(const mcf_params* p, double* box, uint32_t* k, uint32_t* nc)
+{
+    FxGeom g;
+    const int rc = fx_geometry(p, &g);
+    if (rc) return rc;
+    if (box) *box = g.L;
+    if (k) *k = g.k;
+    if (nc) *nc = g.nc;
+    return MC_OK;
+}
+
+int mcf_required_bytes(const mcf_params* p, size_t* bytes)
+{
+    FxGeom g;
+    const int rc = fx_geometry(p, &g);
+    if (rc) return rc;
+    if (!bytes) return fx_fail(MC_EINVAL, "null output");
+    *bytes = fx_layout(p, g).total;
+    return MC_OK;
+}
+
+int mcf_init_system(const mcf_params* p, const double* pos, const uint8_t* types, void* device_buf,
+                    size_t buf_bytes, void* hip_stream, mcf_system** out)
+{
+    if (!out) return fx_fail(MC_EINVAL, "null output handle");
+    *out = nullptr;
+    FxGeom g;
+    int rc = fx_geometry(p, &g);
+    if (rc) return rc;
+    const bool lattice = !pos && !types;
+    if (!lattice && !(pos && types)) return fx_fail(MC_EINVAL, "give pos and types together, or neither");
+    uint32_t nl = 1;
+    while ((nl + 1) * (nl + 1) * (nl + 1) <= p->n_molecules) ++nl;
+    if (lattice && nl * nl * nl != p->n_molecules)
+        return fx_fail(MC_EINVAL, "lattice start needs n_molecules = n^3 (got %u)", p->n_molecules);
+    if (!device_buf) return fx_fail(MC_EINVAL, "null device buffer");
+    if (((uintptr_t)device_buf & 255u) != 0) return fx_fail(MC_EINVAL, "device buffer must be 256-byte aligned");
+    const FxLayout lay = fx_layout(p, g);
+    if (buf_bytes < lay.total) return fx_fail(MC_ENOMEM, "device buffer of %zu bytes, %zu needed", buf_bytes, lay.total);
+
+    mcf_system* s = new mcf_system();
+    s->p = *p;
+    s->g = g;
+    s->lay = lay;
+    s->stream = (hipStream_t)hip_stream;
+    s->sweep = s->origin = 0;
+    FxDev& D = s->host;
+    std::memset(&D, 0, sizeof D);
+    uint8_t* b = (uint8_t*)device_buf;
+    D.geometry = p->geometry;
+    D.n = g.n;
+    D.M = p->n_molecules;
+    D.N = g.N;
+    D.k = g.k;
+    D.nc = g.nc;
+    D.ncell = g.ncell;
+    D.nflip = kNPerm[p->geometry];
+    D.seed_lo = (uint32_t)p->seed;
+    D.seed_hi = (uint32_t)(p->seed >> 32);
+    D.r_trans = g.r_trans;
+    D.r_flip = g.r_flip;
+    for (int bnd = 0; bnd < 6; ++bnd) {
+        const int i = kBondsOf[p->geometry][bnd][0], j = kBondsOf[p->geometry][bnd][1];
+        if (i >= 0) D.bonded |= 1u << (4 * std::min(i, j) + std::max(i, j));
+    }
+    D.resum_interval = p->resum_interval;
+    D.obs_interval = p->obs_interval;
+    D.gofr_interval = p->gofr_interval;
+    D.obs_start = p->obs_start;
+    D.max_samples = p->max_samples;
+    D.L = g.L;
+    D.invL = 1.0 / g.L;
+    D.w = g.w;
+    D.T = p->temperature;
+    D.p_flip = p->p_flip;
+    D.dmax = p->max_displacement;
+    D.rc2f = std::cbrt(2.0);
+    for (int t = 0; t < 4; ++t) D.sigma[t] = t < (int)g.n ? p->sigma[t] : 1.0;
+    const double rmax = std::min(0.5 * g.L, 5.0);
+    D.gofr_nbins = std::min((uint32_t)kGofrBins, (uint32_t)std::floor(rmax / p->gofr_dr + 1e-6));
+    D.gofr_dr = p->gofr_dr;
+    D.gofr_rmax = rmax;
+    D.fs_q = p->fs_q;
+    D.fs_q_cm = p->fs_q_cm;
+    std::memcpy(D.flips, kPerm[p->geometry], sizeof D.flips);
+    D.pos = (double*)(b + lay.pos);
+    D.type = b + lay.type;
+    D.img = (int32_t*)(b + lay.img);
+    D.stats = (Stats*)(b + lay.stats);
+    D.e_samples = (double*)(b + lay.esamp);
+    D.drift_samples = (double*)(b + lay.dsamp);
+    D.gofr_all = (uint64_t*)(b + lay.gall);
+    D.gofr_inter = (uint64_t*)(b + lay.ginter);
+    D.c2 = (double*)(b + lay.c2);
+    D.c2_sweep = (uint64_t*)(b + lay.c2s);
+    D.fs = (double*)(b + lay.fs);
+    D.fs_cm = (double*)(b + lay.fscm);
+    D.u0 = (double*)(b + lay.u0);
+    D.kref = b + lay.kref;
+    D.r0 = (double*)(b + lay.r0);
+    D.rcm0 = (double*)(b + lay.rcm0);
+    D.cell_start = (uint32_t*)(b + lay.cstart);
+    D.cell_list = (uint32_t*)(b + lay.clist);
+    D.cell_id = (uint32_t*)(b + lay.cid);
+    D.ecell = (double*)(b + lay.ecell);
+    D.part = (double*)(b + lay.part);
+    s->dev = (FxDev*)(b + lay.dev);
+    auto bail = [&](int code) {
+        delete s;
+        return code;
+    };
+    hipError_t e = hipMemsetAsync(device_buf, 0, lay.total, s->stream);
+    if (e != hipSuccess) return bail(fx_fail(MC_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e)));
+    if ((rc = fx_upload_desc(s))) return bail(rc);
+    if (lattice) {
+        const double side = p->bond_length > 0 ? p->bond_length : fx_bond_star();
+        hipLaunchKernelGGL(k_fx_init_lattice, dim3((p->n_molecules + 255) / 256), dim3(256), 0, s->stream,
+                           s->dev, nl, side);
+        e = hipGetLastError();
+        if (e != hipSuccess) return bail(fx_fail(MC_EDEVICE, "lattice kernel: %s", hipGetErrorString(e)));
+    } else if ((rc = fx_upload_state(s, pos, types))) {
+        return bail(rc);
+    }
+    if ((rc = fx_events(s, kFlagResumSet | kFlagObsReset))) return bail(rc);
+    Stats st;
+    if ((rc = fx_read_stats(s, &st))) return bail(rc);
+    if (!std::isfinite(st.e_acc)) return bail(fx_fail(MC_ENONFINITE, "initial energy is not finite"));
+    *out = s;
+    return MC_OK;
+}
+
+int mcf_sweep(mcf_system* s, uint64_t n)
+{
+    if (!s) return fx_fail(MC_EINVAL, "null system");
+    while (n > 0) {
+        const uint64_t chunk = std::min<uint64_t>(n, fx_next_event(s) - s->sweep);
+        hipLaunchKernelGGL(k_fx_sweeps, dim3(1), dim3(kFxThreads), 0, s->stream, s->dev, chunk);
+        FXCHK(hipGetLastError());
+        s->sweep += chunk;
+        n -= chunk;
+        const uint32_t f = fx_events_at(s, s->sweep);
+        if (f)
+            if (int rc = fx_events(s, f)) return rc;
+    }
+    return MC_OK;
+}
+
+int mcf_energy(mcf_system* s, double* e_total, double* e_per_molecule, double* drift)
+{
+    if (!s) return fx_fail(MC_EINVAL, "null system");
+    int rc = fx_events(s, kFlagResumReport);
+    if (rc) return rc;
+    Stats st;
+    if ((rc = fx_read_stats(s, &st))) return rc;
+    if (e_total) *e_total = st.e_resum;
+    if (e_per_molecule) *e_per_molecule = st.e_resum / (double)s->p.n_molecules;
+    if (drift) *drift = st.e_acc - st.e_resum;
+    if (!std::isfinite(st.e_resum)) return fx_fail(MC_ENONFINITE, "energy is not finite");
+    return MC_OK;
+}
+
+int mcf_observables(mcf_system* s, mc_obs* o)
+{
+    if (!s || !o) return fx_fail(MC_EINVAL, "null argument");
+    Stats st;
+    int rc = fx_read_stats(s, &st);
+    if (rc) return rc;
+    std::memset(o, 0, sizeof *o);
+    o->sweep = st.sweep;
+    for (int i = 0; i < 3; ++i) {
+        o->attempts[i] = st.attempts[i];
+        o->accepts[i] = st.accepts[i];
+    }
+    o->exits = st.exits;
+    o->pair_terms = st.pair_terms;
+    o->e_acc = st.e_acc;
+    o->e_resum = st.e_resum;
+    o->drift = st.drift;
+    o->max_abs_drift = st.max_abs_drift;
+    o->resum_sweep = st.resum_sweep;
+    o->n_energy_samples = st.n_e;
+    o->n_drift_samples = st.n_drift;
+    o->energy_sum = st.e_sum;
+    o->energy_sumsq = st.e_sumsq;
+    o->n_gofr_frames = st.n_gofr;
+    o->gofr_nbins = s->host.gofr_nbins;
+    o->gofr_dr = s->host.gofr_dr;
+    o->gofr_rmax = s->host.gofr_rmax;
+    o->n_c2 = st.n_c2;
+    FXCHK(hipMemcpyAsync(o->gofr_all, s->host.gofr_all, sizeof o->gofr_all, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->gofr_inter, s->host.gofr_inter, sizeof o->gofr_inter, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->c2, s->host.c2, sizeof o->c2, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->fs, s->host.fs, sizeof o->fs, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->fs_cm, s->host.fs_cm, sizeof o->fs_cm, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->c2_sweep, s->host.c2_sweep, sizeof o->c2_sweep, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipStreamSynchronize(s->stream));
+    // Eq. (3) normalised with N atoms at number density N / L^3
+    const double N = (double)s->g.N, rho = N / (s->g.L * s->g.L * s->g.L), fr = (double)o->n_gofr_frames;
+    for (uint32_t b = 0; b < o->gofr_nbins && fr > 0.0; ++b) {
+        const double r0 = o->gofr_dr * b, r1 = o->gofr_dr * (b + 1);
+        const double ideal = fr * N * rho * 4.0 * M_PI / 3.0 * (r1 * r1 * r1 - r0 * r0 * r0);
+        o->gofr_norm_all[b] = (double)o->gofr_all[b] / ideal;
+        o->gofr_norm_inter[b] = (double)o->gofr_inter[b] / ideal;
+    }
+    return MC_OK;
+}
+
+int mcf_reset_observables(mcf_system* s)
+{
+    if (!s) return fx_fail(MC_EINVAL, "null system");
+    s->origin = s->sweep;
+    return fx_events(s, kFlagObsReset);
+}
+
+int mcf_get_state(mcf_system* s, double* pos, uint8_t* types, uint64_t* sweep, double* e_acc)
+{
+    if (!s) return fx_fail(MC_EINVAL, "null system");
+    const uint32_t N = s->g.N;
+    std::vector<double> x(3 * (size_t)N);
+    FXCHK(hipMemcpyAsync(x.data(), s->host.pos, x.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    if (types) FXCHK(hipMemcpyAsync(types, s->host.type, N, hipMemcpyDeviceToHost, s->stream));
+    Stats st;
+    if (int rc = fx_read_stats(s, &st)) return rc;
+    if (pos)
+        for (uint32_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) pos[3 * i + d] = x[(size_t)d * N + i];
+    if (sweep) *sweep = st.sweep;
+    if (e_acc) *e_acc = st.e_acc;
+    return MC_OK;
+}
+
+int mcf_set_state(mcf_system* s, const double* pos, const uint8_t* types, uint64_t sweep, double e_acc)
+{
+    if (!s || !pos || !types) return fx_fail(MC_EINVAL, "null argument");
+    int rc = fx_upload_state(s, pos, types);
+    if (rc) return rc;
+    Stats st;
+    if ((rc = fx_read_stats(s, &st))) return rc;
+    st.sweep = sweep;
+    st.e_acc = std::isnan(e_acc) ? 0.0 : e_acc;
+    if (sweep < s->origin) {
+        st.obs_origin = sweep;
+        s->origin = sweep;
+    }
+    FXCHK(hipMemcpyAsync(s->host.stats, &st, sizeof st, hipMemcpyHostToDevice, s->stream));
+    FXCHK(hipStreamSynchronize(s->stream));
+    s->sweep = sweep;
+    if (std::isnan(e_acc)) {
+        if ((rc = fx_events(s, kFlagResumSet))) return rc;
+        if ((rc = fx_read_stats(s, &st))) return rc;
+        if (!std::isfinite(st.e_acc)) return fx_fail(MC_ENONFINITE, "energy of the new state is not finite");
+    }
+    return MC_OK;
+}
+
+int mcf_decision_log(mcf_system* s, void* device_records, size_t capacity)
+{
+    if (!s) return fx_fail(MC_EINVAL, "null system");
+    Stats st;
+    if (int rc = fx_read_stats(s, &st)) return rc;
+    s->host.log = (MoveRecord*)device_records;
+    s->host.log_sweep0 = st.sweep;
+    s->host.log_sweeps = device_records ? capacity / s->g.N : 0;
+    return fx_upload_desc(s);
+}
+
+void mcf_destroy(mcf_system* s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    delete s;
+}
+
+}  // extern "C"

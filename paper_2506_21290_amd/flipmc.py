@@ -35,7 +35,12 @@ EXPORTED = [
     "mc_last_error", "mc_batch_required_bytes", "mc_batch_create",
     "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
     "mc_batch_set_workgroups", "mc_dynamics",
+    "mcf_params_default", "mcf_geometry", "mcf_required_bytes", "mcf_init_system", "mcf_sweep",
+    "mcf_energy", "mcf_observables", "mcf_reset_observables", "mcf_get_state", "mcf_set_state",
+    "mcf_decision_log", "mcf_destroy",
 ]
+MC_TRIANGLE, MC_SQUARE, MC_TETRAHEDRON = 0, 1, 2
+SITES = {MC_TRIANGLE: 3, MC_SQUARE: 4, MC_TETRAHEDRON: 4}
 
 
 class McError(RuntimeError):
@@ -109,6 +114,31 @@ class mc_obs(C.Structure):
         ("fs_sq", C.c_double * MC_C2_MAX),
         ("gofr_norm_all", C.c_double * MC_GOFR_MAX_BINS),
         ("gofr_norm_inter", C.c_double * MC_GOFR_MAX_BINS),
+    ]
+
+
+class mcf_params(C.Structure):
+    _fields_ = [
+        ("geometry", C.c_uint32),
+        ("n_molecules", C.c_uint32),
+        ("density", C.c_double),
+        ("temperature", C.c_double),
+        ("sigma", C.c_double * 4),
+        ("bond_length", C.c_double),
+        ("p_flip", C.c_double),
+        ("max_displacement", C.c_double),
+        ("seed", C.c_uint64),
+        ("colours_per_axis", C.c_uint32),
+        ("cells_per_side", C.c_uint32),
+        ("resum_interval", C.c_uint32),
+        ("obs_interval", C.c_uint32),
+        ("gofr_interval", C.c_uint32),
+        ("obs_start", C.c_uint32),
+        ("max_samples", C.c_uint32),
+        ("reserved", C.c_uint32),
+        ("gofr_dr", C.c_double),
+        ("fs_q", C.c_double),
+        ("fs_q_cm", C.c_double),
     ]
 
 
@@ -189,6 +219,21 @@ def lib():
         L.mc_batch_destroy.argtypes = [vp]
         L.mc_batch_destroy.restype = None
         L.mc_dynamics.argtypes = [C.POINTER(mc_obs), C.c_size_t, C.c_uint32, C.POINTER(mc_dyn)]
+        fp = C.POINTER(mcf_params)
+        L.mcf_params_default.argtypes = [fp, C.c_uint32]
+        L.mcf_params_default.restype = None
+        L.mcf_geometry.argtypes = [fp, dp, u32p, u32p]
+        L.mcf_required_bytes.argtypes = [fp, szp]
+        L.mcf_init_system.argtypes = [fp, dp, u8p, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.mcf_sweep.argtypes = [vp, C.c_uint64]
+        L.mcf_energy.argtypes = [vp, dp, dp, dp]
+        L.mcf_observables.argtypes = [vp, C.POINTER(mc_obs)]
+        L.mcf_reset_observables.argtypes = [vp]
+        L.mcf_get_state.argtypes = [vp, dp, u8p, u64p, dp]
+        L.mcf_set_state.argtypes = [vp, dp, u8p, C.c_uint64, C.c_double]
+        L.mcf_decision_log.argtypes = [vp, vp, C.c_size_t]
+        L.mcf_destroy.argtypes = [vp]
+        L.mcf_destroy.restype = None
         _lib = L
     return _lib
 
@@ -221,7 +266,7 @@ def _close_all():
         if isinstance(o, Batch):
             o.close()
     for o in objs:
-        if isinstance(o, System):
+        if isinstance(o, (System, FlexSystem)):
             o.close()
     _live.clear()
 
@@ -509,3 +554,136 @@ class Batch:
     def cancel(self, slot):
         _check(lib().mc_batch_cancel(self.h, int(slot)))
         return self.members.pop(int(slot))
+
+
+# ------------------------------------------------------ flexible molecules --
+
+def mcf_params_default(geometry=MC_TRIANGLE, **overrides) -> mcf_params:
+    p = mcf_params()
+    lib().mcf_params_default(C.byref(p), int(geometry))
+    for k, v in overrides.items():
+        if k == "sigma":
+            p.sigma = (C.c_double * 4)(*(list(v) + [0.0] * (4 - len(v))))
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def mcf_geometry(p: mcf_params):
+    box, k, nc = C.c_double(), C.c_uint32(), C.c_uint32()
+    _check(lib().mcf_geometry(C.byref(p), C.byref(box), C.byref(k), C.byref(nc)))
+    return box.value, k.value, nc.value
+
+
+def mcf_required_bytes(p: mcf_params) -> int:
+    n = C.c_size_t()
+    _check(lib().mcf_required_bytes(C.byref(p), C.byref(n)))
+    return n.value
+
+
+class FlexSystem:
+    """One Markov chain of flexible molecules (atoms as the moving unit) in a
+    torch-owned device buffer."""
+
+    def __init__(self, params: mcf_params, pos=None, types=None, stream=None, device="cuda"):
+        import torch
+
+        self.params = params
+        self.n = SITES[params.geometry]
+        self.M = params.n_molecules
+        self.N = self.n * self.M
+        nbytes = mcf_required_bytes(params)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._stream_handle, self.stream = _stream_handle(stream)
+        self._lib = lib()
+        h = C.c_void_p()
+        if pos is None:
+            args = (None, None)
+        else:
+            pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
+            types = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
+            args = (_ptr(pos, C.c_double), _ptr(types, C.c_uint8))
+        _check(self._lib.mcf_init_system(C.byref(params), *args, C.c_void_p(self.buffer.data_ptr()),
+                                         nbytes, self._stream_handle, C.byref(h)))
+        self.h = h
+        self._log = None
+        _track(self)
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self._lib.mcf_destroy(h)
+        self.h = None
+        self.buffer = None
+        self._log = None
+
+    def __del__(self):
+        self.close()
+
+    def sweep(self, n=1):
+        _check(self._lib.mcf_sweep(self.h, int(n)))
+
+    def energy(self):
+        e, em, d = C.c_double(), C.c_double(), C.c_double()
+        _check(self._lib.mcf_energy(self.h, C.byref(e), C.byref(em), C.byref(d)))
+        return e.value, em.value, d.value
+
+    def obs_struct(self) -> mc_obs:
+        o = mc_obs()
+        _check(self._lib.mcf_observables(self.h, C.byref(o)))
+        return o
+
+    def observables(self) -> dict:
+        o = self.obs_struct()
+        nb = o.gofr_nbins
+        return {
+            "sweep": o.sweep, "attempts": np.array(o.attempts[:], dtype=np.uint64),
+            "accepts": np.array(o.accepts[:], dtype=np.uint64), "exits": o.exits,
+            "pair_terms": o.pair_terms, "e_acc": o.e_acc, "e_resum": o.e_resum, "drift": o.drift,
+            "max_abs_drift": o.max_abs_drift, "n_energy_samples": o.n_energy_samples,
+            "energy_sum": o.energy_sum, "energy_sumsq": o.energy_sumsq,
+            "n_gofr_frames": o.n_gofr_frames, "gofr_dr": o.gofr_dr,
+            "gofr_all": np.array(o.gofr_all[:nb], dtype=np.uint64),
+            "gofr_inter": np.array(o.gofr_inter[:nb], dtype=np.uint64),
+            "gofr_norm_all": np.array(o.gofr_norm_all[:nb]),
+            "gofr_norm_inter": np.array(o.gofr_norm_inter[:nb]),
+            "c2_sweep": np.array(o.c2_sweep[: o.n_c2], dtype=np.uint64),
+            "c2": np.array(o.c2[: o.n_c2]), "fs": np.array(o.fs[: o.n_c2]),
+            "fs_cm": np.array(o.fs_cm[: o.n_c2]),
+        }
+
+    def reset_observables(self):
+        _check(self._lib.mcf_reset_observables(self.h))
+
+    def get_state(self):
+        pos = np.zeros(3 * self.N)
+        types = np.zeros(self.N, dtype=np.uint8)
+        sweep, e = C.c_uint64(), C.c_double()
+        _check(self._lib.mcf_get_state(self.h, _ptr(pos, C.c_double), _ptr(types, C.c_uint8),
+                                       C.byref(sweep), C.byref(e)))
+        return {"pos": pos.reshape(self.N, 3), "types": types, "sweep": sweep.value, "e_acc": e.value}
+
+    def set_state(self, pos, types, sweep, e_acc=math.nan):
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
+        types = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
+        _check(self._lib.mcf_set_state(self.h, _ptr(pos, C.c_double), _ptr(types, C.c_uint8),
+                                       int(sweep), float(e_acc)))
+
+    def decision_log(self, n_sweeps):
+        import torch
+
+        if n_sweeps <= 0:
+            _check(self._lib.mcf_decision_log(self.h, None, 0))
+            self._log = None
+            return None
+        cap = n_sweeps * self.N
+        buf = torch.zeros(cap * MOVE_RECORD_DTYPE.itemsize, dtype=torch.uint8, device=self.buffer.device)
+        _check(self._lib.mcf_decision_log(self.h, C.c_void_p(buf.data_ptr()), cap))
+        self._log = buf
+        return buf
+
+    def read_log(self):
+        if self._log is None:
+            return None
+        self.stream.synchronize()
+        return np.frombuffer(self._log.cpu().numpy().tobytes(), dtype=MOVE_RECORD_DTYPE).copy()

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "flipmc.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mc_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mcf?_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported():

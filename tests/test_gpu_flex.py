@@ -1,0 +1,195 @@
+"""Parity of the flexible-molecule engine (the paper's own FENE-bonded
+molecule, Sec. II.A, and the squares and tetrahedra of Sec. VII) with the
+serial FP64 oracle of oracle/flex_oracle.c, attempt by attempt through the C
+ABI.  Bars: proposals (move, flip rotation, cell exits) identical; dE and S
+within 1e-12 S, infinite on the same attempts (a bond at its limit);
+decisions identical outside |dE + T ln u| < 1e-12 S + 1e-9; positions bitwise
+and types equal while no decision differed; observables within 1e-12."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import flex  # noqa: E402
+from oracle import oracle as rig  # noqa: E402
+from paper_2506_21290_amd import flipmc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "triangle": (flipmc.MC_TRIANGLE, 125, 2.0, 3, 3, 1.2),
+    "square": (flipmc.MC_SQUARE, 125, 2.0, 3, 3, 0.3),
+    "tetrahedron": (flipmc.MC_TETRAHEDRON, 125, 2.0, 3, 3, 1.2),
+    "triangle_1000": (flipmc.MC_TRIANGLE, 1000, 0.75, 3, 6, 1.2),
+}
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gp(g, M, T, k, nc, rho, seed=1, **kw):
+    return flipmc.mcf_params_default(g, n_molecules=M, temperature=T, colours_per_axis=k, cells_per_side=nc,
+                                     density=rho, seed=seed, **kw)
+
+
+def op(g, M, T, k, nc, rho, seed=1, **kw):
+    return flex.Params(n_molecules=M, temperature=T, geometry=g, colours_per_axis=k, cells_per_side=nc,
+                       density=rho, seed=seed, **kw)
+
+
+def compare(lg, lo):
+    """One sweep's records, both indexed by atom; True when a near-tie
+    decision differed."""
+    assert np.array_equal(lg["molecule"], np.arange(len(lg)))
+    assert np.array_equal(lg["sweep"], lo["sweep"])
+    assert np.array_equal(lg["move"], lo["move"])
+    assert np.array_equal(lg["exited"], lo["exited"])
+    assert np.array_equal(lg["axis"], lo["kind"])
+    np.testing.assert_allclose(lg["t_log_u"], lo["t_log_u"], rtol=1e-14, atol=1e-300)
+    ok = lo["exited"] == 0
+    inf_o = np.isinf(lo["delta_e"])
+    assert np.array_equal(np.isinf(lg["delta_e"]), inf_o)
+    fin = ok & ~inf_o
+    tol = 1e-12 * lo["scale"][fin] + 1e-300
+    assert np.all(np.abs(lg["delta_e"][fin] - lo["delta_e"][fin]) <= tol)
+    assert np.all(np.abs(lg["scale"][fin] - lo["scale"][fin]) <= tol)
+    assert not np.any(lg["accepted"][inf_o])
+    band = np.abs(lo["delta_e"] + lo["t_log_u"]) < 1e-12 * lo["scale"] + 1e-9
+    differ = lg["accepted"] != lo["accepted"]
+    assert not np.any(differ & ~band)
+    assert np.mean(lg["pair_terms"][fin] != lo["pair_terms"][fin]) < 1e-3
+    return bool(np.any(differ))
+
+
+def run(case, n_sweeps, seed=1):
+    g, M, T, k, nc, rho = CASES[case]
+    print(f"flex {case} M={M} sweeps={n_sweeps}", flush=True)
+    p = gp(g, M, T, k, nc, rho, seed=seed)
+    assert flipmc.mcf_geometry(p)[1:] == (k, nc)
+    s = flipmc.FlexSystem(p)
+    o = flex.System(op(g, M, T, k, nc, rho, seed=seed))
+    # the engine's own lattice start equals the oracle's up to the last bits of
+    # sin, cos and sqrt; the chains are then compared from the oracle's start
+    st, so = s.get_state(), o.get_state()
+    assert np.array_equal(st["types"], so["types"])
+    assert np.max(np.abs(st["pos"] - so["pos"])) < 1e-12
+    assert s.energy()[0] == pytest.approx(o.energy(), rel=1e-9)
+    s.set_state(so["pos"], so["types"], 0)
+    assert s.energy()[0] == pytest.approx(o.energy(), rel=1e-12)
+    resyncs = 0
+    for _ in range(n_sweeps):
+        s.decision_log(1)
+        s.sweep(1)
+        lg = s.read_log()
+        lo = o.sweep_checkerboard(1, log=True)
+        if compare(lg, lo):
+            x = o.get_state()
+            s.set_state(x["pos"], x["types"], x["sweep"], x["e_acc"])
+            resyncs += 1
+            continue
+        st, so = s.get_state(), o.get_state()
+        assert st["sweep"] == so["sweep"]
+        assert np.array_equal(st["pos"], so["pos"])
+        assert np.array_equal(st["types"], so["types"])
+    return s, o, resyncs
+
+
+@pytest.mark.parametrize("case", ["triangle", "square", "tetrahedron"])
+def test_every_attempt_matches_the_oracle(case):
+    s, o, resyncs = run(case, 12)
+    assert resyncs == 0
+    e, _, drift = s.energy()
+    assert e == pytest.approx(o.energy(), rel=1e-10)
+    # E_0 + the accepted dE, against the fresh FP64 re-sum
+    assert abs(drift) <= 1e-9 * abs(e)
+    c = s.observables()
+    oc = o.counters()
+    assert list(c["attempts"]) == list(oc["attempts"]) and list(c["accepts"]) == list(oc["accepts"])
+    assert c["exits"] == oc["exits"]
+
+
+def test_full_size_1000_triangles():
+    # the paper's system size (M = 1000, N = 3000 atoms) at T = 0.75
+    s, o, resyncs = run("triangle_1000", 3)
+    assert resyncs <= 1
+
+
+def test_fene_wall_on_the_device():
+    # a stretched triangle (bond 0-1 at 1.5 with types B, C): flips that put
+    # A on that bond reach the bond's limit; the engine gives dE = inf on the
+    # same attempts as the oracle and never accepts them
+    print("flex fene wall", flush=True)
+    kw = dict(p_flip=0.5)
+    p = gp(flipmc.MC_TRIANGLE, 1, 1e6, 2, 2, 0.001, seed=5, **kw)
+    o = flex.System(op(flipmc.MC_TRIANGLE, 1, 1e6, 2, 2, 0.001, seed=5, **kw), lattice=False)
+    L = o.box
+    pos = np.array([[L / 2, L / 2, L / 2], [L / 2 + 1.5, L / 2, L / 2], [L / 2 + 0.75, L / 2 + 0.9, L / 2]])
+    types = np.array([1, 2, 0], dtype=np.uint8)
+    s = flipmc.FlexSystem(p, pos=pos, types=types)
+    o.set_state(pos, types, 0)
+    walls = 0
+    for _ in range(60):
+        s.decision_log(1)
+        s.sweep(1)
+        lg = s.read_log()
+        lo = o.sweep_checkerboard(1, log=True)
+        assert not compare(lg, lo)
+        walls += int(np.isinf(lg["delta_e"]).sum())
+    assert walls > 0
+
+
+def test_observables_match_the_oracle():
+    # g(r) counts of every ordered atom pair (Eq. 3), C_2 (Eq. 7), F_s and
+    # F_s^cm (Eqs. 5-6) at the sample sweeps, on the 125-triangle system
+    g, M, T, k, nc, rho = CASES["triangle"]
+    p = gp(g, M, T, k, nc, rho, seed=3, gofr_interval=5, obs_interval=5, resum_interval=10)
+    o = flex.System(op(g, M, T, k, nc, rho, seed=3))
+    so = o.get_state()
+    s = flipmc.FlexSystem(p, pos=so["pos"], types=so["types"])
+    n = 20
+    s.sweep(n)
+    obs = s.observables()
+    nb = len(obs["gofr_all"])
+    ca = np.zeros(nb, dtype=np.uint64)
+    ci = np.zeros(nb, dtype=np.uint64)
+    u0, kref = o.orientation_ref()
+    a0, c0 = o.unwrapped()
+    want = {}
+    for t in range(1, n + 1):
+        o.sweep_checkerboard(1)
+        if t % 5 == 0:
+            o.gofr_accumulate(ca, ci, dr=p.gofr_dr)
+        if t in (1, 2, 5, 10, 20):
+            a, c = o.unwrapped()
+            want[t] = (float(np.mean(o.c2_terms(u0, kref))),
+                       rig.fs_isotropic(a - a0, p.fs_q), rig.fs_isotropic(c - c0, p.fs_q_cm))
+    assert obs["n_gofr_frames"] == 4
+    assert np.abs(obs["gofr_all"].astype(np.int64) - ca.astype(np.int64)).sum() <= 4
+    assert np.abs(obs["gofr_inter"].astype(np.int64) - ci.astype(np.int64)).sum() <= 4
+    assert [int(t) for t in obs["c2_sweep"]] == [1, 2, 5, 10, 20]
+    for j, t in enumerate([1, 2, 5, 10, 20]):
+        assert obs["c2"][j] == pytest.approx(want[t][0], abs=1e-12)
+        assert obs["fs"][j] == pytest.approx(want[t][1], abs=1e-12)
+        assert obs["fs_cm"][j] == pytest.approx(want[t][2], abs=1e-12)
+    g_norm = rig.gofr_normalise(obs["gofr_all"], 4, 3 * M, o.box, p.gofr_dr)
+    np.testing.assert_allclose(obs["gofr_norm_all"], g_norm, rtol=1e-12)
+
+
+def test_state_roundtrip_and_bad_types():
+    g, M, T, k, nc, rho = CASES["tetrahedron"]
+    s = flipmc.FlexSystem(gp(g, M, T, k, nc, rho))
+    s.sweep(3)
+    st = s.get_state()
+    s2 = flipmc.FlexSystem(gp(g, M, T, k, nc, rho), pos=st["pos"], types=st["types"])
+    assert np.array_equal(s2.get_state()["pos"], st["pos"])
+    assert s2.energy()[0] == pytest.approx(s.energy()[0], rel=1e-12)
+    bad = st["types"].copy()
+    bad[0] = bad[1]
+    with pytest.raises(flipmc.McError) as e:
+        s2.set_state(st["pos"], bad, 0)
+    assert e.value.code == flipmc.MC_EINVAL
