@@ -371,6 +371,26 @@ int mcf_required_bytes(const mcf_params* p, size_t* bytes);
 int mcf_init_system(const mcf_params* p, const double* pos, const uint8_t* types, void* device_buf,
                     size_t buf_bytes, void* hip_stream, mcf_system** out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid it): mcf_init_system without any
+ * allocation by the library.  The caller's device_state (256-byte aligned,
+ * at least *state_bytes_needed bytes, must outlive the system) holds the
+ * state and the observables; the work arrays of the sweeps and events (cell
+ * lists, per-cell energies, partial sums) live in one static per-device array
+ * of 4 MiB, so MC_ENOMEM when they would exceed it.  Clearing is done by a
+ * kernel (no memset), host positions are staged through the state buffer, and
+ * the handle comes from a static pool of 16 (MC_EBUSY when all are alive).
+ * With device_state NULL the call only stores *state_bytes_needed (and the
+ * scratch check) and returns.  Every allocation-free system of a device
+ * shares that array: calls on such systems whose work overlaps in time (other
+ * streams, other threads) race; one after another on one stream is safe, as
+ * every launch rewrites what it reads.  mcf_sweep, mcf_energy,
+ * mcf_observables, mcf_reset_observables, mcf_decision_log and mcf_destroy
+ * allocate nothing either. */
+int mcf_init_system_noalloc(const mcf_params* p, const double* pos, const uint8_t* types,
+                            void* device_state, size_t state_bytes, size_t* state_bytes_needed,
+                            void* hip_stream, mcf_system** out);
+
 /* Enqueue n timesteps of N attempts (Sec. II.B).  Asynchronous. */
 int mcf_sweep(mcf_system* s, uint64_t n_sweeps);
 

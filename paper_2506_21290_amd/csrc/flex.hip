@@ -29,6 +29,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -665,6 +666,22 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_events(FxDev* __restrict__ Dp
     }
 }
 
+// Zero n 8-byte words (instead of a memset node, which some callers cannot record).
+__global__ void k_fx_zero(uint64_t* __restrict__ p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Host positions staged as xyz per atom in `aos` -> the SoA state, wrapped.
+__global__ void k_fx_from_aos(FxDev* __restrict__ Dp, const double* __restrict__ aos)
+{
+    const FxDev& D = *Dp;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= D.N) return;
+    for (int d = 0; d < 3; ++d) D.pos[(size_t)d * D.N + i] = fx_wrap(aos[3 * (size_t)i + d], D.L);
+}
+
 __global__ void k_fx_init_lattice(FxDev* __restrict__ Dp, uint32_t nl, double side)
 {
     const FxDev& D = *Dp;
@@ -922,6 +939,7 @@ struct mcf_system {
     FxDev* dev;
     hipStream_t stream;
     uint64_t sweep, origin;
+    int pooled;  // index + 1 of the static handle slot (mcf_init_system_noalloc), 0 otherwise
 };
 
 namespace {
@@ -1067,34 +1085,78 @@ int mcf_required_bytes(const mcf_params* p, size_t* bytes)
     return MC_OK;
 }
 
-int mcf_init_system(const mcf_params* p, const double* pos, const uint8_t* types, void* device_buf,
-                    size_t buf_bytes, void* hip_stream, mcf_system** out)
+}  // extern "C"
+
+namespace {
+
+// Scratch of the allocation-free entry point: the work arrays (cell lists,
+// per-cell energies, partial sums) of one flexible system at a time per
+// device.  Host code takes its address per device with hipGetSymbolAddress.
+constexpr size_t kFxScratchBytes = size_t(4) << 20;
+__device__ __align__(256) unsigned char fx_scratch[kFxScratchBytes];
+
+constexpr int kFxMaxDevices = 64;
+constexpr int kFxPool = 16;  // handles of allocation-free systems alive at once
+std::mutex g_fx_mu;
+void* g_fx_scratch[kFxMaxDevices];
+mcf_system g_fx_pool[kFxPool];
+bool g_fx_used[kFxPool];
+
+// The device address of this device's scratch (once per device).
+int fx_scratch_ptr(void** out)
 {
-    if (!out) return fx_fail(MC_EINVAL, "null output handle");
-    *out = nullptr;
-    FxGeom g;
-    int rc = fx_geometry(p, &g);
-    if (rc) return rc;
+    int dev = 0;
+    FXCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kFxMaxDevices) return fx_fail(MC_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_fx_mu);
+    if (!g_fx_scratch[dev]) {
+        void* p = nullptr;
+        FXCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(fx_scratch)));
+        g_fx_scratch[dev] = p;
+    }
+    *out = g_fx_scratch[dev];
+    return MC_OK;
+}
+
+int fx_validate_input(const mcf_system* s, const double* pos, const uint8_t* types)
+{
+    const uint32_t N = s->g.N, n = s->g.n;
+    for (size_t i = 0; i < 3 * (size_t)N; ++i)
+        if (!std::isfinite(pos[i])) return fx_fail(MC_EINVAL, "position of atom %zu is not finite", i / 3);
+    for (uint32_t m = 0; m < s->p.n_molecules; ++m) {
+        uint32_t seen = 0;
+        for (uint32_t t = 0; t < n; ++t) {
+            const uint32_t ty = types[n * m + t];
+            if (ty >= n || (seen >> ty) & 1u)
+                return fx_fail(MC_EINVAL, "types of molecule %u are not a permutation of 0..%u", m, n - 1);
+            seen |= 1u << ty;
+        }
+    }
+    return MC_OK;
+}
+
+// Lay out, clear and start system s: its state in `state` (the layout's
+// regions before the work arrays), its work arrays at `work` (work_off = the
+// layout offset that lands on `work`).  no_alloc: clear with a kernel and
+// stage host positions through the state's own r0 region, so that nothing is
+// allocated.
+int fx_init(mcf_system* s, const mcf_params* p, const FxGeom& g, const FxLayout& lay, const double* pos,
+            const uint8_t* types, uint8_t* state, uint8_t* work, size_t work_off, hipStream_t stream,
+            bool no_alloc)
+{
     const bool lattice = !pos && !types;
-    if (!lattice && !(pos && types)) return fx_fail(MC_EINVAL, "give pos and types together, or neither");
     uint32_t nl = 1;
     while ((nl + 1) * (nl + 1) * (nl + 1) <= p->n_molecules) ++nl;
-    if (lattice && nl * nl * nl != p->n_molecules)
-        return fx_fail(MC_EINVAL, "lattice start needs n_molecules = n^3 (got %u)", p->n_molecules);
-    if (!device_buf) return fx_fail(MC_EINVAL, "null device buffer");
-    if (((uintptr_t)device_buf & 255u) != 0) return fx_fail(MC_EINVAL, "device buffer must be 256-byte aligned");
-    const FxLayout lay = fx_layout(p, g);
-    if (buf_bytes < lay.total) return fx_fail(MC_ENOMEM, "device buffer of %zu bytes, %zu needed", buf_bytes, lay.total);
-
-    mcf_system* s = new mcf_system();
     s->p = *p;
     s->g = g;
     s->lay = lay;
-    s->stream = (hipStream_t)hip_stream;
+    s->stream = stream;
     s->sweep = s->origin = 0;
+    if (!lattice)
+        if (int rc = fx_validate_input(s, pos, types)) return rc;
     FxDev& D = s->host;
     std::memset(&D, 0, sizeof D);
-    uint8_t* b = (uint8_t*)device_buf;
+    uint8_t* b = state;
     D.geometry = p->geometry;
     D.n = g.n;
     D.M = p->n_molecules;
@@ -1147,32 +1209,120 @@ int mcf_init_system(const mcf_params* p, const double* pos, const uint8_t* types
     D.kref = b + lay.kref;
     D.r0 = (double*)(b + lay.r0);
     D.rcm0 = (double*)(b + lay.rcm0);
-    D.cell_start = (uint32_t*)(b + lay.cstart);
-    D.cell_list = (uint32_t*)(b + lay.clist);
-    D.cell_id = (uint32_t*)(b + lay.cid);
-    D.ecell = (double*)(b + lay.ecell);
-    D.part = (double*)(b + lay.part);
+    D.cell_start = (uint32_t*)(work + (lay.cstart - work_off));
+    D.cell_list = (uint32_t*)(work + (lay.clist - work_off));
+    D.cell_id = (uint32_t*)(work + (lay.cid - work_off));
+    D.ecell = (double*)(work + (lay.ecell - work_off));
+    D.part = (double*)(work + (lay.part - work_off));
     s->dev = (FxDev*)(b + lay.dev);
-    auto bail = [&](int code) {
-        delete s;
-        return code;
-    };
-    hipError_t e = hipMemsetAsync(device_buf, 0, lay.total, s->stream);
-    if (e != hipSuccess) return bail(fx_fail(MC_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e)));
-    if ((rc = fx_upload_desc(s))) return bail(rc);
+    int rc;
+    if (no_alloc) {
+        // both regions are multiples of 256 bytes
+        hipLaunchKernelGGL(k_fx_zero, dim3(256), dim3(256), 0, stream, (uint64_t*)state, lay.cstart / 8);
+        FXCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_fx_zero, dim3(256), dim3(256), 0, stream, (uint64_t*)(work), (lay.total - lay.cstart) / 8);
+        FXCHK(hipGetLastError());
+    } else {
+        FXCHK(hipMemsetAsync(state, 0, lay.total, stream));
+    }
+    if ((rc = fx_upload_desc(s))) return rc;
     if (lattice) {
         const double side = p->bond_length > 0 ? p->bond_length : fx_bond_star();
-        hipLaunchKernelGGL(k_fx_init_lattice, dim3((p->n_molecules + 255) / 256), dim3(256), 0, s->stream,
+        hipLaunchKernelGGL(k_fx_init_lattice, dim3((p->n_molecules + 255) / 256), dim3(256), 0, stream,
                            s->dev, nl, side);
-        e = hipGetLastError();
-        if (e != hipSuccess) return bail(fx_fail(MC_EDEVICE, "lattice kernel: %s", hipGetErrorString(e)));
+        FXCHK(hipGetLastError());
+    } else if (no_alloc) {
+        FXCHK(hipMemcpyAsync(D.r0, pos, 3 * sizeof(double) * g.N, hipMemcpyHostToDevice, stream));
+        FXCHK(hipMemcpyAsync(D.type, types, g.N, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(k_fx_from_aos, dim3((g.N + 255) / 256), dim3(256), 0, stream, s->dev,
+                           (const double*)D.r0);
+        FXCHK(hipGetLastError());
     } else if ((rc = fx_upload_state(s, pos, types))) {
-        return bail(rc);
+        return rc;
     }
-    if ((rc = fx_events(s, kFlagResumSet | kFlagObsReset))) return bail(rc);
+    if ((rc = fx_events(s, kFlagResumSet | kFlagObsReset))) return rc;
     Stats st;
-    if ((rc = fx_read_stats(s, &st))) return bail(rc);
-    if (!std::isfinite(st.e_acc)) return bail(fx_fail(MC_ENONFINITE, "initial energy is not finite"));
+    if ((rc = fx_read_stats(s, &st))) return rc;
+    if (!std::isfinite(st.e_acc)) return fx_fail(MC_ENONFINITE, "initial energy is not finite");
+    return MC_OK;
+}
+
+int fx_check_request(const mcf_params* p, const double* pos, const uint8_t* types, FxGeom* g)
+{
+    int rc = fx_geometry(p, g);
+    if (rc) return rc;
+    const bool lattice = !pos && !types;
+    if (!lattice && !(pos && types)) return fx_fail(MC_EINVAL, "give pos and types together, or neither");
+    uint32_t nl = 1;
+    while ((nl + 1) * (nl + 1) * (nl + 1) <= p->n_molecules) ++nl;
+    if (lattice && nl * nl * nl != p->n_molecules)
+        return fx_fail(MC_EINVAL, "lattice start needs n_molecules = n^3 (got %u)", p->n_molecules);
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcf_init_system(const mcf_params* p, const double* pos, const uint8_t* types, void* device_buf,
+                    size_t buf_bytes, void* hip_stream, mcf_system** out)
+{
+    if (!out) return fx_fail(MC_EINVAL, "null output handle");
+    *out = nullptr;
+    FxGeom g;
+    if (int rc = fx_check_request(p, pos, types, &g)) return rc;
+    if (!device_buf) return fx_fail(MC_EINVAL, "null device buffer");
+    if (((uintptr_t)device_buf & 255u) != 0) return fx_fail(MC_EINVAL, "device buffer must be 256-byte aligned");
+    const FxLayout lay = fx_layout(p, g);
+    if (buf_bytes < lay.total) return fx_fail(MC_ENOMEM, "device buffer of %zu bytes, %zu needed", buf_bytes, lay.total);
+    mcf_system* s = new mcf_system();
+    s->pooled = 0;
+    uint8_t* b = (uint8_t*)device_buf;
+    if (int rc = fx_init(s, p, g, lay, pos, types, b, b, 0, (hipStream_t)hip_stream, false)) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return MC_OK;
+}
+
+int mcf_init_system_noalloc(const mcf_params* p, const double* pos, const uint8_t* types,
+                            void* device_state, size_t state_bytes, size_t* state_bytes_needed,
+                            void* hip_stream, mcf_system** out)
+{
+    FxGeom g;
+    if (int rc = fx_check_request(p, pos, types, &g)) return rc;
+    const FxLayout lay = fx_layout(p, g);
+    const size_t need = lay.cstart, work = lay.total - lay.cstart;
+    if (state_bytes_needed) *state_bytes_needed = need;
+    if (work > kFxScratchBytes)
+        return fx_fail(MC_ENOMEM, "work arrays of %zu bytes exceed the static scratch of %zu bytes", work,
+                       kFxScratchBytes);
+    if (!device_state) return MC_OK;  // size query
+    if (!out) return fx_fail(MC_EINVAL, "null output handle");
+    *out = nullptr;
+    if (((uintptr_t)device_state & 255u) != 0) return fx_fail(MC_EINVAL, "device buffer must be 256-byte aligned");
+    if (state_bytes < need) return fx_fail(MC_ENOMEM, "device buffer of %zu bytes, %zu needed", state_bytes, need);
+    void* scratch = nullptr;
+    if (int rc = fx_scratch_ptr(&scratch)) return rc;
+    int slot = -1;
+    {
+        std::lock_guard<std::mutex> lk(g_fx_mu);
+        for (int i = 0; i < kFxPool && slot < 0; ++i)
+            if (!g_fx_used[i]) {
+                g_fx_used[i] = true;
+                slot = i;
+            }
+    }
+    if (slot < 0) return fx_fail(MC_EBUSY, "%d allocation-free systems are alive already", kFxPool);
+    mcf_system* s = &g_fx_pool[slot];
+    s->pooled = slot + 1;
+    if (int rc = fx_init(s, p, g, lay, pos, types, (uint8_t*)device_state, (uint8_t*)scratch, lay.cstart,
+                         (hipStream_t)hip_stream, true)) {
+        std::lock_guard<std::mutex> lk(g_fx_mu);
+        g_fx_used[slot] = false;
+        return rc;
+    }
     *out = s;
     return MC_OK;
 }
@@ -1316,6 +1466,11 @@ void mcf_destroy(mcf_system* s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
+    if (s->pooled) {
+        std::lock_guard<std::mutex> lk(g_fx_mu);
+        g_fx_used[s->pooled - 1] = false;
+        return;
+    }
     delete s;
 }
 

@@ -37,7 +37,7 @@ EXPORTED = [
     "mc_batch_set_workgroups", "mc_dynamics",
     "mcf_params_default", "mcf_geometry", "mcf_required_bytes", "mcf_init_system", "mcf_sweep",
     "mcf_energy", "mcf_observables", "mcf_reset_observables", "mcf_get_state", "mcf_set_state",
-    "mcf_decision_log", "mcf_destroy",
+    "mcf_decision_log", "mcf_destroy", "mcf_init_system_noalloc",
 ]
 MC_TRIANGLE, MC_SQUARE, MC_TETRAHEDRON = 0, 1, 2
 SITES = {MC_TRIANGLE: 3, MC_SQUARE: 4, MC_TETRAHEDRON: 4}
@@ -232,6 +232,7 @@ def lib():
         L.mcf_get_state.argtypes = [vp, dp, u8p, u64p, dp]
         L.mcf_set_state.argtypes = [vp, dp, u8p, C.c_uint64, C.c_double]
         L.mcf_decision_log.argtypes = [vp, vp, C.c_size_t]
+        L.mcf_init_system_noalloc.argtypes = [fp, dp, u8p, vp, C.c_size_t, szp, vp, C.POINTER(vp)]
         L.mcf_destroy.argtypes = [vp]
         L.mcf_destroy.restype = None
         _lib = L
@@ -585,26 +586,40 @@ class FlexSystem:
     """One Markov chain of flexible molecules (atoms as the moving unit) in a
     torch-owned device buffer."""
 
-    def __init__(self, params: mcf_params, pos=None, types=None, stream=None, device="cuda"):
+    def __init__(self, params: mcf_params, pos=None, types=None, stream=None, device="cuda",
+                 no_alloc=False):
+        """no_alloc: create it with mcf_init_system_noalloc (the work arrays
+        in the library's static scratch, the buffer holds the state only)."""
         import torch
 
         self.params = params
         self.n = SITES[params.geometry]
         self.M = params.n_molecules
         self.N = self.n * self.M
-        nbytes = mcf_required_bytes(params)
-        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self._stream_handle, self.stream = _stream_handle(stream)
         self._lib = lib()
-        h = C.c_void_p()
         if pos is None:
             args = (None, None)
         else:
             pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
             types = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
             args = (_ptr(pos, C.c_double), _ptr(types, C.c_uint8))
-        _check(self._lib.mcf_init_system(C.byref(params), *args, C.c_void_p(self.buffer.data_ptr()),
-                                         nbytes, self._stream_handle, C.byref(h)))
+        if no_alloc:
+            need = C.c_size_t()
+            _check(self._lib.mcf_init_system_noalloc(C.byref(params), *args, None, 0, C.byref(need),
+                                                     None, None))
+            nbytes = need.value
+        else:
+            nbytes = mcf_required_bytes(params)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._stream_handle, self.stream = _stream_handle(stream)
+        h = C.c_void_p()
+        if no_alloc:
+            _check(self._lib.mcf_init_system_noalloc(C.byref(params), *args,
+                                                     C.c_void_p(self.buffer.data_ptr()), nbytes, None,
+                                                     self._stream_handle, C.byref(h)))
+        else:
+            _check(self._lib.mcf_init_system(C.byref(params), *args, C.c_void_p(self.buffer.data_ptr()),
+                                             nbytes, self._stream_handle, C.byref(h)))
         self.h = h
         self._log = None
         _track(self)

@@ -106,3 +106,16 @@ def test_box_must_hold_twice_the_reach():
             with pytest.raises(flipmc.McError) as e:
                 flipmc.mc_geometry(p)
             assert e.value.code == flipmc.MC_EGEOM
+
+
+def test_noalloc_size_query_and_limit_without_a_device():
+    # the state part of the buffer (the work arrays go to the static scratch),
+    # and a clear MC_ENOMEM when the work arrays would exceed the scratch
+    L = flipmc.lib()
+    p = flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=1000)
+    need = C.c_size_t()
+    assert L.mcf_init_system_noalloc(C.byref(p), None, None, None, 0, C.byref(need), None, None) == 0
+    assert 0 < need.value < flipmc.mcf_required_bytes(p)
+    big = flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=100 ** 3)
+    rc = L.mcf_init_system_noalloc(C.byref(big), None, None, None, 0, C.byref(need), None, None)
+    assert rc == flipmc.MC_ENOMEM and b"static scratch" in L.mc_last_error()
