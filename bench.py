@@ -7,13 +7,17 @@ checkerboard sweeps with FP32 energy differences and an FP64 re-sum every 100
 sweeps; a step is 100 sweeps (one re-sum window) including the cell builds,
 the re-sum, E/M samples, the g(r) frame and C_2 samples.  The same run in
 plain FP64 is timed beside it, then the first 200 jobs of the serving stream
-give the p50/p99 request latency ("serving"), then the CPU oracle runs on a
-bounded sample ("cpu_baseline").  Prints one JSON line.
+give the p50/p99 request latency ("serving"), the 8000-molecule system ("c2"),
+the 256-replica batch ("c3") and the paper's flexible molecules with the
+squares and tetrahedra ("flexible") each report their own roofline, and the
+CPU oracle runs on a bounded sample on one core and on all cores
+("cpu_baseline").  Prints one JSON line.
 
-Other workloads (--workload): c2 (8000 molecules), c3 (256 uneven replicas in
-one persistent launch), c4 (the serving loop) and tau (relaxation times of flip
-MC against local MC, with the four-point susceptibility and the Pearson
-coefficient of the same runs).
+Other workloads (--workload): c2, c3, c4 (the serving loop at any job count and
+memory budget), tau (relaxation times of flip MC against local MC from
+equilibrated states, with the four-point susceptibilities and the Pearson
+coefficient), flex (the flexible engine alone) and copy (the HBM calibration
+of the counter summaries).
 """
 from __future__ import annotations
 
@@ -35,11 +39,16 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 SWEEPS_PER_STEP = 100
 
 
+def progress(msg):
+    """A line on stderr when a stage of a long workload ends."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     """Hash of the kernel sources with comments and blank lines left out (a
     change of wording does not change the kernel the counters were taken on)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "engine.h"):
+    for f in ("kernels.hip", "engine.h", "wave.h", "flex.hip"):
         with open(os.path.join(ROOT, "paper_2506_21290_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -248,14 +257,15 @@ def bench_c1(args, flipmc, torch):
     }
     if args.serving_jobs > 0:
         # the request latency of the metric: the serving stream, first jobs
-        sv = bench_c4(args, flipmc, torch, n_jobs=args.serving_jobs)
+        sv = bench_c4(args, flipmc, torch, n_jobs=args.serving_jobs, check_alone=0)
         out["serving"] = {k: sv[k] for k in ("workload", "completed", "p50_latency_s", "p99_latency_s",
                                               "moves_per_s", "wall_s", "peak_concurrent_jobs")}
     if not args.no_sub:
         # the 8000-molecule system and the 256-replica batch, each with the
-        # roofline of its own dominant kernel
+        # roofline of its own dominant kernel, and the flexible molecules
         out["c2"] = bench_c2(args, flipmc, torch)
         out["c3"] = bench_c3(args, flipmc, torch)
+        out["flexible"] = bench_flex(args, flipmc, torch, sweeps=200, bodies=("triangles",))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
@@ -316,52 +326,53 @@ def bench_c2(args, flipmc, torch):
 
 
 def bench_tau(args, flipmc, torch):
-    """Relaxation of flip MC (p_flip = 0.2) and of local MC (p_flip = 0, the
-    same translation to rotation ratio) for replicas of the 1000-molecule
-    system at one temperature: each replica is equilibrated from its own
-    lattice start, then samples F_s(7.4, t), F_s^cm(5.1, t) and C_2(t) at
-    t in {1, 2, 5} x 10^j sweeps.  tau is where the replica mean crosses 1/e
-    (Sec. III.C); chi_4 (Eq. 10) is M (or 3M) times the variance of the
-    replicas' values and chi_4^self (Eq. 11) the mean per-replica variance of
-    the per-particle terms; rho (Eq. 13) is the replica mean of the Pearson
-    coefficient.  All replicas of both dynamics run in one batch."""
+    """Relaxation of flip MC against local MC (the protocol of Sec. III.B-C on
+    the rigid molecules): R replicas of the 1000-molecule system, each from its
+    own lattice start, are equilibrated by flip MC (p_flip = 0.2) for E sweeps;
+    each equilibrated state then starts two runs, one of flip MC and one of
+    local MC (p_flip = 0: translations and rotations only, in the same ratio),
+    which sample F_s(7.4, t), F_s^cm(5.1, t) and C_2(t) at t in {1, 2, 5} x 10^j
+    sweeps from a common origin.  The library forms the ensemble means, chi_4
+    (Eq. 10), chi_4^self (Eq. 11), rho (Eq. 13) and the 1/e times (Sec. III.C)
+    from the runs' observables (mc_dynamics).  Every stage runs in one batch."""
     M, T, R = 1000, args.tau_temperature, args.tau_replicas
+    E, S = args.tau_equilibration, args.tau_sweeps
     b = flipmc.Batch(2 * R, flipmc.MC_FP32_DE)
-    runs = {}
-    for kind, pf in (("flip", 0.2), ("local", 0.0)):
-        runs[kind] = []
-        for r in range(R):
-            p = flipmc.mc_params_default(n_molecules=M, temperature=T, precision=flipmc.MC_FP32_DE,
-                                         seed=r + 1, p_flip=pf, p_translate=(1.0 - pf) / 2,
-                                         resum_interval=1000, obs_interval=0, gofr_interval=0)
-            s = flipmc.System(p, stream=b.stream)
-            runs[kind].append(s)
 
-    def run_all(n):
-        for ss in runs.values():
-            for s in ss:
-                b.add(s, n)
+    def params(seed, pf):
+        return flipmc.mc_params_default(n_molecules=M, temperature=T, precision=flipmc.MC_FP32_DE, seed=seed,
+                                        p_flip=pf, p_translate=(1.0 - pf) / 2, resum_interval=1000,
+                                        obs_interval=0, gofr_interval=0)
+
+    def run_all(systems, n):
+        for s in systems:
+            b.add(s, n)
         done = 0
-        while done < 2 * R:
+        while done < len(systems):
             b.run(0)
             done += len(b.poll())
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_all(args.tau_equilibration)
-    for ss in runs.values():
-        for s in ss:
-            s.reset_observables()
-    run_all(args.tau_sweeps)
+    flip = [flipmc.System(params(r + 1, 0.2), stream=b.stream) for r in range(R)]
+    run_all(flip, E)
+    progress(f"tau: {R} replicas equilibrated ({E} sweeps)")
+    local = []
+    for r, s in enumerate(flip):
+        st = s.get_state()
+        local.append(flipmc.System(params(R + r + 1, 0.0), com=st["com"], quat=st["quat"], types=st["types"],
+                                   stream=b.stream))
+    for s in flip + local:
+        s.reset_observables()
+    run_all(flip + local, S)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out = {"workload": f"tau: {R} replicas x 2 dynamics of {M} molecules, T={T}, FP32 dE, "
-                       f"{args.tau_equilibration} + {args.tau_sweeps} sweeps each",
+    progress(f"tau: {2 * R} production runs done ({S} sweeps)")
+    out = {"workload": f"tau: {R} replicas of {M} molecules, T={T}, FP32 dE; {E} sweeps of flip-MC "
+                       f"equilibration, then {S} sweeps each of flip MC and of local MC from the same states",
            "wall_s": wall,
-           "moves_per_s": 2 * R * M * (args.tau_equilibration + args.tau_sweeps) / wall}
-    for kind, ss in runs.items():
-        # means, chi_4 (Eq. 10), chi_4^self (Eq. 11), rho (Eq. 13) and the 1/e
-        # times (Sec. III.C), formed by the library from the runs' observables
+           "moves_per_s": M * (R * E + 2 * R * S) / wall}
+    for kind, ss in (("flip", flip), ("local", local)):
         d = flipmc.mc_dynamics([s.obs_struct() for s in ss], M)
         res = {"t": [int(x) for x in d["t"]]}
         for key in ("fs", "fs_cm", "c2"):
@@ -370,9 +381,64 @@ def bench_tau(args, flipmc, torch):
                         "chi4_over_self_peak": float(np.max(ratio))}
         res["pearson_peak"] = float(np.max(d["rho"]))
         out[kind] = res
+        for s in ss:
+            s.close()
+    b.close()
+    out["equilibration_over_tau"] = {key: (E / out["flip"][key]["tau"] if out["flip"][key]["tau"] else None)
+                                     for key in ("fs", "fs_cm", "c2")}
     out["speedup"] = {key: (out["local"][key]["tau"] / out["flip"][key]["tau"]
                             if out["local"][key]["tau"] and out["flip"][key]["tau"] else None)
                       for key in ("fs", "fs_cm", "c2")}
+    return out
+
+
+def bench_flex(args, flipmc, torch, sweeps=None, bodies=("triangles", "squares", "tetrahedra")):
+    """The paper's own flexible molecules (FENE-bonded A/B/C triangles, Sec.
+    II.A) and the squares and tetrahedra of Sec. VII on the flexible engine,
+    FP64: attempted atom moves per second after a warm-up from the lattice
+    start, with the roofline of the sweep kernel (pair terms x 25 FLOP over
+    its launch time, against the FP64 vector peak)."""
+    out = {}
+    n_sweeps = sweeps or args.flex_sweeps
+    for name, g, M, T, rho in (("triangles", flipmc.MC_TRIANGLE, 1000, 0.75, 1.2),
+                               ("squares", flipmc.MC_SQUARE, 1000, 1.0, 1.2),
+                               ("tetrahedra", flipmc.MC_TETRAHEDRON, 1000, 1.0, 1.2)):
+        if name not in bodies:
+            continue
+        p = flipmc.mcf_params_default(g, n_molecules=M, temperature=T, density=rho, seed=1,
+                                      resum_interval=100, gofr_interval=0)
+        _, k, nc = flipmc.mcf_geometry(p)
+        s = flipmc.FlexSystem(p)
+        s.sweep(args.flex_warmup)
+        torch.cuda.synchronize()
+        o0 = s.observables()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        s.sweep(n_sweeps)
+        z.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(z)
+        o1 = s.observables()
+        e, em, drift = s.energy()
+        s.close()
+        N = flipmc.SITES[g] * M
+        att = o1["attempts"] - o0["attempts"]
+        acc = o1["accepts"] - o0["accepts"]
+        terms = int(o1["pair_terms"] - o0["pair_terms"])
+        achieved = terms * FLOP_PER_PAIR_TERM / (ms / 1e3) / 1e12
+        out[name] = {
+            "workload": f"{M} flexible {name} ({N} atoms), density {rho}, T={T}, k={k} n_c={nc}, FP64, "
+                        f"{args.flex_warmup} warm-up + {n_sweeps} timed sweeps of N attempts",
+            "atom_moves_per_s": N * n_sweeps / (ms / 1e3),
+            "molecule_equivalent_moves_per_s": M * n_sweeps / (ms / 1e3),
+            "accept_rate": {"translate": float(acc[0] / max(1, att[0])), "flip": float(acc[2] / max(1, att[2]))},
+            "energy_per_molecule": em,
+            "pair_interactions_per_s": terms / (ms / 1e3),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_TFLOPS["f64"], "kernel": "k_fx_sweeps", "cus_used": 1},
+            "ms": ms,
+        }
+        progress(f"flex: {name} done")
     return out
 
 
@@ -456,7 +522,7 @@ def bench_c3(args, flipmc, torch):
     }
 
 
-def bench_c4(args, flipmc, torch, n_jobs=None):
+def bench_c4(args, flipmc, torch, n_jobs=None, check_alone=None):
     """Poisson stream of sampling jobs served with continuous batching."""
     from paper_2506_21290_amd import serve, workloads
 
@@ -465,10 +531,35 @@ def bench_c4(args, flipmc, torch, n_jobs=None):
     srv = serve.Server(memory_budget=args.budget, backend=serve.GpuBackend(flipmc.MC_FP32_DE),
                        quantum_moves=args.quantum)
     t0 = time.perf_counter()
-    res = srv.serve(jobs, time_limit=args.time_limit)
+    mark = [0]
+
+    def on_done(n):
+        if n >= mark[0] + 100 or n == len(jobs):
+            mark[0] = n
+            progress(f"c4: {n} of {len(jobs)} jobs done, {time.perf_counter() - t0:.1f} s")
+
+    res = srv.serve(jobs, time_limit=args.time_limit, on_done=on_done)
     wall = time.perf_counter() - t0
     lat = np.array([r.latency for r in res])
     moves = sum(r.moves for r in res)
+    # the same result alone and in the mix: sampled jobs re-run alone, bitwise
+    same = checked = 0
+    n_check = args.check_alone if check_alone is None else check_alone
+    if n_check:
+        by_index = {r.job.index: r for r in res}
+        pick = sorted(by_index)[:: max(1, len(by_index) // n_check)][:n_check]
+        be = srv.backend
+        for i in pick:
+            j = by_index[i].job
+            s = flipmc.System(serve.job_params(j, flipmc.MC_FP32_DE))
+            s.sweep(j.sweeps)
+            alone = be.result(j, s)
+            s.close()
+            mixed = by_index[i]
+            checked += 1
+            same += (alone["energy_per_molecule"] == mixed.energy_per_molecule and
+                     np.array_equal(alone["gofr"], mixed.gofr) and np.array_equal(alone["c2"], mixed.c2))
+        progress(f"c4: {same} of {checked} sampled jobs identical alone and in the mix")
     offered = sum(j.n_molecules * j.sweeps for j in jobs) / (jobs[-1].arrival - jobs[0].arrival)
     return {
         "workload": f"c4: {len(jobs)} Poisson jobs at 200/s, M=n^3 log-uniform in [125,{args.m_max}], "
@@ -483,6 +574,7 @@ def bench_c4(args, flipmc, torch, n_jobs=None):
         "peak_bytes": srv.peak_bytes,
         "budget_bytes": args.budget,
         "launches": srv.launches,
+        "alone_vs_mix": {"checked": checked, "bitwise_identical": same},
     }
 
 
@@ -511,10 +603,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "tau", "copy"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "tau", "flex", "copy"])
     ap.add_argument("--tau-temperature", type=float, default=2.2)
-    ap.add_argument("--tau-replicas", type=int, default=8)
-    ap.add_argument("--tau-equilibration", type=int, default=2000)
+    ap.add_argument("--tau-replicas", type=int, default=16)
+    ap.add_argument("--tau-equilibration", type=int, default=40000)
+    ap.add_argument("--flex-warmup", type=int, default=200)
+    ap.add_argument("--flex-sweeps", type=int, default=1000)
     ap.add_argument("--tau-sweeps", type=int, default=50000)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--serving-jobs", type=int, default=200,
@@ -524,6 +618,8 @@ def main():
     ap.add_argument("--budget", type=int, default=4 << 30)
     ap.add_argument("--quantum", type=int, default=100_000)
     ap.add_argument("--time-limit", type=float, default=None)
+    ap.add_argument("--check-alone", type=int, default=20,
+                    help="c4: sampled jobs re-run alone and compared with their result in the mix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-sub", action="store_true", help="leave out the c2 and c3 sub-objects")
@@ -542,7 +638,7 @@ def main():
     if args.workload == "c1":
         out = bench_c1(args, flipmc, torch)
     else:
-        out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "tau": bench_tau,
+        out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "tau": bench_tau, "flex": bench_flex,
                "copy": bench_copy}[args.workload](args, flipmc, torch)
     print(json.dumps(out), flush=True)
 

@@ -49,7 +49,7 @@ constexpr uint32_t kFxParts = 1024;  // workgroups of the event kernel
 struct FxDev {
     uint32_t geometry, n, M, N;
     uint32_t k, nc, ncell, nflip;
-    uint32_t seed_lo, seed_hi, r_trans, r_flip;
+    uint32_t seed_lo, seed_hi, pad2, pad3;
     uint32_t bonded;  // bit 4 i + j: atoms i, j of a molecule are bonded
     uint32_t resum_interval, obs_interval, gofr_interval, obs_start, max_samples, gofr_nbins;
     uint32_t pad;
@@ -200,7 +200,6 @@ __device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const dou
     const double thr = D.T * log(uacc);
     const bool flip = ut < D.p_flip;
     const uint32_t base = n * (a / n), sa = a - base;
-    const uint32_t cx = cell % D.nc, cy = (cell / D.nc) % D.nc, cz = cell / (D.nc * D.nc);
 
     // the molecule's atoms before and after (wave-uniform)
     double ox[4], oy[4], oz[4], nx[4], ny[4], nz[4];
@@ -285,25 +284,30 @@ __device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const dou
                 sc += un + uo;
             }
     }
-    // intermolecular pairs: the atoms of the stencil cells, a lane each
-    uint32_t total;
-    const int nseg = fx_segments(D, (int)cx, (int)cy, (int)cz, flip ? (int)D.r_flip : (int)D.r_trans,
-                                 W, &total);
-    for (uint32_t b = 0; b < total; b += 64u) {
-        const uint32_t idx = b + (uint32_t)lane;
-        uint32_t j = 0xFFFFFFFFu;
-        if (idx < total) j = fx_stencil_atom(D, W, nseg, idx);
-        const bool valid = j != 0xFFFFFFFFu && j / n != a / n;
-        double xj = 0.0, yj = 0.0, zj = 0.0;
-        uint32_t tj = 0;
-        if (valid) {
-            xj = D.pos[j]; yj = D.pos[N + j]; zj = D.pos[2 * N + j];
-            tj = D.type[j];
-        }
-        const double sj = D.sigma[tj];
+    // intermolecular pairs: for each changed atom, the atoms of the 27 cells
+    // around the cell it was sorted into this sweep, a lane each (cells are at
+    // least r_c + 2 sqrt(3) d wide, and either atom has moved at most
+    // sqrt(3) d since the sort, so every partner within r_c is there)
 #pragma unroll
-        for (uint32_t s = 0; s < 4; ++s) {
-            if (!((changed >> s) & 1u)) continue;  // wave-uniform
+    for (uint32_t s = 0; s < 4; ++s) {
+        if (!((changed >> s) & 1u)) continue;  // wave-uniform
+        const uint32_t cy_id = D.cell_id[base + s];
+        const uint32_t ux = cy_id % D.nc, uy = (cy_id / D.nc) % D.nc, uz = cy_id / (D.nc * D.nc);
+        uint32_t total;
+        const int nseg = fx_segments(D, (int)ux, (int)uy, (int)uz, 1, W, &total);
+        const double sos = D.sigma[ot[s]], sns = D.sigma[nt[s]];
+        for (uint32_t b = 0; b < total; b += 64u) {
+            const uint32_t idx = b + (uint32_t)lane;
+            uint32_t j = 0xFFFFFFFFu;
+            if (idx < total) j = fx_stencil_atom(D, W, nseg, idx);
+            const bool valid = j != 0xFFFFFFFFu && j / n != a / n;
+            double xj = 0.0, yj = 0.0, zj = 0.0;
+            uint32_t tj = 0;
+            if (valid) {
+                xj = D.pos[j]; yj = D.pos[N + j]; zj = D.pos[2 * N + j];
+                tj = D.type[j];
+            }
+            const double sj = D.sigma[tj];
             const double dxo = fx_mi(ox[s] - xj, D.L, D.invL), dyo = fx_mi(oy[s] - yj, D.L, D.invL),
                          dzo = fx_mi(oz[s] - zj, D.L, D.invL);
             const double r2o = valid ? dxo * dxo + dyo * dyo + dzo * dzo : 1e30;
@@ -313,8 +317,8 @@ __device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const dou
                              dzn = fx_mi(nz[s] - zj, D.L, D.invL);
                 r2n = valid ? dxn * dxn + dyn * dyn + dzn * dzn : 1e30;
             }
-            const double so = 0.5 * (D.sigma[ot[s]] + sj);
-            const double sn = 0.5 * (D.sigma[nt[s]] + sj);
+            const double so = 0.5 * (sos + sj);
+            const double sn = 0.5 * (sns + sj);
             const double uo = fx_wca(so * so, r2o, D.rc2f), un = fx_wca(sn * sn, r2n, D.rc2f);
             de += un - uo;
             sc += un + uo;
@@ -793,26 +797,20 @@ double fx_bond_star()
 }
 
 struct FxGeom {
-    uint32_t n, N, k, nc, ncell, r_trans, r_flip;
+    uint32_t n, N, k, nc, ncell;
     double L, w, D, rc, reach;
 };
 
-uint32_t segments_of(uint32_t r, uint32_t nc)
-{
-    const bool full = 2 * r + 1 >= nc;
-    const uint32_t nrow = full ? nc : 2 * r + 1;
-    return nrow * nrow * (full ? 1u : 2u);
-}
-
-// Is (k, nc) a valid decomposition?  Fills the stencil radii.
-bool fx_valid(const FxGeom& g0, uint32_t k, uint32_t nc, FxGeom* out)
+// Is (k, nc) a valid decomposition?  Same-colour cells must be 2 D + r_c
+// apart, and a cell must be r_c + 2 sqrt(3) d wide so that the 27 cells
+// around an atom's cell hold its partners however the two have moved since
+// the sort at the start of the sweep.
+bool fx_valid(const FxGeom& g0, double dmax, uint32_t k, uint32_t nc, FxGeom* out)
 {
     if (k < 2 || nc < 2 || nc % k != 0) return false;
     const double w = g0.L / (double)nc;
-    if ((double)(k - 1) * w < g0.reach) return false;  // same-colour cells independent
-    if (w < g0.rc) return false;                       // a translation's partners in +-1 cells
-    const uint32_t rf = (uint32_t)std::ceil((g0.D + g0.rc) / w);
-    if (segments_of(rf, nc) > (uint32_t)kFxSeg || segments_of(1, nc) > (uint32_t)kFxSeg) return false;
+    if ((double)(k - 1) * w < g0.reach) return false;
+    if (w < g0.rc + 2.0 * std::sqrt(3.0) * dmax) return false;
     if ((double)nc * nc * nc > 16777216.0) return false;
     if (out) {
         *out = g0;
@@ -820,8 +818,6 @@ bool fx_valid(const FxGeom& g0, uint32_t k, uint32_t nc, FxGeom* out)
         out->nc = nc;
         out->ncell = nc * nc * nc;
         out->w = w;
-        out->r_trans = 1;
-        out->r_flip = rf;
     }
     return true;
 }
@@ -857,13 +853,14 @@ int fx_geometry(const mcf_params* p, FxGeom* gout)
         return fx_fail(MC_EGEOM, "box side %.4f below %.4f (minimum image)", g.L, need);
     uint32_t k = p->colours_per_axis, nc = p->cells_per_side;
     if (k == 0 && nc == 0) {
-        // most cells per colour, then fewest colours
+        // most cells per colour, then the smallest cells (the fewest
+        // candidates per attempt)
         double best = -1.0;
         for (uint32_t kk = 2; kk <= 8; ++kk)
             for (uint32_t cc = kk; cc <= 256; cc += kk) {
-                if (!fx_valid(g, kk, cc, nullptr)) continue;
+                if (!fx_valid(g, p->max_displacement, kk, cc, nullptr)) continue;
                 const double act = std::pow((double)(cc / kk), 3.0);
-                if (act > best) {
+                if (act > best || (act == best && cc > nc)) {
                     best = act;
                     k = kk;
                     nc = cc;
@@ -873,10 +870,9 @@ int fx_geometry(const mcf_params* p, FxGeom* gout)
     } else if (k == 0 || nc == 0) {
         return fx_fail(MC_EINVAL, "give both colours_per_axis and cells_per_side, or neither");
     }
-    if (!fx_valid(g, k, nc, gout))
-        return fx_fail(MC_EGEOM, "k = %u, n_c = %u: cells of %.4f need (k-1) w >= %.4f, w >= %.4f and a "
-                                 "flip stencil of at most %d row segments", k, nc, g.L / nc, g.reach, g.rc,
-                       kFxSeg);
+    if (!fx_valid(g, p->max_displacement, k, nc, gout))
+        return fx_fail(MC_EGEOM, "k = %u, n_c = %u: cells of %.4f need (k-1) w >= %.4f and w >= %.4f", k, nc,
+                       g.L / nc, g.reach, g.rc + 2.0 * std::sqrt(3.0) * p->max_displacement);
     return MC_OK;
 }
 
@@ -1167,8 +1163,6 @@ int fx_init(mcf_system* s, const mcf_params* p, const FxGeom& g, const FxLayout&
     D.nflip = kNPerm[p->geometry];
     D.seed_lo = (uint32_t)p->seed;
     D.seed_hi = (uint32_t)(p->seed >> 32);
-    D.r_trans = g.r_trans;
-    D.r_flip = g.r_flip;
     for (int bnd = 0; bnd < 6; ++bnd) {
         const int i = kBondsOf[p->geometry][bnd][0], j = kBondsOf[p->geometry][bnd][1];
         if (i >= 0) D.bonded |= 1u << (4 * std::min(i, j) + std::max(i, j));

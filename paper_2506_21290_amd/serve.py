@@ -161,9 +161,11 @@ class Server:
         self.used -= need
         return job
 
-    def serve(self, jobs, time_limit=None, clock=None):
+    def serve(self, jobs, time_limit=None, clock=None, on_done=None):
         """Run an arrival stream to completion; returns results in completion
-        order.  `clock` (seconds since start) defaults to the wall clock."""
+        order.  `clock` (seconds since start) defaults to the wall clock;
+        `on_done(n)` is called with the number of finished jobs after each
+        harvest that finished some."""
         t0 = time.perf_counter()
         clock = clock or (lambda: time.perf_counter() - t0)
         jobs = sorted(jobs, key=lambda j: j.arrival)
@@ -188,6 +190,8 @@ class Server:
             done = self.backend.harvest()
             for bi, slot, _ in done:
                 results.append(self.finish(bi, slot, clock()))
+            if done and on_done is not None:
+                on_done(len(results))
             if n == 0 and not done:
                 time.sleep(2e-4)  # only slices in flight: wait a little
 
