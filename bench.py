@@ -44,11 +44,15 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the kernel sources with comments and blank lines left out (a
-    change of wording does not change the kernel the counters were taken on)."""
+RIGID_SOURCES = ("kernels.hip", "engine.h", "wave.h")
+FLEX_SOURCES = ("flex.hip", "engine.h", "wave.h")
+
+
+def kernel_source_hash(files=RIGID_SOURCES):
+    """Hash of kernel sources with comments and blank lines left out (a change
+    of wording does not change the kernel the counters were taken on)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "engine.h", "wave.h", "flex.hip"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2506_21290_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -60,13 +64,13 @@ def kernel_source_hash():
 def measured_counters(name):
     """The committed rocprofv3 counter summary of a kernel (HBM bytes per
     launch, VALU busy fraction), or {} when it is missing or was taken on
-    another version of the kernel."""
+    another version of the kernel's sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
         return {}
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash(tuple(t.get("sources", RIGID_SOURCES))):
         return {}
     return t
 
