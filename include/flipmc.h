@@ -336,7 +336,9 @@ typedef struct {
     uint32_t gofr_interval;    /* sweeps between g(r) frames (0 = never)           */
     uint32_t obs_start;        /* samples from this sweep after the origin on      */
     uint32_t max_samples;      /* capacity of the E/M and drift sample arrays      */
-    uint32_t reserved;         /* 0                                                */
+    uint32_t flags;            /* MC_FLAG_HBM_STATE: positions, types and cell
+                                  lists stay in the buffer even when they fit one
+                                  workgroup's LDS (same results, slower)           */
     double   gofr_dr;          /* g(r) bin width; r_max = min(L/2, 5)              */
     double   fs_q;             /* |q| of F_s over the atoms (Sec. III.B: 7.4)      */
     double   fs_q_cm;          /* |q| of F_s^cm over the centres of mass (5.1)     */
@@ -357,6 +359,14 @@ void mcf_params_default(mcf_params* p, uint32_t geometry);
  * 2 (max(D, r_c) + 2 d).  Any output may be NULL. */
 int mcf_geometry(const mcf_params* p, double* box, uint32_t* colours_per_axis,
                  uint32_t* cells_per_side);
+
+/* Where the sweep kernel keeps positions, types and cell lists for these
+ * parameters: *resident = 1 when they fit in one workgroup's LDS on the
+ * current device (then *lds_bytes of dynamic LDS per launch, loaded at the
+ * start of a launch and written back at its end), 0 when it works on them in
+ * the system's buffer (MC_FLAG_HBM_STATE in flags forces that).  Either
+ * output may be NULL.  Host only. */
+int mcf_placement(const mcf_params* p, int* resident, size_t* lds_bytes);
 
 /* Bytes of device memory mcf_init_system needs.  Host only. */
 int mcf_required_bytes(const mcf_params* p, size_t* bytes);

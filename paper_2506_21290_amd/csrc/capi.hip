@@ -43,6 +43,18 @@ int api_error(int code, const char* msg)
     return code;
 }
 
+size_t device_lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 163840;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0) {
+        (void)hipGetLastError();
+        return 163840;
+    }
+    return (size_t)v;
+}
+
 }  // namespace flipmc
 
 namespace {
@@ -73,18 +85,6 @@ double bond_star()
         x = nx;
     }
     return x;
-}
-
-size_t device_lds_limit()
-{
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 163840;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-        v <= 0) {
-        (void)hipGetLastError();
-        return 163840;
-    }
-    return (size_t)v;
 }
 
 struct Geometry {

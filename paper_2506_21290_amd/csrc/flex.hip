@@ -128,10 +128,41 @@ struct FxWaveLds {
     uint32_t* segoff;
 };
 
+// Where the sweep kernel reads and writes the state and the cell lists: the
+// workgroup's LDS for systems that fit there, the system's buffer otherwise.
+struct FxView {
+    double* pos;          // SoA [3][N]
+    uint8_t* type;        // [N]
+    uint32_t* cell_start; // [ncell + 1]
+    uint32_t* cell_list;  // [N]
+    uint32_t* cell_id;    // [N]
+    double* ecell;        // [ncell]
+};
+
+struct FxLds {
+    size_t pos, type, cstart, clist, cid, ecell, total;
+};
+
+__host__ __device__ inline FxLds fx_lds_layout(uint32_t N, uint32_t ncell)
+{
+    FxLds l{};
+    size_t o = 0;
+    auto a16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+    l.pos = o;    o = a16(o + 3 * size_t(N) * sizeof(double));
+    l.ecell = o;  o = a16(o + size_t(ncell) * sizeof(double));
+    l.type = o;   o = a16(o + size_t(N));
+    l.cstart = o; o = a16(o + (size_t(ncell) + 1) * sizeof(uint32_t));
+    l.clist = o;  o = a16(o + size_t(N) * sizeof(uint32_t));
+    l.cid = o;    o = a16(o + size_t(N) * sizeof(uint32_t));
+    l.total = o;
+    return l;
+}
+
 // Row segments of the cells within radius r of cell (cx, cy, cz): rows along
 // x of one or two contiguous cell ranges (every cell once when the stencil
 // covers the whole axis).  Returns the number of segments; *total = atoms.
-__device__ int fx_segments(const FxDev& D, int cx, int cy, int cz, int r, const FxWaveLds& W,
+__device__ __forceinline__ int fx_segments(const FxDev& D, const FxView& V, int cx, int cy, int cz, int r,
+                                           const FxWaveLds& W,
                            uint32_t* total)
 {
     const int lane = __lane_id();
@@ -157,8 +188,8 @@ __device__ int fx_segments(const FxDev& D, int cx, int cy, int cz, int r, const 
         const int z = full ? iz : (cz - r + iz + nc) % nc;
         const int xa = ixr ? xa1 : xa0, xb = ixr ? xb1 : xb0;
         const uint32_t row = (uint32_t)(nc * (y + nc * z));
-        lo = D.cell_start[row + xa];
-        cnt = D.cell_start[row + xb + 1] - lo;
+        lo = V.cell_start[row + xa];
+        cnt = V.cell_start[row + xb + 1] - lo;
     }
     const uint32_t off = wave_excl_scan(cnt, total);
     if (lane < nseg) {
@@ -169,14 +200,14 @@ __device__ int fx_segments(const FxDev& D, int cx, int cy, int cz, int r, const 
     return nseg;
 }
 
-__device__ __forceinline__ uint32_t fx_stencil_atom(const FxDev& D, const FxWaveLds& W, int nseg, uint32_t idx)
+__device__ __forceinline__ uint32_t fx_stencil_atom(const FxView& V, const FxWaveLds& W, int nseg, uint32_t idx)
 {
     int lo = 0, hi = nseg;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (W.segoff[mid] <= idx) lo = mid; else hi = mid;
     }
-    return D.cell_list[W.seglo[lo] + (idx - W.segoff[lo])];
+    return V.cell_list[W.seglo[lo] + (idx - W.segoff[lo])];
 }
 
 template <typename T>
@@ -187,7 +218,8 @@ __device__ __forceinline__ T fx_pick(const T v[4], uint32_t i)
 
 // One attempt on atom a (Sec. II.B) by a whole wave.  `cell` is the atom's
 // cell for the sweep's shift h: a translation that leaves it is rejected.
-__device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const double h[3], uint32_t cell,
+__device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint32_t a, uint64_t sweep,
+                                           const double h[3], uint32_t cell,
                            bool logging, const FxWaveLds& W, FxCount& wc)
 {
     const int lane = __lane_id();
@@ -207,10 +239,10 @@ __device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const dou
 #pragma unroll
     for (uint32_t s = 0; s < 4; ++s) {
         const uint32_t at = base + (s < n ? s : 0u);
-        ox[s] = nx[s] = D.pos[at];
-        oy[s] = ny[s] = D.pos[N + at];
-        oz[s] = nz[s] = D.pos[2 * N + at];
-        ot[s] = nt[s] = D.type[at];
+        ox[s] = nx[s] = V.pos[at];
+        oy[s] = ny[s] = V.pos[N + at];
+        oz[s] = nz[s] = V.pos[2 * N + at];
+        ot[s] = nt[s] = V.type[at];
     }
     uint32_t changed = 0;  // bit s: atom base + s moves or changes type
     uint32_t kind = 255;
@@ -291,21 +323,21 @@ __device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const dou
 #pragma unroll
     for (uint32_t s = 0; s < 4; ++s) {
         if (!((changed >> s) & 1u)) continue;  // wave-uniform
-        const uint32_t cy_id = D.cell_id[base + s];
+        const uint32_t cy_id = V.cell_id[base + s];
         const uint32_t ux = cy_id % D.nc, uy = (cy_id / D.nc) % D.nc, uz = cy_id / (D.nc * D.nc);
         uint32_t total;
-        const int nseg = fx_segments(D, (int)ux, (int)uy, (int)uz, 1, W, &total);
+        const int nseg = fx_segments(D, V, (int)ux, (int)uy, (int)uz, 1, W, &total);
         const double sos = D.sigma[ot[s]], sns = D.sigma[nt[s]];
         for (uint32_t b = 0; b < total; b += 64u) {
             const uint32_t idx = b + (uint32_t)lane;
             uint32_t j = 0xFFFFFFFFu;
-            if (idx < total) j = fx_stencil_atom(D, W, nseg, idx);
+            if (idx < total) j = fx_stencil_atom(V, W, nseg, idx);
             const bool valid = j != 0xFFFFFFFFu && j / n != a / n;
             double xj = 0.0, yj = 0.0, zj = 0.0;
             uint32_t tj = 0;
             if (valid) {
-                xj = D.pos[j]; yj = D.pos[N + j]; zj = D.pos[2 * N + j];
-                tj = D.type[j];
+                xj = V.pos[j]; yj = V.pos[N + j]; zj = V.pos[2 * N + j];
+                tj = V.type[j];
             }
             const double sj = D.sigma[tj];
             const double dxo = fx_mi(ox[s] - xj, D.L, D.invL), dyo = fx_mi(oy[s] - yj, D.L, D.invL),
@@ -341,11 +373,11 @@ __device__ void fx_attempt(const FxDev& D, uint32_t a, uint64_t sweep, const dou
             if (flip) {
 #pragma unroll
                 for (uint32_t s = 0; s < 4; ++s)
-                    if ((changed >> s) & 1u) D.type[base + s] = (uint8_t)nt[s];
+                    if ((changed >> s) & 1u) V.type[base + s] = (uint8_t)nt[s];
             } else {
-                D.pos[a] = fx_pick(nx, sa);
-                D.pos[N + a] = fx_pick(ny, sa);
-                D.pos[2 * N + a] = fx_pick(nz, sa);
+                V.pos[a] = fx_pick(nx, sa);
+                V.pos[N + a] = fx_pick(ny, sa);
+                V.pos[2 * N + a] = fx_pick(nz, sa);
                 // periodic images crossed (the shifts the wrap took off)
                 const int ix = (int)floor(tx / D.L), iy = (int)floor(ty / D.L), iz = (int)floor(tz / D.L);
                 if (ix) D.img[a] += ix;
@@ -395,17 +427,31 @@ __device__ void fx_sort_cells(uint32_t* list, const uint32_t* start, uint32_t c0
     }
 }
 
-// The hot kernel: n sweeps of one system on one workgroup.
+// The hot kernel: n sweeps of one system on one workgroup.  With kRes the
+// positions, types and cell lists live in LDS for the whole launch (copied in
+// at the start, positions and types written back at the end); otherwise the
+// same code runs on the arrays in the system's buffer.
+template <bool kRes>
 __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp, uint64_t n_sweeps)
 {
     __shared__ uint32_t seg[kFxWaves][2][kFxSeg];
     __shared__ uint32_t scratch[kFxWaves];
     __shared__ double misc[2];
+    extern __shared__ __align__(16) unsigned char fx_smem[];
     const FxDev& D = *Dp;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     FxWaveLds W{seg[wave][0], seg[wave][1]};
     Stats* st = D.stats;
     const uint32_t N = D.N, ncell = D.ncell, nc = D.nc, k = D.k;
+    FxView V{D.pos, D.type, D.cell_start, D.cell_list, D.cell_id, D.ecell};
+    if (kRes) {
+        const FxLds l = fx_lds_layout(N, ncell);
+        V = FxView{(double*)(fx_smem + l.pos), (uint8_t*)(fx_smem + l.type), (uint32_t*)(fx_smem + l.cstart),
+                   (uint32_t*)(fx_smem + l.clist), (uint32_t*)(fx_smem + l.cid), (double*)(fx_smem + l.ecell)};
+        for (uint32_t i = tid; i < 3 * N; i += kFxThreads) V.pos[i] = D.pos[i];
+        for (uint32_t i = tid; i < N; i += kFxThreads) V.type[i] = D.type[i];
+        __syncthreads();
+    }
     const uint32_t na = nc / k, nact = na * na * na;
     uint64_t sweep = st->sweep;
     const uint64_t origin = st->obs_origin;
@@ -415,19 +461,19 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp
         const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, D.seed_lo, D.seed_hi);
         const double h[3] = {D.w * unit_open(g.x), D.w * unit_open(g.y), D.w * unit_open(g.z)};
         // counting sort of the atoms by cell
-        for (uint32_t c = tid; c <= ncell; c += kFxThreads) D.cell_start[c] = 0;
+        for (uint32_t c = tid; c <= ncell; c += kFxThreads) V.cell_start[c] = 0;
         __syncthreads();
         for (uint32_t i = tid; i < N; i += kFxThreads) {
-            const uint32_t c = fx_cell(D.pos[i], D.pos[N + i], D.pos[2 * N + i], h, D);
-            D.cell_id[i] = c;
-            atomicAdd(&D.cell_start[c + 1], 1u);
+            const uint32_t c = fx_cell(V.pos[i], V.pos[N + i], V.pos[2 * N + i], h, D);
+            V.cell_id[i] = c;
+            atomicAdd(&V.cell_start[c + 1], 1u);
         }
         __syncthreads();
-        block_excl_scan_t<kFxThreads>(D.cell_start + 1, ncell, scratch);
+        block_excl_scan_t<kFxThreads>(V.cell_start + 1, ncell, scratch);
         for (uint32_t i = tid; i < N; i += kFxThreads)
-            D.cell_list[atomicAdd(&D.cell_start[D.cell_id[i] + 1], 1u)] = i;
+            V.cell_list[atomicAdd(&V.cell_start[V.cell_id[i] + 1], 1u)] = i;
         __syncthreads();
-        fx_sort_cells(D.cell_list, D.cell_start, (uint32_t)wave, kFxWaves, ncell);
+        fx_sort_cells(V.cell_list, V.cell_start, (uint32_t)wave, kFxWaves, ncell);
         __syncthreads();
         const bool logging = D.log != nullptr && sweep - D.log_sweep0 < D.log_sweeps;
         for (uint32_t col = 0; col < k * k * k; ++col) {
@@ -436,17 +482,17 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp
                 const uint32_t cell = (kx + k * (ci % na)) + nc * ((ky + k * ((ci / na) % na)) +
                                                                   nc * (kz + k * (ci / (na * na))));
                 wc.e = 0.0;
-                const uint32_t b = D.cell_start[cell], e = D.cell_start[cell + 1];
+                const uint32_t b = V.cell_start[cell], e = V.cell_start[cell + 1];
                 for (uint32_t q = b; q < e; ++q)
-                    fx_attempt(D, D.cell_list[q], sweep, h, cell, logging, W, wc);
-                if (lane == 0) D.ecell[cell] = wc.e;
+                    fx_attempt(D, V, V.cell_list[q], sweep, h, cell, logging, W, wc);
+                if (lane == 0) V.ecell[cell] = wc.e;
             }
             __syncthreads();
         }
         ++sweep;
         // E_acc += the sweep's dE, the cells in a fixed order; E/M samples
         if (wave == 0) {
-            const double e = misc[0] + sweep_energy(D.ecell, ncell);
+            const double e = misc[0] + sweep_energy(V.ecell, ncell);
             if (lane == 0) misc[0] = e;
         }
         if (tid == 0) {
@@ -470,6 +516,10 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp
         if (wc.terms) atomicAdd((unsigned long long*)&st->pair_terms, (unsigned long long)wc.terms);
     }
     __syncthreads();
+    if (kRes) {
+        for (uint32_t i = tid; i < 3 * N; i += kFxThreads) D.pos[i] = V.pos[i];
+        for (uint32_t i = tid; i < N; i += kFxThreads) D.type[i] = V.type[i];
+    }
     if (tid == 0) {
         st->sweep = sweep;
         st->e_acc = misc[0];
@@ -935,10 +985,21 @@ struct mcf_system {
     FxDev* dev;
     hipStream_t stream;
     uint64_t sweep, origin;
+    size_t lds;  // dynamic LDS of the resident sweep kernel; 0 = state in the buffer
     int pooled;  // index + 1 of the static handle slot (mcf_init_system_noalloc), 0 otherwise
 };
 
 namespace {
+
+// Dynamic LDS of the resident sweep kernel for these parameters, 0 when the
+// state stays in the buffer (MC_FLAG_HBM_STATE, or too large for one
+// workgroup next to the kernel's static LDS of about 4 KiB).
+size_t fx_resident_lds(const mcf_params* p, const FxGeom& g)
+{
+    if (p->flags & MC_FLAG_HBM_STATE) return 0;
+    const size_t lds = fx_lds_layout(g.N, g.ncell).total;
+    return lds + 8192 <= device_lds_limit() ? lds : 0;
+}
 
 uint32_t fx_parts(const mcf_system* s) { return (s->g.N + kFxThreads - 1) / kFxThreads; }
 
@@ -1071,6 +1132,17 @@ int mcf_geometry(const mcf_params* p, double* box, uint32_t* k, uint32_t* nc)
     return MC_OK;
 }
 
+int mcf_placement(const mcf_params* p, int* resident, size_t* lds_bytes)
+{
+    FxGeom g;
+    const int rc = fx_geometry(p, &g);
+    if (rc) return rc;
+    const size_t lds = fx_resident_lds(p, g);
+    if (resident) *resident = lds ? 1 : 0;
+    if (lds_bytes) *lds_bytes = lds;
+    return MC_OK;
+}
+
 int mcf_required_bytes(const mcf_params* p, size_t* bytes)
 {
     FxGeom g;
@@ -1148,6 +1220,17 @@ int fx_init(mcf_system* s, const mcf_params* p, const FxGeom& g, const FxLayout&
     s->lay = lay;
     s->stream = stream;
     s->sweep = s->origin = 0;
+    s->lds = fx_resident_lds(p, g);
+    if (s->lds) {
+        static std::mutex mu;
+        static size_t configured = 0;
+        std::lock_guard<std::mutex> lk(mu);
+        if (s->lds > configured) {
+            FXCHK(hipFuncSetAttribute((const void*)&k_fx_sweeps<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)s->lds));
+            configured = s->lds;
+        }
+    }
     if (!lattice)
         if (int rc = fx_validate_input(s, pos, types)) return rc;
     FxDev& D = s->host;
@@ -1326,7 +1409,10 @@ int mcf_sweep(mcf_system* s, uint64_t n)
     if (!s) return fx_fail(MC_EINVAL, "null system");
     while (n > 0) {
         const uint64_t chunk = std::min<uint64_t>(n, fx_next_event(s) - s->sweep);
-        hipLaunchKernelGGL(k_fx_sweeps, dim3(1), dim3(kFxThreads), 0, s->stream, s->dev, chunk);
+        if (s->lds)
+            hipLaunchKernelGGL(k_fx_sweeps<true>, dim3(1), dim3(kFxThreads), s->lds, s->stream, s->dev, chunk);
+        else
+            hipLaunchKernelGGL(k_fx_sweeps<false>, dim3(1), dim3(kFxThreads), 0, s->stream, s->dev, chunk);
         FXCHK(hipGetLastError());
         s->sweep += chunk;
         n -= chunk;

@@ -35,7 +35,7 @@ EXPORTED = [
     "mc_last_error", "mc_batch_required_bytes", "mc_batch_create",
     "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
     "mc_batch_set_workgroups", "mc_dynamics",
-    "mcf_params_default", "mcf_geometry", "mcf_required_bytes", "mcf_init_system", "mcf_sweep",
+    "mcf_params_default", "mcf_geometry", "mcf_placement", "mcf_required_bytes", "mcf_init_system", "mcf_sweep",
     "mcf_energy", "mcf_observables", "mcf_reset_observables", "mcf_get_state", "mcf_set_state",
     "mcf_decision_log", "mcf_destroy", "mcf_init_system_noalloc",
 ]
@@ -135,7 +135,7 @@ class mcf_params(C.Structure):
         ("gofr_interval", C.c_uint32),
         ("obs_start", C.c_uint32),
         ("max_samples", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("flags", C.c_uint32),
         ("gofr_dr", C.c_double),
         ("fs_q", C.c_double),
         ("fs_q_cm", C.c_double),
@@ -223,6 +223,7 @@ def lib():
         L.mcf_params_default.argtypes = [fp, C.c_uint32]
         L.mcf_params_default.restype = None
         L.mcf_geometry.argtypes = [fp, dp, u32p, u32p]
+        L.mcf_placement.argtypes = [fp, C.POINTER(C.c_int), szp]
         L.mcf_required_bytes.argtypes = [fp, szp]
         L.mcf_init_system.argtypes = [fp, dp, u8p, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.mcf_sweep.argtypes = [vp, C.c_uint64]
@@ -574,6 +575,13 @@ def mcf_geometry(p: mcf_params):
     box, k, nc = C.c_double(), C.c_uint32(), C.c_uint32()
     _check(lib().mcf_geometry(C.byref(p), C.byref(box), C.byref(k), C.byref(nc)))
     return box.value, k.value, nc.value
+
+
+def mcf_placement(p: mcf_params):
+    """(positions, types and cell lists resident in LDS?, dynamic LDS bytes)"""
+    r, n = C.c_int(), C.c_size_t()
+    _check(lib().mcf_placement(C.byref(p), C.byref(r), C.byref(n)))
+    return bool(r.value), n.value
 
 
 def mcf_required_bytes(p: mcf_params) -> int:

@@ -119,3 +119,16 @@ def test_noalloc_size_query_and_limit_without_a_device():
     big = flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=100 ** 3)
     rc = L.mcf_init_system_noalloc(C.byref(big), None, None, None, 0, C.byref(need), None, None)
     assert rc == flipmc.MC_ENOMEM and b"static scratch" in L.mc_last_error()
+
+
+def test_flexible_placement_without_a_device():
+    # the paper's 1000 molecules (3000 or 4000 atoms) fit one workgroup's LDS
+    # (160 KiB on gfx950, the fallback when no device answers); MC_FLAG_HBM_STATE
+    # and 8000 triangles (24000 atoms) keep the state in the buffer
+    for g in (flipmc.MC_TRIANGLE, flipmc.MC_SQUARE, flipmc.MC_TETRAHEDRON):
+        res, lds = flipmc.mcf_placement(flipmc.mcf_params_default(g, n_molecules=1000))
+        assert res and 3 * 8 * 1000 * flipmc.SITES[g] < lds < 160 * 1024
+    res, lds = flipmc.mcf_placement(flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=1000,
+                                                              flags=flipmc.MC_FLAG_HBM_STATE))
+    assert not res and lds == 0
+    assert not flipmc.mcf_placement(flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=8000))[0]

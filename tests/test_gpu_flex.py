@@ -194,3 +194,27 @@ def test_state_roundtrip_and_bad_types():
     with pytest.raises(flipmc.McError) as e:
         s2.set_state(st["pos"], bad, 0)
     assert e.value.code == flipmc.MC_EINVAL
+
+
+@pytest.mark.parametrize("case", ["triangle", "square", "tetrahedron", "triangle_1000"])
+def test_lds_and_buffer_state_agree(case):
+    # the sweep kernel with positions, types and cell lists in LDS and the same
+    # kernel on the arrays in the system's buffer give bitwise equal chains
+    g, M, T, k, nc, rho = CASES[case]
+    print(f"flex lds-vs-buffer {case}", flush=True)
+    kw = dict(gofr_interval=5, obs_interval=5, resum_interval=10, max_samples=64)
+    pr = gp(g, M, T, k, nc, rho, seed=7, **kw)
+    ph = gp(g, M, T, k, nc, rho, seed=7, flags=flipmc.MC_FLAG_HBM_STATE, **kw)
+    assert flipmc.mcf_placement(pr)[0] and not flipmc.mcf_placement(ph)[0]
+    a, b = flipmc.FlexSystem(pr), flipmc.FlexSystem(ph)
+    for n in (1, 7, 22):
+        a.sweep(n)
+        b.sweep(n)
+        sa, sb = a.get_state(), b.get_state()
+        assert sa["sweep"] == sb["sweep"]
+        assert np.array_equal(sa["pos"], sb["pos"]) and np.array_equal(sa["types"], sb["types"])
+    oa, ob = a.observables(), b.observables()
+    for key in ("attempts", "accepts", "gofr_all", "gofr_inter", "c2", "fs", "fs_cm"):
+        assert np.array_equal(np.asarray(oa[key]), np.asarray(ob[key])), key
+    assert oa["exits"] == ob["exits"] and oa["e_acc"] == ob["e_acc"]
+    assert a.energy() == b.energy()
