@@ -230,7 +230,4 @@ hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t st
 // Record msg as the calling thread's last error (mc_last_error) and return code.
 int api_error(int code, const char* msg);
 
-// LDS bytes one workgroup may use on the current device.
-size_t device_lds_limit();
-
 }  // namespace flipmc

@@ -38,6 +38,11 @@
 #include "wave.h"
 
 namespace flipmc {
+
+// LDS bytes one workgroup may use on the current device (defined with the
+// rigid engine's host code).
+size_t device_lds_limit();
+
 namespace {
 
 constexpr int kFxThreads = 512;
