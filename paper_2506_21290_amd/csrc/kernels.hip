@@ -1072,13 +1072,21 @@ __device__ uint32_t gather_near(const Ctx<Real, kRes>& C, const PhaseConst& P, i
         // the staged molecules' sites, a slot per lane at a time with its
         // three loads in flight (nine at once did not fit the registers and
         // went through scratch memory one load at a time)
+        // (copied as 16-byte words: copying R4 values made the compiler keep
+        // one of them in a scratch slot, a dead store per slot whose line the
+        // release of every barrier then wrote back to memory)
+        using W4 = uint32_t __attribute__((ext_vector_type(4)));
+        constexpr int kW = 3 * (int)(sizeof(R4<Real>) / sizeof(W4));
 #pragma unroll 1
         for (uint32_t sl = (uint32_t)lane; sl < nnear; sl += 64u) {
             const uint32_t g = S.gid[sl];
-            const R4<Real> a0 = C.site[3 * g], a1 = C.site[3 * g + 1], a2 = C.site[3 * g + 2];
-            S.site[3 * sl] = a0;
-            S.site[3 * sl + 1] = a1;
-            S.site[3 * sl + 2] = a2;
+            const W4* src = reinterpret_cast<const W4*>(C.site + 3 * g);
+            W4* dst = reinterpret_cast<W4*>(S.site + 3 * sl);
+            W4 v[kW];
+#pragma unroll
+            for (int i = 0; i < kW; ++i) v[i] = src[i];
+#pragma unroll
+            for (int i = 0; i < kW; ++i) dst[i] = v[i];
         }
         wave_lds_sync();
     }
