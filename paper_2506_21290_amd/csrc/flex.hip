@@ -48,6 +48,10 @@ namespace {
 constexpr int kFxThreads = 512;
 constexpr int kFxWaves = kFxThreads / 64;
 constexpr int kFxSeg = 64;          // stencil row segments per attempt (radius <= 2: <= 50)
+constexpr int kFxCand = 384;        // atoms of a cell's 27-cell stencil listed per wave
+// static LDS of the sweep kernel: segments and candidate lists per wave, scan
+// scratch and the energy accumulator (with room to spare)
+constexpr size_t kFxStaticLds = (size_t)kFxWaves * (2 * kFxSeg + kFxCand) * 4 + 256;
 constexpr uint32_t kFxParts = 1024;  // workgroups of the event kernel
 
 // Everything a workgroup needs about one system; in the system's buffer.
@@ -87,17 +91,46 @@ struct FxDev {
     uint64_t log_sweep0, log_sweeps;
 };
 
+// The constants of the sweep kernel, copied from the system's descriptor into
+// registers at the start of a launch (read through the descriptor, every
+// store to LDS or memory could alias them and force a reload).
+struct FxK {
+    uint32_t n, N, nc, nflip, bonded, seed_lo, seed_hi;
+    uint32_t flipw[4];  // byte s of word q: flips[q][s]
+    double L, invL, w, T, p_flip, dmax, rc2f;
+    double sigma[4];
+    int32_t* img;
+    MoveRecord* log;
+    uint64_t log_sweep0;
+};
+
+__device__ __forceinline__ FxK fx_const(const FxDev& D)
+{
+    FxK K;
+    K.n = D.n; K.N = D.N; K.nc = D.nc; K.nflip = D.nflip; K.bonded = D.bonded;
+    K.seed_lo = D.seed_lo; K.seed_hi = D.seed_hi;
+    for (int q = 0; q < 4; ++q)
+        K.flipw[q] = (uint32_t)D.flips[q][0] | ((uint32_t)D.flips[q][1] << 8) | ((uint32_t)D.flips[q][2] << 16) |
+                     ((uint32_t)D.flips[q][3] << 24);
+    K.L = D.L; K.invL = D.invL; K.w = D.w; K.T = D.T; K.p_flip = D.p_flip; K.dmax = D.dmax; K.rc2f = D.rc2f;
+    for (int t = 0; t < 4; ++t) K.sigma[t] = D.sigma[t];
+    K.img = D.img;
+    K.log = D.log;
+    K.log_sweep0 = D.log_sweep0;
+    return K;
+}
+
 __device__ __forceinline__ double fx_wrap(double x, double L) { return x - L * floor(x / L); }
 __device__ __forceinline__ double fx_mi(double d, double L, double invL) { return d - L * rint(d * invL); }
 
-__device__ __forceinline__ int fx_axis(double x, double h, const FxDev& D)
+__device__ __forceinline__ int fx_axis(double x, double h, const FxK& D)
 {
     int c = (int)floor(fx_wrap(x - h, D.L) / D.w);
     c = c < 0 ? 0 : c;
     return c >= (int)D.nc ? (int)D.nc - 1 : c;
 }
 
-__device__ __forceinline__ uint32_t fx_cell(double x, double y, double z, const double h[3], const FxDev& D)
+__device__ __forceinline__ uint32_t fx_cell(double x, double y, double z, const double h[3], const FxK& D)
 {
     const uint32_t nc = D.nc;
     return (uint32_t)fx_axis(x, h[0], D) +
@@ -131,6 +164,7 @@ struct FxCount {
 struct FxWaveLds {
     uint32_t* seglo;
     uint32_t* segoff;
+    uint32_t* cand;  // [kFxCand] atoms of the current cell's stencil
 };
 
 // Where the sweep kernel reads and writes the state and the cell lists: the
@@ -166,7 +200,7 @@ __host__ __device__ inline FxLds fx_lds_layout(uint32_t N, uint32_t ncell)
 // Row segments of the cells within radius r of cell (cx, cy, cz): rows along
 // x of one or two contiguous cell ranges (every cell once when the stencil
 // covers the whole axis).  Returns the number of segments; *total = atoms.
-__device__ __forceinline__ int fx_segments(const FxDev& D, const FxView& V, int cx, int cy, int cz, int r,
+__device__ __forceinline__ int fx_segments(const FxK& D, const FxView& V, int cx, int cy, int cz, int r,
                                            const FxWaveLds& W,
                            uint32_t* total)
 {
@@ -221,22 +255,98 @@ __device__ __forceinline__ T fx_pick(const T v[4], uint32_t i)
     return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
 }
 
-// One attempt on atom a (Sec. II.B) by a whole wave.  `cell` is the atom's
-// cell for the sweep's shift h: a translation that leaves it is rejected.
-__device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint32_t a, uint64_t sweep,
-                                           const double h[3], uint32_t cell,
-                           bool logging, const FxWaveLds& W, FxCount& wc)
+// The proposal of the attempt on atom a (Sec. II.B): move kind, flip
+// rotation or translation target, the cell-exit test and T ln u.  Drawn for
+// the atoms of a cell by one lane each before the cell's attempts (an atom's
+// position changes only in its own attempt, so the draws do not depend on
+// the attempts before it).
+struct FxProp {
+    double thr;         // T ln u
+    double tx, ty, tz;  // translation target before the wrap
+    uint32_t kind;      // flip: rotation index; translation: 255
+    uint32_t flip, exited;
+};
+
+__device__ __forceinline__ FxProp fx_propose(const FxK& D, const FxView& V, uint32_t a, uint64_t sweep,
+                                             const double h[3], uint32_t cell)
 {
-    const int lane = __lane_id();
-    const uint32_t n = D.n, N = D.N;
+    const uint32_t N = D.N;
     const uint32_t slo = (uint32_t)sweep, shi = (uint32_t)(sweep >> 32);
     const U4 b0 = philox10(a, slo, shi, 0u, D.seed_lo, D.seed_hi);
     const U4 b1 = philox10(a, slo, shi, 1u, D.seed_lo, D.seed_hi);
     const double uacc = unit_53(b0.x, b0.y), ut = unit_open(b0.z);
     const double p0 = unit_open(b1.x), p1 = unit_open(b1.y), p2 = unit_open(b1.z);
-    const double thr = D.T * log(uacc);
-    const bool flip = ut < D.p_flip;
+    FxProp pr;
+    pr.thr = D.T * log(uacc);
+    pr.flip = ut < D.p_flip ? 1u : 0u;
+    pr.kind = 255;
+    pr.exited = 0;
+    pr.tx = pr.ty = pr.tz = 0.0;
+    if (pr.flip) {
+        uint32_t q = (uint32_t)((double)D.nflip * p0);
+        pr.kind = q >= D.nflip ? D.nflip - 1 : q;
+    } else {
+        pr.tx = V.pos[a] + D.dmax * (2.0 * p0 - 1.0);
+        pr.ty = V.pos[N + a] + D.dmax * (2.0 * p1 - 1.0);
+        pr.tz = V.pos[2 * N + a] + D.dmax * (2.0 * p2 - 1.0);
+        pr.exited = fx_cell(fx_wrap(pr.tx, D.L), fx_wrap(pr.ty, D.L), fx_wrap(pr.tz, D.L), h, D) != cell;
+    }
+    return pr;
+}
+
+__device__ __forceinline__ double rl_dbl(double v, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ FxProp fx_prop_of_lane(const FxProp& p, int l)
+{
+    FxProp r;
+    r.thr = rl_dbl(p.thr, l);
+    r.tx = rl_dbl(p.tx, l);
+    r.ty = rl_dbl(p.ty, l);
+    r.tz = rl_dbl(p.tz, l);
+    r.kind = (uint32_t)__builtin_amdgcn_readlane((int)p.kind, l);
+    r.flip = (uint32_t)__builtin_amdgcn_readlane((int)p.flip, l);
+    r.exited = (uint32_t)__builtin_amdgcn_readlane((int)p.exited, l);
+    return r;
+}
+
+// The atoms of the 27-cell stencil around `cell` into the wave's candidate
+// list, in the order fx_stencil_atom gives them.  Returns their count, or
+// 0xFFFFFFFF when they exceed the list (attempts then walk the stencil).
+__device__ __forceinline__ uint32_t fx_gather_candidates(const FxK& D, const FxView& V, uint32_t cell,
+                                                         const FxWaveLds& W)
+{
+    const uint32_t nc = D.nc;
+    uint32_t total;
+    const int nseg = fx_segments(D, V, (int)(cell % nc), (int)((cell / nc) % nc), (int)(cell / (nc * nc)), 1,
+                                 W, &total);
+    if (total > (uint32_t)kFxCand) return 0xFFFFFFFFu;
+    for (uint32_t b = 0; b < total; b += 64u) {
+        const uint32_t idx = b + (uint32_t)__lane_id();
+        if (idx < total) W.cand[idx] = fx_stencil_atom(V, W, nseg, idx);
+    }
+    wave_lds_sync();
+    return total;
+}
+
+// One attempt on atom a (Sec. II.B) by a whole wave, with its proposal pr
+// (wave-uniform).  `cell` is the atom's cell for the sweep's shift h: a
+// translation that leaves it is rejected.  ncand: the size of the wave's
+// candidate list of this cell's stencil (0xFFFFFFFF: no list).
+__device__ __forceinline__ void fx_attempt(const FxK& D, const FxView& V, uint32_t a, const FxProp& pr,
+                                           uint64_t sweep, uint32_t cell, uint32_t ncand, bool logging,
+                                           const FxWaveLds& W, FxCount& wc)
+{
+    const int lane = __lane_id();
+    const uint32_t n = D.n, N = D.N;
+    const bool flip = pr.flip != 0u;
     const uint32_t base = n * (a / n), sa = a - base;
+    const double sig[4] = {D.sigma[0], D.sigma[1], D.sigma[2], D.sigma[3]};
 
     // the molecule's atoms before and after (wave-uniform)
     double ox[4], oy[4], oz[4], nx[4], ny[4], nz[4];
@@ -250,24 +360,18 @@ __device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint
         ot[s] = nt[s] = V.type[at];
     }
     uint32_t changed = 0;  // bit s: atom base + s moves or changes type
-    uint32_t kind = 255;
-    bool exited = false;
-    double tx = 0.0, ty = 0.0, tz = 0.0;
+    double wx = 0.0, wy = 0.0, wz = 0.0;
     if (flip) {
-        uint32_t q = (uint32_t)((double)D.nflip * p0);
-        q = q >= D.nflip ? D.nflip - 1 : q;
-        kind = q;
 #pragma unroll
         for (uint32_t s = 0; s < 4; ++s) {
             if (s >= n) continue;
-            nt[s] = fx_pick(ot, D.flips[q][s]);
+            nt[s] = fx_pick(ot, (fx_pick(D.flipw, pr.kind) >> (8 * s)) & 0xFFu);
             if (nt[s] != ot[s]) changed |= 1u << s;
         }
     } else {
-        tx = fx_pick(ox, sa) + D.dmax * (2.0 * p0 - 1.0);
-        ty = fx_pick(oy, sa) + D.dmax * (2.0 * p1 - 1.0);
-        tz = fx_pick(oz, sa) + D.dmax * (2.0 * p2 - 1.0);
-        const double wx = fx_wrap(tx, D.L), wy = fx_wrap(ty, D.L), wz = fx_wrap(tz, D.L);
+        wx = fx_wrap(pr.tx, D.L);
+        wy = fx_wrap(pr.ty, D.L);
+        wz = fx_wrap(pr.tz, D.L);
 #pragma unroll
         for (uint32_t s = 0; s < 4; ++s)
             if (s == sa) {
@@ -275,15 +379,14 @@ __device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint
                 ny[s] = wy;
                 nz[s] = wz;
             }
-        exited = fx_cell(wx, wy, wz, h, D) != cell;
         changed = 1u << sa;
     }
     if (flip) wc.att_f += 1; else wc.att_t += 1;
-    if (exited) {
+    if (pr.exited) {
         wc.exits += 1;
         if (logging && lane == 0) {
             MoveRecord rec;
-            rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = thr; rec.sweep = sweep;
+            rec.delta_e = 0.0; rec.scale = 0.0; rec.t_log_u = pr.thr; rec.sweep = sweep;
             rec.molecule = a; rec.move = MC_TRANSLATE; rec.accepted = 0; rec.exited = 1;
             rec.axis = 255; rec.pair_terms = 0; rec.pad = 0;
             D.log[(sweep - D.log_sweep0) * N + a] = rec;
@@ -292,34 +395,42 @@ __device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint
     }
 
     double de = 0.0, sc = 0.0;
-    uint32_t terms = 0;
-    // intramolecular pairs touching a changed atom: lane 0's partial
-    if (lane == 0) {
-#pragma unroll
-        for (uint32_t i = 0; i < 4; ++i)
-#pragma unroll
-            for (uint32_t j = i + 1; j < 4; ++j) {
-                if (j >= n || !(((changed >> i) | (changed >> j)) & 1u)) continue;
-                const bool bonded = (D.bonded >> (4 * i + j)) & 1u;
-                const double dxo = fx_mi(ox[i] - ox[j], D.L, D.invL), dyo = fx_mi(oy[i] - oy[j], D.L, D.invL),
-                             dzo = fx_mi(oz[i] - oz[j], D.L, D.invL);
-                const double dxn = fx_mi(nx[i] - nx[j], D.L, D.invL), dyn = fx_mi(ny[i] - ny[j], D.L, D.invL),
-                             dzn = fx_mi(nz[i] - nz[j], D.L, D.invL);
-                const double r2o = dxo * dxo + dyo * dyo + dzo * dzo;
-                const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
-                const double so = 0.5 * (D.sigma[ot[i]] + D.sigma[ot[j]]);
-                const double sn = 0.5 * (D.sigma[nt[i]] + D.sigma[nt[j]]);
-                double uo = fx_wca(so * so, r2o, D.rc2f), un = fx_wca(sn * sn, r2n, D.rc2f);
-                terms += (r2o < D.rc2f * so * so ? 1u : 0u) + (r2n < D.rc2f * sn * sn ? 1u : 0u);
-                if (bonded) {
-                    const double fo = fx_fene(so, r2o), fn = fx_fene(sn, r2n);
-                    uo += fo;
-                    un += fn;
-                    terms += (fo < __builtin_inf() ? 1u : 0u) + (fn < __builtin_inf() ? 1u : 0u);
-                }
-                de += un - uo;
-                sc += un + uo;
+    uint32_t terms = 0;  // wave totals (popcounts of ballots)
+    // intramolecular pairs touching a changed atom: pair (i, j), i < j, on
+    // lane 0 .. 5 in the order (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+    {
+        const uint32_t i = lane < 3 ? 0u : (lane < 5 ? 1u : 2u);
+        const uint32_t j = lane < 3 ? (uint32_t)lane + 1u : (lane < 5 ? (uint32_t)lane - 1u : 3u);
+        const bool on = lane < 6 && j < n && (((changed >> i) | (changed >> j)) & 1u);
+        bool ino = false, inn = false, fino = false, finn = false;
+        if (on) {
+            const double xi = fx_pick(ox, i), yi = fx_pick(oy, i), zi = fx_pick(oz, i);
+            const double xj = fx_pick(ox, j), yj = fx_pick(oy, j), zj = fx_pick(oz, j);
+            const double xin = fx_pick(nx, i), yin = fx_pick(ny, i), zin = fx_pick(nz, i);
+            const double xjn = fx_pick(nx, j), yjn = fx_pick(ny, j), zjn = fx_pick(nz, j);
+            const double dxo = fx_mi(xi - xj, D.L, D.invL), dyo = fx_mi(yi - yj, D.L, D.invL),
+                         dzo = fx_mi(zi - zj, D.L, D.invL);
+            const double dxn = fx_mi(xin - xjn, D.L, D.invL), dyn = fx_mi(yin - yjn, D.L, D.invL),
+                         dzn = fx_mi(zin - zjn, D.L, D.invL);
+            const double r2o = dxo * dxo + dyo * dyo + dzo * dzo;
+            const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
+            const double so = 0.5 * (fx_pick(sig, fx_pick(ot, i)) + fx_pick(sig, fx_pick(ot, j)));
+            const double sn = 0.5 * (fx_pick(sig, fx_pick(nt, i)) + fx_pick(sig, fx_pick(nt, j)));
+            double uo = fx_wca(so * so, r2o, D.rc2f), un = fx_wca(sn * sn, r2n, D.rc2f);
+            ino = r2o < D.rc2f * so * so;
+            inn = r2n < D.rc2f * sn * sn;
+            if ((D.bonded >> (4 * i + j)) & 1u) {
+                const double fo = fx_fene(so, r2o), fn = fx_fene(sn, r2n);
+                uo += fo;
+                un += fn;
+                fino = fo < __builtin_inf();
+                finn = fn < __builtin_inf();
             }
+            de = un - uo;
+            sc = un + uo;
+        }
+        terms += (uint32_t)__popcll(__ballot(ino)) + (uint32_t)__popcll(__ballot(inn)) +
+                 (uint32_t)__popcll(__ballot(fino)) + (uint32_t)__popcll(__ballot(finn));
     }
     // intermolecular pairs: for each changed atom, the atoms of the 27 cells
     // around the cell it was sorted into this sweep, a lane each (cells are at
@@ -329,22 +440,26 @@ __device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint
     for (uint32_t s = 0; s < 4; ++s) {
         if (!((changed >> s) & 1u)) continue;  // wave-uniform
         const uint32_t cy_id = V.cell_id[base + s];
-        const uint32_t ux = cy_id % D.nc, uy = (cy_id / D.nc) % D.nc, uz = cy_id / (D.nc * D.nc);
-        uint32_t total;
-        const int nseg = fx_segments(D, V, (int)ux, (int)uy, (int)uz, 1, W, &total);
-        const double sos = D.sigma[ot[s]], sns = D.sigma[nt[s]];
+        const bool listed = ncand != 0xFFFFFFFFu && cy_id == cell;  // wave-uniform
+        uint32_t total = ncand;
+        int nseg = 0;
+        if (!listed) {
+            const uint32_t ux = cy_id % D.nc, uy = (cy_id / D.nc) % D.nc, uz = cy_id / (D.nc * D.nc);
+            nseg = fx_segments(D, V, (int)ux, (int)uy, (int)uz, 1, W, &total);
+        }
+        const double sos = fx_pick(sig, ot[s]), sns = fx_pick(sig, nt[s]);
         for (uint32_t b = 0; b < total; b += 64u) {
             const uint32_t idx = b + (uint32_t)lane;
             uint32_t j = 0xFFFFFFFFu;
-            if (idx < total) j = fx_stencil_atom(V, W, nseg, idx);
-            const bool valid = j != 0xFFFFFFFFu && j / n != a / n;
+            if (idx < total) j = listed ? W.cand[idx] : fx_stencil_atom(V, W, nseg, idx);
+            const bool valid = j != 0xFFFFFFFFu && j - base >= n;  // not an atom of the molecule
             double xj = 0.0, yj = 0.0, zj = 0.0;
             uint32_t tj = 0;
             if (valid) {
                 xj = V.pos[j]; yj = V.pos[N + j]; zj = V.pos[2 * N + j];
                 tj = V.type[j];
             }
-            const double sj = D.sigma[tj];
+            const double sj = fx_pick(sig, tj);
             const double dxo = fx_mi(ox[s] - xj, D.L, D.invL), dyo = fx_mi(oy[s] - yj, D.L, D.invL),
                          dzo = fx_mi(oz[s] - zj, D.L, D.invL);
             const double r2o = valid ? dxo * dxo + dyo * dyo + dzo * dzo : 1e30;
@@ -363,11 +478,9 @@ __device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint
                      (uint32_t)__popcll(__ballot(r2n < D.rc2f * sn * sn));
         }
     }
-    // lane 0 holds the intramolecular counts plus the ballots' (wave totals)
-    terms = (uint32_t)__builtin_amdgcn_readlane((int)terms, 0);
     const double dE = wave_sum_dpp(de);
     const double S = logging ? wave_sum_dpp(sc) : 0.0;
-    const bool accept = (dE <= 0.0) || (thr < -dE);
+    const bool accept = (dE <= 0.0) || (pr.thr < -dE);
     wc.terms += terms;
     if (accept) {
         if (flip) wc.acc_f += 1; else wc.acc_t += 1;
@@ -380,11 +493,12 @@ __device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint
                 for (uint32_t s = 0; s < 4; ++s)
                     if ((changed >> s) & 1u) V.type[base + s] = (uint8_t)nt[s];
             } else {
-                V.pos[a] = fx_pick(nx, sa);
-                V.pos[N + a] = fx_pick(ny, sa);
-                V.pos[2 * N + a] = fx_pick(nz, sa);
+                V.pos[a] = wx;
+                V.pos[N + a] = wy;
+                V.pos[2 * N + a] = wz;
                 // periodic images crossed (the shifts the wrap took off)
-                const int ix = (int)floor(tx / D.L), iy = (int)floor(ty / D.L), iz = (int)floor(tz / D.L);
+                const int ix = (int)floor(pr.tx / D.L), iy = (int)floor(pr.ty / D.L),
+                          iz = (int)floor(pr.tz / D.L);
                 if (ix) D.img[a] += ix;
                 if (iy) D.img[N + a] += iy;
                 if (iz) D.img[2 * N + a] += iz;
@@ -392,9 +506,9 @@ __device__ __forceinline__ void fx_attempt(const FxDev& D, const FxView& V, uint
         }
         if (logging) {
             MoveRecord rec;
-            rec.delta_e = dE; rec.scale = S; rec.t_log_u = thr; rec.sweep = sweep;
+            rec.delta_e = dE; rec.scale = S; rec.t_log_u = pr.thr; rec.sweep = sweep;
             rec.molecule = a; rec.move = flip ? MC_FLIP : MC_TRANSLATE; rec.accepted = accept ? 1 : 0;
-            rec.exited = 0; rec.axis = (uint8_t)kind; rec.pair_terms = terms; rec.pad = 0;
+            rec.exited = 0; rec.axis = (uint8_t)pr.kind; rec.pair_terms = terms; rec.pad = 0;
             D.log[(sweep - D.log_sweep0) * N + a] = rec;
         }
     }
@@ -440,12 +554,14 @@ template <bool kRes>
 __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp, uint64_t n_sweeps)
 {
     __shared__ uint32_t seg[kFxWaves][2][kFxSeg];
+    __shared__ uint32_t cand[kFxWaves][kFxCand];
     __shared__ uint32_t scratch[kFxWaves];
     __shared__ double misc[2];
     extern __shared__ __align__(16) unsigned char fx_smem[];
     const FxDev& D = *Dp;
+    const FxK K = fx_const(D);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    FxWaveLds W{seg[wave][0], seg[wave][1]};
+    FxWaveLds W{seg[wave][0], seg[wave][1], cand[wave]};
     Stats* st = D.stats;
     const uint32_t N = D.N, ncell = D.ncell, nc = D.nc, k = D.k;
     FxView V{D.pos, D.type, D.cell_start, D.cell_list, D.cell_id, D.ecell};
@@ -463,13 +579,13 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp
     if (tid == 0) misc[0] = st->e_acc;
     FxCount wc{};
     for (uint64_t it = 0; it < n_sweeps; ++it) {
-        const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, D.seed_lo, D.seed_hi);
-        const double h[3] = {D.w * unit_open(g.x), D.w * unit_open(g.y), D.w * unit_open(g.z)};
+        const U4 g = philox10(0xFFFFFFFFu, (uint32_t)sweep, (uint32_t)(sweep >> 32), 3u, K.seed_lo, K.seed_hi);
+        const double h[3] = {K.w * unit_open(g.x), K.w * unit_open(g.y), K.w * unit_open(g.z)};
         // counting sort of the atoms by cell
         for (uint32_t c = tid; c <= ncell; c += kFxThreads) V.cell_start[c] = 0;
         __syncthreads();
         for (uint32_t i = tid; i < N; i += kFxThreads) {
-            const uint32_t c = fx_cell(V.pos[i], V.pos[N + i], V.pos[2 * N + i], h, D);
+            const uint32_t c = fx_cell(V.pos[i], V.pos[N + i], V.pos[2 * N + i], h, K);
             V.cell_id[i] = c;
             atomicAdd(&V.cell_start[c + 1], 1u);
         }
@@ -488,8 +604,21 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp
                                                                   nc * (kz + k * (ci / (na * na))));
                 wc.e = 0.0;
                 const uint32_t b = V.cell_start[cell], e = V.cell_start[cell + 1];
-                for (uint32_t q = b; q < e; ++q)
-                    fx_attempt(D, V, V.cell_list[q], sweep, h, cell, logging, W, wc);
+                if (b < e) {
+                    const uint32_t ncand = fx_gather_candidates(K, V, cell, W);
+                    for (uint32_t q0 = b; q0 < e; q0 += 64u) {
+                        const uint32_t cnt = min(64u, e - q0);
+                        uint32_t at = 0;
+                        FxProp pr{};
+                        if ((uint32_t)lane < cnt) {
+                            at = V.cell_list[q0 + lane];
+                            pr = fx_propose(K, V, at, sweep, h, cell);
+                        }
+                        for (uint32_t q = 0; q < cnt; ++q)
+                            fx_attempt(K, V, (uint32_t)__builtin_amdgcn_readlane((int)at, (int)q),
+                                       fx_prop_of_lane(pr, (int)q), sweep, cell, ncand, logging, W, wc);
+                    }
+                }
                 if (lane == 0) V.ecell[cell] = wc.e;
             }
             __syncthreads();
@@ -998,12 +1127,12 @@ namespace {
 
 // Dynamic LDS of the resident sweep kernel for these parameters, 0 when the
 // state stays in the buffer (MC_FLAG_HBM_STATE, or too large for one
-// workgroup next to the kernel's static LDS of about 4 KiB).
+// workgroup next to the kernel's static LDS).
 size_t fx_resident_lds(const mcf_params* p, const FxGeom& g)
 {
     if (p->flags & MC_FLAG_HBM_STATE) return 0;
     const size_t lds = fx_lds_layout(g.N, g.ncell).total;
-    return lds + 8192 <= device_lds_limit() ? lds : 0;
+    return lds + kFxStaticLds <= device_lds_limit() ? lds : 0;
 }
 
 uint32_t fx_parts(const mcf_system* s) { return (s->g.N + kFxThreads - 1) / kFxThreads; }
