@@ -269,7 +269,7 @@ def bench_c1(args, flipmc, torch):
         # roofline of its own dominant kernel, and the flexible molecules
         out["c2"] = bench_c2(args, flipmc, torch)
         out["c3"] = bench_c3(args, flipmc, torch)
-        out["flexible"] = bench_flex(args, flipmc, torch, sweeps=200, bodies=("triangles",))
+        out["flexible"] = bench_flex(args, flipmc, torch, sweeps=200, bodies=("triangles",), replicas=256)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
@@ -396,7 +396,7 @@ def bench_tau(args, flipmc, torch):
     return out
 
 
-def bench_flex(args, flipmc, torch, sweeps=None, bodies=("triangles", "squares", "tetrahedra")):
+def bench_flex(args, flipmc, torch, sweeps=None, bodies=("triangles", "squares", "tetrahedra"), replicas=None):
     """The paper's own flexible molecules (FENE-bonded A/B/C triangles, Sec.
     II.A) and the squares and tetrahedra of Sec. VII on the flexible engine,
     FP64: attempted atom moves per second after a warm-up from the lattice
@@ -404,6 +404,7 @@ def bench_flex(args, flipmc, torch, sweeps=None, bodies=("triangles", "squares",
     its launch time, against the FP64 vector peak)."""
     out = {}
     n_sweeps = sweeps or args.flex_sweeps
+    replicas = args.flex_replicas if replicas is None else replicas
     for name, g, M, T, rho in (("triangles", flipmc.MC_TRIANGLE, 1000, 0.75, 1.2),
                                ("squares", flipmc.MC_SQUARE, 1000, 1.0, 1.2),
                                ("tetrahedra", flipmc.MC_TETRAHEDRON, 1000, 1.0, 1.2)):
@@ -443,7 +444,44 @@ def bench_flex(args, flipmc, torch, sweeps=None, bodies=("triangles", "squares",
             "ms": ms,
         }
         progress(f"flex: {name} done")
+    if replicas:
+        out["replicas"] = bench_flex_replicas(args, flipmc, torch, replicas, n_sweeps)
     return out
+
+
+def bench_flex_replicas(args, flipmc, torch, R, n_sweeps):
+    """R replicas of the 1000 flexible triangles (seeds 1..R) advanced
+    together by mcf_sweep_many, one workgroup each: the device-wide rate of
+    the flexible engine when the paper's replica averages fill it."""
+    M, T, rho = 1000, 0.75, 1.2
+    ps = [flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=M, temperature=T, density=rho, seed=r + 1,
+                                    resum_interval=100, gofr_interval=0) for r in range(R)]
+    systems = [flipmc.FlexSystem(p) for p in ps]
+    flipmc.flex_sweep_many(systems, args.flex_warmup)
+    torch.cuda.synchronize()
+    o0 = [s.observables() for s in systems]
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    flipmc.flex_sweep_many(systems, n_sweeps)
+    z.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(z)
+    o1 = [s.observables() for s in systems]
+    terms = sum(int(b["pair_terms"] - x["pair_terms"]) for x, b in zip(o0, o1))
+    for s in systems:
+        s.close()
+    N = 3 * M
+    achieved = terms * FLOP_PER_PAIR_TERM / (ms / 1e3) / 1e12
+    progress("flex: replicas done")
+    return {
+        "workload": f"{R} replicas of {M} flexible triangles ({N} atoms each), density {rho}, T={T}, FP64, "
+                    f"{args.flex_warmup} warm-up + {n_sweeps} timed sweeps, one launch per event interval",
+        "atom_moves_per_s": R * N * n_sweeps / (ms / 1e3),
+        "pair_interactions_per_s": terms / (ms / 1e3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["f64"], "kernel": "k_fx_sweeps", "cus_used": min(R, 256)},
+        "ms": ms,
+    }
 
 
 def bench_c3(args, flipmc, torch):
@@ -567,7 +605,8 @@ def bench_c4(args, flipmc, torch, n_jobs=None, check_alone=None):
     offered = sum(j.n_molecules * j.sweeps for j in jobs) / (jobs[-1].arrival - jobs[0].arrival)
     return {
         "workload": f"c4: {len(jobs)} Poisson jobs at 200/s, M=n^3 log-uniform in [125,{args.m_max}], "
-                    f"T in [0.75,3], sweeps log-uniform in [100,{args.s_max}], FP32 dE",
+                    f"T in [0.75,3], sweeps log-uniform in [100,{args.s_max}], FP32 dE, memory budget "
+                    f"{args.budget / 2**20:g} MiB",
         "completed": len(res),
         "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
@@ -613,6 +652,8 @@ def main():
     ap.add_argument("--tau-equilibration", type=int, default=40000)
     ap.add_argument("--flex-warmup", type=int, default=200)
     ap.add_argument("--flex-sweeps", type=int, default=1000)
+    ap.add_argument("--flex-replicas", type=int, default=256,
+                    help="flex: replicas of the 1000 flexible triangles advanced together (0: none)")
     ap.add_argument("--tau-sweeps", type=int, default=50000)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--serving-jobs", type=int, default=200,

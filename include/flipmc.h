@@ -404,6 +404,16 @@ int mcf_init_system_noalloc(const mcf_params* p, const double* pos, const uint8_
 /* Enqueue n timesteps of N attempts (Sec. II.B).  Asynchronous. */
 int mcf_sweep(mcf_system* s, uint64_t n_sweeps);
 
+/* Enqueue n timesteps (Sec. II.B) of each of `count` distinct systems -- the
+ * independent replicas over which the paper's averages (Sec. III) are taken --
+ * one workgroup per system, up to 256 systems per launch, so that many
+ * systems fill the device.  Each system's chain and observables are bitwise
+ * those of mcf_sweep on it alone; systems may differ in size and parameters.
+ * All must have been created on the same stream, where the launches go.
+ * MC_EINVAL for an empty or NULL list, a NULL or repeated system, or systems
+ * on different streams (nothing is enqueued then).  Asynchronous. */
+int mcf_sweep_many(mcf_system* const* systems, uint32_t count, uint64_t n_sweeps);
+
 /* FP64 total energy now (Eq. 1 over all atom pairs + Eq. 2 over the bonds, a
  * fresh re-sum), E/M and the drift e_acc - E.  Synchronises. */
 int mcf_energy(mcf_system* s, double* e_total, double* e_per_molecule, double* drift);
@@ -478,7 +488,8 @@ int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn*
  * multi-workgroup engine, each on up to the workgroups its cells allow.
  * Systems on one workgroup share one persistent launch per
  * placement class (state in LDS / in HBM); systems on the multi-workgroup
- * engine share one cooperative launch on a second stream the batch creates.
+ * engine share one cooperative launch on the caller's second stream
+ * (hip_stream_aux of mc_batch_create).
  * All engines make the same decisions and sum the energy in the same order,
  * so a system gives bitwise the same results in a batch as alone, whichever
  * engines its runs used. */

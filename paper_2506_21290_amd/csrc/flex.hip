@@ -53,6 +53,7 @@ constexpr int kFxCand = 384;        // atoms of a cell's 27-cell stencil listed 
 // scratch and the energy accumulator (with room to spare)
 constexpr size_t kFxStaticLds = (size_t)kFxWaves * (2 * kFxSeg + kFxCand) * 4 + 256;
 constexpr uint32_t kFxParts = 1024;  // workgroups of the event kernel
+constexpr uint32_t kFxMany = 256;    // systems of one sweep launch (a workgroup each)
 
 // Everything a workgroup needs about one system; in the system's buffer.
 struct FxDev {
@@ -89,6 +90,12 @@ struct FxDev {
     double* part;         // [kFxParts] partial energies of the event kernel
     MoveRecord* log;
     uint64_t log_sweep0, log_sweeps;
+};
+
+// The systems of one sweep launch, passed by value (2 KiB of kernel
+// arguments): workgroup b runs d[b].
+struct FxList {
+    FxDev* d[kFxMany];
 };
 
 // The constants of the sweep kernel, copied from the system's descriptor into
@@ -551,8 +558,9 @@ __device__ void fx_sort_cells(uint32_t* list, const uint32_t* start, uint32_t c0
 // at the start, positions and types written back at the end); otherwise the
 // same code runs on the arrays in the system's buffer.
 template <bool kRes>
-__global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxDev* __restrict__ Dp, uint64_t n_sweeps)
+__global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxList list, uint64_t n_sweeps)
 {
+    FxDev* __restrict__ Dp = list.d[blockIdx.x];
     __shared__ uint32_t seg[kFxWaves][2][kFxSeg];
     __shared__ uint32_t cand[kFxWaves][kFxCand];
     __shared__ uint32_t scratch[kFxWaves];
@@ -1538,23 +1546,75 @@ int mcf_init_system_noalloc(const mcf_params* p, const double* pos, const uint8_
     return MC_OK;
 }
 
+namespace {
+
+// `chunk` sweeps of systems s[0 .. n), n <= kFxMany, on `stream`: one launch
+// for those with their state in LDS, one for the others.
+int fx_launch_sweeps(mcf_system* const* s, uint32_t n, uint64_t chunk, hipStream_t stream)
+{
+    FxList res{}, buf{};
+    uint32_t nr = 0, nb = 0;
+    size_t lds = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (s[i]->lds) {
+            res.d[nr++] = s[i]->dev;
+            lds = std::max(lds, s[i]->lds);
+        } else {
+            buf.d[nb++] = s[i]->dev;
+        }
+    }
+    if (nr) {
+        hipLaunchKernelGGL(k_fx_sweeps<true>, dim3(nr), dim3(kFxThreads), lds, stream, res, chunk);
+        FXCHK(hipGetLastError());
+    }
+    if (nb) {
+        hipLaunchKernelGGL(k_fx_sweeps<false>, dim3(nb), dim3(kFxThreads), 0, stream, buf, chunk);
+        FXCHK(hipGetLastError());
+    }
+    return MC_OK;
+}
+
+// n sweeps of the systems s[0 .. count), split at every sweep where one of
+// them has events.
+int fx_sweep_systems(mcf_system* const* s, uint32_t count, uint64_t n)
+{
+    while (n > 0) {
+        uint64_t chunk = n;
+        for (uint32_t i = 0; i < count; ++i) chunk = std::min<uint64_t>(chunk, fx_next_event(s[i]) - s[i]->sweep);
+        for (uint32_t i0 = 0; i0 < count; i0 += kFxMany)
+            if (int rc = fx_launch_sweeps(s + i0, std::min(kFxMany, count - i0), chunk, s[0]->stream)) return rc;
+        n -= chunk;
+        for (uint32_t i = 0; i < count; ++i) {
+            s[i]->sweep += chunk;
+            const uint32_t f = fx_events_at(s[i], s[i]->sweep);
+            if (f)
+                if (int rc = fx_events(s[i], f)) return rc;
+        }
+    }
+    return MC_OK;
+}
+
+}  // namespace
+
 int mcf_sweep(mcf_system* s, uint64_t n)
 {
     if (!s) return fx_fail(MC_EINVAL, "null system");
-    while (n > 0) {
-        const uint64_t chunk = std::min<uint64_t>(n, fx_next_event(s) - s->sweep);
-        if (s->lds)
-            hipLaunchKernelGGL(k_fx_sweeps<true>, dim3(1), dim3(kFxThreads), s->lds, s->stream, s->dev, chunk);
-        else
-            hipLaunchKernelGGL(k_fx_sweeps<false>, dim3(1), dim3(kFxThreads), 0, s->stream, s->dev, chunk);
-        FXCHK(hipGetLastError());
-        s->sweep += chunk;
-        n -= chunk;
-        const uint32_t f = fx_events_at(s, s->sweep);
-        if (f)
-            if (int rc = fx_events(s, f)) return rc;
+    return fx_sweep_systems(&s, 1, n);
+}
+
+int mcf_sweep_many(mcf_system* const* systems, uint32_t count, uint64_t n)
+{
+    if (!systems || count == 0) return fx_fail(MC_EINVAL, "no systems");
+    std::vector<mcf_system*> v(systems, systems + count);
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!v[i]) return fx_fail(MC_EINVAL, "null system at %u", i);
+        if (v[i]->stream != v[0]->stream) return fx_fail(MC_EINVAL, "system %u is on another stream", i);
     }
-    return MC_OK;
+    std::vector<mcf_system*> sorted(v);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fx_fail(MC_EINVAL, "a system appears twice");
+    return fx_sweep_systems(v.data(), count, n);
 }
 
 int mcf_energy(mcf_system* s, double* e_total, double* e_per_molecule, double* drift)

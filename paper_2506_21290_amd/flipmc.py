@@ -35,7 +35,8 @@ EXPORTED = [
     "mc_last_error", "mc_batch_required_bytes", "mc_batch_create",
     "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
     "mc_batch_set_workgroups", "mc_dynamics",
-    "mcf_params_default", "mcf_geometry", "mcf_placement", "mcf_required_bytes", "mcf_init_system", "mcf_sweep",
+    "mcf_params_default", "mcf_geometry", "mcf_placement", "mcf_required_bytes", "mcf_init_system",
+    "mcf_sweep", "mcf_sweep_many",
     "mcf_energy", "mcf_observables", "mcf_reset_observables", "mcf_get_state", "mcf_set_state",
     "mcf_decision_log", "mcf_destroy", "mcf_init_system_noalloc",
 ]
@@ -227,6 +228,7 @@ def lib():
         L.mcf_required_bytes.argtypes = [fp, szp]
         L.mcf_init_system.argtypes = [fp, dp, u8p, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.mcf_sweep.argtypes = [vp, C.c_uint64]
+        L.mcf_sweep_many.argtypes = [C.POINTER(vp), C.c_uint32, C.c_uint64]
         L.mcf_energy.argtypes = [vp, dp, dp, dp]
         L.mcf_observables.argtypes = [vp, C.POINTER(mc_obs)]
         L.mcf_reset_observables.argtypes = [vp]
@@ -710,3 +712,10 @@ class FlexSystem:
             return None
         self.stream.synchronize()
         return np.frombuffer(self._log.cpu().numpy().tobytes(), dtype=MOVE_RECORD_DTYPE).copy()
+
+
+def flex_sweep_many(systems, n=1):
+    """n timesteps of each FlexSystem in `systems`, one workgroup per system
+    (mcf_sweep_many); all must share one stream."""
+    arr = (C.c_void_p * len(systems))(*[x.h for x in systems])
+    _check(lib().mcf_sweep_many(arr, len(systems), int(n)))

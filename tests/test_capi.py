@@ -132,3 +132,11 @@ def test_flexible_placement_without_a_device():
                                                               flags=flipmc.MC_FLAG_HBM_STATE))
     assert not res and lds == 0
     assert not flipmc.mcf_placement(flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=8000))[0]
+
+
+def test_flexible_sweep_many_rejects_empty_lists_without_a_device():
+    L = flipmc.lib()
+    assert L.mcf_sweep_many(None, 0, 1) == flipmc.MC_EINVAL
+    arr = (C.c_void_p * 2)(None, None)
+    assert L.mcf_sweep_many(arr, 2, 1) == flipmc.MC_EINVAL
+    assert b"null system" in L.mc_last_error()

@@ -218,3 +218,31 @@ def test_lds_and_buffer_state_agree(case):
         assert np.array_equal(np.asarray(oa[key]), np.asarray(ob[key])), key
     assert oa["exits"] == ob["exits"] and oa["e_acc"] == ob["e_acc"]
     assert a.energy() == b.energy()
+
+
+def test_sweep_many_equals_each_system_alone():
+    # one launch of four systems of different geometry, size and placement
+    # (the 1000-triangle system keeps its state in the buffer) against each
+    # system advanced alone: bitwise the same states and observables
+    print("flex sweep_many", flush=True)
+    kw = dict(gofr_interval=5, obs_interval=5, resum_interval=10, max_samples=64)
+    specs = [("triangle", 1, 0), ("tetrahedron", 2, 0), ("square", 3, 0),
+             ("triangle_1000", 4, flipmc.MC_FLAG_HBM_STATE)]
+    many = [flipmc.FlexSystem(gp(*CASES[c], seed=sd, flags=fl, **kw)) for c, sd, fl in specs]
+    alone = [flipmc.FlexSystem(gp(*CASES[c], seed=sd, flags=fl, **kw)) for c, sd, fl in specs]
+    for n in (1, 7, 22):
+        flipmc.flex_sweep_many(many, n)
+        for s in alone:
+            s.sweep(n)
+    for a, b in zip(many, alone):
+        sa, sb = a.get_state(), b.get_state()
+        assert sa["sweep"] == sb["sweep"] == 30
+        assert np.array_equal(sa["pos"], sb["pos"]) and np.array_equal(sa["types"], sb["types"])
+        oa, ob = a.observables(), b.observables()
+        for key in ("attempts", "accepts", "gofr_all", "c2", "fs", "fs_cm"):
+            assert np.array_equal(np.asarray(oa[key]), np.asarray(ob[key])), key
+        assert oa["e_acc"] == ob["e_acc"]
+    with pytest.raises(flipmc.McError) as e:
+        flipmc.flex_sweep_many([many[0], many[1], many[0]], 1)
+    assert e.value.code == flipmc.MC_EINVAL
+    assert many[0].get_state()["sweep"] == 30  # nothing was enqueued
