@@ -14,7 +14,11 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# FLIPMC_ORACLE_SANITIZE=1 builds and loads a copy instrumented with
+# AddressSanitizer and UndefinedBehaviorSanitizer (a process that loads it
+# needs the ASan runtime preloaded; tests/test_sanitizers.py does that).
+SANITIZE = os.environ.get("FLIPMC_ORACLE_SANITIZE") == "1"
+LIB_PATH = os.path.join(HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 SRC_PATH = os.path.join(HERE, "flipmc_oracle.c")
 SOURCES = [SRC_PATH, os.path.join(HERE, "flex_oracle.c")]
 
@@ -46,9 +50,11 @@ def build(force: bool = False) -> str:
         os.path.getmtime(LIB_PATH) < os.path.getmtime(f)
         for f in SOURCES + [os.path.join(HERE, "flipmc_oracle.h"), os.path.join(HERE, "flex_oracle.h")])
     if force or stale:
+        san = (["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                "-fno-sanitize-recover=undefined"] if SANITIZE else [])
         subprocess.check_call(
             [
-                "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", *san,
                 "-fPIC", "-shared", *SOURCES, "-o", LIB_PATH, "-lm",
             ]
         )
