@@ -405,6 +405,7 @@ def bench_flex(args, flipmc, torch, sweeps=None, bodies=("triangles", "squares",
     out = {}
     n_sweeps = sweeps or args.flex_sweeps
     replicas = args.flex_replicas if replicas is None else replicas
+    counters = measured_counters("k_fx_sweeps_flex")
     for name, g, M, T, rho in (("triangles", flipmc.MC_TRIANGLE, 1000, 0.75, 1.2),
                                ("squares", flipmc.MC_SQUARE, 1000, 1.0, 1.2),
                                ("tetrahedra", flipmc.MC_TETRAHEDRON, 1000, 1.0, 1.2)):
@@ -440,7 +441,11 @@ def bench_flex(args, flipmc, torch, sweeps=None, bodies=("triangles", "squares",
             "energy_per_molecule": em,
             "pair_interactions_per_s": terms / (ms / 1e3),
             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_TFLOPS["f64"], "kernel": "k_fx_sweeps", "cus_used": 1},
+                         "frac": achieved / PEAK_TFLOPS["f64"], "kernel": "k_fx_sweeps", "cus_used": 1,
+                         # counters of the 1000 triangles' launches (null for
+                         # the other bodies or other kernel sources)
+                         "traffic": counters.get("bytes_per_launch") if name == "triangles" else None,
+                         "valu_busy_on_its_cu": counters.get("valu_busy_on_its_cu") if name == "triangles" else None},
             "ms": ms,
         }
         progress(f"flex: {name} done")

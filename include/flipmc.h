@@ -104,7 +104,13 @@ typedef struct {
                                   a barrier of its system before it gives up and the
                                   system is marked faulted (reads then return
                                   MC_EDEVICE); 0 = default (about 2^23, seconds)       */
-    uint32_t reserved;         /* 0                                                  */
+    uint32_t workgroups;       /* workgroups of mc_sweep's launches: 0 = the engine's
+                                  cost model; 1 = one workgroup (as
+                                  MC_FLAG_SINGLE_WORKGROUP); n >= 2 = the
+                                  multi-workgroup engine on min(n, cells of a colour
+                                  / 4 rounded up, device limit) workgroups, also the
+                                  most a batch gives the system.  Every choice gives
+                                  bitwise the same chain (an autotuner's knob)       */
     double   fs_q;             /* |q| of F_s(q, t) over the sites (Sec. III.B: 7.4,
                                   the first peak of the structure factor)             */
     double   fs_q_cm;          /* |q| of F_s^cm(q, t) over the centres (5.1)         */

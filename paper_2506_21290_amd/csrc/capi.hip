@@ -198,7 +198,8 @@ int geometry(const mc_params* p, Geometry* g)
     const LdsLayout res = lds_layout(fp64, true, p->n_molecules, g->ncell);
     g->resident = res.total <= limit && !(p->flags & MC_FLAG_HBM_STATE);
     g->lds = g->resident ? res.total : lds_layout(fp64, false, p->n_molecules, g->ncell).total;
-    g->spread = !g->resident && !(p->flags & MC_FLAG_SINGLE_WORKGROUP);
+    const bool one_wg = (p->flags & MC_FLAG_SINGLE_WORKGROUP) || p->workgroups == 1;
+    g->spread = !g->resident && !one_wg;
     g->spread_blocks = 1;
     // the model is fitted to the LDS state; with the state in HBM a sweep on
     // one workgroup takes about 1.3 times as long (measured 1.1 - 1.4 over
@@ -206,12 +207,13 @@ int geometry(const mc_params* p, Geometry* g)
     const double cost = cost_estimate(p->n_molecules, g->L, g->reach, k, nc);
     g->sweep_cost = cost * (g->resident ? 1.0 : 1.3);
     g->spread_cost = cost * 1.3;
-    if (!(p->flags & MC_FLAG_SINGLE_WORKGROUP)) {
+    if (!one_wg) {
         // one wave per cell of a colour, within one cooperative wave of the
         // device.  A system whose state fits one workgroup's LDS runs alone on
         // the multi-workgroup engine too when that is modelled faster (many
-        // cells per colour); otherwise it keeps the count for a batch, which
-        // may move it there when compute units are idle
+        // cells per colour) or when the caller asks for a workgroup count;
+        // otherwise it keeps the count for a batch, which may move it there
+        // when compute units are idle
         uint32_t maxb = 0;
         const hipError_t e = spread_max_blocks(fp64, &maxb);
         if (e != hipSuccess || maxb == 0) {
@@ -221,9 +223,13 @@ int geometry(const mc_params* p, Geometry* g)
             const uint32_t na = nc / k;
             const uint32_t want = (na * na * na + kSpreadWaves - 1) / kSpreadWaves;
             g->spread_blocks = std::max(1u, std::min({want, maxb, (uint32_t)(kMaxParts / kSpreadWaves)}));
-            if (g->resident && g->spread_blocks >= 2 &&
-                spread_pays(*g, g->spread_blocks, kCycleRatio[0], kCycleRatio[2]))
+            if (p->workgroups >= 2) {
+                g->spread_blocks = std::min(g->spread_blocks, p->workgroups);
+                if (g->spread_blocks >= 2) g->spread = true;
+            } else if (g->resident && g->spread_blocks >= 2 &&
+                       spread_pays(*g, g->spread_blocks, kCycleRatio[0], kCycleRatio[2])) {
                 g->spread = true;
+            }
         }
     }
     return MC_OK;
@@ -582,7 +588,7 @@ void mc_params_default(mc_params* p)
     p->barrier_polls = 0;
     p->fs_q = 7.4;     // first peak of the site structure factor (Sec. III.B)
     p->fs_q_cm = 5.1;  // first peak of the centres' structure factor
-    p->reserved = 0;
+    p->workgroups = 0;
 }
 
 int mc_geometry(const mc_params* p, double* box, uint32_t* k, uint32_t* nc)

@@ -73,7 +73,7 @@ class mc_params(C.Structure):
         ("flags", C.c_uint32),
         ("gofr_dr", C.c_double),
         ("barrier_polls", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("workgroups", C.c_uint32),
         ("fs_q", C.c_double),
         ("fs_q_cm", C.c_double),
     ]

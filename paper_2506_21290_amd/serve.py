@@ -48,15 +48,16 @@ class Result:
 
 
 def job_params(job, precision):
-    """Engine parameters of a job: the tuned decomposition for its size, FP64
+    """Engine parameters of a job: the tuned decomposition and workgroup count
+    for its size (the latter caps what a batch gives the job), FP64
     re-sum every 100 sweeps, E/M every 10 sweeps and about five g(r) frames over
     the second half of the run."""
     S = job.sweeps
     gofr_every = max(10, (S // 2) // 5 // 10 * 10)
-    k, nc = tune.choose(job.n_molecules, precision)
+    k, nc, wg = tune.choose(job.n_molecules, precision)
     return flipmc.mc_params_default(
         n_molecules=job.n_molecules, temperature=job.temperature, precision=precision,
-        seed=job.seed, colours_per_axis=k, cells_per_side=nc, resum_interval=100,
+        seed=job.seed, colours_per_axis=k, cells_per_side=nc, workgroups=wg, resum_interval=100,
         obs_interval=10, gofr_interval=gofr_every, obs_start=S // 2,
         max_samples=max(16, S // 10 + 2))
 

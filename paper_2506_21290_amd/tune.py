@@ -1,13 +1,16 @@
-"""Autotuner of the checkerboard decomposition.
+"""Autotuner of the checkerboard decomposition and of the molecules per
+workgroup.
 
 For a system size M and a precision, every valid (k, n_c) is a correct
 sampler with its own trajectory; they differ in speed (colour phases, cells per
-wave, neighbour-list length, and for the multi-workgroup engine the number of
-workgroups, one wave per cell of a colour).  The tuner times each candidate on
-the engine mc_sweep picks for it (mc_engine) and records the fastest in
-``tuned.json`` next to this file.  ``choose`` reads the table (falling back to
-the engine's own model when a size is missing), so a job's decomposition is a
-fixed function of (M, precision) and can be reproduced by the oracle.
+wave, neighbour-list length).  For each (k, n_c) the number of workgroups a
+sweep runs on (one, or the multi-workgroup engine on a wave per cell of a
+colour, or on fewer workgroups with several cells per wave) changes only the
+speed: every count gives bitwise the same chain.  The tuner times each
+candidate (k, n_c, workgroups) and records the fastest in ``tuned.json`` next
+to this file.  ``choose`` reads the table (falling back to the engine's own
+model when a size is missing), so a job's decomposition is a fixed function of
+(M, precision) and can be reproduced by the oracle.
 
 Run on the GPU:  python -m paper_2506_21290_amd.tune --out tuned.json
 """
@@ -54,6 +57,20 @@ def candidates(M, precision, per_k=4):
     return resident or out
 
 
+def workgroup_counts(M, precision, k, nc):
+    """Workgroup counts worth timing for one decomposition: the most its cells
+    allow (a wave per cell of a colour), half and a quarter of that, and one
+    workgroup when the state fits its LDS."""
+    p = flipmc.mc_params_default(n_molecules=M, precision=precision, colours_per_axis=k, cells_per_side=nc,
+                                 workgroups=1 << 20)
+    _, most = flipmc.mc_engine(p)
+    counts = {w for w in (most, most // 2, most // 4) if w >= 2}
+    p.workgroups = 1
+    if flipmc.mc_placement(p)[0] or not counts:
+        counts.add(1)
+    return sorted(counts)
+
+
 def table():
     global _table
     if _table is None:
@@ -65,19 +82,20 @@ def table():
 
 
 def choose(M, precision):
-    """(k, n_c) for M molecules: the tuned entry, else (0, 0) = engine model."""
+    """(k, n_c, workgroups) for M molecules: the tuned entry, else (0, 0, 0) =
+    the engine's model."""
     entry = table().get(PREC_NAME[precision], {}).get(str(M))
     if entry:
-        return int(entry["k"]), int(entry["n_c"])
-    return 0, 0
+        return int(entry["k"]), int(entry["n_c"]), int(entry.get("tuned_workgroups", 0))
+    return 0, 0, 0
 
 
-def time_candidate(M, precision, k, nc, sweeps, T=1.0):
+def time_candidate(M, precision, k, nc, sweeps, T=1.0, workgroups=0):
     import torch
 
     p = flipmc.mc_params_default(n_molecules=M, temperature=T, precision=precision,
                                  colours_per_axis=k, cells_per_side=nc, resum_interval=0,
-                                 obs_interval=0, gofr_interval=0)
+                                 obs_interval=0, gofr_interval=0, workgroups=workgroups)
     s = flipmc.System(p)
     s.sweep(max(5, sweeps // 5))
     torch.cuda.synchronize()
@@ -96,15 +114,17 @@ def tune(sizes, precisions, budget_moves=600_000):
             sweeps = max(10, min(200, budget_moves // M))
             timed = []
             for k, nc in candidates(M, prec):
-                dt = time_candidate(M, prec, k, nc, sweeps)
-                timed.append((dt, k, nc))
-                print(f"{name} M={M} k={k} n_c={nc}: {dt * 1e6:.1f} us/sweep", flush=True)
-            dt, k, nc = min(timed)
+                for wg in workgroup_counts(M, prec, k, nc):
+                    dt = time_candidate(M, prec, k, nc, sweeps, workgroups=wg)
+                    timed.append((dt, k, nc, wg))
+                    print(f"{name} M={M} k={k} n_c={nc} workgroups={wg}: {dt * 1e6:.1f} us/sweep", flush=True)
+            dt, k, nc, wg = min(timed)
             p = flipmc.mc_params_default(n_molecules=M, precision=prec, colours_per_axis=k,
-                                         cells_per_side=nc)
-            engine, wg = flipmc.mc_engine(p)
-            result[name][str(M)] = {"k": k, "n_c": nc, "us_per_sweep": dt * 1e6,
-                                    "moves_per_s": M / dt, "engine": engine, "workgroups": wg}
+                                         cells_per_side=nc, workgroups=wg)
+            engine, used = flipmc.mc_engine(p)
+            result[name][str(M)] = {"k": k, "n_c": nc, "tuned_workgroups": wg, "us_per_sweep": dt * 1e6,
+                                    "moves_per_s": M / dt, "engine": engine, "workgroups": used,
+                                    "molecules_per_workgroup": M / used}
     return result
 
 

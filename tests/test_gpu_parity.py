@@ -163,6 +163,32 @@ def test_engines_make_identical_decisions(fp32):
         assert abs(sg["e_acc"] - s0["e_acc"]) <= 1e-12 * (abs(s0["e_acc"]) + 1.0)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_workgroup_count_changes_nothing_but_speed(fp32):
+    # the tuner's knob: the 1000-molecule system (k = 3, n_c = 9: 27 cells per
+    # colour) on one workgroup and on the multi-workgroup engine with 2, 5 and
+    # 7 workgroups (several cells per wave, or one each) gives the same dE
+    # bits, decisions and states
+    n = 6
+    runs = []
+    for wg, want in [(1, (flipmc.MC_ENGINE_LDS, 1)), (2, (flipmc.MC_ENGINE_SPREAD, 2)),
+                     (5, (flipmc.MC_ENGINE_SPREAD, 5)), (1000, (flipmc.MC_ENGINE_SPREAD, 7))]:
+        gp = gparams(1000, 0.9, 3, 9, fp32=fp32, seed=41, workgroups=wg, resum_interval=0,
+                     obs_interval=0, gofr_interval=0)
+        assert flipmc.mc_engine(gp) == want
+        g = flipmc.System(gp)
+        g.decision_log(n)
+        g.sweep(n)
+        runs.append((g.read_log(), g.get_state()))
+        g.close()
+    (l0, s0) = runs[0]
+    for lg, sg in runs[1:]:
+        assert np.array_equal(lg["delta_e"], l0["delta_e"])
+        assert np.array_equal(lg["accepted"], l0["accepted"])
+        assert np.array_equal(sg["com"], s0["com"]) and np.array_equal(sg["quat"], s0["quat"])
+        assert np.array_equal(sg["types"], s0["types"])
+
+
 def test_barrier_timeout_marks_the_system_faulted():
     # failure handling forced from the host: a one-poll bound on the waits at
     # the multi-workgroup engine's barriers.  Workgroups give up instead of
