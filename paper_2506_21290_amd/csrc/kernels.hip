@@ -1464,6 +1464,62 @@ __device__ __forceinline__ void load_ctx(Ctx<Real, kRes>& C, const SysDev* __res
     C.gpart = Dp->g_part;
 }
 
+// The scheduled re-sum and C_2 sample of a sweep inside the batch's sweep
+// kernel (not inlined: its registers stay out of the sweep loop's).  The
+// context is rebuilt from the descriptor and the LDS layout the kernel uses.
+template <typename Real, bool kRes>
+__device__ __attribute__((noinline)) void inline_events(const SysDev* __restrict__ Dp, unsigned char* smem,
+                                                       uint64_t sweep, uint64_t origin, bool resum, bool c2)
+{
+    Ctx<Real, kRes> E;
+    load_ctx(E, Dp);
+    const int tid = threadIdx.x;
+    const bool fp64 = sizeof(Real) == 8;
+    const LdsLayout L = lds_layout(fp64, kRes, E.M, E.ncell);
+    E.bins = nullptr;
+    E.misc = (double*)(smem + L.misc);
+    E.red = E.misc + 8;
+    if (kRes) {
+        E.com = (double*)(smem + L.com);
+        E.site = (R4<Real>*)(smem + L.site);
+        E.cellb = (uint32_t*)(smem + L.cell);
+        E.cellid = (uint16_t*)(smem + L.cellid);
+        E.list = (uint16_t*)(smem + L.list);
+        E.ecell = (double*)(smem + L.ecell);
+    } else {
+        E.com = E.gcom;
+        E.site = (R4<Real>*)Dp->g_site;
+        E.cellb = Dp->g_cell;
+        E.cellid = Dp->g_cellid;
+        E.list = Dp->g_list;
+        E.ecell = Dp->g_ecell;
+    }
+    E.off = nullptr;
+    Stats* st = E.stats;
+    __syncthreads();
+    if (resum) {
+        const double e = resum_energy(E, tid, kThreads);
+        if (tid == 0) {
+            // re-anchor the accumulated energy: each drift sample is the
+            // error of one window
+            const double drift = E.misc[0] - e;
+            E.misc[0] = e;
+            st->e_resum = e;
+            st->drift = drift;
+            st->resum_sweep = sweep;
+            st->n_resum += 1;
+            if (st->n_drift < E.max_samples) E.drift_samples[st->n_drift] = drift;
+            st->n_drift += 1;
+            if (sweep > E.resum_interval && fabs(drift) > st->max_abs_drift) st->max_abs_drift = fabs(drift);
+        }
+        __syncthreads();
+    }
+    if (c2) {
+        store_dyn(E, st, sweep - origin);
+        __syncthreads();
+    }
+}
+
 // The hot kernel: n checkerboard sweeps of every slot's system, one
 // workgroup per system, with the state resident in LDS when it fits.  The
 // variant with kInl also takes the scheduled re-sums and C_2 samples of slots
@@ -1567,33 +1623,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(const Slot* __restrict__ sl
             // that a slice need not end at them
             const bool resum = C.resum_interval && sweep % C.resum_interval == 0;
             const bool c2 = is_c2_time(sweep - origin);
-            if (resum || c2) {
-                __syncthreads();
-                Ctx<Real, kRes> E = C;
-                E.red = C.misc + 8;
-                if (resum) {
-                    const double e = resum_energy(E, tid, kThreads);
-                    if (tid == 0) {
-                        // re-anchor the accumulated energy: each drift sample
-                        // is the error of one window
-                        const double drift = C.misc[0] - e;
-                        C.misc[0] = e;
-                        st->e_resum = e;
-                        st->drift = drift;
-                        st->resum_sweep = sweep;
-                        st->n_resum += 1;
-                        if (st->n_drift < C.max_samples) C.drift_samples[st->n_drift] = drift;
-                        st->n_drift += 1;
-                        if (sweep > C.resum_interval && fabs(drift) > st->max_abs_drift)
-                            st->max_abs_drift = fabs(drift);
-                    }
-                    __syncthreads();
-                }
-                if (c2) {
-                    store_dyn(E, st, sweep - origin);
-                    __syncthreads();
-                }
-            }
+            if (resum || c2) inline_events<Real, kRes>(Dp, smem, sweep, origin, resum, c2);
         }
     }
 
