@@ -8,16 +8,18 @@ sweeps; a step is 100 sweeps (one re-sum window) including the cell builds,
 the re-sum, E/M samples, the g(r) frame and C_2 samples.  The same run in
 plain FP64 is timed beside it, then the first 200 jobs of the serving stream
 give the p50/p99 request latency ("serving"), the 8000-molecule system ("c2"),
-the 256-replica batch ("c3") and the paper's flexible molecules with the
-squares and tetrahedra ("flexible") each report their own roofline, and the
+the 256-replica batch ("c3") and the paper's flexible triangles, one system
+and 256 replicas ("flexible"), each report their own roofline, and the
 CPU oracle runs on a bounded sample on one core and on all cores
 ("cpu_baseline").  Prints one JSON line.
 
 Other workloads (--workload): c2, c3, c4 (the serving loop at any job count and
 memory budget), tau (relaxation times of flip MC against local MC from
 equilibrated states, with the four-point susceptibilities and the Pearson
-coefficient), flex (the flexible engine alone) and copy (the HBM calibration
-of the counter summaries).
+coefficient), flex (the flexible engine alone, one system of each body and
+replicas of the triangles), flex_tau (the same relaxation comparison on the
+paper's own flexible triangles) and copy (the HBM calibration of the counter
+summaries).
 """
 from __future__ import annotations
 
@@ -489,6 +491,70 @@ def bench_flex_replicas(args, flipmc, torch, R, n_sweeps):
     }
 
 
+def bench_flex_tau(args, flipmc, torch):
+    """Relaxation of flip MC against local MC on the paper's own flexible
+    triangles (the protocol of Sec. III.B-C): R replicas of 1000 molecules,
+    each from its own lattice start, are equilibrated by flip MC (p_flip = 0.2)
+    for E sweeps, all replicas advanced together (mcf_sweep_many); each
+    equilibrated state then starts one run of flip MC and one of local MC
+    (p_flip = 0: atom translations only), which sample F_s(7.4, t) over the
+    atoms, F_s^cm(5.1, t) and C_2(t) at t in {1, 2, 5} x 10^j sweeps from a
+    common origin.  The library forms the ensemble means, chi_4, chi_4^self,
+    rho and the 1/e times (mcf_dynamics)."""
+    M, T, R = 1000, args.flex_tau_temperature, args.flex_tau_replicas
+    E, S = args.flex_tau_equilibration, args.flex_tau_sweeps
+    step = 2000
+
+    def params(seed, pf):
+        return flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=M, temperature=T, seed=seed, p_flip=pf,
+                                         resum_interval=1000, obs_interval=0, gofr_interval=0)
+
+    def advance(systems, n, what):
+        done = 0
+        while done < n:
+            k = min(step, n - done)
+            flipmc.flex_sweep_many(systems, k)
+            torch.cuda.synchronize()
+            done += k
+            progress(f"flex tau: {what} {done} of {n} sweeps")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flip = [flipmc.FlexSystem(params(r + 1, 0.2)) for r in range(R)]
+    advance(flip, E, f"{R} replicas equilibrating")
+    local = []
+    for r, s in enumerate(flip):
+        st = s.get_state()
+        local.append(flipmc.FlexSystem(params(R + r + 1, 0.0), pos=st["pos"], types=st["types"]))
+    for s in flip + local:
+        s.reset_observables()
+    advance(flip + local, S, f"{2 * R} production runs")
+    wall = time.perf_counter() - t0
+    N = 3 * M
+    out = {"workload": f"flex tau: {R} replicas of {M} flexible triangles ({N} atoms), T={T}, FP64; {E} sweeps "
+                       f"of flip-MC equilibration, then {S} sweeps each of flip MC and of local MC from the same "
+                       f"states",
+           "wall_s": wall,
+           "atom_moves_per_s": N * (R * E + 2 * R * S) / wall}
+    for kind, ss in (("flip", flip), ("local", local)):
+        d = flipmc.mc_dynamics([s.obs_struct() for s in ss], M, atoms_per_molecule=3)
+        res = {"t": [int(x) for x in d["t"]]}
+        for key in ("fs", "fs_cm", "c2"):
+            ratio = d["chi4_" + key] / np.maximum(d["chi4s_" + key], 1e-300)
+            res[key] = {"mean": d[key].tolist(), "tau": d["tau_" + key],
+                        "chi4_over_self_peak": float(np.max(ratio))}
+        res["pearson_peak"] = float(np.max(d["rho"]))
+        out[kind] = res
+        for s in ss:
+            s.close()
+    out["equilibration_over_tau"] = {key: (E / out["flip"][key]["tau"] if out["flip"][key]["tau"] else None)
+                                     for key in ("fs", "fs_cm", "c2")}
+    out["speedup"] = {key: (out["local"][key]["tau"] / out["flip"][key]["tau"]
+                            if out["local"][key]["tau"] and out["flip"][key]["tau"] else None)
+                      for key in ("fs", "fs_cm", "c2")}
+    return out
+
+
 def bench_c3(args, flipmc, torch):
     """256 independent replicas, M in {216, 512, 1000, 1728}, T over the
     paper's range, FP32 dE, 1000 sweeps each, all advanced by one batch."""
@@ -651,7 +717,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "tau", "flex", "copy"])
+    ap.add_argument("--workload", default="c1",
+                    choices=["c1", "c2", "c3", "c4", "tau", "flex", "flex_tau", "copy"])
     ap.add_argument("--tau-temperature", type=float, default=2.2)
     ap.add_argument("--tau-replicas", type=int, default=16)
     ap.add_argument("--tau-equilibration", type=int, default=40000)
@@ -660,6 +727,10 @@ def main():
     ap.add_argument("--flex-replicas", type=int, default=256,
                     help="flex: replicas of the 1000 flexible triangles advanced together (0: none)")
     ap.add_argument("--tau-sweeps", type=int, default=50000)
+    ap.add_argument("--flex-tau-temperature", type=float, default=1.5)
+    ap.add_argument("--flex-tau-replicas", type=int, default=16)
+    ap.add_argument("--flex-tau-equilibration", type=int, default=10000)
+    ap.add_argument("--flex-tau-sweeps", type=int, default=20000)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--serving-jobs", type=int, default=200,
                     help="jobs of the serving stream run after the c1 line's own work (0: none)")
@@ -689,7 +760,7 @@ def main():
         out = bench_c1(args, flipmc, torch)
     else:
         out = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "tau": bench_tau, "flex": bench_flex,
-               "copy": bench_copy}[args.workload](args, flipmc, torch)
+               "flex_tau": bench_flex_tau, "copy": bench_copy}[args.workload](args, flipmc, torch)
     print(json.dumps(out), flush=True)
 
 

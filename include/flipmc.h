@@ -428,9 +428,11 @@ int mcf_energy(mcf_system* s, double* e_total, double* e_per_molecule, double* d
  * (index MC_TRANSLATE) and flips (MC_FLIP), exits, pair terms, E/M moments,
  * g(r) over atoms (Eq. 3, counts and normalised), C_2 (Eq. 7, the vector from
  * the centre of mass to the atom that was of type B at the origin), F_s over
- * atoms and F_s^cm over centres of mass (Eqs. 5-6).  The per-particle moments
- * are not computed (zero).  Synchronises. */
+ * atoms and F_s^cm over centres of mass (Eqs. 5-6), and at the same sweeps the
+ * per-particle moments of Sec. V.A: means over molecules of (C_2^i)^2,
+ * (F_s^cm,i)^2 and C_2^i F_s^cm,i and over atoms of (F_s^i)^2.  Synchronises. */
 int mcf_observables(mcf_system* s, mc_obs* out);
+
 
 /* New observable origin (C_2 reference, unwrapped positions).  Asynchronous. */
 int mcf_reset_observables(mcf_system* s);
@@ -477,6 +479,14 @@ typedef struct {
 } mc_dyn;
 
 int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn* out);
+
+/* mc_dynamics for flexible systems (Sec. III.C, Sec. V): the ensemble means,
+ * chi_4 (Eq. 10; the atoms' F_s counts atoms_per_molecule * M particles),
+ * chi_4^self (Eq. 11), rho (Eq. 13) and the 1/e times of n independent runs,
+ * formed from what mcf_observables returns.  MC_EINVAL as mc_dynamics, or
+ * when atoms_per_molecule is not 3 or 4.  Host only. */
+int mcf_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, uint32_t atoms_per_molecule,
+                 mc_dyn* out);
 
 /* ---- batches: many systems in one persistent launch ---------------------- */
 

@@ -19,8 +19,12 @@ HIPCC_FLAGS = [
 ]
 
 
+# roctx ranges of the host API calls (rocprofv3 --marker-trace)
+LINK_FLAGS = ["-lrocprofiler-sdk-roctx"]
+
+
 def build(verbose: bool = False) -> str:
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), *SOURCES, "-o", OUT]
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), *SOURCES, "-o", OUT, *LINK_FLAGS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -13,6 +13,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "engine.h"
 #include "flipmc.h"
 
@@ -58,6 +60,16 @@ size_t device_lds_limit()
 }  // namespace flipmc
 
 namespace {
+
+// A named range on the host timeline of a profiler that records roctx
+// markers (rocprofv3 --marker-trace): one per API call that enqueues work,
+// one per launch of sweeps or events inside it.
+struct TraceRange {
+    explicit TraceRange(const char* what) { roctxRangePushA(what); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 #define HIPCHK(x)                                                                       \
     do {                                                                                \
@@ -410,6 +422,8 @@ void timing_stop(mc_system* s, hipEvent_t a, bool sweep_kernel)
 
 int launch_events_one(mc_system* s, uint32_t flags)
 {
+    TraceRange tr((flags & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) ? "flipmc events: FP64 re-sum"
+                                                                                    : "flipmc events");
     Slot one{};
     one.sys = s->dev;
     one.flags = flags;
@@ -486,6 +500,7 @@ int advance(mc_system* s, uint64_t n)
         const uint64_t chunk = std::min<uint64_t>({n, next_event(s) - s->sweep, kMaxSweepsPerLaunch});
         one.n_sweeps = chunk;
         one.flags = 0;
+        TraceRange tr(s->g.spread ? "flipmc sweeps: multi-workgroup launch" : "flipmc sweeps: one-workgroup launch");
         if (s->g.spread) HIPCHK(hipMemsetAsync(s->host.g_bar, 0, sizeof(uint32_t), s->stream));
         hipEvent_t t0 = timing_start(s);
         if (s->g.spread) {
@@ -761,6 +776,7 @@ int mc_init_system(const mc_params* p, const double* com, const double* quat, co
 
 int mc_sweep(mc_system* s, uint64_t n)
 {
+    TraceRange tr("mc_sweep");
     if (!s) return fail(MC_EINVAL, "null system");
     if (s->batch) return fail(MC_EBUSY, "system is in a batch");
     return advance(s, n);
@@ -768,6 +784,7 @@ int mc_sweep(mc_system* s, uint64_t n)
 
 int mc_energy(mc_system* s, double* e_total, double* e_per_molecule, double* drift)
 {
+    TraceRange tr("mc_energy");
     if (!s) return fail(MC_EINVAL, "null system");
     if (s->batch) return fail(MC_EBUSY, "system is in a batch");
     int rc = launch_events_one(s, kFlagResumReport);
@@ -1013,9 +1030,13 @@ double crossing_time(const uint64_t* t, const double* c, uint32_t n, double leve
 
 }  // namespace
 
-int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn* out)
+namespace {
+
+// mc_dynamics and mcf_dynamics: sites = particles of F_s per molecule (the
+// susceptibility of F_s counts n M of them).
+int dynamics_of(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, uint32_t sites, mc_dyn* out)
 {
-    if (!runs || !out || n_runs == 0 || n_molecules == 0) return fail(MC_EINVAL, "bad arguments");
+    if (!runs || !out || n_runs == 0 || n_molecules == 0 || sites == 0) return fail(MC_EINVAL, "bad arguments");
     std::memset(out, 0, sizeof *out);
     const uint32_t n = runs[0].n_c2;
     if (n > MC_C2_MAX) return fail(MC_EINVAL, "n_c2 above %d", MC_C2_MAX);
@@ -1043,7 +1064,7 @@ int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn*
             cross += o.c2_fs_cm[j];
         }
         double chi[3], self[3];
-        const double npart[3] = {M, 3.0 * M, M};
+        const double npart[3] = {M, (double)sites * M, M};
         for (int a = 0; a < 3; ++a) {
             m[a] /= R;
             chi[a] = npart[a] * (m2[a] / R - m[a] * m[a]);
@@ -1059,6 +1080,20 @@ int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn*
     out->tau_fs = crossing_time(out->t, out->fs, n, e1);
     out->tau_fs_cm = crossing_time(out->t, out->fs_cm, n, e1);
     return MC_OK;
+}
+
+}  // namespace
+
+int mc_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, mc_dyn* out)
+{
+    return dynamics_of(runs, n_runs, n_molecules, 3u, out);
+}
+
+int mcf_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, uint32_t atoms_per_molecule,
+                 mc_dyn* out)
+{
+    if (atoms_per_molecule < 3 || atoms_per_molecule > 4) return fail(MC_EINVAL, "atoms_per_molecule must be 3 or 4");
+    return dynamics_of(runs, n_runs, n_molecules, atoms_per_molecule, out);
 }
 
 // ------------------------------------------------------------------ batches --
@@ -1223,6 +1258,7 @@ int mc_batch_set_workgroups(mc_batch* b, uint32_t max_workgroups)
 
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
 {
+    TraceRange tr("mc_batch_run");
     if (!b) return fail(MC_EINVAL, "null batch");
     const int par = b->parity;
     b->parity ^= 1;

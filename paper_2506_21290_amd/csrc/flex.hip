@@ -79,6 +79,7 @@ struct FxDev {
     uint64_t* c2_sweep;
     double* fs;
     double* fs_cm;
+    double* mom;          // [4][kC2Max] per-particle moments at the C_2 samples
     double* u0;           // [3][M] orientation at the observable origin
     uint8_t* kref;        // [M] atom the orientation follows
     double* r0;           // [3][N] unwrapped atoms at the origin
@@ -823,7 +824,9 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_events(FxDev* __restrict__ Dp
     }
     if ((flags & kFlagGofr) && tid == 0) st->n_gofr += 1;
     if (flags & kFlagC2) {
-        double a2 = 0.0, afs = 0.0, acm = 0.0;
+        // means of C_2^i, F_s^cm,i, F_s^i and of (C_2^i)^2, (F_s^cm,i)^2,
+        // C_2^i F_s^cm,i, (F_s^i)^2 (Sec. V.A)
+        double a2 = 0.0, afs = 0.0, acm = 0.0, a2sq = 0.0, acmsq = 0.0, a2cm = 0.0, afssq = 0.0;
         for (uint32_t m = tid; m < M; m += kFxThreads) {
             double c[3], u[3], nrm = 0.0, dot = 0.0, dc2 = 0.0;
             fx_centre(D, m, c);
@@ -837,8 +840,13 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_events(FxDev* __restrict__ Dp
             }
             nrm = sqrt(nrm);
             for (int d = 0; d < 3; ++d) dot += (u[d] / nrm) * D.u0[d * M + m];
-            a2 += 0.5 * (3.0 * dot * dot - 1.0);
-            acm += fx_sinc(D.fs_q_cm * sqrt(dc2));
+            const double c2i = 0.5 * (3.0 * dot * dot - 1.0);
+            const double fcmi = fx_sinc(D.fs_q_cm * sqrt(dc2));
+            a2 += c2i;
+            acm += fcmi;
+            a2sq += c2i * c2i;
+            acmsq += fcmi * fcmi;
+            a2cm += c2i * fcmi;
         }
         for (uint32_t i = tid; i < N; i += kFxThreads) {
             double d2 = 0.0;
@@ -846,16 +854,26 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_events(FxDev* __restrict__ Dp
                 const double dd = D.pos[d * N + i] + D.L * (double)D.img[d * N + i] - D.r0[d * N + i];
                 d2 += dd * dd;
             }
-            afs += fx_sinc(D.fs_q * sqrt(d2));
+            const double fsi = fx_sinc(D.fs_q * sqrt(d2));
+            afs += fsi;
+            afssq += fsi * fsi;
         }
         const double c2 = block_sum(a2) / (double)M;
         const double fcm = block_sum(acm) / (double)M;
         const double fs = block_sum(afs) / (double)N;
+        const double c2sq = block_sum(a2sq) / (double)M;
+        const double fcmsq = block_sum(acmsq) / (double)M;
+        const double c2fcm = block_sum(a2cm) / (double)M;
+        const double fssq = block_sum(afssq) / (double)N;
         if (tid == 0 && st->n_c2 < kC2Max) {
             const uint32_t j = st->n_c2;
             D.c2[j] = c2;
             D.fs_cm[j] = fcm;
             D.fs[j] = fs;
+            D.mom[j] = c2sq;
+            D.mom[kC2Max + j] = fcmsq;
+            D.mom[2 * kC2Max + j] = c2fcm;
+            D.mom[3 * kC2Max + j] = fssq;
             D.c2_sweep[j] = sweep - st->obs_origin;
             st->n_c2 = j + 1;
         }
@@ -1075,7 +1093,7 @@ namespace {
 size_t fx_al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct FxLayout {
-    size_t dev, stats, pos, type, img, esamp, dsamp, gall, ginter, c2, c2s, fs, fscm, u0, kref, r0, rcm0;
+    size_t dev, stats, pos, type, img, esamp, dsamp, gall, ginter, c2, c2s, fs, fscm, mom, u0, kref, r0, rcm0;
     size_t cstart, clist, cid, ecell, part, total;
 };
 
@@ -1097,6 +1115,7 @@ FxLayout fx_layout(const mcf_params* p, const FxGeom& g)
     l.c2s = o;    o = fx_al(o + kC2Max * sizeof(uint64_t));
     l.fs = o;     o = fx_al(o + kC2Max * sizeof(double));
     l.fscm = o;   o = fx_al(o + kC2Max * sizeof(double));
+    l.mom = o;    o = fx_al(o + 4 * kC2Max * sizeof(double));
     l.u0 = o;     o = fx_al(o + 3 * M * sizeof(double));
     l.kref = o;   o = fx_al(o + M);
     l.r0 = o;     o = fx_al(o + 3 * N * sizeof(double));
@@ -1424,6 +1443,7 @@ int fx_init(mcf_system* s, const mcf_params* p, const FxGeom& g, const FxLayout&
     D.c2_sweep = (uint64_t*)(b + lay.c2s);
     D.fs = (double*)(b + lay.fs);
     D.fs_cm = (double*)(b + lay.fscm);
+    D.mom = (double*)(b + lay.mom);
     D.u0 = (double*)(b + lay.u0);
     D.kref = b + lay.kref;
     D.r0 = (double*)(b + lay.r0);
@@ -1665,6 +1685,11 @@ int mcf_observables(mcf_system* s, mc_obs* o)
     FXCHK(hipMemcpyAsync(o->fs, s->host.fs, sizeof o->fs, hipMemcpyDeviceToHost, s->stream));
     FXCHK(hipMemcpyAsync(o->fs_cm, s->host.fs_cm, sizeof o->fs_cm, hipMemcpyDeviceToHost, s->stream));
     FXCHK(hipMemcpyAsync(o->c2_sweep, s->host.c2_sweep, sizeof o->c2_sweep, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->c2_sq, s->host.mom, sizeof o->c2_sq, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->fs_cm_sq, s->host.mom + kC2Max, sizeof o->fs_cm_sq, hipMemcpyDeviceToHost, s->stream));
+    FXCHK(hipMemcpyAsync(o->c2_fs_cm, s->host.mom + 2 * kC2Max, sizeof o->c2_fs_cm, hipMemcpyDeviceToHost,
+                         s->stream));
+    FXCHK(hipMemcpyAsync(o->fs_sq, s->host.mom + 3 * kC2Max, sizeof o->fs_sq, hipMemcpyDeviceToHost, s->stream));
     FXCHK(hipStreamSynchronize(s->stream));
     // Eq. (3) normalised with N atoms at number density N / L^3
     const double N = (double)s->g.N, rho = N / (s->g.L * s->g.L * s->g.L), fr = (double)o->n_gofr_frames;

@@ -38,7 +38,7 @@ EXPORTED = [
     "mcf_params_default", "mcf_geometry", "mcf_placement", "mcf_required_bytes", "mcf_init_system",
     "mcf_sweep", "mcf_sweep_many",
     "mcf_energy", "mcf_observables", "mcf_reset_observables", "mcf_get_state", "mcf_set_state",
-    "mcf_decision_log", "mcf_destroy", "mcf_init_system_noalloc",
+    "mcf_decision_log", "mcf_destroy", "mcf_init_system_noalloc", "mcf_dynamics",
 ]
 MC_TRIANGLE, MC_SQUARE, MC_TETRAHEDRON = 0, 1, 2
 SITES = {MC_TRIANGLE: 3, MC_SQUARE: 4, MC_TETRAHEDRON: 4}
@@ -220,6 +220,7 @@ def lib():
         L.mc_batch_destroy.argtypes = [vp]
         L.mc_batch_destroy.restype = None
         L.mc_dynamics.argtypes = [C.POINTER(mc_obs), C.c_size_t, C.c_uint32, C.POINTER(mc_dyn)]
+        L.mcf_dynamics.argtypes = [C.POINTER(mc_obs), C.c_size_t, C.c_uint32, C.c_uint32, C.POINTER(mc_dyn)]
         fp = C.POINTER(mcf_params)
         L.mcf_params_default.argtypes = [fp, C.c_uint32]
         L.mcf_params_default.restype = None
@@ -318,12 +319,17 @@ def mc_required_bytes(p: mc_params) -> int:
     return n.value
 
 
-def mc_dynamics(runs, n_molecules) -> dict:
+def mc_dynamics(runs, n_molecules, atoms_per_molecule=None) -> dict:
     """Ensemble means, chi_4 (Eq. 10), chi_4^self (Eq. 11), rho (Eq. 13) and
-    the 1/e relaxation times of independent runs (mc_obs structures)."""
+    the 1/e relaxation times of independent runs (mc_obs structures) of rigid
+    molecules (mc_dynamics), or of flexible ones with atoms_per_molecule
+    given (mcf_dynamics)."""
     arr = (mc_obs * len(runs))(*runs)
     d = mc_dyn()
-    _check(lib().mc_dynamics(arr, len(runs), int(n_molecules), C.byref(d)))
+    if atoms_per_molecule is None:
+        _check(lib().mc_dynamics(arr, len(runs), int(n_molecules), C.byref(d)))
+    else:
+        _check(lib().mcf_dynamics(arr, len(runs), int(n_molecules), int(atoms_per_molecule), C.byref(d)))
     n = d.n_times
     out = {"t": np.array(d.t[:n], dtype=np.uint64), "n_runs": d.n_runs}
     for k in ("c2", "fs", "fs_cm", "chi4_c2", "chi4_fs", "chi4_fs_cm", "chi4s_c2", "chi4s_fs",
@@ -675,6 +681,8 @@ class FlexSystem:
             "c2_sweep": np.array(o.c2_sweep[: o.n_c2], dtype=np.uint64),
             "c2": np.array(o.c2[: o.n_c2]), "fs": np.array(o.fs[: o.n_c2]),
             "fs_cm": np.array(o.fs_cm[: o.n_c2]),
+            "c2_sq": np.array(o.c2_sq[: o.n_c2]), "fs_cm_sq": np.array(o.fs_cm_sq[: o.n_c2]),
+            "c2_fs_cm": np.array(o.c2_fs_cm[: o.n_c2]), "fs_sq": np.array(o.fs_sq[: o.n_c2]),
         }
 
     def reset_observables(self):

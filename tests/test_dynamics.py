@@ -123,3 +123,21 @@ def test_mc_dynamics_rejects_runs_sampled_at_other_times():
     with pytest.raises(flipmc.McError) as e:
         flipmc.mc_dynamics([a, b], 10)
     assert e.value.code == flipmc.MC_EINVAL
+
+
+def test_mcf_dynamics_counts_the_atoms_of_each_body():
+    # flexible bodies: chi_4 of F_s counts atoms_per_molecule * M particles;
+    # everything else is mc_dynamics' definition (one population per run)
+    t = [1, 2, 5]
+    vals = [0.2, 0.5, 0.9, 0.4]
+    M = 10
+    var = np.var(vals)
+    for n in (3, 4):
+        obs = [_obs(np.full((3, M), v), np.full((3, M), v), np.full((3, n * M), v), t) for v in vals]
+        d = flipmc.mc_dynamics(obs, M, atoms_per_molecule=n)
+        assert np.allclose(d["chi4_fs"], n * M * var, rtol=1e-12)
+        assert np.allclose(d["chi4_c2"], M * var, rtol=1e-12)
+        assert np.allclose(d["chi4s_fs"], var, rtol=1e-12)
+    with pytest.raises(flipmc.McError) as e:
+        flipmc.mc_dynamics(obs, M, atoms_per_molecule=5)
+    assert e.value.code == flipmc.MC_EINVAL

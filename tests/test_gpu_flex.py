@@ -160,7 +160,7 @@ def test_observables_match_the_oracle():
     ci = np.zeros(nb, dtype=np.uint64)
     u0, kref = o.orientation_ref()
     a0, c0 = o.unwrapped()
-    want = {}
+    want, terms = {}, {}
     for t in range(1, n + 1):
         o.sweep_checkerboard(1)
         if t % 5 == 0:
@@ -169,6 +169,11 @@ def test_observables_match_the_oracle():
             a, c = o.unwrapped()
             want[t] = (float(np.mean(o.c2_terms(u0, kref))),
                        rig.fs_isotropic(a - a0, p.fs_q), rig.fs_isotropic(c - c0, p.fs_q_cm))
+            # per-particle contributions (Sec. V.A): sin(q d)/(q d) of each
+            # atom and centre, C_2 of each molecule
+            fs_i = np.sinc(p.fs_q * np.linalg.norm(a - a0, axis=1) / np.pi)
+            fcm_i = np.sinc(p.fs_q_cm * np.linalg.norm(c - c0, axis=1) / np.pi)
+            terms[t] = (o.c2_terms(u0, kref), fcm_i, fs_i)
     assert obs["n_gofr_frames"] == 4
     assert np.abs(obs["gofr_all"].astype(np.int64) - ca.astype(np.int64)).sum() <= 4
     assert np.abs(obs["gofr_inter"].astype(np.int64) - ci.astype(np.int64)).sum() <= 4
@@ -177,6 +182,11 @@ def test_observables_match_the_oracle():
         assert obs["c2"][j] == pytest.approx(want[t][0], abs=1e-12)
         assert obs["fs"][j] == pytest.approx(want[t][1], abs=1e-12)
         assert obs["fs_cm"][j] == pytest.approx(want[t][2], abs=1e-12)
+        c2_i, fcm_i, fs_i = terms[t]
+        assert obs["c2_sq"][j] == pytest.approx(np.mean(c2_i ** 2), abs=1e-12)
+        assert obs["fs_cm_sq"][j] == pytest.approx(np.mean(fcm_i ** 2), abs=1e-12)
+        assert obs["c2_fs_cm"][j] == pytest.approx(np.mean(c2_i * fcm_i), abs=1e-12)
+        assert obs["fs_sq"][j] == pytest.approx(np.mean(fs_i ** 2), abs=1e-12)
     g_norm = rig.gofr_normalise(obs["gofr_all"], 4, 3 * M, o.box, p.gofr_dr)
     np.testing.assert_allclose(obs["gofr_norm_all"], g_norm, rtol=1e-12)
 

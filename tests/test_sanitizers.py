@@ -63,7 +63,7 @@ def test_c_abi_host_code_passes_under_asan_and_ubsan(tmp_path):
     host_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                 "-Xarch_host", "-fno-omit-frame-pointer", "-shared-libsan"]
     cmd = ["hipcc", *flags, "-O1", "-g", *host_san, "-I" + os.path.join(ROOT, "include"), *libbuild.SOURCES,
-           "-o", out]
+           "-o", out, *libbuild.LINK_FLAGS]
     res = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
     assert res.returncode == 0, res.stderr[-4000:]
     child = ("import sys; sys.path.insert(0, %r)\n"
