@@ -727,9 +727,9 @@ def main():
     ap.add_argument("--flex-replicas", type=int, default=256,
                     help="flex: replicas of the 1000 flexible triangles advanced together (0: none)")
     ap.add_argument("--tau-sweeps", type=int, default=50000)
-    ap.add_argument("--flex-tau-temperature", type=float, default=1.5)
+    ap.add_argument("--flex-tau-temperature", type=float, default=2.0)
     ap.add_argument("--flex-tau-replicas", type=int, default=16)
-    ap.add_argument("--flex-tau-equilibration", type=int, default=10000)
+    ap.add_argument("--flex-tau-equilibration", type=int, default=20000)
     ap.add_argument("--flex-tau-sweeps", type=int, default=20000)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--serving-jobs", type=int, default=200,

@@ -145,12 +145,17 @@ __device__ __forceinline__ uint32_t fx_cell(double x, double y, double z, const 
            nc * ((uint32_t)fx_axis(y, h[1], D) + nc * (uint32_t)fx_axis(z, h[2], D));
 }
 
-// Eq. (1) as (2 (s/r)^6 - 1)^2 below the cut-off, FP64 with a true division.
+// Eq. (1) as (2 (s/r)^6 - 1)^2 below the cut-off, FP64.  1 / r^2 is the
+// hardware estimate refined by two Newton steps (within an ulp or two of the
+// quotient; r^2 is a normal number for every pair inside the cut-off).
 __device__ __forceinline__ double fx_wca(double s2, double r2, double rc2f)
 {
     if (!(r2 < rc2f * s2)) return 0.0;
-    const double x = s2 / r2;
-    const double t = 2.0 * x * x * x - 1.0;
+    double y = __builtin_amdgcn_rcp(r2);
+    y = fma(fma(-r2, y, 1.0), y, y);
+    y = fma(fma(-r2, y, 1.0), y, y);
+    const double x = s2 * y;
+    const double t = fma(2.0, x * x * x, -1.0);
     return t * t;
 }
 
