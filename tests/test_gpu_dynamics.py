@@ -62,3 +62,56 @@ def test_dynamics_of_independent_runs_match_the_oracle():
             assert got == pytest.approx(ref, rel=1e-12)
     # at T = 3 the sites' F_s(7.4, t) decays below 1/e within the run
     assert d["tau_fs"] is not None
+
+
+def test_flexible_dynamics_of_independent_runs_match_the_oracle():
+    # the paper's flexible triangles: 3 runs of 125 molecules at T = 2 from
+    # the oracle's lattice starts; mcf_dynamics on the device's samples
+    # against the oracle's per-particle terms at the same sweeps
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import flex
+
+    Mf, Tf, sweeps, seeds = 125, 2.0, 200, [1, 2, 3]
+    print("flexible dynamics", flush=True)
+    obs, terms = [], {}
+    for seed in seeds:
+        kw = dict(n_molecules=Mf, temperature=Tf, colours_per_axis=3, cells_per_side=3, density=1.2, seed=seed)
+        o = flex.System(flex.Params(geometry=flipmc.MC_TRIANGLE, **kw))
+        so = o.get_state()
+        s = flipmc.FlexSystem(flipmc.mcf_params_default(flipmc.MC_TRIANGLE, **kw), pos=so["pos"],
+                              types=so["types"])
+        s.reset_observables()
+        s.sweep(sweeps)
+        obs.append(s.obs_struct())
+        s.close()
+        u0, kref = o.orientation_ref()
+        a0, c0 = o.unwrapped()
+        for step in range(1, sweeps + 1):
+            o.sweep_checkerboard(1)
+            if step in (1, 2, 5, 10, 20, 50, 100, 200):
+                a, c = o.unwrapped()
+                fs_i = np.sinc(7.4 * np.linalg.norm(a - a0, axis=1) / np.pi)
+                fcm_i = np.sinc(5.1 * np.linalg.norm(c - c0, axis=1) / np.pi)
+                terms.setdefault(step, []).append((o.c2_terms(u0, kref), fcm_i, fs_i))
+    d = flipmc.mc_dynamics(obs, Mf, atoms_per_molecule=3)
+    t = [int(x) for x in d["t"]]
+    assert t == [1, 2, 5, 10, 20, 50, 100, 200]
+    tol = dict(rel=1e-9, abs=1e-12)
+    for j, tt in enumerate(t):
+        c2_r = [x[0] for x in terms[tt]]
+        fcm_r = [x[1] for x in terms[tt]]
+        fs_r = [x[2] for x in terms[tt]]
+        assert d["c2"][j] == pytest.approx(np.mean([x.mean() for x in c2_r]), **tol)
+        assert d["fs"][j] == pytest.approx(np.mean([x.mean() for x in fs_r]), **tol)
+        assert d["chi4_fs"][j] == pytest.approx(oracle.chi4([x.mean() for x in fs_r], 3 * Mf), **tol)
+        assert d["chi4_c2"][j] == pytest.approx(oracle.chi4([x.mean() for x in c2_r], Mf), **tol)
+        assert d["chi4s_fs"][j] == pytest.approx(oracle.chi4_self(np.concatenate(fs_r)), **tol)
+        assert d["rho"][j] == pytest.approx(oracle.pearson(np.concatenate(c2_r), np.concatenate(fcm_r)),
+                                            rel=1e-8, abs=1e-10)
+    for key in ("c2", "fs", "fs_cm"):
+        ref = oracle.relaxation_time(t, d[key])
+        got = d["tau_" + key]
+        assert (got is None) == (ref is None)
+        if ref is not None:
+            assert got == pytest.approx(ref, rel=1e-12)
