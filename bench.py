@@ -47,7 +47,7 @@ def progress(msg):
 
 
 RIGID_SOURCES = ("kernels.hip", "engine.h", "wave.h")
-FLEX_SOURCES = ("flex.hip", "engine.h", "wave.h")
+FLEX_SOURCES = ("flex_sweep.h", "engine.h", "wave.h")
 
 
 def kernel_source_hash(files=RIGID_SOURCES):
