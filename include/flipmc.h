@@ -60,6 +60,11 @@ enum { MC_TRANSLATE = 0, MC_ROTATE = 1, MC_FLIP = 2 };
  * multi-workgroup engine. */
 enum { MC_FLAG_HBM_STATE = 1, MC_FLAG_SINGLE_WORKGROUP = 2 };
 
+/* mcf_params.flags only: MC_FLAG_SERIAL_CELLS attempts the cells of a colour
+ * one at a time even when they cannot interact (the same chain, slower; for
+ * checking the side-by-side execution). */
+enum { MC_FLAG_SERIAL_CELLS = 4 };
+
 /* Engines (mc_engine): one workgroup with the state in LDS, one workgroup
  * with the state in HBM, many workgroups in one cooperative launch with the
  * state in HBM and each cell's neighbourhood staged in LDS. */

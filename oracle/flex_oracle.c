@@ -23,9 +23,13 @@
  *     a permutation of the types at fixed positions; the rotation is uniform
  *     over the body's list;
  *   - the attempt order: the checkerboard over atoms (a random shift of a
- *     cubic cell grid per sweep, colours in order, every atom attempted once
- *     in ascending index inside its cell, translations confined to the
- *     cell), or N attempts on uniformly drawn atoms (random sequential);
+ *     cubic cell grid per sweep, colours in order, the cells of a colour in
+ *     ascending index, every atom attempted once in ascending index inside
+ *     its cell, translations confined to the cell), or N attempts on
+ *     uniformly drawn atoms (random sequential).  When same-colour cells are
+ *     at least the reach 2 D + r_c apart the order of the cells of a colour
+ *     does not matter (cell_order_seed shuffles it to show that); closer,
+ *     the ascending order defines the chain;
  *   - the start: a simple-cubic lattice of ideal bodies of side b* with
  *     uniformly random orientations, types 0, 1, ... on atoms 0, 1, ...;
  *   - random numbers: Philox4x32-10 on (slot, sweep low, sweep high, tag) as in
@@ -207,8 +211,9 @@ fx_system* fx_create(const fx_params* p, char* err)
         free(s); return NULL;
     }
     s->w = s->L / (double)nc;
-    if ((double)(k - 1) * s->w < s->reach) {
-        snprintf(err, 256, "(k-1) w = %.6f is below the reach %.6f", (double)(k - 1) * s->w, s->reach);
+    if (s->w < s->rc_max + 2.0 * sqrt(3.0) * p->max_displacement) {
+        snprintf(err, 256, "cell side %.6f is below r_c + 2 sqrt(3) d = %.6f", s->w,
+                 s->rc_max + 2.0 * sqrt(3.0) * p->max_displacement);
         free(s); return NULL;
     }
     double D = kGraphDiameter[p->geometry] * s->bond_max;

@@ -373,17 +373,20 @@ double fx_bond_star()
 struct FxGeom {
     uint32_t n, N, k, nc, ncell;
     double L, w, D, rc, reach;
+    double D_est;  // the ideal body's largest atom distance, 15 % stretched
 };
 
-// Is (k, nc) a valid decomposition?  Same-colour cells must be 2 D + r_c
-// apart, and a cell must be r_c + 2 sqrt(3) d wide so that the 27 cells
-// around an atom's cell hold its partners however the two have moved since
-// the sort at the start of the sweep.
+// Is (k, nc) a valid decomposition?  A cell must be r_c + 2 sqrt(3) d wide so
+// that the 27 cells around an atom's cell hold its partners however the two
+// have moved since the sort at the start of the sweep.  The cells of a colour
+// are attempted in ascending index (that order defines the chain); when they
+// are at least the reach 2 D + r_c apart they cannot interact and run side by
+// side, and when (k - 1) w is below the worst-case reach the sweep kernel
+// decides so per sweep from the largest intramolecular distance it finds.
 bool fx_valid(const FxGeom& g0, double dmax, uint32_t k, uint32_t nc, FxGeom* out)
 {
     if (k < 2 || nc < 2 || nc % k != 0) return false;
     const double w = g0.L / (double)nc;
-    if ((double)(k - 1) * w < g0.reach) return false;
     if (w < g0.rc + 2.0 * std::sqrt(3.0) * dmax) return false;
     if ((double)nc * nc * nc > 16777216.0) return false;
     if (out) {
@@ -422,17 +425,22 @@ int fx_geometry(const mcf_params* p, FxGeom* gout)
     g.rc = std::pow(2.0, 1.0 / 6.0) * smax;
     g.D = kGraphDiam[p->geometry] * bmax;
     g.reach = (2.0 * g.D + g.rc) * (1.0 + 1e-12);
+    const double side = p->bond_length > 0 ? p->bond_length : fx_bond_star();
+    g.D_est = 1.15 * side * (p->geometry == MC_SQUARE ? std::sqrt(2.0) : 1.0);
     const double need = 2.0 * (std::max(g.D, g.rc) + 2.0 * p->max_displacement);
     if (g.L < need)
         return fx_fail(MC_EGEOM, "box side %.4f below %.4f (minimum image)", g.L, need);
     uint32_t k = p->colours_per_axis, nc = p->cells_per_side;
     if (k == 0 && nc == 0) {
-        // most cells per colour, then the smallest cells (the fewest
-        // candidates per attempt)
+        // most cells per colour that can run side by side when the bodies
+        // stay within 15 % of their ideal size, then the smallest cells (the
+        // fewest candidates per attempt)
+        const double reach_est = 2.0 * (g.D_est + 2.0 * std::sqrt(3.0) * p->max_displacement) + g.rc;
         double best = -1.0;
         for (uint32_t kk = 2; kk <= 8; ++kk)
             for (uint32_t cc = kk; cc <= 256; cc += kk) {
                 if (!fx_valid(g, p->max_displacement, kk, cc, nullptr)) continue;
+                if ((double)(kk - 1) * g.L / (double)cc < std::min(reach_est, g.reach)) continue;
                 const double act = std::pow((double)(cc / kk), 3.0);
                 if (act > best || (act == best && cc > nc)) {
                     best = act;
@@ -445,8 +453,8 @@ int fx_geometry(const mcf_params* p, FxGeom* gout)
         return fx_fail(MC_EINVAL, "give both colours_per_axis and cells_per_side, or neither");
     }
     if (!fx_valid(g, p->max_displacement, k, nc, gout))
-        return fx_fail(MC_EGEOM, "k = %u, n_c = %u: cells of %.4f need (k-1) w >= %.4f and w >= %.4f", k, nc,
-                       g.L / nc, g.reach, g.rc + 2.0 * std::sqrt(3.0) * p->max_displacement);
+        return fx_fail(MC_EGEOM, "k = %u, n_c = %u: cells of %.4f need w >= %.4f (and n_c a multiple of k >= 2)", k,
+                       nc, g.L / nc, g.rc + 2.0 * std::sqrt(3.0) * p->max_displacement);
     return MC_OK;
 }
 
@@ -796,6 +804,9 @@ int fx_init(mcf_system* s, const mcf_params* p, const FxGeom& g, const FxLayout&
     D.p_flip = p->p_flip;
     D.dmax = p->max_displacement;
     D.rc2f = std::cbrt(2.0);
+    D.sep = (double)(g.k - 1) * g.w;
+    D.dyn_base = g.rc + 4.0 * std::sqrt(3.0) * p->max_displacement + 1e-9;
+    D.together = (p->flags & MC_FLAG_SERIAL_CELLS) ? 2u : (D.sep >= g.reach ? 1u : 0u);
     for (int t = 0; t < 4; ++t) D.sigma[t] = t < (int)g.n ? p->sigma[t] : 1.0;
     const double rmax = std::min(0.5 * g.L, 5.0);
     D.gofr_nbins = std::min((uint32_t)kGofrBins, (uint32_t)std::floor(rmax / p->gofr_dr + 1e-6));

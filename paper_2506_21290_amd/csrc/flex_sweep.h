@@ -59,6 +59,12 @@ struct FxDev {
     double L, invL, w, T, p_flip, dmax, rc2f;
     double sigma[4];
     double gofr_dr, gofr_rmax, fs_q, fs_q_cm;
+    // same-colour cells run side by side when sep >= 2 D_sweep + dyn_base,
+    // D_sweep the largest atom distance inside a molecule at the sweep's
+    // start plus 2 sqrt(3) d; always when `together` is 1 ((k - 1) w covers
+    // the worst case), never when it is 2 (forced one cell at a time)
+    double sep, dyn_base;
+    uint32_t together, pad4;
     uint8_t flips[4][4];  // new type of atom s = old type of atom flips[q][s]
     double* pos;          // SoA [3][N], wrapped into [0, L)
     uint8_t* type;        // [N]
@@ -96,9 +102,9 @@ struct FxList {
 // registers at the start of a launch (read through the descriptor, every
 // store to LDS or memory could alias them and force a reload).
 struct FxK {
-    uint32_t n, N, nc, nflip, bonded, seed_lo, seed_hi;
+    uint32_t n, N, nc, nflip, bonded, seed_lo, seed_hi, together;
     uint32_t flipw[4];  // byte s of word q: flips[q][s]
-    double L, invL, w, T, p_flip, dmax, rc2f;
+    double L, invL, w, T, p_flip, dmax, rc2f, sep, dyn_base;
     double sigma[4];
     int32_t* img;
     MoveRecord* log;
@@ -114,6 +120,7 @@ __device__ __forceinline__ FxK fx_const(const FxDev& D)
         K.flipw[q] = (uint32_t)D.flips[q][0] | ((uint32_t)D.flips[q][1] << 8) | ((uint32_t)D.flips[q][2] << 16) |
                      ((uint32_t)D.flips[q][3] << 24);
     K.L = D.L; K.invL = D.invL; K.w = D.w; K.T = D.T; K.p_flip = D.p_flip; K.dmax = D.dmax; K.rc2f = D.rc2f;
+    K.sep = D.sep; K.dyn_base = D.dyn_base; K.together = D.together;
     for (int t = 0; t < 4; ++t) K.sigma[t] = D.sigma[t];
     K.img = D.img;
     K.log = D.log;
@@ -564,6 +571,7 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxList list, uint64_t 
     __shared__ uint32_t cand[kFxWaves][kFxCand];
     __shared__ uint32_t scratch[kFxWaves];
     __shared__ double misc[2];
+    __shared__ double dmax2[kFxWaves];
     extern __shared__ __align__(16) unsigned char fx_smem[];
     const FxDev& D = *Dp;
     const FxK K = fx_const(D);
@@ -604,31 +612,69 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxList list, uint64_t 
         fx_sort_cells(V.cell_list, V.cell_start, (uint32_t)wave, kFxWaves, ncell);
         __syncthreads();
         const bool logging = D.log != nullptr && sweep - D.log_sweep0 < D.log_sweeps;
+        // The cells of a colour are attempted in ascending index; they run
+        // side by side when no attempt in one can reach an atom another
+        // reads or writes: their gap (k - 1) w is at least 2 D_sweep + r_c,
+        // D_sweep = the largest atom distance inside a molecule now plus
+        // 2 sqrt(3) d (each atom moves at most once per sweep).  Otherwise
+        // one cell at a time, in that order (the same chain either way).
+        bool together = K.together == 1u;
+        if (K.together == 0u) {
+            double d2 = 0.0;
+            const uint32_t n = K.n;
+            for (uint32_t m = tid; m < D.M; m += kFxThreads) {
+                const uint32_t base = n * m;
+                for (uint32_t i = 0; i + 1 < n; ++i)
+                    for (uint32_t j = i + 1; j < n; ++j) {
+                        const double dx = fx_mi(V.pos[base + i] - V.pos[base + j], K.L, K.invL);
+                        const double dy = fx_mi(V.pos[N + base + i] - V.pos[N + base + j], K.L, K.invL);
+                        const double dz = fx_mi(V.pos[2 * N + base + i] - V.pos[2 * N + base + j], K.L, K.invL);
+                        d2 = fmax(d2, dx * dx + dy * dy + dz * dz);
+                    }
+            }
+#pragma unroll
+            for (int o = 32; o; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o));
+            if (lane == 0) dmax2[wave] = d2;
+            __syncthreads();
+            double dm = 0.0;
+            for (int w2 = 0; w2 < kFxWaves; ++w2) dm = fmax(dm, dmax2[w2]);
+            together = K.sep >= 2.0 * sqrt(dm) + K.dyn_base;
+            __syncthreads();
+        }
+        // the attempts of cell `ci` of a colour by this wave
+        auto run_cell = [&](uint32_t kx, uint32_t ky, uint32_t kz, uint32_t ci) __attribute__((always_inline)) {
+            const uint32_t cell = (kx + k * (ci % na)) + nc * ((ky + k * ((ci / na) % na)) +
+                                                              nc * (kz + k * (ci / (na * na))));
+            wc.e = 0.0;
+            const uint32_t b = V.cell_start[cell], e = V.cell_start[cell + 1];
+            if (b < e) {
+                const uint32_t ncand = fx_gather_candidates(K, V, cell, W);
+                for (uint32_t q0 = b; q0 < e; q0 += 64u) {
+                    const uint32_t cnt = min(64u, e - q0);
+                    uint32_t at = 0;
+                    FxProp pr{};
+                    if ((uint32_t)lane < cnt) {
+                        at = V.cell_list[q0 + lane];
+                        pr = fx_propose(K, V, at, sweep, h, cell);
+                    }
+                    for (uint32_t q = 0; q < cnt; ++q)
+                        fx_attempt(K, V, (uint32_t)__builtin_amdgcn_readlane((int)at, (int)q),
+                                   fx_prop_of_lane(pr, (int)q), sweep, cell, ncand, logging, W, wc);
+                }
+            }
+            if (lane == 0) V.ecell[cell] = wc.e;
+        };
         for (uint32_t col = 0; col < k * k * k; ++col) {
             const uint32_t kx = col % k, ky = (col / k) % k, kz = col / (k * k);
-            for (uint32_t ci = (uint32_t)wave; ci < nact; ci += kFxWaves) {
-                const uint32_t cell = (kx + k * (ci % na)) + nc * ((ky + k * ((ci / na) % na)) +
-                                                                  nc * (kz + k * (ci / (na * na))));
-                wc.e = 0.0;
-                const uint32_t b = V.cell_start[cell], e = V.cell_start[cell + 1];
-                if (b < e) {
-                    const uint32_t ncand = fx_gather_candidates(K, V, cell, W);
-                    for (uint32_t q0 = b; q0 < e; q0 += 64u) {
-                        const uint32_t cnt = min(64u, e - q0);
-                        uint32_t at = 0;
-                        FxProp pr{};
-                        if ((uint32_t)lane < cnt) {
-                            at = V.cell_list[q0 + lane];
-                            pr = fx_propose(K, V, at, sweep, h, cell);
-                        }
-                        for (uint32_t q = 0; q < cnt; ++q)
-                            fx_attempt(K, V, (uint32_t)__builtin_amdgcn_readlane((int)at, (int)q),
-                                       fx_prop_of_lane(pr, (int)q), sweep, cell, ncand, logging, W, wc);
-                    }
+            if (together) {
+                for (uint32_t ci = (uint32_t)wave; ci < nact; ci += kFxWaves) run_cell(kx, ky, kz, ci);
+                __syncthreads();
+            } else {
+                for (uint32_t ci = 0; ci < nact; ++ci) {
+                    if (ci % kFxWaves == (uint32_t)wave) run_cell(kx, ky, kz, ci);
+                    __syncthreads();
                 }
-                if (lane == 0) V.ecell[cell] = wc.e;
             }
-            __syncthreads();
         }
         ++sweep;
         // E_acc += the sweep's dE, the cells in a fixed order; E/M samples

@@ -22,7 +22,7 @@ MC_OK, MC_EINVAL, MC_ENOMEM, MC_EDEVICE, MC_EGEOM, MC_ENONFINITE, MC_EBUSY, MC_E
     0, -1, -2, -3, -4, -5, -6, -7)
 MC_FP64, MC_FP32_DE = 0, 1
 MC_TRANSLATE, MC_ROTATE, MC_FLIP = 0, 1, 2
-MC_FLAG_HBM_STATE, MC_FLAG_SINGLE_WORKGROUP = 1, 2
+MC_FLAG_HBM_STATE, MC_FLAG_SINGLE_WORKGROUP, MC_FLAG_SERIAL_CELLS = 1, 2, 4
 MC_ENGINE_LDS, MC_ENGINE_HBM, MC_ENGINE_SPREAD = 0, 1, 2
 MC_GOFR_MAX_BINS = 256
 MC_C2_MAX = 32

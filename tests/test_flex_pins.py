@@ -237,10 +237,40 @@ def test_flip_chain_samples_boltzmann_exactly(g):
 
 
 def test_invalid_parameters_are_rejected():
+    # cells narrower than r_c + 2 sqrt(3) d = 1.58 (125 triangles: L = 6.79,
+    # n_c = 6 gives 1.13): the 27 cells around an atom would miss partners
     with pytest.raises(ValueError):
         flex.System(flex.Params(n_molecules=125, temperature=1.0, colours_per_axis=3, cells_per_side=6))
-    with pytest.raises(ValueError):  # squares need (k - 1) w >= 2 * 2 * 1.6 + 1.23
-        flex.System(flex.Params(n_molecules=125, temperature=1.0, geometry=flex.SQUARE,
-                                colours_per_axis=3, cells_per_side=3))
     with pytest.raises(ValueError):
         flex.System(flex.Params(n_molecules=125, temperature=1.0, geometry=7))
+    # same-colour cells closer than the worst-case reach 2 D + r_c are allowed:
+    # the cells of a colour are then attempted in ascending index, and that
+    # order defines the chain (125 squares at density 1.2: (k - 1) w = 4.98
+    # below 2 * 3.2 + 1.23)
+    p = flex.Params(n_molecules=125, temperature=1.0, geometry=flex.SQUARE, colours_per_axis=3, cells_per_side=3)
+    s = flex.System(p)
+    assert (3 - 1) * s.box / 3 < flex.reach(p)
+
+
+def test_checkerboard_order_is_colour_cell_atom_ascending():
+    # the attempt order that defines the chain when same-colour cells can
+    # interact (125 squares at density 1.2, k = 3, n_c = 3: (k - 1) w below the
+    # reach): colours in order, the cells of a colour in ascending index, the
+    # atoms of a cell in ascending index, cells from the positions at the
+    # sweep's start and the sweep's shift
+    p = flex.Params(n_molecules=125, temperature=1.0, geometry=flex.SQUARE, colours_per_axis=3,
+                    cells_per_side=3, density=1.2, seed=11)
+    s = flex.System(p)
+    rp = bf.Replayer(p, s.box)
+    k = p.colours_per_axis
+    nc = p.cells_per_side
+    for sw in range(2):
+        pos = s.get_state()["pos"].copy()
+        h = rp.shift(sw)
+        cells = np.array([rp.cell(pos[i], h) for i in range(s.N)])
+        cx, cy, cz = cells % nc, (cells // nc) % nc, cells // (nc * nc)
+        colour = (cx % k) + k * (cy % k) + k * k * (cz % k)
+        want = np.lexsort((np.arange(s.N), cells, colour))
+        log = s.sweep_checkerboard(1, log=True)
+        got = log["atom"][np.argsort(log["seq"], kind="stable")]
+        assert np.array_equal(got, want)

@@ -23,6 +23,12 @@ CASES = {
     "square": (flipmc.MC_SQUARE, 125, 2.0, 3, 3, 0.3),
     "tetrahedron": (flipmc.MC_TETRAHEDRON, 125, 2.0, 3, 3, 1.2),
     "triangle_1000": (flipmc.MC_TRIANGLE, 1000, 0.75, 3, 6, 1.2),
+    # same-colour cells closer than the worst-case reach 2 D + r_c: one cell
+    # at a time (the gap is below the reach of any square) ...
+    "square_serial": (flipmc.MC_SQUARE, 125, 1.0, 2, 4, 0.3),
+    # ... and side by side while the squares stay small enough (the bench's
+    # 1000 squares, 8 cells per colour instead of 1)
+    "square_1000": (flipmc.MC_SQUARE, 1000, 1.0, 4, 8, 1.2),
 }
 
 
@@ -112,6 +118,28 @@ def test_every_attempt_matches_the_oracle(case):
     oc = o.counters()
     assert list(c["attempts"]) == list(oc["attempts"]) and list(c["accepts"]) == list(oc["accepts"])
     assert c["exits"] == oc["exits"]
+
+
+@pytest.mark.parametrize("case", ["square_serial", "square_1000"])
+def test_cells_closer_than_the_reach_match_the_oracle(case):
+    # the oracle attempts the cells of a colour in ascending index; the engine
+    # runs them one at a time or, when this sweep's bodies cannot reach across
+    # the gap, side by side: every attempt identical either way
+    s, o, resyncs = run(case, 4 if case == "square_serial" else 2)
+    assert resyncs == 0
+
+
+def test_side_by_side_cells_equal_one_at_a_time():
+    # MC_FLAG_SERIAL_CELLS forces one cell at a time: bitwise the same chain
+    g, M, T, k, nc, rho = CASES["square_1000"]
+    print("flex serial vs side by side", flush=True)
+    a = flipmc.FlexSystem(gp(g, M, T, k, nc, rho, seed=5))
+    b = flipmc.FlexSystem(gp(g, M, T, k, nc, rho, seed=5, flags=flipmc.MC_FLAG_SERIAL_CELLS))
+    a.sweep(10)
+    b.sweep(10)
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa["pos"], sb["pos"]) and np.array_equal(sa["types"], sb["types"])
+    assert sa["e_acc"] == sb["e_acc"]
 
 
 def test_full_size_1000_triangles():
