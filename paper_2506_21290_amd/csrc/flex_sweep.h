@@ -59,10 +59,11 @@ struct FxDev {
     double L, invL, w, T, p_flip, dmax, rc2f;
     double sigma[4];
     double gofr_dr, gofr_rmax, fs_q, fs_q_cm;
-    // same-colour cells run side by side when sep >= 2 D_sweep + dyn_base,
-    // D_sweep the largest atom distance inside a molecule at the sweep's
-    // start plus 2 sqrt(3) d; always when `together` is 1 ((k - 1) w covers
-    // the worst case), never when it is 2 (forced one cell at a time)
+    // a colour's cells run side by side when sep = (k - 1) w >= 2 D + dyn_base
+    // (dyn_base = r_c + 4 sqrt(3) d), D the largest atom distance inside a
+    // molecule with an atom in those cells at the colour's start; always
+    // when `together` is 1 (the gap covers the worst case), never when it is
+    // 2 (forced one cell at a time)
     double sep, dyn_base;
     uint32_t together, pad4;
     uint8_t flips[4][4];  // new type of atom s = old type of atom flips[q][s]
@@ -614,23 +615,33 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxList list, uint64_t 
         const bool logging = D.log != nullptr && sweep - D.log_sweep0 < D.log_sweeps;
         // The cells of a colour are attempted in ascending index; they run
         // side by side when no attempt in one can reach an atom another
-        // reads or writes: their gap (k - 1) w is at least 2 D_sweep + r_c,
-        // D_sweep = the largest atom distance inside a molecule now plus
-        // 2 sqrt(3) d (each atom moves at most once per sweep).  Otherwise
-        // one cell at a time, in that order (the same chain either way).
-        bool together = K.together == 1u;
-        if (K.together == 0u) {
+        // reads or writes.  Two attempted atoms of different cells are at
+        // least the gap (k - 1) w apart, and their attempts can meet only
+        // through pairs within r_c of their molecules' atoms: so the cells
+        // cannot interact when the gap is at least 2 D_c + r_c, D_c the
+        // largest atom distance inside a molecule with an atom in the
+        // colour's cells at the colour's start plus 2 sqrt(3) d (each atom
+        // moves at most once per sweep).  Otherwise one cell at a time, in
+        // that order: the same chain either way.
+        auto colour_together = [&](uint32_t kx, uint32_t ky, uint32_t kz) __attribute__((always_inline)) {
+            if (K.together != 0u) return K.together == 1u;
             double d2 = 0.0;
             const uint32_t n = K.n;
-            for (uint32_t m = tid; m < D.M; m += kFxThreads) {
-                const uint32_t base = n * m;
-                for (uint32_t i = 0; i + 1 < n; ++i)
-                    for (uint32_t j = i + 1; j < n; ++j) {
-                        const double dx = fx_mi(V.pos[base + i] - V.pos[base + j], K.L, K.invL);
-                        const double dy = fx_mi(V.pos[N + base + i] - V.pos[N + base + j], K.L, K.invL);
-                        const double dz = fx_mi(V.pos[2 * N + base + i] - V.pos[2 * N + base + j], K.L, K.invL);
-                        d2 = fmax(d2, dx * dx + dy * dy + dz * dz);
-                    }
+            for (uint32_t ci = (uint32_t)wave; ci < nact; ci += kFxWaves) {
+                const uint32_t cell = (kx + k * (ci % na)) + nc * ((ky + k * ((ci / na) % na)) +
+                                                                  nc * (kz + k * (ci / (na * na))));
+                const uint32_t b = V.cell_start[cell], e = V.cell_start[cell + 1];
+                for (uint32_t q = b + (uint32_t)lane; q < e; q += 64u) {
+                    const uint32_t base = n * (V.cell_list[q] / n);
+                    for (uint32_t i = 0; i + 1 < n; ++i)
+                        for (uint32_t j = i + 1; j < n; ++j) {
+                            const double dx = fx_mi(V.pos[base + i] - V.pos[base + j], K.L, K.invL);
+                            const double dy = fx_mi(V.pos[N + base + i] - V.pos[N + base + j], K.L, K.invL);
+                            const double dz =
+                                fx_mi(V.pos[2 * N + base + i] - V.pos[2 * N + base + j], K.L, K.invL);
+                            d2 = fmax(d2, dx * dx + dy * dy + dz * dz);
+                        }
+                }
             }
 #pragma unroll
             for (int o = 32; o; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o));
@@ -638,9 +649,9 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxList list, uint64_t 
             __syncthreads();
             double dm = 0.0;
             for (int w2 = 0; w2 < kFxWaves; ++w2) dm = fmax(dm, dmax2[w2]);
-            together = K.sep >= 2.0 * sqrt(dm) + K.dyn_base;
             __syncthreads();
-        }
+            return K.sep >= 2.0 * sqrt(dm) + K.dyn_base;
+        };
         // the attempts of cell `ci` of a colour by this wave
         auto run_cell = [&](uint32_t kx, uint32_t ky, uint32_t kz, uint32_t ci) __attribute__((always_inline)) {
             const uint32_t cell = (kx + k * (ci % na)) + nc * ((ky + k * ((ci / na) % na)) +
@@ -666,7 +677,7 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxList list, uint64_t 
         };
         for (uint32_t col = 0; col < k * k * k; ++col) {
             const uint32_t kx = col % k, ky = (col / k) % k, kz = col / (k * k);
-            if (together) {
+            if (colour_together(kx, ky, kz)) {
                 for (uint32_t ci = (uint32_t)wave; ci < nact; ci += kFxWaves) run_cell(kx, ky, kz, ci);
                 __syncthreads();
             } else {
