@@ -148,6 +148,39 @@ def test_full_size_1000_triangles():
     assert resyncs <= 1
 
 
+@pytest.mark.parametrize("g,T", [(flipmc.MC_TRIANGLE, 0.75), (flipmc.MC_SQUARE, 1.0),
+                                 (flipmc.MC_TETRAHEDRON, 1.0)], ids=["triangle", "square", "tetrahedron"])
+def test_timed_regime_in_the_bench_decomposition(g, T):
+    # the flexible bench's systems (1000 molecules, density 1.2, the
+    # decomposition mcf_geometry picks) after the default line's 200 warm-up
+    # sweeps on the device: that state into the oracle, then 2 sweeps attempt
+    # by attempt
+    print(f"flex timed regime geometry={g}", flush=True)
+    p = flipmc.mcf_params_default(g, n_molecules=1000, temperature=T, density=1.2, seed=1)
+    _, k, nc = flipmc.mcf_geometry(p)
+    s = flipmc.FlexSystem(p)
+    s.sweep(200)
+    st = s.get_state()
+    assert st["sweep"] == 200
+    o = flex.System(op(g, 1000, T, k, nc, 1.2, seed=1))
+    o.set_state(st["pos"], st["types"], st["sweep"], st["e_acc"])
+    assert s.energy()[0] == pytest.approx(o.energy(), rel=1e-12)
+    resyncs = 0
+    for _ in range(2):
+        s.decision_log(1)
+        s.sweep(1)
+        lg = s.read_log()
+        lo = o.sweep_checkerboard(1, log=True)
+        if compare(lg, lo):  # a near-tie decision differed: go on from the oracle's state
+            x = o.get_state()
+            s.set_state(x["pos"], x["types"], x["sweep"], x["e_acc"])
+            resyncs += 1
+            continue
+        a, b = s.get_state(), o.get_state()
+        assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["types"], b["types"])
+    assert resyncs <= 1
+
+
 def test_fene_wall_on_the_device():
     # a stretched triangle (bond 0-1 at 1.5 with types B, C): flips that put
     # A on that bond reach the bond's limit; the engine gives dE = inf on the
