@@ -362,12 +362,18 @@ typedef struct mcf_system mcf_system;
  * re-sum every 100 sweeps).  Never fails. */
 void mcf_params_default(mcf_params* p, uint32_t geometry);
 
-/* Box side L = (n M / density)^(1/3) and the decomposition (k, n_c): same-
- * colour cells must be (k - 1) L / n_c >= 2 D + r_c apart (D the farthest two
- * atoms of one molecule can be: one bond of at most 1.5 sigma_ij, two for the
- * square's diagonal; r_c the largest WCA cut-off), cells at least r_c wide.
- * MC_EGEOM when no decomposition fits or the box is below
- * 2 (max(D, r_c) + 2 d).  Any output may be NULL. */
+/* Box side L = (n M / density)^(1/3) and the decomposition (k, n_c, n_c a
+ * multiple of k >= 2): cells at least r_c + 2 sqrt(3) d wide (r_c the largest
+ * WCA cut-off, d the largest displacement per axis).  The cells of a colour
+ * are attempted in ascending index; they run side by side when their gap
+ * (k - 1) L / n_c is at least 2 D + r_c for the largest atom distance D any
+ * body can have (one bond of 1.5 sigma_ij, two for the square's diagonal), or
+ * at least 2 D + r_c + 4 sqrt(3) d for D measured over the molecules with an
+ * atom in them when the colour starts; otherwise one at a time.  The chain
+ * does not depend on it.  With k = n_c = 0 the choice is the most cells per
+ * colour that run side by side while the bodies stay within 15 % of their
+ * ideal size.  MC_EGEOM when no decomposition fits or the box is below
+ * 2 (max(D, r_c) + 2 d), D the largest possible.  Any output may be NULL. */
 int mcf_geometry(const mcf_params* p, double* box, uint32_t* colours_per_axis,
                  uint32_t* cells_per_side);
 

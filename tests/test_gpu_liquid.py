@@ -150,3 +150,51 @@ def test_batched_systems_match_the_oracle(fp32):
                 assert np.array_equal(sg["com"], so["com"])
                 assert np.array_equal(sg["types"], so["types"])
                 assert np.max(np.abs(sg["quat"] - so["quat"])) < 1e-13
+
+
+def test_replica_batch_launch_sampled_against_the_oracle():
+    # the 256-replica set in the launch the bench times (one batch, FP32 dE,
+    # every replica on its workgroup, re-sums and C_2 samples inside the
+    # sweep kernel), a few sweeps: 8 replicas sampled 2 per size, trial by
+    # trial against the oracle run alone on the same seeds and decomposition
+    from paper_2506_21290_amd import workloads
+
+    n = 3
+    jobs = workloads.replica_set(256, sweeps=n, seed=1)
+    by_size = {}
+    for j in jobs:
+        by_size.setdefault(j.n_molecules, []).append(j)
+    sample = [j for m in sorted(by_size) for j in by_size[m][:2]]
+    print(f"replica batch: {len(jobs)} replicas, sampled {[j.index for j in sample]}", flush=True)
+    b = flipmc.Batch(256, flipmc.MC_FP32_DE)
+    systems = {}
+    for j in jobs:
+        p = flipmc.mc_params_default(n_molecules=j.n_molecules, temperature=j.temperature,
+                                     precision=flipmc.MC_FP32_DE, seed=j.seed, resum_interval=100,
+                                     obs_interval=10, gofr_interval=0)
+        s = flipmc.System(p, stream=b.stream)
+        if j in sample:
+            s.decision_log(n)
+        b.add(s, j.sweeps)
+        systems[j.index] = (s, p)
+    launches = done = 0
+    while done < len(jobs):
+        launches += b.run(0) > 0
+        done += len(b.poll())
+    assert launches == 1
+    compared = 0
+    for j in sample:
+        s, p = systems[j.index]
+        _, k, nc = flipmc.mc_geometry(p)
+        lg = s.read_log()
+        o = oracle.System(oparams(j.n_molecules, j.temperature, k, nc, seed=j.seed))
+        M = j.n_molecules
+        for sw in range(n):
+            lo = o.sweep_checkerboard(1, log=True)
+            compared += 1
+            if compare_sweep(lg[sw * M:(sw + 1) * M], lo, True):
+                break  # a near tie: the chains part from here
+    assert compared >= 2 * len(sample)
+    for s, _ in systems.values():
+        s.close()
+    b.close()
