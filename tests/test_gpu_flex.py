@@ -317,3 +317,38 @@ def test_sweep_many_equals_each_system_alone():
         flipmc.flex_sweep_many([many[0], many[1], many[0]], 1)
     assert e.value.code == flipmc.MC_EINVAL
     assert many[0].get_state()["sweep"] == 30  # nothing was enqueued
+
+
+def test_replica_launch_sampled_against_the_oracle():
+    # the bench's replica launch: 256 systems of 1000 flexible triangles
+    # (T = 0.75, seeds 1 .. 256) advanced together by mcf_sweep_many, two
+    # sweeps; replicas 1 and 256 attempt by attempt against the oracle (both
+    # from the oracle's lattice start)
+    print("flex replica launch", flush=True)
+    R, n, N = 256, 2, 3000
+    ps = [flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=1000, temperature=0.75, density=1.2,
+                                    seed=r + 1, gofr_interval=0) for r in range(R)]
+    runs = [flipmc.FlexSystem(p) for p in ps]
+    oracles = {}
+    for r in (0, R - 1):
+        _, k, nc = flipmc.mcf_geometry(ps[r])
+        o = flex.System(op(flipmc.MC_TRIANGLE, 1000, 0.75, k, nc, 1.2, seed=r + 1))
+        so = o.get_state()
+        runs[r].set_state(so["pos"], so["types"], 0)
+        runs[r].decision_log(n)
+        oracles[r] = o
+    flipmc.flex_sweep_many(runs, n)
+    for r, o in oracles.items():
+        lg = runs[r].read_log()
+        tie = False
+        for sw in range(n):
+            lo = o.sweep_checkerboard(1, log=True)
+            if compare(lg[sw * N:(sw + 1) * N], lo):
+                tie = True
+                break
+        if not tie:
+            a, b = runs[r].get_state(), o.get_state()
+            assert a["sweep"] == b["sweep"] == n
+            assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["types"], b["types"])
+    for s in runs:
+        s.close()
