@@ -555,6 +555,15 @@ int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
  * engine). */
 int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched);
 
+/* Put the launch of the systems that run on one workgroup with their state in
+ * HBM on a third caller stream, beside the launch of those whose state is in
+ * LDS (on hip_stream), instead of after it; the run's event work and all
+ * later work on hip_stream follow both.  NULL (the default) or hip_stream
+ * itself: after it on hip_stream.  The stream must outlive the batch.  Either
+ * way the results are the same; only the overlap changes.  MC_EINVAL for a
+ * NULL batch.  Host only. */
+int mc_batch_set_hbm_stream(mc_batch* b, void* hip_stream);
+
 /* At most max_workgroups workgroups of the batch's runs at once (0 = one per
  * compute unit of the current device, the default): fewer leaves compute units
  * to other work and moves fewer systems onto the multi-workgroup engine. */

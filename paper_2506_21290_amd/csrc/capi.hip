@@ -357,6 +357,11 @@ struct mc_batch {
     // stream2, overlapping the batch stream's launches
     hipStream_t stream2;              // caller's second stream (or the batch stream)
     hipEvent_t go, done;              // stream2 waits for go (stream), stream for done (stream2)
+    // systems on one workgroup with the state in HBM: their launch on stream3
+    // (a third caller stream) runs beside the LDS class's launch on stream;
+    // nullptr = after it on stream
+    hipStream_t stream3;
+    hipEvent_t go3, done3;            // stream3 waits for go3 (stream), stream for done3 (stream3)
     SpreadSlot* dev_spread[2];        // per parity: [systems | (events as Slot)] x max_slots
     SpreadSlot* host_spread[2];
     Slot* dev_ev2[2];
@@ -999,6 +1004,7 @@ void mc_destroy(mc_system* s)
     if (s->batch) {
         (void)hipStreamSynchronize(s->batch->stream);
         if (s->batch->stream2) (void)hipStreamSynchronize(s->batch->stream2);
+        if (s->batch->stream3) (void)hipStreamSynchronize(s->batch->stream3);
     }
     for (auto& pr : s->ev_sweep) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
     for (auto& pr : s->ev_event) { s->ev_pool.push_back(pr.first); s->ev_pool.push_back(pr.second); }
@@ -1154,6 +1160,8 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* device_buf, si
     b->parity = 0;
     b->stream2 = nullptr;
     b->go = b->done = nullptr;
+    b->stream3 = nullptr;
+    b->go3 = b->done3 = nullptr;
     b->spread_max = 0;
     b->ncu = 1;
     b->wg_limit = 0;
@@ -1197,7 +1205,9 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* device_buf, si
         }
     b->stream2 = hip_stream_aux ? (hipStream_t)hip_stream_aux : b->stream;
     if (hipEventCreateWithFlags(&b->go, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->go3, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done3, hipEventDisableTiming) != hipSuccess) {
         mc_batch_destroy(b);
         return fail(MC_EDEVICE, "could not create the stream events");
     }
@@ -1253,6 +1263,15 @@ int mc_batch_set_workgroups(mc_batch* b, uint32_t max_workgroups)
 {
     if (!b) return fail(MC_EINVAL, "null batch");
     b->wg_limit = max_workgroups ? max_workgroups : b->ncu;
+    return MC_OK;
+}
+
+int mc_batch_set_hbm_stream(mc_batch* b, void* hip_stream)
+{
+    if (!b) return fail(MC_EINVAL, "null batch");
+    // the previous run's launch on the old stream was joined into the batch
+    // stream, so later work there already follows it
+    b->stream3 = (hipStream_t)hip_stream == b->stream ? nullptr : (hipStream_t)hip_stream;
     return MC_OK;
 }
 
@@ -1451,14 +1470,27 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         HIPCHK(hipEventRecord(b->copied[par], b->stream));
         b->pending[par] = true;
         Slot none{};
+        // with a third stream the HBM class's launch runs beside the LDS
+        // class's (each on its own compute units) instead of after it; the
+        // events below follow both
+        const bool side = n[0] && n[1] && b->stream3;
+        if (side) {
+            HIPCHK(hipEventRecord(b->go3, b->stream));
+            HIPCHK(hipStreamWaitEvent(b->stream3, b->go3, 0));
+        }
         for (int cls = 0; cls < 2; ++cls)
             if (n[cls]) {
-                HIPCHK(hipEventRecord(b->t_beg[cls], b->stream));
+                hipStream_t st = cls == 1 && side ? b->stream3 : b->stream;
+                HIPCHK(hipEventRecord(b->t_beg[cls], st));
                 HIPCHK(launch_sweeps(fp64, cls == 0, b->dev_slots[par] + cls * S, none, n[cls],
-                                     lds[cls], b->stream, true));
-                HIPCHK(hipEventRecord(b->t_end[cls], b->stream));
+                                     lds[cls], st, true));
+                HIPCHK(hipEventRecord(b->t_end[cls], st));
                 b->pred[cls] = pred[cls];
             }
+        if (side) {
+            HIPCHK(hipEventRecord(b->done3, b->stream3));
+            HIPCHK(hipStreamWaitEvent(b->stream, b->done3, 0));
+        }
         for (const auto& pe : parts1) {
             Slot one{};
             one.sys = pe.first->dev;
@@ -1509,6 +1541,7 @@ void mc_batch_destroy(mc_batch* b)
     for (auto* s : b->sys)
         if (s) s->batch = nullptr;
     if (b->stream2) (void)hipStreamSynchronize(b->stream2);
+    if (b->stream3) (void)hipStreamSynchronize(b->stream3);
     for (int i = 0; i < 2; ++i) {
         if (b->host_slots[i]) (void)hipHostFree(b->host_slots[i]);
         if (b->copied[i]) (void)hipEventDestroy(b->copied[i]);
@@ -1522,6 +1555,8 @@ void mc_batch_destroy(mc_batch* b)
     }
     if (b->go) (void)hipEventDestroy(b->go);
     if (b->done) (void)hipEventDestroy(b->done);
+    if (b->go3) (void)hipEventDestroy(b->go3);
+    if (b->done3) (void)hipEventDestroy(b->done3);
     delete b;
 }
 

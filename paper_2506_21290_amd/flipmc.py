@@ -34,7 +34,7 @@ EXPORTED = [
     "mc_set_state", "mc_decision_log", "mc_timing_enable", "mc_timing_read", "mc_destroy",
     "mc_last_error", "mc_batch_required_bytes", "mc_batch_create",
     "mc_batch_add", "mc_batch_run", "mc_batch_poll", "mc_batch_cancel", "mc_batch_destroy",
-    "mc_batch_set_workgroups", "mc_dynamics",
+    "mc_batch_set_workgroups", "mc_batch_set_hbm_stream", "mc_dynamics",
     "mcf_params_default", "mcf_geometry", "mcf_placement", "mcf_required_bytes", "mcf_init_system",
     "mcf_sweep", "mcf_sweep_many",
     "mcf_energy", "mcf_observables", "mcf_reset_observables", "mcf_get_state", "mcf_set_state",
@@ -217,6 +217,7 @@ def lib():
         L.mc_batch_poll.argtypes = [vp, u32p, C.POINTER(vp), C.c_size_t, szp]
         L.mc_batch_cancel.argtypes = [vp, C.c_uint32]
         L.mc_batch_set_workgroups.argtypes = [vp, C.c_uint32]
+        L.mc_batch_set_hbm_stream.argtypes = [vp, vp]
         L.mc_batch_destroy.argtypes = [vp]
         L.mc_batch_destroy.restype = None
         L.mc_dynamics.argtypes = [C.POINTER(mc_obs), C.c_size_t, C.c_uint32, C.POINTER(mc_dyn)]
@@ -503,13 +504,15 @@ class Batch:
     each, spare workgroups to the large systems with the most work left."""
 
     def __init__(self, max_slots, precision=MC_FP32_DE, stream=None, aux_stream=None,
-                 device="cuda"):
+                 hbm_stream=None, device="cuda"):
         import torch
 
         self._stream_handle, self.stream = _stream_handle(stream)
-        # the multi-workgroup launches overlap the others on a second stream
-        # (default priority, like every stream here)
+        # the multi-workgroup launches overlap the others on a second stream,
+        # and the one-workgroup launch of systems with their state in HBM the
+        # LDS class's on a third (default priority, like every stream here)
         self.aux_stream = aux_stream if aux_stream is not None else torch.cuda.Stream()
+        self.hbm_stream = hbm_stream if hbm_stream is not None else torch.cuda.Stream()
         self._lib = lib()
         n = C.c_size_t()
         _check(self._lib.mc_batch_required_bytes(int(max_slots), C.byref(n)))
@@ -520,6 +523,7 @@ class Batch:
                                          self._stream_handle, C.c_void_p(self.aux_stream.cuda_stream),
                                          C.byref(h)))
         self.h = h
+        _check(self._lib.mc_batch_set_hbm_stream(h, C.c_void_p(self.hbm_stream.cuda_stream)))
         self.max_slots = max_slots
         self.members = {}
         _track(self)

@@ -140,3 +140,10 @@ def test_flexible_sweep_many_rejects_empty_lists_without_a_device():
     arr = (C.c_void_p * 2)(None, None)
     assert L.mcf_sweep_many(arr, 2, 1) == flipmc.MC_EINVAL
     assert b"null system" in L.mc_last_error()
+
+
+def test_batch_setters_reject_a_null_batch_without_a_device():
+    L = flipmc.lib()
+    assert L.mc_batch_set_workgroups(None, 8) == flipmc.MC_EINVAL
+    assert L.mc_batch_set_hbm_stream(None, None) == flipmc.MC_EINVAL
+    assert b"null batch" in L.mc_last_error()
