@@ -436,7 +436,10 @@ int launch_events_one(mc_system* s, uint32_t flags)
     const uint32_t nb = event_blocks(s->p.n_molecules);
     if (nb > 1 && (flags & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic | kFlagGofr))) {
         // the O(M^2) re-sum and g(r) frame on many workgroups, then the rest
-        HIPCHK(launch_event_parts(one, nb, s->stream));
+        PartList pl{};
+        pl.s[0] = PartSlot{s->dev, flags, 0u, nb, 0u};
+        pl.n = 1;
+        HIPCHK(launch_event_parts(pl, nb, s->stream));
         one.flags = flags | kFlagParts;
         one.pad = nb;
     }
@@ -572,6 +575,25 @@ int upload_state(mc_system* s, const double* com, const double* quat, const uint
     HIPCHK(hipMemcpyAsync(s->host.types, t.data(), t.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return MC_OK;
+}
+
+// The event work over many workgroups of several systems: one launch per
+// kPartSlots systems, each system on its own event_blocks() workgroups.
+hipError_t launch_parts_of(const std::vector<std::pair<mc_system*, uint32_t>>& parts,
+                                  hipStream_t stream)
+{
+    for (size_t i0 = 0; i0 < parts.size(); i0 += kPartSlots) {
+        PartList pl{};
+        uint32_t blocks = 0;
+        for (size_t i = i0; i < std::min(parts.size(), i0 + kPartSlots); ++i) {
+            const uint32_t nb = event_blocks(parts[i].first->p.n_molecules);
+            pl.s[pl.n++] = PartSlot{parts[i].first->dev, parts[i].second, blocks, nb, 0u};
+            blocks += nb;
+        }
+        const hipError_t e = launch_event_parts(pl, blocks, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -1453,12 +1475,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
         HIPCHK(launch_spread(fp64, b->dev_spread[par], ns, none, blocks, b->stream2));
         HIPCHK(hipEventRecord(b->t_end[2], b->stream2));
         b->pred[2] = pred[2];
-        for (const auto& pe : parts2) {
-            Slot one{};
-            one.sys = pe.first->dev;
-            one.flags = pe.second;
-            HIPCHK(launch_event_parts(one, event_blocks(pe.first->p.n_molecules), b->stream2));
-        }
+        HIPCHK(launch_parts_of(parts2, b->stream2));
         Slot none2{};
         if (ne) HIPCHK(launch_events(b->dev_ev2[par], none2, ne, b->stream2));
         HIPCHK(hipEventRecord(b->done, b->stream2));
@@ -1491,12 +1508,7 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
             HIPCHK(hipEventRecord(b->done3, b->stream3));
             HIPCHK(hipStreamWaitEvent(b->stream, b->done3, 0));
         }
-        for (const auto& pe : parts1) {
-            Slot one{};
-            one.sys = pe.first->dev;
-            one.flags = pe.second;
-            HIPCHK(launch_event_parts(one, event_blocks(pe.first->p.n_molecules), b->stream));
-        }
+        HIPCHK(launch_parts_of(parts1, b->stream));
         if (n[2]) HIPCHK(launch_events(b->dev_slots[par] + 2 * S, none, n[2], b->stream));
     }
     // later work on the batch stream (the next run, poll, reads) follows the

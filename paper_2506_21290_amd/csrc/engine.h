@@ -222,10 +222,23 @@ hipError_t launch_spread(bool fp64, const SpreadSlot* dev_slots, uint32_t n_slot
 hipError_t launch_zero_barriers(const SpreadSlot* dev_slots, uint32_t n_slots, hipStream_t stream);
 // Largest cooperative grid of the spread kernel on the current device.
 hipError_t spread_max_blocks(bool fp64, uint32_t* n_blocks);
-// The O(M^2) part of an event (re-sum partial energies into g_part, g(r)
-// frame into the histograms) over n_blocks workgroups; follow with
-// launch_events(flags | kFlagParts, pad = n_blocks).
-hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t stream);
+// The systems of one launch of the event work over many workgroups, passed by
+// value (no table in memory): system i owns workgroups [first, first + count)
+// and splits its work over them as a launch of count workgroups of its own
+// would, so its partial sums do not depend on the systems beside it.
+struct PartSlot {
+    SysDev* sys;
+    uint32_t flags, first, count, pad;
+};
+constexpr uint32_t kPartSlots = 128;
+struct PartList {
+    PartSlot s[kPartSlots];
+    uint32_t n;
+};
+// The O(M^2) part of the events of list.s[0 .. n) (re-sum partial energies
+// into g_part, g(r) frame into the histograms), n_blocks = the sum of their
+// counts; follow with launch_events(flags | kFlagParts, pad = count).
+hipError_t launch_event_parts(const PartList& list, uint32_t n_blocks, hipStream_t stream);
 
 // Record msg as the calling thread's last error (mc_last_error) and return code.
 int api_error(int code, const char* msg);

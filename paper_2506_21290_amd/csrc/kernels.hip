@@ -2005,8 +2005,17 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SpreadSlot* __r
 
 // The O(M^2) work of an event on many workgroups: the re-sum's partial energy
 // of each workgroup into g_part, the g(r) frame into the histograms.
-__global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
+__global__ void __launch_bounds__(kThreads) k_event_parts(PartList list)
 {
+    // this workgroup's system: the last slot whose first workgroup is at or
+    // below it (the slots are in ascending first)
+    uint32_t lo = 0, hi = list.n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (list.s[mid].first <= blockIdx.x) lo = mid; else hi = mid;
+    }
+    const PartSlot one = list.s[lo];
+    const uint32_t bid = blockIdx.x - one.first;
     __shared__ double red[kWaves];
     __shared__ double misc[16];
     __shared__ uint32_t bins[2 * kGofrBins];
@@ -2030,14 +2039,14 @@ __global__ void __launch_bounds__(kThreads) k_event_parts(Slot one)
     }
     __syncthreads();
     const uint32_t f = one.flags;
-    const uint32_t m0 = blockIdx.x * kThreads + threadIdx.x, step = gridDim.x * kThreads;
+    const uint32_t m0 = bid * kThreads + threadIdx.x, step = one.count * kThreads;
     if (f & (kFlagResumSet | kFlagResumReport | kFlagResumPeriodic)) {
         // a scheduled re-sum follows sweeps, whose cell lists are still there
         const int span = (int)ceil((sqrt(C.reach2) + 2.0 * 1.7320508075688772 * C.dmax + 1e-9) / C.w);
         const bool cells = (f & (kFlagResumSet | kFlagResumReport)) == 0 && C.cellb != nullptr &&
                            2 * span + 1 <= (int)C.nc;
         const double e = cells ? resum_energy_cells(C, m0, step, span) : resum_energy(C, m0, step);
-        if (threadIdx.x == 0) C.gpart[blockIdx.x] = e;
+        if (threadIdx.x == 0) C.gpart[bid] = e;
         __syncthreads();
     }
     if (f & kFlagGofr) gofr_frame(C, m0, step, true, gqueue);
@@ -2182,9 +2191,9 @@ hipError_t launch_zero_barriers(const SpreadSlot* dev_slots, uint32_t n_slots, h
     return hipGetLastError();
 }
 
-hipError_t launch_event_parts(const Slot& one, uint32_t n_blocks, hipStream_t stream)
+hipError_t launch_event_parts(const PartList& list, uint32_t n_blocks, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_event_parts, dim3(n_blocks), dim3(kThreads), 0, stream, one);
+    hipLaunchKernelGGL(k_event_parts, dim3(n_blocks), dim3(kThreads), 0, stream, list);
     return hipGetLastError();
 }
 
