@@ -514,9 +514,10 @@ int mcf_dynamics(const mc_obs* runs, size_t n_runs, uint32_t n_molecules, uint32
  * idle to make them modelled 25 % faster), which then run on the
  * multi-workgroup engine, each on up to the workgroups its cells allow.
  * Systems on one workgroup share one persistent launch per
- * placement class (state in LDS / in HBM); systems on the multi-workgroup
- * engine share one cooperative launch on the caller's second stream
- * (hip_stream_aux of mc_batch_create).
+ * placement class (state in LDS / in HBM; the HBM class beside the LDS
+ * class on a third caller stream when mc_batch_set_hbm_stream gives one);
+ * systems on the multi-workgroup engine share one cooperative launch on the
+ * caller's second stream (hip_stream_aux of mc_batch_create).
  * All engines make the same decisions and sum the energy in the same order,
  * so a system gives bitwise the same results in a batch as alone, whichever
  * engines its runs used. */
