@@ -650,8 +650,11 @@ def bench_c4(args, flipmc, torch, n_jobs=None, check_alone=None):
 
     jobs = workloads.serving_stream(n_jobs=n_jobs or args.jobs, rate=200.0, seed=1, m_max=args.m_max,
                                     s_max=args.s_max)
+    cap = None
+    if args.policy == "sjf":
+        cap = args.max_active or torch.cuda.get_device_properties(0).multi_processor_count
     srv = serve.Server(memory_budget=args.budget, backend=serve.GpuBackend(flipmc.MC_FP32_DE),
-                       quantum_moves=args.quantum)
+                       quantum_moves=args.quantum, policy=args.policy, max_active=cap)
     t0 = time.perf_counter()
     mark = [0]
 
@@ -686,7 +689,8 @@ def bench_c4(args, flipmc, torch, n_jobs=None, check_alone=None):
     return {
         "workload": f"c4: {len(jobs)} Poisson jobs at 200/s, M=n^3 log-uniform in [125,{args.m_max}], "
                     f"T in [0.75,3], sweeps log-uniform in [100,{args.s_max}], FP32 dE, memory budget "
-                    f"{args.budget / 2**20:g} MiB",
+                    f"{args.budget / 2**20:g} MiB, admission "
+                    + ("in arrival order" if cap is None else f"shortest job first, at most {cap} jobs at once"),
         "completed": len(res),
         "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
@@ -747,6 +751,10 @@ def main():
     ap.add_argument("--s-max", type=int, default=10000)
     ap.add_argument("--budget", type=int, default=4 << 30)
     ap.add_argument("--quantum", type=int, default=100_000)
+    ap.add_argument("--policy", choices=["fifo", "sjf"], default="fifo",
+                    help="serving admission: arrival order, or shortest job first")
+    ap.add_argument("--max-active", type=int, default=0,
+                    help="jobs admitted at once under sjf (0 = the device's compute units)")
     ap.add_argument("--time-limit", type=float, default=None)
     ap.add_argument("--check-alone", type=int, default=20,
                     help="c4: sampled jobs re-run alone and compared with their result in the mix")

@@ -2,7 +2,8 @@
 
 Requests are sampling jobs (M molecules at temperature T for S sweeps).  Their
 configurations stay resident in HBM for the job's life; a job is admitted as
-soon as a slot and enough of the memory budget are free, and every run
+soon as a slot and enough of the memory budget are free (in arrival order, or
+the shortest queued job first with a cap on the jobs admitted), and every run
 advances all admitted jobs by one time slice, so jobs that arrive while others
 run join the next run and their work overlaps on the device.  Every job gets
 one workgroup per run (systems whose working set fits one workgroup's LDS keep
@@ -125,11 +126,22 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, memory_budget, backend=None, quantum_moves=100_000):
+    """Admission policies: "fifo" admits jobs in arrival order as soon as the
+    budget and a slot allow; "sjf" admits the queued job with the least work
+    (molecules x sweeps) first, and at most max_active jobs at once, so that
+    short jobs do not share the device with every long one (the smallest mean
+    and median latency for known job sizes; the longest jobs finish last)."""
+
+    def __init__(self, memory_budget, backend=None, quantum_moves=100_000, policy="fifo",
+                 max_active=None):
+        if policy not in ("fifo", "sjf"):
+            raise ValueError(f"unknown admission policy {policy!r}")
         self.backend = backend if backend is not None else GpuBackend()
         self.budget = int(memory_budget)
         self.used = 0
         self.quantum = int(quantum_moves)
+        self.policy = policy
+        self.max_active = max_active
         self.active = {}  # (batch, slot) -> (job, handle, bytes, t_admit)
         self.peak_active = 0
         self.peak_bytes = 0
@@ -177,10 +189,15 @@ class Server:
             now = clock()
             if time_limit is not None and now > time_limit:
                 break
+            arrived = False
             while i < len(jobs) and jobs[i].arrival <= now:
                 queue.append(jobs[i])
                 i += 1
-            while queue and self.try_admit(queue[0], now):
+                arrived = True
+            if self.policy == "sjf" and arrived:
+                queue = collections.deque(sorted(queue, key=lambda j: (j.n_molecules * j.sweeps, j.arrival)))
+            while queue and (self.max_active is None or len(self.active) < self.max_active) and \
+                    self.try_admit(queue[0], now):
                 queue.popleft()
             if not self.active:
                 if i < len(jobs):

@@ -116,3 +116,30 @@ def test_replica_set():
     assert len(jobs) == 256 and {j.n_molecules for j in jobs} == set(workloads.REPLICA_SIZES)
     assert [j.seed for j in jobs] == list(range(1, 257))
     assert all(0.75 <= j.temperature <= 3.0 for j in jobs)
+
+
+def test_shortest_job_first_admits_the_least_work_and_respects_the_cap():
+    fb = FakeBackend(slots=100)
+    fb.quantum = 1000
+    srv = serve.Server(10**9, backend=fb, quantum_moves=1000, policy="sjf", max_active=2)
+    # all arrive together: work 125 * 900, 1728 * 100, 512 * 100, 1000 * 1000
+    jobs = [workloads.Job(0, 125, 1.0, 900, 1, 0.0), workloads.Job(1, 1728, 1.0, 100, 2, 0.0),
+            workloads.Job(2, 512, 1.0, 100, 3, 0.0), workloads.Job(3, 1000, 1.0, 1000, 4, 0.0)]
+    admitted = []
+    orig = fb.start
+
+    def start(job, bi):
+        admitted.append(job.index)
+        assert len(fb.running) < 2  # never more than max_active at once
+        return orig(job, bi)
+
+    fb.start = start
+    res = srv.serve(jobs, clock=lambda: 0.0)
+    assert sorted(r.job.index for r in res) == [0, 1, 2, 3]
+    assert admitted[:2] == [2, 0]  # 51 200 and 112 500 moves before 172 800 and 10^6
+    assert srv.peak_active <= 2 and srv.used == 0
+
+
+def test_unknown_policy_is_rejected():
+    with pytest.raises(ValueError):
+        serve.Server(1, backend=FakeBackend(), policy="lifo")
