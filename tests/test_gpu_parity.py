@@ -439,14 +439,16 @@ def test_checkpoint_resume_is_exact():
     assert np.array_equal(sa["types"], sc["types"]) and sa["e_acc"] == sc["e_acc"]
 
 
-@pytest.mark.parametrize("fp32,workgroups", [(False, 0), (True, 0), (True, 9), (False, 8)])
-def test_batch_equals_alone(fp32, workgroups):
+@pytest.mark.parametrize("fp32,workgroups,third", [(False, 0, True), (True, 0, True), (True, 9, True),
+                                                   (False, 8, True), (True, 9, False)])
+def test_batch_equals_alone(fp32, workgroups, third):
     # one batch over uneven systems gives bitwise the results of running each
     # alone; the last two are beyond one workgroup's LDS and run on the
     # multi-workgroup engine alone; in the batch they take the spare
     # workgroups, and with a limit of 8 or 9 workgroups they start on one
     # workgroup each and move to the multi-workgroup engine as the others
-    # finish
+    # finish (two one-workgroup launches per run then: the LDS class and, on
+    # the batch's third stream or after it, the HBM class)
     specs = [(64, 3.0, 2, 2, 3), (216, 1.0, 3, 6, 4), (343, 0.8, 3, 6, 5), (216, 2.0, 2, 2, 6),
              (2197, 1.3, 2, 4, 7), (2744, 2.2, 2, 6, 8)]
     sweeps = [30, 17, 25, 9, 14, 11]
@@ -457,6 +459,8 @@ def test_batch_equals_alone(fp32, workgroups):
         alone.append(s.get_state())
     b = flipmc.Batch(8, flipmc.MC_FP32_DE if fp32 else flipmc.MC_FP64)
     b.set_workgroups(workgroups)
+    if not third:  # the HBM class's launch after the LDS class's on the batch stream
+        assert flipmc.lib().mc_batch_set_hbm_stream(b.h, None) == flipmc.MC_OK
     systems = []
     for (M, T, k, nc, seed), n in zip(specs, sweeps):
         s = flipmc.System(gparams(M, T, k, nc, fp32=fp32, seed=seed), stream=b.stream)
