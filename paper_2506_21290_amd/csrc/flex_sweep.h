@@ -430,18 +430,23 @@ __device__ __forceinline__ void fx_attempt(const FxK& D, const FxView& V, uint32
             const double r2n = dxn * dxn + dyn * dyn + dzn * dzn;
             const double so = 0.5 * (fx_pick(sig, fx_pick(ot, i)) + fx_pick(sig, fx_pick(ot, j)));
             const double sn = 0.5 * (fx_pick(sig, fx_pick(nt, i)) + fx_pick(sig, fx_pick(nt, j)));
-            double uo = fx_wca(so * so, r2o, D.rc2f), un = fx_wca(sn * sn, r2n, D.rc2f);
+            const double uo = fx_wca(so * so, r2o, D.rc2f), un = fx_wca(sn * sn, r2n, D.rc2f);
             ino = r2o < D.rc2f * so * so;
             inn = r2n < D.rc2f * sn * sn;
-            if ((D.bonded >> (4 * i + j)) & 1u) {
-                const double fo = fx_fene(so, r2o), fn = fx_fene(sn, r2n);
-                uo += fo;
-                un += fn;
-                fino = fo < __builtin_inf();
-                finn = fn < __builtin_inf();
-            }
             de = un - uo;
             sc = un + uo;
+            if ((D.bonded >> (4 * i + j)) & 1u) {
+                // the change of Eq. (2) in one logarithm: the ratio of the
+                // arguments before and after; +inf at or beyond the limit
+                const double lo2 = 2.25 * so * so, ln2 = 2.25 * sn * sn;
+                fino = r2o < lo2;
+                finn = r2n < ln2;
+                if (fino && finn)
+                    de += -33.75 * log((1.0 - r2n / ln2) / (1.0 - r2o / lo2));
+                else
+                    de += (finn ? 0.0 : __builtin_inf()) - (fino ? 0.0 : __builtin_inf());
+                if (logging) sc += fx_fene(so, r2o) + fx_fene(sn, r2n);
+            }
         }
         terms += (uint32_t)__popcll(__ballot(ino)) + (uint32_t)__popcll(__ballot(inn)) +
                  (uint32_t)__popcll(__ballot(fino)) + (uint32_t)__popcll(__ballot(finn));
