@@ -498,6 +498,13 @@ uint64_t next_event(const mc_system* s, bool gofr_only = false)
 
 constexpr uint64_t kMaxSweepsPerLaunch = 1u << 16;
 
+// Zero a system's barrier counter with a kernel, not a memset: mc_sweep stays
+// free of memset nodes for callers that capture it into a graph.
+__global__ void k_zero_counter(uint32_t* c)
+{
+    if (threadIdx.x == 0) *c = 0u;
+}
+
 // Enqueue n sweeps of one system, split at event sweeps.
 int advance(mc_system* s, uint64_t n)
 {
@@ -509,7 +516,10 @@ int advance(mc_system* s, uint64_t n)
         one.n_sweeps = chunk;
         one.flags = 0;
         TraceRange tr(s->g.spread ? "flipmc sweeps: multi-workgroup launch" : "flipmc sweeps: one-workgroup launch");
-        if (s->g.spread) HIPCHK(hipMemsetAsync(s->host.g_bar, 0, sizeof(uint32_t), s->stream));
+        if (s->g.spread) {
+            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s->stream, s->host.g_bar);
+            HIPCHK(hipGetLastError());
+        }
         hipEvent_t t0 = timing_start(s);
         if (s->g.spread) {
             SpreadSlot sl{};
