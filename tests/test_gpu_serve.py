@@ -21,7 +21,8 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def test_results_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("policy,cap", [("fifo", None), ("sjf", 4)])
+def test_results_same_alone_and_in_the_mix(policy, cap):
     jobs = workloads.serving_stream(n_jobs=14, rate=200.0, seed=3, m_min=125, m_max=1728,
                                     s_min=60, s_max=300)
     # two jobs too large for one workgroup's LDS: the multi-workgroup engine
@@ -30,10 +31,13 @@ def test_results_same_alone_and_in_the_mix():
     prec = flipmc.MC_FP32_DE
     sizes = [flipmc.mc_required_bytes(serve.job_params(j, prec)) for j in jobs]
     budget = 3 * max(sizes)  # a few jobs at a time: later arrivals must wait
-    srv = serve.Server(budget, backend=serve.GpuBackend(prec, max_slots=8), quantum_moves=20_000)
+    srv = serve.Server(budget, backend=serve.GpuBackend(prec, max_slots=8), quantum_moves=20_000,
+                       policy=policy, max_active=cap)
     res = srv.serve(jobs)
     assert sorted(r.job.index for r in res) == list(range(len(jobs)))
     assert srv.peak_bytes <= budget and srv.used == 0
+    if cap:
+        assert srv.peak_active <= cap
     assert srv.launches > len(jobs)  # time-sliced, not one launch per job
     assert any(r.wait > 0 for r in res)
     be = srv.backend
