@@ -1,7 +1,10 @@
 """The relaxation analysis of Sec. III.C and V on device data: the C_2, F_s
 and F_s^cm series of independent runs, their per-particle moments, and what
 mc_dynamics forms from them (chi_4 of Eq. 10, chi_4^self of Eq. 11, rho of
-Eq. 13, the 1/e relaxation times) against the oracle run on the same seeds."""
+Eq. 13, the 1/e relaxation times) against the oracle run on the same seeds;
+and the flip-MC relaxation time of the flexible triangles at the onset
+temperature against the value the paper prints."""
+import os
 import numpy as np
 import pytest
 
@@ -115,3 +118,45 @@ def test_flexible_dynamics_of_independent_runs_match_the_oracle():
         assert (got is None) == (ref is None)
         if ref is not None:
             assert got == pytest.approx(ref, rel=1e-12)
+
+
+def read_paper_onset():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "flip_mc_onset_tau.txt")
+    vals = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = float(v)
+    return vals
+
+
+def test_flip_mc_relaxation_time_at_the_onset_matches_the_paper():
+    # the paper prints the flip-MC relaxation time of its flexible triangles
+    # at the onset temperature (tests/golden/flip_mc_onset_tau.txt, Sec.
+    # III.C); 8 runs of 1000 molecules from their lattice starts, 4000 sweeps
+    # of flip MC, then 6000 sweeps sampled from a new origin: tau of F_s from
+    # mcf_dynamics within [0.75, 1.33] of the printed value (two digits, and
+    # the statistics of 8 short runs; the full protocol of 16 runs and
+    # 20 000 + 20 000 sweeps gives 1.21e3)
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ref = read_paper_onset()
+    R, E, S, M = 8, 4000, 6000, 1000
+    runs = [flipmc.FlexSystem(flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=M, temperature=ref["T_o"],
+                                                        seed=r + 1, p_flip=0.2, resum_interval=1000,
+                                                        obs_interval=0, gofr_interval=0)) for r in range(R)]
+    for done in range(0, E, 2000):
+        flipmc.flex_sweep_many(runs, 2000)
+        torch.cuda.synchronize()
+        print(f"onset tau: equilibration {done + 2000} of {E}", flush=True)
+    for s in runs:
+        s.reset_observables()
+    for done in range(0, S, 2000):
+        flipmc.flex_sweep_many(runs, 2000)
+        torch.cuda.synchronize()
+        print(f"onset tau: sampling {done + 2000} of {S}", flush=True)
+    d = flipmc.mc_dynamics([s.obs_struct() for s in runs], M, atoms_per_molecule=3)
+    for s in runs:
+        s.close()
+    print(f"onset tau: tau_fs = {d['tau_fs']:.1f}", flush=True)
+    assert 0.75 * ref["tau_o"] <= d["tau_fs"] <= 1.33 * ref["tau_o"]
