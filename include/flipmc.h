@@ -544,7 +544,10 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* device_buf, si
 int mc_batch_add(mc_batch* b, mc_system* s, uint64_t n_sweeps, uint32_t* slot);
 
 /* Enqueue one run in which each occupied slot runs a time slice of its
- * remaining sweeps (0 = all remaining).  Every launch of the run is sized to
+ * remaining sweeps (0 = all remaining); with more occupied slots than the
+ * batch's workgroup limit, a run takes the largest multiple of the limit of
+ * them, in turn from run to run, so that no run ends with a partly filled
+ * round of workgroups.  Every launch of the run is sized to
  * the time a 1000-molecule system (k = 2, n_c = 4) takes for
  * max_moves_per_slot moves on one workgroup: each system's slice is that time
  * over its modelled sweep time (one-workgroup cost model, divided by its

@@ -371,6 +371,8 @@ struct mc_batch {
     uint32_t spread_max;              // co-resident workgroups of the cooperative launch
     uint32_t ncu;                     // compute units of the device
     uint32_t wg_limit;                // compute units the batch's runs use at once
+    uint32_t turn;                    // where the next run starts taking systems when
+                                      // there are more than wg_limit
     // slice calibration per engine class (one workgroup with the state in LDS,
     // one workgroup with the state in HBM, multi-workgroup): milliseconds per
     // modelled cycle, learnt from the timed launches of earlier runs
@@ -1197,6 +1199,7 @@ int mc_batch_create(uint32_t max_slots, uint32_t precision, void* device_buf, si
     b->spread_max = 0;
     b->ncu = 1;
     b->wg_limit = 0;
+    b->turn = 0;
     for (int c = 0; c < 3; ++c) {
         b->ms_per_cycle[c] = ms_per_model_cycle() * kCycleRatio[c];
         b->pred[c] = 0.0;
@@ -1354,11 +1357,23 @@ int mc_batch_run(mc_batch* b, uint64_t max_moves_per_slot, uint32_t* n_launched)
     // on its own one.  The engines make the same decisions, so a system may
     // change engine from run to run.
     std::vector<uint32_t> active;
+    for (uint32_t i = 0; i < S; ++i)
+        if (b->sys[i] && b->remaining[i] != 0) active.push_back(i);
+    // More systems than workgroups at once: a run takes whole rounds of them
+    // (the largest multiple of the limit), the systems in turn from run to
+    // run, so that no run ends with a partly filled round of workgroups
+    if (b->wg_limit && active.size() > b->wg_limit) {
+        const size_t A = active.size(), m = (A / b->wg_limit) * b->wg_limit;
+        std::vector<uint32_t> chosen;
+        chosen.reserve(m);
+        for (size_t i = 0; i < m; ++i) chosen.push_back(active[(b->turn + i) % A]);
+        b->turn = (uint32_t)((b->turn + m) % A);
+        std::sort(chosen.begin(), chosen.end());
+        active.swap(chosen);
+    }
     std::vector<std::pair<double, uint32_t>> cand;  // (-remaining moves, slot)
-    for (uint32_t i = 0; i < S; ++i) {
-        mc_system* s = b->sys[i];
-        if (!s || b->remaining[i] == 0) continue;
-        active.push_back(i);
+    for (uint32_t i : active) {
+        const mc_system* s = b->sys[i];
         if (s->g.spread_blocks >= 2 && b->spread_max >= 2)
             cand.emplace_back(-(double)b->remaining[i] * (double)s->p.n_molecules, i);
     }

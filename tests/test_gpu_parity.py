@@ -440,7 +440,7 @@ def test_checkpoint_resume_is_exact():
 
 
 @pytest.mark.parametrize("fp32,workgroups,third", [(False, 0, True), (True, 0, True), (True, 9, True),
-                                                   (False, 8, True), (True, 9, False)])
+                                                   (False, 8, True), (True, 9, False), (True, 4, True)])
 def test_batch_equals_alone(fp32, workgroups, third):
     # one batch over uneven systems gives bitwise the results of running each
     # alone; the last two are beyond one workgroup's LDS and run on the
@@ -448,7 +448,8 @@ def test_batch_equals_alone(fp32, workgroups, third):
     # workgroups, and with a limit of 8 or 9 workgroups they start on one
     # workgroup each and move to the multi-workgroup engine as the others
     # finish (two one-workgroup launches per run then: the LDS class and, on
-    # the batch's third stream or after it, the HBM class)
+    # the batch's third stream or after it, the HBM class); with a limit of 4
+    # each run takes 4 of the 6 systems, in turn
     specs = [(64, 3.0, 2, 2, 3), (216, 1.0, 3, 6, 4), (343, 0.8, 3, 6, 5), (216, 2.0, 2, 2, 6),
              (2197, 1.3, 2, 4, 7), (2744, 2.2, 2, 6, 8)]
     sweeps = [30, 17, 25, 9, 14, 11]
