@@ -488,6 +488,9 @@ def bench_flex_replicas(args, flipmc, torch, R, n_sweeps):
         s.close()
     N = 3 * M
     achieved = terms * FLOP_PER_PAIR_TERM / (ms / 1e3) / 1e12
+    # counters of the 256-replica launch (null for another replica count or
+    # other kernel sources)
+    counted = measured_counters("k_fx_sweeps_flex").get("replicas", {}) if R == 256 else {}
     progress("flex: replicas done")
     return {
         "workload": f"{R} replicas of {M} flexible triangles ({N} atoms each), density {rho}, T={T}, FP64, "
@@ -495,7 +498,9 @@ def bench_flex_replicas(args, flipmc, torch, R, n_sweeps):
         "atom_moves_per_s": R * N * n_sweeps / (ms / 1e3),
         "pair_interactions_per_s": terms / (ms / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["f64"], "kernel": "k_fx_sweeps", "cus_used": min(R, 256)},
+                     "frac": achieved / PEAK_TFLOPS["f64"], "kernel": "k_fx_sweeps", "cus_used": min(R, 256),
+                     "traffic": counted.get("bytes_per_launch"),
+                     "valu_busy_on_its_cus": counted.get("valu_busy_on_its_cus")},
         "ms": ms,
     }
 
