@@ -146,6 +146,16 @@ __device__ __forceinline__ uint32_t fx_cell(double x, double y, double z, const 
            nc * ((uint32_t)fx_axis(y, h[1], D) + nc * (uint32_t)fx_axis(z, h[2], D));
 }
 
+// Whether every atom within distance m of coordinate x (one axis, grid shift
+// h) was sorted into the three cells c - 1, c, c + 1 of that axis: x lies at
+// least m inside the outer faces of the three
+__device__ __forceinline__ bool fx_in_stencil(double x, double h, uint32_t c, const FxK& D, double m)
+{
+    if (D.nc <= 3u) return true;  // the three cells are the whole axis
+    const double t = fx_mi(fx_wrap(x - h, D.L) - (double)c * D.w, D.L, D.invL);
+    return t >= m - D.w && t <= 2.0 * D.w - m;
+}
+
 // Eq. (1) as (2 (s/r)^6 - 1)^2 below the cut-off, FP64.  1 / r^2 is the
 // hardware estimate refined by two Newton steps (within an ulp or two of the
 // quotient; r^2 is a normal number for every pair inside the cut-off).
@@ -353,8 +363,8 @@ __device__ __forceinline__ uint32_t fx_gather_candidates(const FxK& D, const FxV
 // translation that leaves it is rejected.  ncand: the size of the wave's
 // candidate list of this cell's stencil (0xFFFFFFFF: no list).
 __device__ __forceinline__ void fx_attempt(const FxK& D, const FxView& V, uint32_t a, const FxProp& pr,
-                                           uint64_t sweep, uint32_t cell, uint32_t ncand, bool logging,
-                                           const FxWaveLds& W, FxCount& wc)
+                                           uint64_t sweep, const double h[3], uint32_t cell, uint32_t ncand,
+                                           bool logging, const FxWaveLds& W, FxCount& wc)
 {
     const int lane = __lane_id();
     const uint32_t n = D.n, N = D.N;
@@ -459,7 +469,19 @@ __device__ __forceinline__ void fx_attempt(const FxK& D, const FxView& V, uint32
     for (uint32_t s = 0; s < 4; ++s) {
         if (!((changed >> s) & 1u)) continue;  // wave-uniform
         const uint32_t cy_id = V.cell_id[base + s];
-        const bool listed = ncand != 0xFFFFFFFFu && cy_id == cell;  // wave-uniform
+        bool listed = ncand != 0xFFFFFFFFu && cy_id == cell;  // wave-uniform
+        if (!listed && ncand != 0xFFFFFFFFu && flip) {
+            // an atom of another cell whose type changes (its position does
+            // not) is served by the list too when every atom that can reach
+            // it was sorted into the list's 27 cells: those within the largest
+            // cut-off now were within it plus sqrt(3) d at the sort
+            const double m = sqrt(D.rc2f) * fmax(fmax(sig[0], sig[1]), fmax(sig[2], sig[3])) +
+                             1.7320508075688772 * D.dmax + 1e-9;
+            const uint32_t nc = D.nc;
+            listed = fx_in_stencil(ox[s], h[0], cell % nc, D, m) &&
+                     fx_in_stencil(oy[s], h[1], (cell / nc) % nc, D, m) &&
+                     fx_in_stencil(oz[s], h[2], cell / (nc * nc), D, m);
+        }
         uint32_t total = ncand;
         int nseg = 0;
         if (!listed) {
@@ -675,7 +697,7 @@ __global__ void __launch_bounds__(kFxThreads) k_fx_sweeps(FxList list, uint64_t 
                     }
                     for (uint32_t q = 0; q < cnt; ++q)
                         fx_attempt(K, V, (uint32_t)__builtin_amdgcn_readlane((int)at, (int)q),
-                                   fx_prop_of_lane(pr, (int)q), sweep, cell, ncand, logging, W, wc);
+                                   fx_prop_of_lane(pr, (int)q), sweep, h, cell, ncand, logging, W, wc);
                 }
             }
             if (lane == 0) V.ecell[cell] = wc.e;
