@@ -1,4 +1,5 @@
-"""Statistical parity: the FP32 engine samples the oracle's distribution.
+"""Statistical parity: the FP32 engine samples the oracle's distribution, and
+flip MC samples the same equilibrium as local MC on the flexible molecules.
 
 64 molecules at T = 3 (the highest temperature the paper studies), 16
 independent seeds on each side: the engine with FP32 energy differences
@@ -79,4 +80,55 @@ def test_fp32_engine_matches_oracle_within_two_sigma():
         se = np.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
         diff = a.mean() - b.mean()
         print(f"{name}: engine {a.mean():.5f} oracle {b.mean():.5f} diff {diff:.2e} se {se:.2e}", flush=True)
+        assert se > 0 and abs(diff) <= 2.0 * se, name
+
+
+# The paper checks flip MC against local MC by the equilibrium they sample
+# (Sec. II.C): with and without flips the flexible molecules must have the
+# same energy distribution.  125 flexible triangles at T = 3, 32 independent
+# runs (seeds 1 - 32) each equilibrated from its own lattice start by flip MC
+# (p_flip = 0.2) for 2000 sweeps, as the paper prepares its local-MC and MD
+# starts; then 16 of them go on with flip MC and the other 16 with local MC
+# (atom translations only, new seeds) for 2000 sweeps with E/M every 10 sweeps
+# and g(r) every 50.  The run means of E/M and of the intermolecular g(r)
+# over its first-peak window agree within twice the standard error of their
+# difference.  (Local MC from the lattice start itself relaxes the molecules'
+# orientations too slowly for 2000 sweeps to reach equilibrium.)
+FM, FT, FK, FNC, FRHO = 125, 3.0, 3, 3, 1.2
+FEQ, FPROD = 2000, 2000
+
+
+def test_flip_and_local_mc_sample_the_same_flexible_equilibrium():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+    def params(seed, p_flip):
+        return flipmc.mcf_params_default(flipmc.MC_TRIANGLE, n_molecules=FM, temperature=FT,
+                                         colours_per_axis=FK, cells_per_side=FNC, density=FRHO, seed=seed,
+                                         p_flip=p_flip, resum_interval=100, obs_interval=10,
+                                         gofr_interval=50, obs_start=0, gofr_dr=DR, max_samples=256)
+
+    runs = [flipmc.FlexSystem(params(seed, 0.2)) for seed in range(1, 33)]
+    print(f"flexible flip vs local: {len(runs)} runs of {FM} triangles, {FEQ} + {FPROD} sweeps", flush=True)
+    flipmc.flex_sweep_many(runs, FEQ)
+    for i in range(16, 32):
+        st = runs[i].get_state()
+        runs[i].close()
+        runs[i] = flipmc.FlexSystem(params(i + 1001, 0.0), pos=st["pos"], types=st["types"])
+    for s in runs:
+        s.reset_observables()
+    flipmc.flex_sweep_many(runs, FPROD)
+    vals = []
+    for s in runs:
+        o = s.observables()
+        assert o["n_energy_samples"] > 0 and o["n_gofr_frames"] > 0
+        vals.append((o["energy_sum"] / o["n_energy_samples"], _window(o["gofr_norm_inter"], DR)))
+        s.close()
+    vals = np.array(vals)
+    flip, local = vals[:16], vals[16:]
+    for i, name in enumerate(["E/M", "g(r) first peak"]):
+        a, b = flip[:, i], local[:, i]
+        se = np.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+        diff = a.mean() - b.mean()
+        print(f"{name}: flip {a.mean():.5f} local {b.mean():.5f} diff {diff:.2e} se {se:.2e}", flush=True)
         assert se > 0 and abs(diff) <= 2.0 * se, name
